@@ -1,0 +1,441 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix.
+
+None of these tests retypes an oracle formula: each compares the oracle with
+a closed form, a published table or test vector, an invariant of the scheme,
+or an independent formulation solved by a library integrator.
+"""
+import math
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_15122_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10: published known-answer vectors
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert oracle.philox_block(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_philox_stream_counter_layout():
+    out = oracle.philox(0x1234567890ABCDEF, 7, 9, 5)
+    for i in range(5):
+        assert tuple(out[i]) == oracle.philox_block((i, 0, 7, 9), (0x90ABCDEF, 0x12345678))
+
+
+# --------------------------------------------------------------------------
+# Yoshida weights: printed table vs closed form of the symmetric triple jump
+# --------------------------------------------------------------------------
+def _printed_weights():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "yoshida_weights.txt")) if not l.startswith("#")]
+    out = {}
+    for r in rows:
+        out.setdefault(r[0], []).append(Decimal(r[2]))
+    return out
+
+
+def test_yoshida_vv4_weights_closed_form():
+    getcontext().prec = 40
+    c = Decimal(2) ** (Decimal(1) / Decimal(3))
+    w1 = Decimal(1) / (Decimal(2) - c)
+    w2 = -c / (Decimal(2) - c)
+    printed = _printed_weights()["VV4"]
+    # printed w1 agrees with the triple jump to double precision
+    assert abs(printed[0] - w1) < Decimal("3e-16") and printed[2] == printed[0]
+    # printed w2 is a misprint: off by 2.0e-8, so the printed row does not sum to 1
+    assert abs(printed[1] - w2 - Decimal("-1.9956523e-8")) < Decimal("1e-14")
+    assert abs(sum(printed) - 1) > Decimal("1e-8")
+    # the oracle uses the closed form, which sums to one
+    w = oracle.VV_WEIGHTS["vv4"]
+    assert abs(w[0] - float(w1)) <= 5e-16 and abs(w[1] - float(w2)) <= 5e-16
+    assert abs(sum(w) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("name,s", [("VV6", 7), ("VV8", 15), ("VV10", 31)])
+def test_yoshida_higher_rows_sum_to_one(name, s):
+    half = _printed_weights()[name]
+    full = half[:-1] + [half[-1]] + list(reversed(half[:-1]))
+    assert len(full) == s
+    assert abs(sum(full) - 1) < Decimal("1e-18")
+    w = oracle.VV_WEIGHTS[name.lower()]
+    assert len(w) == s and abs(sum(w) - 1.0) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Free massive field: one lattice Fourier mode evolves by an exact 2x2 map
+# whose frequency is the lattice dispersion w^2 = m^2 + sum (2/dx sin(pi n/N))^2
+# --------------------------------------------------------------------------
+def _mode(N, nvec, phase=0.3):
+    x = np.arange(N)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    return np.cos(2 * math.pi * (nvec[0] * X + nvec[1] * Y + nvec[2] * Z) / N + phase)
+
+
+def _flat_free(N, m2, kIR=0.7, nf=1):
+    return dict(model="scalar", nf=nf, N=N, kIR=kIR, alpha=1.0, fstar_over_mp=1.0,
+                m2=(m2, m2), lam=0.0, q=0.0, expansion=False)
+
+
+def _vv_matrix(h, w2):
+    return np.array([[1 - h * h * w2 / 2, h], [-h * w2 * (1 - h * h * w2 / 4), 1 - h * h * w2 / 2]])
+
+
+@pytest.mark.parametrize("nvec", [(1, 0, 0), (2, 3, 1), (4, 4, 4), (0, 5, 2)])
+@pytest.mark.parametrize("integ", ["vv2", "vv4"])
+def test_dispersion_single_mode_vv(nvec, integ):
+    N, m2, h, nsteps = 8, 0.37, 0.05, 40
+    cfg = _flat_free(N, m2)
+    m = oracle.scalar_model(cfg)
+    dx = oracle.lattice_dx(N, cfg["kIR"])
+    w2 = m2 + sum((2.0 / dx * math.sin(math.pi * n / N)) ** 2 for n in nvec)
+    mode = _mode(N, nvec)
+    A0, B0 = 0.8, -0.35
+    phi = (A0 * mode)[None].copy()
+    pi = (B0 * mode)[None].copy()
+    oracle.vv_steps(m, phi, pi, 1.0, 0.0, h, integ, nsteps)
+    if integ == "vv2":
+        M1 = _vv_matrix(h, w2)
+    else:
+        w = oracle.VV_WEIGHTS["vv4"]
+        M1 = _vv_matrix(w[2] * h, w2) @ _vv_matrix(w[1] * h, w2) @ _vv_matrix(w[0] * h, w2)
+    A, B = np.linalg.matrix_power(M1, nsteps) @ np.array([A0, B0])
+    assert np.max(np.abs(phi[0] - A * mode)) < 1e-12
+    assert np.max(np.abs(pi[0] - B * mode)) < 1e-12 * max(1.0, math.sqrt(w2))
+
+
+def test_dispersion_single_mode_leapfrog():
+    N, m2, h, nsteps = 8, 0.21, 0.04, 50
+    nvec = (3, 1, 2)
+    cfg = _flat_free(N, m2)
+    m = oracle.scalar_model(cfg)
+    dx = oracle.lattice_dx(N, cfg["kIR"])
+    w2 = m2 + sum((2.0 / dx * math.sin(math.pi * n / N)) ** 2 for n in nvec)
+    mode = _mode(N, nvec, phase=1.1)
+    A0, B0 = 0.5, 0.25
+    phi = (A0 * mode)[None].copy()
+    pi = (B0 * mode)[None].copy()
+    oracle.lf_startup(m, phi, pi, 1.0, 0.0, h)
+    # start-up: pi_{-1/2} = pi_0 - (h/2) K = pi_0 + (h/2) w^2 phi_0
+    assert np.max(np.abs(pi[0] - (B0 + 0.5 * h * w2 * A0) * mode)) < 1e-13
+    oracle.lf_steps(m, phi, pi, 1.0, 0.0, h, nsteps)
+    L = np.array([[1 - h * h * w2, h], [-h * w2, 1.0]])
+    A, B = np.linalg.matrix_power(L, nsteps) @ np.array([A0, B0 + 0.5 * h * w2 * A0])
+    assert np.max(np.abs(phi[0] - A * mode)) < 1e-12
+    assert np.max(np.abs(pi[0] - B * mode)) < 1e-12
+
+
+def test_dispersion_two_fields_independent_masses():
+    N, h = 6, 0.03
+    cfg = dict(_flat_free(N, 0.0, nf=2), m2=(0.5, 2.0))
+    m = oracle.scalar_model(cfg)
+    dx = oracle.lattice_dx(N, cfg["kIR"])
+    nvec = (1, 2, 0)
+    kl2 = sum((2.0 / dx * math.sin(math.pi * n / N)) ** 2 for n in nvec)
+    mode = _mode(N, nvec)
+    phi = np.stack([mode, 0.5 * mode])
+    pi = np.zeros_like(phi)
+    oracle.vv_steps(m, phi, pi, 1.0, 0.0, h, "vv2", 30)
+    for f, (m2, A0) in enumerate([(0.5, 1.0), (2.0, 0.5)]):
+        A, _ = np.linalg.matrix_power(_vv_matrix(h, m2 + kl2), 30) @ np.array([A0, 0.0])
+        assert np.max(np.abs(phi[f] - A * mode)) < 1e-12
+
+
+def test_vv_phase_converges_to_continuum_at_second_order():
+    # the discrete phase advance per step, acos(1 - h^2 w^2/2), approaches h w as O(h^3)
+    w = 1.7
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        errs.append(abs(math.acos(1 - h * h * w * w / 2) / h - w))
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2
+
+
+# --------------------------------------------------------------------------
+# Time reversibility (Sec. 3.6): flip momenta and b, evolve, flip back
+# --------------------------------------------------------------------------
+def _interacting_cfg(N=6, expansion=True, alpha=1.0):
+    return dict(model="scalar", nf=2, N=N, kIR=0.9, alpha=alpha, fstar_over_mp=2.0,
+                m2=(0.1, 0.2), lam=1.0, q=50.0, expansion=expansion, phi0=(1.0, 0.0))
+
+
+@pytest.mark.parametrize("integ", ["vv2", "vv4"])
+def test_reversibility_vv_expanding(integ):
+    cfg = _interacting_cfg()
+    m = oracle.scalar_model(cfg)
+    st = synth.random_state(cfg, seed=11, amp=0.2, mom=0.3)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    a, b = 1.0, 0.3
+    h, n = 0.01, 60
+    a1, b1 = oracle.vv_steps(m, phi, pi, a, b, h, integ, n)
+    assert abs(a1 - 1.0) > 1e-3
+    pi *= -1
+    a2, b2 = oracle.vv_steps(m, phi, pi, a1, -b1, h, integ, n)
+    pi *= -1
+    assert abs(a2 - a) < 1e-13 and abs(-b2 - b) < 1e-13
+    assert np.max(np.abs(phi - st["phi"])) < 1e-12
+    assert np.max(np.abs(pi - st["pi"])) < 1e-12
+
+
+def test_reversibility_leapfrog_expanding():
+    cfg = _interacting_cfg()
+    m = oracle.scalar_model(cfg)
+    st = synth.random_state(cfg, seed=12, amp=0.2, mom=0.3)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    h, n = 0.01, 60
+    a, b = oracle.lf_startup(m, phi, pi, 1.0, 0.3, h)
+    phi0, pim = phi.copy(), pi.copy()
+    a0, bm = a, b
+    a, b = oracle.lf_steps(m, phi, pi, a, b, h, n)
+    # one more kick gives pi_{n+1/2}, b_{n+1/2}; stepping with -h from there
+    # reproduces the sequence backwards
+    a_k, b_k = oracle.lf_steps(m, phi.copy(), pi.copy(), a, b, h, 0)
+    pf, pp = phi.copy(), pi.copy()
+    K = oracle.kernel(m, a, pf)
+    o = oracle.lf_observe(m, pf, pp, a, b, h)
+    pp_ahead = pp + h * K
+    b_ahead = 2 * o["b"] - b
+    a2, b2 = oracle.lf_steps(m, pf, pp_ahead, a, b_ahead, -h, n)
+    # now pf = phi_0, pp_ahead = pi_{+1/2}; undo the first kick by hand
+    K0 = oracle.kernel(m, a2, pf)
+    assert abs(a2 - a0) < 1e-13
+    assert np.max(np.abs(pf - phi0)) < 1e-12
+    assert np.max(np.abs(pp_ahead - h * K0 - pim)) < 1e-12
+    o0 = oracle.lf_observe(m, phi0, pim, a0, bm, h)
+    assert abs(b2 - (2 * o0["b"] - bm)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Convergence order (Sec. 3.6): error ratio 4 for LF2 / VV2, 16 for VV4
+# --------------------------------------------------------------------------
+def _run_to(cfg, integ, h, T, seed=21):
+    m = oracle.scalar_model(cfg)
+    st = synth.random_state(cfg, seed=seed, amp=0.3, mom=0.3)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    n = int(round(T / h))
+    if integ == "lf2":
+        a, b = oracle.lf_startup(m, phi, pi, 1.0, 0.4, h)
+        a, b = oracle.lf_steps(m, phi, pi, a, b, h, n)
+        o = oracle.lf_observe(m, phi, pi, a, b, h)
+        return phi, a, o["b"], o["hc"]
+    a, b = oracle.vv_steps(m, phi, pi, 1.0, 0.4, h, integ, n)
+    o = oracle.sync_observe(m, phi, pi, a, b)
+    return phi, a, b, o["hc"]
+
+
+@pytest.mark.parametrize("integ,ratio", [("vv2", 4.0), ("lf2", 4.0), ("vv4", 16.0)])
+def test_convergence_order(integ, ratio):
+    cfg = _interacting_cfg(N=6)
+    T = 0.4
+    hs = [0.02, 0.01, 0.005, 0.0025]
+    res = [_run_to(cfg, integ, h, T) for h in hs]
+    ephi = [np.max(np.abs(res[i][0] - res[i + 1][0])) for i in range(3)]
+    ea = [abs(res[i][1] - res[i + 1][1]) for i in range(3)]
+    for e in (ephi, ea):
+        r1, r2 = e[0] / e[1], e[1] / e[2]
+        assert 0.85 * ratio < r2 < 1.15 * ratio, (integ, e)
+        assert 0.75 * ratio < r1 < 1.25 * ratio, (integ, e)
+
+
+@pytest.mark.parametrize("integ,ratio", [("vv2", 4.0), ("vv4", 16.0), ("lf2", 4.0)])
+def test_hubble_constraint_order(integ, ratio):
+    # with b_0 on the constraint, the residual grows as h^2 (VV2, LF2) or h^4 (VV4)
+    cfg = _interacting_cfg(N=6)
+    m = oracle.scalar_model(cfg)
+    st = synth.random_state(cfg, seed=5, amp=0.3, mom=0.3)
+    o = oracle.sync_observe(m, st["phi"], st["pi"], 1.0, 1.0)
+    b0 = math.sqrt(oracle.hc_rhs(m, 1.0, o["rho"]))
+    hcs = []
+    for h in (0.02, 0.01, 0.005):
+        phi, pi = st["phi"].copy(), st["pi"].copy()
+        n = int(round(0.5 / h))
+        if integ == "lf2":
+            a, b = oracle.lf_startup(m, phi, pi, 1.0, b0, h)
+            a, b = oracle.lf_steps(m, phi, pi, a, b, h, n)
+            hcs.append(oracle.lf_observe(m, phi, pi, a, b, h)["hc"])
+        else:
+            a, b = oracle.vv_steps(m, phi, pi, 1.0, b0, h, integ, n)
+            hcs.append(oracle.sync_observe(m, phi, pi, a, b)["hc"])
+    assert 0.7 * ratio < hcs[0] / hcs[1] < 1.3 * ratio, hcs
+    assert 0.7 * ratio < hcs[1] / hcs[2] < 1.3 * ratio, hcs
+
+
+# --------------------------------------------------------------------------
+# Homogeneous pin: a k = 0 lattice against Klein-Gordon plus the first
+# Friedmann equation in cosmic time, integrated by scipy (independent form)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+@pytest.mark.parametrize("integ,order", [("vv4", 4), ("vv2", 2), ("lf2", 2)])
+def test_homogeneous_against_friedmann_ode(alpha, integ, order):
+    from scipy.integrate import solve_ivp
+
+    fmp, lam, m2, phi0, dphi0 = 2.0, 1.0, 0.3, 1.0, -0.2
+    cfg = dict(model="scalar", nf=1, N=4, kIR=1.0, alpha=alpha, fstar_over_mp=fmp,
+               m2=(m2, 0.0), lam=lam, q=0.0, expansion=True)
+    m = oracle.scalar_model(cfg)
+    V = lambda p: 0.5 * m2 * p * p + 0.25 * lam * p ** 4
+    dV = lambda p: m2 * p + lam * p ** 3
+    T = 1.5
+
+    # cosmic time t: phi'' + 3 H phi' + V' = 0, H = (f*/m_p) sqrt(rho/3), a' = a H,
+    # and the alpha-time clock d eta/dt = a^-alpha; stop at eta = T
+    def rhs(t, y):
+        p, v, aa, eta = y
+        H = fmp * math.sqrt((0.5 * v * v + V(p)) / 3.0)
+        return [v, -3.0 * H * v - dV(p), aa * H, aa ** (-alpha)]
+
+    ev = lambda t, y: y[3] - T
+    ev.terminal = True
+    sol = solve_ivp(rhs, [0, 50], [phi0, dphi0, 1.0, 0.0], method="DOP853", rtol=1e-13,
+                    atol=1e-14, events=ev)
+    p_ode, v_ode, a_ode, _ = sol.y_events[0][0]
+
+    errs = []
+    for h in (0.02, 0.01, 0.005):
+        phi = np.full((1, 4, 4, 4), phi0)
+        pi = np.full((1, 4, 4, 4), dphi0)         # pi = a^{3-alpha} phi' and a = 1
+        b0 = math.sqrt(fmp ** 2 / 3.0 * (0.5 * dphi0 ** 2 + V(phi0)))
+        n = int(round(T / h))
+        if integ == "lf2":
+            a, b = oracle.lf_startup(m, phi, pi, 1.0, b0, h)
+            a, b = oracle.lf_steps(m, phi, pi, a, b, h, n)
+            piT = oracle.lf_observe(m, phi, pi, a, b, h)  # noqa: F841 (staggered momentum)
+            errs.append((abs(a - a_ode) / a_ode, abs(phi[0, 0, 0, 0] - p_ode)))
+        else:
+            a, b = oracle.vv_steps(m, phi, pi, 1.0, b0, h, integ, n)
+            # pi = a^{3-alpha} d phi/d eta = a^3 d phi/dt
+            pode = a_ode ** 3 * v_ode
+            errs.append((abs(a - a_ode) / a_ode, abs(phi[0, 0, 0, 0] - p_ode),
+                         abs(pi[0, 0, 0, 0] - pode) / abs(pode)))
+    ratio = 2.0 ** order
+    for j in range(len(errs[0])):
+        r = errs[1][j] / errs[2][j]
+        assert 0.8 * ratio < r < 1.25 * ratio, (errs, j)
+    assert max(errs[2]) < (2e-8 if order == 4 else 2e-4)
+
+
+# --------------------------------------------------------------------------
+# Flat space: symplectic energy error stays bounded, no secular drift
+# --------------------------------------------------------------------------
+def test_flat_space_energy_bounded():
+    cfg = _interacting_cfg(N=6, expansion=False)
+    m = oracle.scalar_model(cfg)
+    st = synth.random_state(cfg, seed=3, amp=0.4, mom=0.4)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    E0 = oracle.sync_observe(m, phi, pi, 1.0, 0.0)["rho"]
+    dev = []
+    for k in range(40):
+        oracle.vv_steps(m, phi, pi, 1.0, 0.0, 0.01, "vv2", 250)
+        dev.append(abs(oracle.sync_observe(m, phi, pi, 1.0, 0.0)["rho"] / E0 - 1))
+    assert max(dev) < 5e-4
+    assert max(dev[20:]) < 2.0 * max(dev[:20]) + 1e-12
+
+
+# --------------------------------------------------------------------------
+# Spectrum: Parseval sum rule, bin placement, brute-force DFT
+# --------------------------------------------------------------------------
+def test_paper_dft_brute_force():
+    N = 5
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((N, N, N))
+    F = oracle.paper_dft(f)
+    n = np.arange(N)
+    for nt in [(1, 0, 0), (2, 3, 4), (4, 4, 1)]:
+        ph = np.exp(2j * math.pi * (nt[0] * n[:, None, None] + nt[1] * n[None, :, None] + nt[2] * n[None, None, :]) / N)
+        assert abs(F[nt] - np.sum(ph * f)) < 1e-11
+    assert np.max(np.abs(oracle.paper_idft(F) - f)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [8, 12])
+def test_spectrum_parseval(N):
+    rng = np.random.default_rng(N)
+    f = 0.3 + rng.standard_normal((N, N, N))
+    sp = oracle.spectrum(f, kIR=0.6)
+    nb = len(sp["delta"])
+    lhs = sum(sp["delta"][b] / b for b in range(1, nb))
+    assert abs(lhs - (np.mean(f ** 2) - np.mean(f) ** 2)) < 1e-12 * np.mean(f ** 2)
+    assert sp["count"].sum() == N ** 3 and sp["count"][0] == 1
+    assert nb == int(math.floor(math.sqrt(3) * N / 2)) + 1
+
+
+def test_spectrum_single_mode_bin():
+    N = 12
+    nvec = (2, 3, 5)
+    f = _mode(N, nvec)
+    sp = oracle.spectrum(f, kIR=1.0)
+    b = int(math.floor(math.sqrt(sum(n * n for n in nvec))))
+    assert abs(sp["S"][b] - N ** 6 / 2) < 1e-6
+    others = np.delete(sp["S"], b)
+    assert np.max(others) < 1e-12 * N ** 6
+
+
+# --------------------------------------------------------------------------
+# Initial conditions (Sec. 7.1): Gaussian statistics of the modes
+# --------------------------------------------------------------------------
+def test_vacuum_ic_mode_statistics():
+    N, nseeds = 12, 48
+    base = dict(synth.config2(q=100.0, N=N), omega_over_f=1.0, expansion=True)
+    lin, par = oracle.conjugate_partner(N)
+    rep = (lin < par)
+    _, _, _, nabs = oracle.reciprocal(N)
+    k = base["kIR"] * nabs
+    dx = oracle.lattice_dx(N, base["kIR"])
+    m2 = oracle.potential_curvature(base, [1.0, 0.0])
+    ratios, z = [], []
+    imag_max = 0.0
+    for s in range(nseeds):
+        cfg = dict(base, seed=100 + s)
+        for f in range(2):
+            F, Fd = oracle.vacuum_modes(cfg, f, m2[f], Hhom=0.37)
+            om = np.sqrt(k * k + m2[f])
+            P = (N / dx) ** 3 / (2.0 * np.where(rep, om, 1.0))
+            ratios.append((np.abs(F) ** 2 / P)[rep])
+            z.append((F.real / np.sqrt(P / 2))[rep])
+            x = oracle.paper_idft(F)
+            imag_max = max(imag_max, np.max(np.abs(x.imag)) / np.max(np.abs(x.real)))
+            # derivative modes: E|df'|^2 = (w^2 + H^2) P
+            if s == 0 and f == 1:
+                rd = (np.abs(Fd) ** 2 / (P * (om * om + 0.37 ** 2)))[rep]
+                assert abs(rd.mean() - 1) < 4 / math.sqrt(rd.size)
+    r = np.concatenate(ratios)
+    assert abs(r.mean() - 1) < 3 * r.std() / math.sqrt(r.size)
+    zz = np.concatenate(z)
+    kurt = np.mean(zz ** 4) / np.mean(zz ** 2) ** 2
+    assert abs(kurt - 3) < 0.1
+    assert imag_max < 1e-12
+
+
+def test_vacuum_ic_hermitian_and_empty_selfconjugate():
+    N = 8
+    cfg = synth.small(synth.config2(q=100.0), N)
+    F, Fd = oracle.vacuum_modes(cfg, 0, 1.0, 0.1)
+    lin, par = oracle.conjugate_partner(N)
+    Ff = F.ravel()
+    assert np.allclose(Ff[par.ravel()], np.conj(Ff[lin.ravel()]), rtol=0, atol=0)
+    selfc = (lin == par).ravel()
+    assert selfc.sum() == 8 and np.all(Ff[selfc] == 0)
+
+
+def test_vacuum_ic_variance_matches_continuum_sum():
+    # <df^2>_V = sum_b dlogk Delta(k) with Delta = k^3/(2 pi^2) P(k) (Sec. 7.1): checked
+    # in ensemble mean against the spectrum of the generated field itself
+    N = 16
+    cfg = dict(synth.small(synth.config2(q=100.0), N), omega_over_f=1.0)
+    vals = []
+    for s in range(8):
+        st = oracle.vacuum_ic(dict(cfg, seed=300 + s, expansion=False))
+        f = st["phi"][1]
+        sp = oracle.spectrum(f, cfg["kIR"])
+        nb = len(sp["delta"])
+        vals.append((sum(sp["delta"][b] / b for b in range(1, nb)), np.var(f)))
+    for a, b in vals:
+        assert abs(a - b) < 1e-10 * b
