@@ -1,0 +1,194 @@
+/*
+ * cosmolat.h -- C ABI of the MI355X (gfx950) lattice library.
+ *
+ * The library advances interacting scalar fields (and a compact U(1) gauge
+ * field) on a periodic N^3 lattice in a self-consistently expanding FLRW
+ * background, following Figueroa, Florio, Torrenti, Valkenburg, "The art of
+ * simulating the early Universe - Part I" (arXiv:2006.15122).  All variables
+ * are the paper's program variables (Sec. 4.1): fields in units of f_*,
+ * times and lengths in units of 1/omega_*, alpha-time d eta = a^-alpha w_* dt.
+ *
+ * Conventions shared by every entry point
+ *  - Return value 0 on success, a negative LAT_E* code on failure; the text
+ *    of the last failure of the calling thread is lattice_last_error().
+ *  - Memory crossing the boundary is owned by the caller.  Device memory
+ *    (the workspace) is allocated by the caller; the library never calls
+ *    hipMalloc.  Host arrays are only read or written during the call.
+ *  - Device work is issued on the HIP stream given to lattice_init.  Calls
+ *    that return host data synchronise that stream; lattice_step does not.
+ *  - One handle per host thread; handles are independent.
+ *  - Site (x, y, z), 0 <= x, y, z < N, has linear index (x*N + y)*N + z
+ *    (z fastest).  Host arrays are FP64, component-major: component c of a
+ *    multi-component array starts at c*N^3.
+ */
+#ifndef COSMOLAT_H
+#define COSMOLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes */
+#define LAT_OK 0
+#define LAT_EINVAL (-1)     /* bad parameters, unsupported N, Courant bound  */
+#define LAT_ENOMEM (-2)     /* workspace or caller buffer too small          */
+#define LAT_EHIP (-3)       /* HIP runtime failure (text in last_error)      */
+#define LAT_ENONFINITE (-4) /* NaN or Inf in the volume averages             */
+#define LAT_ESTATE (-5)     /* call out of order, or invalid state           */
+
+/* Models */
+#define LAT_MODEL_SCALAR 0  /* nf = 1 or 2 real scalars (Sec. 4):
+                               V = sum_f m2[f] phi_f^2/2 + lambda phi_0^4/4
+                                   + q phi_0^2 phi_1^2/2                      */
+#define LAT_MODEL_U1 1      /* complex scalar with compact U(1) links (Sec. 5.3):
+                               V = lambda |phi|^4 + m2[0] |phi|^2            */
+
+/* Integrators (Sec. 3.3-3.5, 4.2-4.4) */
+#define LAT_LF2 0   /* staggered leapfrog, scheme III (pi = a^{3-alpha} phi')    */
+#define LAT_VV2 1   /* velocity Verlet                                          */
+#define LAT_VV4 2   /* Yoshida composition of VV2, 3 sub-steps                  */
+
+/* Storage precision of fields and momenta.  Volume averages, a and b are
+   always accumulated and kept in FP64. */
+#define LAT_FP64 0
+#define LAT_FP32 1
+
+/* Initial conditions */
+#define LAT_IC_VACUUM 0       /* homogeneous values + vacuum fluctuations (Sec. 7) */
+#define LAT_IC_HOMOGENEOUS 1  /* homogeneous values only                           */
+
+typedef struct lattice_params {
+  int32_t model;       /* LAT_MODEL_*                                      */
+  int32_t nf;          /* LAT_MODEL_SCALAR: 1 or 2; LAT_MODEL_U1: 2        */
+  int32_t N;           /* sites per side: multiple of 32, 32 <= N <= 1024  */
+  int32_t integrator;  /* LAT_LF2, LAT_VV2, LAT_VV4                         */
+  int32_t precision;   /* LAT_FP64 or LAT_FP32                              */
+  int32_t expansion;   /* 1: self-consistent a(eta); 0: flat, a = 1, b = 0  */
+  int32_t ic;          /* LAT_IC_*                                          */
+  int32_t reserved;
+  uint64_t seed;       /* random seed of the initial fluctuations           */
+  double kIR;          /* infrared momentum 2 pi/(N dx)                     */
+  double dt;           /* time step (program units)                         */
+  double alpha;        /* alpha-time exponent                               */
+  double fstar_over_mp;/* f_* / m_p                                         */
+  double omega_over_f; /* w_* / f_*, amplitude factor of the vacuum spectrum */
+  double m2[2];        /* mass terms                                         */
+  double lambda;       /* quartic coupling                                   */
+  double q;            /* phi^2 chi^2 coupling                               */
+  double e;            /* gauge coupling g_A Q_A (LAT_MODEL_U1)              */
+  double phi0[2];      /* homogeneous field values                           */
+  double dphi0[2];     /* homogeneous d phi / d eta                          */
+  double a0;           /* initial scale factor (1)                           */
+  double kcut;         /* 0: no cut; else fluctuations only for k <= kcut    */
+} lattice_params;
+
+/* Homogeneous variables of a state.  For LAT_LF2, staggered = 1 means the
+   momenta and b are half a step behind phi and a (pi_{n-1/2}, b_{n-1/2}). */
+typedef struct lattice_scalars {
+  double a;
+  double b;            /* a' = d a / d eta                                  */
+  double eta;
+  int64_t step;
+  int32_t staggered;
+  int32_t reserved;
+} lattice_scalars;
+
+/* Observables (Sec. 4.5, 5.4), all FP64 volume averages in program units. */
+typedef struct lattice_obs {
+  double eta, a, b;    /* b at the same time as a (LF2: mean of the two    */
+                       /* neighbouring half-step values)                   */
+  double H;            /* b / a                                             */
+  double EK, EG, EV;   /* total kinetic, gradient, potential energy         */
+  double EV_term[3];   /* mass, quartic, interaction parts of EV            */
+  double EK_f[2];      /* kinetic energy per scalar field                   */
+  double EG_f[2];      /* gradient energy per scalar field                  */
+  double mean_f[2];    /* <phi_f> (U1: <Re phi>, <Im phi>)                  */
+  double meansq_f[2];  /* <phi_f^2>                                         */
+  double EK_A, EG_A;   /* U(1) electric and magnetic energy                 */
+  double rho, p, w;    /* energy density, pressure, p/rho                   */
+  double hc;           /* Hubble-constraint residual |b^2 - rhs| / b^2      */
+  double gauss;        /* U(1) Gauss-law residual (NaN for scalars)         */
+  int64_t step;
+  int32_t staggered;
+  int32_t reserved;
+} lattice_obs;
+
+typedef struct lattice lattice_t;
+
+/* Device bytes lattice_init needs for p.  Errors: LAT_EINVAL. */
+int lattice_workspace_size(const lattice_params* p, size_t* bytes);
+
+/* Validate p, carve dev_ws (device memory of ws_bytes >= the size above,
+   owned by the caller and kept alive until lattice_destroy), and build the
+   initial state on the device: homogeneous values plus, for LAT_IC_VACUUM,
+   the vacuum fluctuations of Sec. 7.1 (Rayleigh moduli and uniform phases
+   drawn from Philox4x32-10 keyed by seed), b fixed by the Hubble constraint.
+   hip_stream is a hipStream_t (NULL: the default stream).
+   Errors: LAT_EINVAL (parameters, Courant bound dt <= dx/sqrt(3)),
+   LAT_ENOMEM (ws_bytes too small), LAT_EHIP. */
+int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                 lattice_t** out);
+
+/* Replace the state by host FP64 arrays (converted to the storage
+   precision).  Scalar model: fields and momenta are nf*N^3 values.  U1:
+   fields and momenta are 2*N^3 (Re, Im of the complex scalar phi), links
+   3*2*N^3 (direction i, then Re/Im, of V_i), link_momenta 3*N^3 (pi_A,i);
+   links and link_momenta must be NULL for scalar models.
+   Errors: LAT_EINVAL (NULL arrays), LAT_ENONFINITE, LAT_EHIP. */
+int lattice_set_state(lattice_t* h, const double* fields, const double* momenta,
+                      const double* links, const double* link_momenta,
+                      const lattice_scalars* s);
+
+/* Copy the state to host FP64 arrays of the sizes above (any may be NULL to
+   skip it).  Synchronises the stream.  Errors: LAT_EHIP. */
+int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* links,
+                      double* link_momenta, lattice_scalars* s);
+
+/* Advance nsteps >= 0 full time steps with the configured integrator:
+   VV2/VV4 end synchronised at an integer time; LF2 ends staggered
+   (phi_n, a_n; pi_{n-1/2}, b_{n-1/2}).  Asynchronous on the stream.
+   Errors: LAT_EINVAL (nsteps < 0), LAT_EHIP. */
+int lattice_step(lattice_t* h, int64_t nsteps);
+
+/* Observables of the current state.  Synchronises the stream.
+   Errors: LAT_ENONFINITE (NaN/Inf in a volume average), LAT_EHIP. */
+int lattice_energies(lattice_t* h, lattice_obs* out);
+
+/* Radially binned power spectrum of one field component (Sec. 3.1, eq. of
+   the discrete spectrum; Sec. 4.5.2, 5.4.2).  Shell b holds the modes with
+   floor(|n~|) = b, b = 0 .. floor(sqrt(3) N / 2).  Per shell: k[b] = mean
+   k_IR |n~|, sum_sq[b] = sum |f(n~)|^2 with f(n~) = sum_n e^{+2 pi i n~.n/N}
+   f(n), counts[b], and delta[b] = (k_IR b)^3/(2 pi^2) (dx/N)^3 sum_sq[b] /
+   (4 pi b^2) for b >= 1 (0 for b = 0).  which: for scalar models 0..nf-1 =
+   field f, 16+f = momentum f.  Caller-owned host arrays of nbins_cap
+   entries; *nbins receives the number of shells.  Synchronises the stream.
+   Errors: LAT_EINVAL (which), LAT_ENOMEM (nbins_cap too small), LAT_EHIP. */
+int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* k, double* delta,
+                     double* sum_sq, int64_t* counts, int* nbins);
+
+/* Release the handle (not the workspace).  Synchronises the stream. */
+int lattice_destroy(lattice_t* h);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* lattice_last_error(void);
+
+/* Tile shape of the fused scalar pass: threads along z (32 or 64), rows of
+   threads along y, rows per thread, x-planes per block.  lattice_init picks
+   one with the built-in autotuner; this call reports it.  */
+int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc);
+
+/* Force a tile shape (for the autotuner and tests).  Errors: LAT_EINVAL if
+   the shape is not compiled or does not divide N. */
+int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t xc);
+
+/* Device pointer to component c of the current fields (storage precision),
+   and the storage element size in bytes; for zero-copy consumers. */
+int lattice_field_device_ptr(lattice_t* h, int c, void** ptr, int32_t* elem_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COSMOLAT_H */

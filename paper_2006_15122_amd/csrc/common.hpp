@@ -1,0 +1,80 @@
+// Shared declarations of the HIP lattice library (device and host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/cosmolat.h"
+
+namespace cl {
+
+// Thread-local error text, set by every failing entry point.
+void set_error(const std::string& msg);
+
+#define CL_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      ::cl::set_error(std::string(#call) + ": " + hipGetErrorString(_e));         \
+      return LAT_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+// Device-resident homogeneous state and observables of one lattice.
+// Written only by the last-arriving block of a pass (one thread), read by all
+// blocks of the next pass.
+struct DevState {
+  double a;          // scale factor at the current (sub-)step time
+  double b;          // a' (half a step ahead inside a run of passes)
+  double eta;        // program time of a
+  double aux[5];     // reserved
+  lattice_obs obs;   // observables of the last pass
+  unsigned int counter;   // arrival counter of the pass in flight
+  int nonfinite;          // set when a volume average is NaN/Inf
+};
+
+// Parameters of one fused pass (Sec. 3.4/4.4 velocity Verlet with merged
+// kicks; Sec. 4.2.1 staggered leapfrog):
+//   a'   = a + wd h b
+//   phi  = phi + wd h pi a_mid^{-(3-alpha)},       a_mid = (a + a')/2
+//   K    = a'^{1+alpha} lap(phi) - a'^{3+alpha} V_{,phi}
+//   pi   = pi + (wk1 + wk2) h K
+//   b    = b + (wk1 + wk2) h K_a(a', E)
+// In VV mode E_K is taken from pi + wk1 h K (the synchronised momentum); in
+// LF mode from the mean of <pi_in^2> and <pi_out^2>.
+enum PassMode { MODE_VV = 0, MODE_LF = 1 };
+
+struct PassDesc {
+  double wd, wk1, wk2;
+  int mode;
+  int write;    // store phi and pi into the destination buffer
+  int update;   // store a, b, eta into DevState
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), device and host.
+struct Philox4 {
+  uint32_t v[4];
+};
+
+__host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = 0xD2511F53ull * (uint64_t)c0;
+    const uint64_t p1 = 0xCD9E8D57ull * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Philox4 o;
+  o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+}  // namespace cl

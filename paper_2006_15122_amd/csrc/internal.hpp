@@ -1,0 +1,67 @@
+// Internal declarations shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace cl {
+
+constexpr int kSpecBlocks = 1024;  // blocks of the spectrum binning kernel
+
+struct Tiling {
+  int tz, by, ry, xc;
+};
+
+}  // namespace cl
+
+// Opaque handle of the C ABI.
+struct lattice {
+  lattice_params p;
+  hipStream_t stream;
+  char* ws;
+  cl::DevState* st;
+  double* partials;
+  char* spec;           // spectrum partial histograms
+  int64_t max_blocks;
+  int ncomp;
+  size_t comp_bytes;
+  void* buf[2][16];     // ping-pong state buffers, per component
+  void* fft;            // complex FP64 scratch of N^3 entries
+  int cur;
+  double dx;
+  std::vector<double> weights;
+  int staggered;
+  int64_t step;
+  cl::Tiling tile;
+};
+
+namespace cl {
+
+int ncomponents(const lattice_params* p);
+std::vector<double> vv_weights(int integrator);
+int upload_components(lattice* h, const double* const* comps, int n);
+int download_components(lattice* h, double* const* comps, int n);
+int upload_scalars(lattice* h, double a, double b, double eta);
+int init_state(lattice* h);
+int scalar_pass(lattice* h, const PassDesc& pd);
+int scalar_step(lattice* h, int64_t n);
+int scalar_energies(lattice* h);
+int u1_step(lattice* h, int64_t n);
+int u1_energies(lattice* h);
+int u1_init_gauge(lattice* h, double Hhom);
+int run_fft3d(lattice* h, int sign, double scale);
+bool tiling_ok(const lattice* h, const Tiling& t);
+void default_tiling(lattice* h);
+int autotune(lattice* h);
+
+int num_shapes();
+void get_shape(int i, int* tz, int* by, int* ry);
+hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,
+                              int ry, int xc, int swizzle, const double* phys, int expand, const PassDesc& pd,
+                              double* partials, DevState* st, hipStream_t s, int* nblocks_out);
+
+}  // namespace cl

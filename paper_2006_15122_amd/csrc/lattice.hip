@@ -1,0 +1,484 @@
+// Host side of the C ABI declared in include/cosmolat.h: parameter checks,
+// workspace carving, the sequence of fused passes for each integrator, state
+// transfer, observables and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace cl {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Yoshida weights of VVn (Sec. 3.5.1, appendix table).  VV4 is the symmetric
+// triple jump w1 = w3 = 1/(2 - 2^{1/3}), w2 = -2^{1/3}/(2 - 2^{1/3}), which
+// sums to one.
+std::vector<double> vv_weights(int integrator) {
+  if (integrator == LAT_VV4) {
+    const double c = std::cbrt(2.0);
+    const double w1 = 1.0 / (2.0 - c), w2 = -c / (2.0 - c);
+    return {w1, w2, w1};
+  }
+  return {1.0};
+}
+
+static int validate(const lattice_params* p) {
+  if (!p) { set_error("params is NULL"); return LAT_EINVAL; }
+  if (p->model != LAT_MODEL_SCALAR && p->model != LAT_MODEL_U1) { set_error("unknown model"); return LAT_EINVAL; }
+  if (p->model == LAT_MODEL_SCALAR && (p->nf < 1 || p->nf > 2)) { set_error("scalar model needs nf = 1 or 2"); return LAT_EINVAL; }
+  if (p->model == LAT_MODEL_U1 && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
+  if (p->N < 32 || p->N > 1024 || p->N % 32 != 0) { set_error("N must be a multiple of 32 in [32, 1024]"); return LAT_EINVAL; }
+  if (p->integrator < LAT_LF2 || p->integrator > LAT_VV4) { set_error("unknown integrator"); return LAT_EINVAL; }
+  if (p->model == LAT_MODEL_U1 && p->integrator != LAT_LF2) { set_error("U1 model supports LAT_LF2"); return LAT_EINVAL; }
+  if (p->precision != LAT_FP32 && p->precision != LAT_FP64) { set_error("unknown precision"); return LAT_EINVAL; }
+  if (!(p->kIR > 0.0) || !(p->dt > 0.0)) { set_error("kIR and dt must be positive"); return LAT_EINVAL; }
+  const double dx = 2.0 * M_PI / (p->kIR * p->N);
+  if (p->dt > dx / std::sqrt(3.0)) { set_error("time step above the Courant bound dx/sqrt(3)"); return LAT_EINVAL; }
+  if (p->ic != LAT_IC_VACUUM && p->ic != LAT_IC_HOMOGENEOUS) { set_error("unknown ic"); return LAT_EINVAL; }
+  if (p->expansion && !(p->fstar_over_mp > 0.0)) { set_error("expansion needs fstar_over_mp > 0"); return LAT_EINVAL; }
+  if (!(p->a0 > 0.0)) { set_error("a0 must be positive"); return LAT_EINVAL; }
+  return LAT_OK;
+}
+
+// Workspace layout (each region 256-byte aligned):
+//   DevState | pass partials | spectrum partials | state buffer 0 | state buffer 1 | FFT scratch
+static int spec_bins(int N) { return (int)std::floor(std::sqrt(3.0) * N / 2.0) + 1; }
+
+static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, size_t* off_buf0,
+                   size_t* off_buf1, size_t* off_fft, size_t* total, size_t* comp_bytes, int* ncomp,
+                   int64_t* max_blocks) {
+  const int64_t N = p->N;
+  const int64_t V = N * N * N;
+  const size_t elem = p->precision == LAT_FP32 ? 4 : 8;
+  const int nc = ncomponents(p);
+  const int64_t mb = (N / 32) * (N / 8) * (N / 4);
+  const int nacc = 32;
+  size_t o = align_up(sizeof(DevState), 256);
+  *off_part = o;
+  o = align_up(o + (size_t)mb * nacc * sizeof(double), 256);
+  *off_spec = o;
+  o = align_up(o + (size_t)(kSpecBlocks + 2) * spec_bins((int)N) * 24, 256);
+  *off_buf0 = o;
+  *comp_bytes = align_up((size_t)V * elem, 256);
+  o += (size_t)nc * (*comp_bytes);
+  *off_buf1 = o;
+  o += (size_t)nc * (*comp_bytes);
+  *off_fft = o;
+  o = align_up(o + (size_t)V * 16, 256);
+  *total = o;
+  *ncomp = nc;
+  *max_blocks = mb;
+}
+
+int ncomponents(const lattice_params* p) {
+  if (p->model == LAT_MODEL_U1) return 13;  // phi (2), pi (2), links (3x2), piA (3)
+  return 2 * p->nf;
+}
+
+}  // namespace cl
+
+using namespace cl;
+
+extern "C" {
+
+const char* lattice_last_error(void) { return g_err.c_str(); }
+
+int lattice_workspace_size(const lattice_params* p, size_t* bytes) {
+  const int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) { set_error("bytes is NULL"); return LAT_EINVAL; }
+  size_t a, b, c, d, e, t, cb;
+  int nc;
+  int64_t mb;
+  layout(p, &a, &e, &b, &c, &d, &t, &cb, &nc, &mb);
+  *bytes = t;
+  return LAT_OK;
+}
+
+int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, lattice_t** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out || !dev_ws) { set_error("out or dev_ws is NULL"); return LAT_EINVAL; }
+  size_t off_part, off_spec, off_b0, off_b1, off_fft, total, cb;
+  int nc;
+  int64_t mb;
+  layout(p, &off_part, &off_spec, &off_b0, &off_b1, &off_fft, &total, &cb, &nc, &mb);
+  if (ws_bytes < total) {
+    set_error("workspace too small: need " + std::to_string(total) + " bytes");
+    return LAT_ENOMEM;
+  }
+  if (((uintptr_t)dev_ws) % 256 != 0) { set_error("workspace must be 256-byte aligned"); return LAT_EINVAL; }
+  lattice* L = new lattice();
+  L->p = *p;
+  L->stream = (hipStream_t)hip_stream;
+  char* ws = (char*)dev_ws;
+  L->ws = ws;
+  L->st = (DevState*)ws;
+  L->partials = (double*)(ws + off_part);
+  L->spec = ws + off_spec;
+  L->max_blocks = mb;
+  L->ncomp = nc;
+  L->comp_bytes = cb;
+  for (int c = 0; c < nc; ++c) {
+    L->buf[0][c] = ws + off_b0 + (size_t)c * cb;
+    L->buf[1][c] = ws + off_b1 + (size_t)c * cb;
+  }
+  L->fft = ws + off_fft;
+  L->cur = 0;
+  L->dx = 2.0 * M_PI / (p->kIR * p->N);
+  L->weights = vv_weights(p->integrator);
+  L->staggered = 0;
+  L->step = 0;
+  default_tiling(L);
+  rc = init_state(L);
+  if (rc) { delete L; return rc; }
+  if (p->model == LAT_MODEL_SCALAR && p->N >= 128) {
+    rc = autotune(L);
+    if (rc) { delete L; return rc; }
+  }
+  *out = L;
+  return LAT_OK;
+}
+
+int lattice_destroy(lattice_t* h) {
+  if (!h) return LAT_OK;
+  hipStreamSynchronize(h->stream);
+  delete h;
+  return LAT_OK;
+}
+
+int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  if (tz) *tz = h->tile.tz;
+  if (by) *by = h->tile.by;
+  if (ry) *ry = h->tile.ry;
+  if (xc) *xc = h->tile.xc;
+  return LAT_OK;
+}
+
+int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t xc) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  Tiling t{tz, by, ry, xc};
+  if (!tiling_ok(h, t)) { set_error("tile shape not compiled or does not divide N"); return LAT_EINVAL; }
+  h->tile = t;
+  return LAT_OK;
+}
+
+int lattice_field_device_ptr(lattice_t* h, int c, void** ptr, int32_t* elem_bytes) {
+  if (!h || !ptr) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (c < 0 || c >= h->ncomp) { set_error("component out of range"); return LAT_EINVAL; }
+  *ptr = h->buf[h->cur][c];
+  if (elem_bytes) *elem_bytes = h->p.precision == LAT_FP32 ? 4 : 8;
+  return LAT_OK;
+}
+
+int lattice_set_state(lattice_t* h, const double* fields, const double* momenta, const double* links,
+                      const double* link_momenta, const lattice_scalars* s) {
+  if (!h || !fields || !momenta || !s) { set_error("NULL argument"); return LAT_EINVAL; }
+  const bool u1 = h->p.model == LAT_MODEL_U1;
+  if (u1 && (!links || !link_momenta)) { set_error("U1 state needs links and link momenta"); return LAT_EINVAL; }
+  if (!u1 && (links || link_momenta)) { set_error("scalar state takes no links"); return LAT_EINVAL; }
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const int nf = h->p.nf;
+  std::vector<const double*> comps;
+  for (int f = 0; f < nf; ++f) comps.push_back(fields + f * V);
+  for (int f = 0; f < nf; ++f) comps.push_back(momenta + f * V);
+  if (u1) {
+    for (int c = 0; c < 6; ++c) comps.push_back(links + c * V);
+    for (int c = 0; c < 3; ++c) comps.push_back(link_momenta + c * V);
+  }
+  for (size_t c = 0; c < comps.size(); ++c)
+    for (int64_t i = 0; i < V; ++i)
+      if (!std::isfinite(comps[c][i])) { set_error("non-finite value in state"); return LAT_ENONFINITE; }
+  int rc = upload_components(h, comps.data(), (int)comps.size());
+  if (rc) return rc;
+  rc = upload_scalars(h, s->a, s->b, s->eta);
+  if (rc) return rc;
+  h->staggered = s->staggered ? 1 : 0;
+  h->step = s->step;
+  return LAT_OK;
+}
+
+int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* links, double* link_momenta,
+                      lattice_scalars* s) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const int nf = h->p.nf;
+  const bool u1 = h->p.model == LAT_MODEL_U1;
+  std::vector<double*> comps((size_t)h->ncomp, nullptr);
+  for (int f = 0; f < nf; ++f) {
+    if (fields) comps[f] = fields + f * V;
+    if (momenta) comps[nf + f] = momenta + f * V;
+  }
+  if (u1) {
+    for (int c = 0; c < 6; ++c) if (links) comps[4 + c] = links + c * V;
+    for (int c = 0; c < 3; ++c) if (link_momenta) comps[10 + c] = link_momenta + c * V;
+  }
+  int rc = download_components(h, comps.data(), (int)comps.size());
+  if (rc) return rc;
+  if (s) {
+    DevState d;
+    CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    CL_HIP(hipStreamSynchronize(h->stream));
+    s->a = d.a;
+    s->b = d.b;
+    s->eta = d.eta;
+    s->step = h->step;
+    s->staggered = h->staggered;
+    s->reserved = 0;
+  }
+  return LAT_OK;
+}
+
+int lattice_step(lattice_t* h, int64_t nsteps) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  if (nsteps < 0) { set_error("nsteps < 0"); return LAT_EINVAL; }
+  if (h->p.model == LAT_MODEL_U1) return u1_step(h, nsteps);
+  return scalar_step(h, nsteps);
+}
+
+int lattice_energies(lattice_t* h, lattice_obs* out) {
+  if (!h || !out) { set_error("NULL argument"); return LAT_EINVAL; }
+  int rc = (h->p.model == LAT_MODEL_U1) ? u1_energies(h) : scalar_energies(h);
+  if (rc) return rc;
+  DevState d;
+  CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  *out = d.obs;
+  out->step = h->step;
+  out->staggered = h->staggered;
+  if (d.nonfinite) { set_error("non-finite volume average"); return LAT_ENONFINITE; }
+  return LAT_OK;
+}
+
+}  // extern "C"
+
+namespace cl {
+
+// ---------------------------------------------------------------------------
+// state transfer
+// ---------------------------------------------------------------------------
+int upload_components(lattice* h, const double* const* comps, int n) {
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const bool f32 = h->p.precision == LAT_FP32;
+  std::vector<float> tmp32;
+  for (int c = 0; c < n; ++c) {
+    void* d = h->buf[h->cur][c];
+    if (f32) {
+      tmp32.resize((size_t)V);
+      for (int64_t i = 0; i < V; ++i) tmp32[(size_t)i] = (float)comps[c][i];
+      CL_HIP(hipMemcpyAsync(d, tmp32.data(), (size_t)V * 4, hipMemcpyHostToDevice, h->stream));
+      CL_HIP(hipStreamSynchronize(h->stream));
+    } else {
+      CL_HIP(hipMemcpyAsync(d, comps[c], (size_t)V * 8, hipMemcpyHostToDevice, h->stream));
+      CL_HIP(hipStreamSynchronize(h->stream));
+    }
+  }
+  return LAT_OK;
+}
+
+int download_components(lattice* h, double* const* comps, int n) {
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const bool f32 = h->p.precision == LAT_FP32;
+  std::vector<float> tmp32;
+  for (int c = 0; c < n; ++c) {
+    if (!comps[c]) continue;
+    const void* d = h->buf[h->cur][c];
+    if (f32) {
+      tmp32.resize((size_t)V);
+      CL_HIP(hipMemcpyAsync(tmp32.data(), d, (size_t)V * 4, hipMemcpyDeviceToHost, h->stream));
+      CL_HIP(hipStreamSynchronize(h->stream));
+      for (int64_t i = 0; i < V; ++i) comps[c][i] = (double)tmp32[(size_t)i];
+    } else {
+      CL_HIP(hipMemcpyAsync(comps[c], d, (size_t)V * 8, hipMemcpyDeviceToHost, h->stream));
+      CL_HIP(hipStreamSynchronize(h->stream));
+    }
+  }
+  return LAT_OK;
+}
+
+int upload_scalars(lattice* h, double a, double b, double eta) {
+  DevState d;
+  std::memset(&d, 0, sizeof(d));
+  d.a = a;
+  d.b = b;
+  d.eta = eta;
+  d.obs.gauss = NAN;
+  CL_HIP(hipMemcpyAsync(h->st, &d, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  return LAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scalar passes
+// ---------------------------------------------------------------------------
+static void phys_of(const lattice* h, double* phys) {
+  phys[0] = h->dx;
+  phys[1] = h->p.alpha;
+  phys[2] = h->p.fstar_over_mp * h->p.fstar_over_mp;
+  phys[3] = h->p.m2[0];
+  phys[4] = h->p.m2[1];
+  phys[5] = h->p.lambda;
+  phys[6] = h->p.q;
+  phys[7] = h->p.dt;
+}
+
+int scalar_pass(lattice* h, const PassDesc& pd) {
+  double phys[8];
+  phys_of(h, phys);
+  const int nf = h->p.nf;
+  const void* src[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* dst[4] = {nullptr, nullptr, nullptr, nullptr};
+  // component order in buffers: phi_0..phi_{nf-1}, pi_0..pi_{nf-1};
+  // kernel slots: phi_0, phi_1, pi_0, pi_1
+  for (int f = 0; f < nf; ++f) {
+    src[f] = h->buf[h->cur][f];
+    src[2 + f] = h->buf[h->cur][nf + f];
+    dst[f] = h->buf[1 - h->cur][f];
+    dst[2 + f] = h->buf[1 - h->cur][nf + f];
+  }
+  int nb = 0;
+  hipError_t e = launch_scalar_pass(h->p.precision == LAT_FP32, nf, src, dst, h->p.N, h->tile.tz, h->tile.by,
+                                    h->tile.ry, h->tile.xc, 1, phys, h->p.expansion, pd, h->partials, h->st,
+                                    h->stream, &nb);
+  if (e != hipSuccess) {
+    set_error(std::string("scalar pass launch: ") + hipGetErrorString(e));
+    return LAT_EHIP;
+  }
+  if (pd.write) h->cur ^= 1;
+  return LAT_OK;
+}
+
+static PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update) {
+  PassDesc p;
+  p.wd = wd;
+  p.wk1 = wk1;
+  p.wk2 = wk2;
+  p.mode = mode;
+  p.write = write;
+  p.update = update;
+  return p;
+}
+
+int scalar_step(lattice* h, int64_t n) {
+  int rc;
+  if (h->p.integrator == LAT_LF2) {
+    if (!h->staggered) {
+      // pi_{-1/2} = pi_0 - (h/2) K, b_{-1/2} = b_0 - (h/2) K_a
+      rc = scalar_pass(h, pass(0.0, 0.0, -0.5, MODE_VV, 1, 1));
+      if (rc) return rc;
+      h->staggered = 1;
+    }
+    if (n == 0) return LAT_OK;
+    rc = scalar_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 1, 1));  // kick at phi_n
+    if (rc) return rc;
+    for (int64_t j = 1; j < n; ++j) {
+      rc = scalar_pass(h, pass(1.0, 0.0, 1.0, MODE_LF, 1, 1));  // drift, then kick
+      if (rc) return rc;
+    }
+    rc = scalar_pass(h, pass(1.0, 0.0, 0.0, MODE_LF, 1, 1));  // closing drift
+    if (rc) return rc;
+    h->step += n;
+    return LAT_OK;
+  }
+  if (n == 0) return LAT_OK;
+  const std::vector<double>& w = h->weights;
+  const int s = (int)w.size();
+  rc = scalar_pass(h, pass(0.0, 0.0, 0.5 * w[0], MODE_VV, 1, 1));  // opening half kick
+  if (rc) return rc;
+  for (int64_t it = 0; it < n; ++it) {
+    for (int p = 0; p < s; ++p) {
+      const bool last = (it == n - 1) && (p == s - 1);
+      const double nxt = last ? 0.0 : w[(p + 1) % s];
+      rc = scalar_pass(h, pass(w[p], 0.5 * w[p], 0.5 * nxt, MODE_VV, 1, 1));
+      if (rc) return rc;
+    }
+  }
+  h->step += n;
+  return LAT_OK;
+}
+
+int scalar_energies(lattice* h) {
+  if (h->p.integrator == LAT_LF2 && h->staggered) return scalar_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 0, 0));
+  return scalar_pass(h, pass(0.0, 0.0, 0.0, MODE_VV, 0, 0));
+}
+
+// ---------------------------------------------------------------------------
+// tiling
+// ---------------------------------------------------------------------------
+bool tiling_ok(const lattice* h, const Tiling& t) {
+  bool compiled = false;
+  for (int i = 0; i < num_shapes(); ++i) {
+    int tz, by, ry;
+    get_shape(i, &tz, &by, &ry);
+    if (tz == t.tz && by == t.by && ry == t.ry) compiled = true;
+  }
+  if (!compiled) return false;
+  const int N = h->p.N;
+  const int ty = t.by * t.ry;
+  if (N % t.tz || N % ty || t.xc < 1 || N % t.xc) return false;
+  const int64_t nb = (int64_t)(N / t.tz) * (N / ty) * (N / t.xc);
+  return nb <= h->max_blocks;
+}
+
+void default_tiling(lattice* h) {
+  const int N = h->p.N;
+  Tiling cands[] = {{64, 4, 4, 16}, {64, 4, 2, 8}, {32, 8, 2, 8}, {32, 4, 4, 4}};
+  for (const Tiling& t : cands)
+    if (tiling_ok(h, t)) { h->tile = t; return; }
+  h->tile = Tiling{32, 4, 4, 4};
+  (void)N;
+}
+
+// Time every compiled tile shape and x-chunk on the real state with a full
+// pass that writes the scratch buffer and leaves a, b untouched; keep the
+// fastest.  The state itself is not modified (the written buffer is the
+// ping-pong scratch).
+int autotune(lattice* h) {
+  hipEvent_t e0, e1;
+  CL_HIP(hipEventCreate(&e0));
+  CL_HIP(hipEventCreate(&e1));
+  const int xcs[] = {4, 8, 16, 32};
+  float best = 1e30f;
+  Tiling bt = h->tile;
+  const int saved_cur = h->cur;
+  for (int i = 0; i < num_shapes(); ++i) {
+    int tz, by, ry;
+    get_shape(i, &tz, &by, &ry);
+    for (int xc : xcs) {
+      Tiling t{tz, by, ry, xc};
+      if (!tiling_ok(h, t)) continue;
+      h->tile = t;
+      PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
+      int rc = scalar_pass(h, pd);  // warm-up
+      h->cur = saved_cur;
+      if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
+      CL_HIP(hipEventRecord(e0, h->stream));
+      for (int k = 0; k < 3; ++k) {
+        rc = scalar_pass(h, pd);
+        h->cur = saved_cur;
+        if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
+      }
+      CL_HIP(hipEventRecord(e1, h->stream));
+      CL_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; bt = t; }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  h->tile = bt;
+  return LAT_OK;
+}
+
+}  // namespace cl

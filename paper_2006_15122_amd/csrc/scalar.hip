@@ -1,0 +1,430 @@
+// Fused scalar-field pass for gfx950: drift, 7-point stencil kick, FP64
+// volume averages and the scale-factor update, in one sweep over the lattice.
+//
+// Method (arXiv:2006.15122): Hamiltonian form of the scalar EOM (Sec. 4.3)
+//   phi' = a^{-(3-alpha)} pi,  pi' = a^{1+alpha} lap phi - a^{3+alpha} V_{,phi},
+//   b'   = (1/3)(f*/m_p)^2 a^{1+2 alpha}[(alpha-2) E_K + alpha E_G + (alpha+1) E_V],
+// integrated by velocity Verlet / Yoshida (Sec. 4.4) or staggered leapfrog
+// scheme III (Sec. 4.2.1).  Consecutive kicks of the Verlet chain are merged
+// (Sec. 3.4: velocity Verlet is leapfrog plus a synchronising half kick), so
+// one pass = drift of sub-step p followed by the kick that closes p and opens
+// p+1.  The drift needs the global energies of the previous pass; the last
+// block to finish a pass reduces them and advances a and b in FP64.
+//
+// Tiling: a block owns a TY x TZ tile of the (y, z) plane and marches along x
+// over XC planes.  z is the fastest index, so each wavefront loads contiguous
+// rows.  The drifted plane x (with a one-site y/z halo) sits in LDS; the x-1,
+// x+1 neighbours stay in registers.  Halo sites are drifted redundantly by the
+// neighbouring tiles, which removes a separate drift pass over HBM.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace cl {
+
+template <typename T>
+struct ScalarArgs {
+  const T* src[4];   // phi_0, phi_1, pi_0, pi_1 (nf = 1 uses entries 0 and 2)
+  T* dst[4];
+  int N;
+  int XC;            // x-planes per block
+  int swizzle;       // map consecutive blocks of one XCD to neighbouring tiles
+  double dx, alpha, fmp2, m2_0, m2_1, lam, q, h;
+  int expand;
+  PassDesc pd;
+  double* partials;  // [gridDim.x][NACC]
+  DevState* st;
+};
+
+template <int NF>
+struct Acc {
+  static constexpr int N = 5 * NF + 3;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, int NF>
+__device__ __forceinline__ T dpot(int f, const T (&p)[NF], T m2_0, T m2_1, T lam, T q) {
+  if (f == 0) {
+    T d = m2_0 * p[0] + lam * p[0] * p[0] * p[0];
+    if constexpr (NF > 1) d += q * p[1] * p[1] * p[0];
+    return d;
+  } else {
+    if constexpr (NF > 1) return m2_1 * p[1] + q * p[0] * p[0] * p[1];
+    return T(0);
+  }
+}
+
+// Reduce the per-thread accumulators of a block into partials[blockIdx.x];
+// the last block to arrive combines all partials in block order and
+// performs the FP64 scale-factor update.
+template <typename T, int NF, int NT>
+__device__ void finish_pass(const ScalarArgs<T>& A, double (&acc)[Acc<NF>::N], double anew,
+                            double a_in, double b_in) {
+  constexpr int NACC = Acc<NF>::N;
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW][NACC];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid < NACC) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][tid];
+    A.partials[(size_t)blockIdx.x * NACC + tid] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(&A.st->counter, 1u);
+    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  double tot[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
+  for (int b = tid; b < nb; b += NT) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) tot[k] += __builtin_nontemporal_load(&A.partials[(size_t)b * NACC + k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wave_sum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double S[NACC];
+  for (int k = 0; k < NACC; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][k];
+    S[k] = s;
+  }
+  const double V = (double)A.N * (double)A.N * (double)A.N;
+  const double al = A.alpha;
+  const double a6 = pow(anew, 6.0), a2 = anew * anew, dx2 = A.dx * A.dx;
+  lattice_obs o;
+  // obs is a plain struct; zero-fill the fields this model does not use
+  o.EK = o.EG = 0.0;
+  o.EK_f[0] = o.EK_f[1] = o.EG_f[0] = o.EG_f[1] = 0.0;
+  o.mean_f[0] = o.mean_f[1] = o.meansq_f[0] = o.meansq_f[1] = 0.0;
+  bool bad = false;
+  for (int f = 0; f < NF; ++f) {
+    const double k1 = S[5 * f + 0] / V, k2 = S[5 * f + 1] / V;
+    const double ek = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+    const double eg = S[5 * f + 2] / V / (2.0 * a2 * dx2);
+    o.EK_f[f] = ek;
+    o.EG_f[f] = eg;
+    o.mean_f[f] = S[5 * f + 3] / V;
+    o.meansq_f[f] = S[5 * f + 4] / V;
+    o.EK += ek;
+    o.EG += eg;
+  }
+  o.EV_term[0] = S[5 * NF + 0] / V;
+  o.EV_term[1] = S[5 * NF + 1] / V;
+  o.EV_term[2] = S[5 * NF + 2] / V;
+  o.EV = o.EV_term[0] + o.EV_term[1] + o.EV_term[2];
+  for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
+  const double rho = o.EK + o.EG + o.EV;
+  double b_out = b_in, b_sync = b_in, hc = 0.0;
+  if (A.expand) {
+    const double Ka = A.fmp2 / 3.0 * pow(anew, 1.0 + 2.0 * al) *
+                      ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV);
+    b_out = b_in + (A.pd.wk1 + A.pd.wk2) * A.h * Ka;
+    b_sync = (A.pd.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in + A.pd.wk1 * A.h * Ka;
+    const double rhs = A.fmp2 / 3.0 * pow(anew, 2.0 * (al + 1.0)) * rho;
+    hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
+  }
+  const double eta_new = A.st->eta + A.pd.wd * A.h;
+  o.eta = eta_new;
+  o.a = anew;
+  o.b = b_sync;
+  o.H = b_sync / anew;
+  o.EK_A = o.EG_A = 0.0;
+  o.rho = rho;
+  o.p = o.EK - o.EG / 3.0 - o.EV;
+  o.w = rho != 0.0 ? o.p / rho : 0.0;
+  o.hc = hc;
+  o.gauss = NAN;
+  o.step = 0;
+  o.staggered = (A.pd.mode == MODE_LF) ? 1 : 0;
+  o.reserved = 0;
+  A.st->obs = o;
+  if (bad) A.st->nonfinite = 1;
+  if (A.pd.update) {
+    A.st->a = anew;
+    A.st->b = b_out;
+    A.st->eta = eta_new;
+  }
+  (void)a_in;
+  A.st->counter = 0u;
+}
+
+template <typename T, int NF, int TZ, int BY, int RY>
+__global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
+  constexpr int TY = BY * RY;
+  constexpr int NT = TZ * BY;
+  constexpr int LZ = TZ + 2;
+  constexpr int NACC = Acc<NF>::N;
+  __shared__ T lds[NF][TY + 2][LZ];
+
+  const int N = A.N;
+  const int tid = threadIdx.x;
+  const int tz = tid % TZ, ty = tid / TZ;
+  const int nzt = N / TZ, nyt = N / TY;
+  int bid = blockIdx.x;
+  if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const int zt = bid % nzt;
+  bid /= nzt;
+  const int yt = bid % nyt;
+  const int xcI = bid / nyt;
+  const int z0 = zt * TZ, y0 = yt * TY, x0 = xcI * A.XC;
+  const size_t NN = (size_t)N * N;
+
+  // homogeneous coefficients (FP64, identical in every block)
+  const double a_in = A.st->a, b_in = A.st->b;
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double amid = 0.5 * (a_in + anew);
+  const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
+  const T clap = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cpot = (T)pow(anew, 3.0 + A.alpha);
+  const T ckick = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
+  const T cE = (T)((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
+  const T m2_0 = (T)A.m2_0, m2_1 = (T)A.m2_1, lam = (T)A.lam, q = (T)A.q;
+  const T half = T(0.5), quarter = T(0.25);
+
+  double acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+
+  const int z = z0 + tz;
+  T pm[NF][RY], pc[NF][RY], pn[NF][RY], qc[NF][RY], qn[NF][RY];
+
+  // halo item owned by this thread (at most one: 2 TZ + 2 TY <= NT)
+  constexpr int NH = 2 * TZ + 2 * TY;
+  static_assert(NH <= NT, "halo larger than block");
+  int hy = 0, hz = 0, hly = 0, hlz = 0;
+  const bool has_halo = tid < NH;
+  if (has_halo) {
+    if (tid < TZ) { hly = 0; hlz = 1 + tid; hy = (y0 - 1 + N) % N; hz = z0 + tid; }
+    else if (tid < 2 * TZ) { hly = TY + 1; hlz = 1 + tid - TZ; hy = (y0 + TY) % N; hz = z0 + tid - TZ; }
+    else if (tid < 2 * TZ + TY) { hly = 1 + tid - 2 * TZ; hlz = 0; hy = y0 + tid - 2 * TZ; hz = (z0 - 1 + N) % N; }
+    else { hly = 1 + tid - 2 * TZ - TY; hlz = TZ + 1; hy = y0 + tid - 2 * TZ - TY; hz = (z0 + TZ) % N; }
+  }
+  T hp[NF], hq[NF];
+
+  auto row_off = [&](int x, int y) -> size_t { return (size_t)x * NN + (size_t)y * N; };
+
+  // load own columns of plane x (raw phi and pi)
+  auto load_own = [&](int x, T (&p)[NF][RY], T (&pq)[NF][RY]) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const size_t o = row_off(x, y0 + r * BY + ty) + z;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        p[f][r] = A.src[f][o];
+        pq[f][r] = A.src[2 + f][o];
+      }
+    }
+  };
+  auto load_halo = [&](int x) {
+    if (has_halo) {
+      const size_t o = row_off(x, hy) + hz;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        hp[f] = A.src[f][o];
+        hq[f] = A.src[2 + f][o];
+      }
+    }
+  };
+  auto store_lds = [&](const T (&p)[NF][RY]) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) lds[f][1 + r * BY + ty][1 + tz] = p[f][r];
+    if (has_halo) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) lds[f][hly][hlz] = hp[f] + cdrift * hq[f];
+    }
+  };
+
+  // prologue: plane x0-1 (own columns, drifted) and plane x0
+  {
+    const int xm = (x0 - 1 + N) % N;
+    load_own(xm, pm, qn);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) pm[f][r] = pm[f][r] + cdrift * qn[f][r];
+    load_own(x0, pc, qc);
+    load_halo(x0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) pc[f][r] = pc[f][r] + cdrift * qc[f][r];
+    store_lds(pc);
+  }
+
+  for (int i = 0; i < A.XC; ++i) {
+    const int x = x0 + i;
+    const int xp = (x + 1) % N;
+    // issue loads of plane x+1 before the stencil of plane x
+    load_own(xp, pn, qn);
+    const bool more = (i + 1 < A.XC);
+    if (more) load_halo(xp);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 1 + r * BY + ty;
+      T cur[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cur[f] = pc[f][r];
+      const size_t o = row_off(x, y0 + r * BY + ty) + z;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const T pnext = pn[f][r] + cdrift * qn[f][r];
+        const T yp = lds[f][ly + 1][1 + tz], ym = lds[f][ly - 1][1 + tz];
+        const T zp = lds[f][ly][2 + tz], zm = lds[f][ly][tz];
+        const T lap = (pm[f][r] + pnext) + (yp + ym) + (zp + zm) - T(6) * cur[f];
+        const T K = clap * lap - cpot * dpot<T, NF>(f, cur, m2_0, m2_1, lam, q);
+        const T pin = qc[f][r];
+        const T pout = pin + ckick * K;
+        const T pe = pin + cE * K;
+        if (A.pd.write) {
+          A.dst[f][o] = cur[f];
+          A.dst[2 + f][o] = pout;
+        }
+        const T gx = pnext - cur[f], gy = yp - cur[f], gz = zp - cur[f];
+        acc[5 * f + 0] += (double)(pin * pin);
+        acc[5 * f + 1] += (double)(pe * pe);
+        acc[5 * f + 2] += (double)(gx * gx + gy * gy + gz * gz);
+        acc[5 * f + 3] += (double)cur[f];
+        acc[5 * f + 4] += (double)(cur[f] * cur[f]);
+      }
+      const T p2 = cur[0] * cur[0];
+      if constexpr (NF > 1) {
+        const T c2 = cur[1] * cur[1];
+        acc[5 * NF + 0] += (double)(half * (m2_0 * p2 + m2_1 * c2));
+        acc[5 * NF + 2] += (double)(half * q * p2 * c2);
+      } else {
+        acc[5 * NF + 0] += (double)(half * m2_0 * p2);
+      }
+      acc[5 * NF + 1] += (double)(quarter * lam * p2 * p2);
+    }
+    __syncthreads();
+    // shift registers: plane x+1 becomes current
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        pm[f][r] = pc[f][r];
+        pc[f][r] = pn[f][r] + cdrift * qn[f][r];
+        qc[f][r] = qn[f][r];
+      }
+    if (more) store_lds(pc);
+  }
+  finish_pass<T, NF, NT>(A, acc, anew, a_in, b_in);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch table
+// ---------------------------------------------------------------------------
+struct Shape {
+  int tz, by, ry;
+};
+
+template <typename T, int NF, int TZ, int BY, int RY>
+hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((scalar_pass_kernel<T, NF, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
+  return hipGetLastError();
+}
+
+#define CL_SHAPES(X, T, NF) \
+  X(T, NF, 64, 4, 4)        \
+  X(T, NF, 64, 4, 2)        \
+  X(T, NF, 64, 8, 2)        \
+  X(T, NF, 64, 4, 8)        \
+  X(T, NF, 32, 8, 2)        \
+  X(T, NF, 32, 4, 4)        \
+  X(T, NF, 32, 8, 4)
+
+static const Shape kShapes[] = {{64, 4, 4}, {64, 4, 2}, {64, 8, 2}, {64, 4, 8},
+                                {32, 8, 2}, {32, 4, 4}, {32, 8, 4}};
+static const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+template <typename T, int NF>
+hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s) {
+#define X(TT, NFF, a, b, c) \
+  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, a, b, c>(A, nblocks, s);
+  CL_SHAPES(X, T, NF)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int num_shapes() { return kNumShapes; }
+void get_shape(int i, int* tz, int* by, int* ry) {
+  *tz = kShapes[i].tz;
+  *by = kShapes[i].by;
+  *ry = kShapes[i].ry;
+}
+
+int nacc_for(int nf) { return 5 * nf + 3; }
+
+// Launch one pass.  buffers: src/dst arrays [4] in storage precision.
+hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz,
+                              int by, int ry, int xc, int swizzle, const double* phys, int expand,
+                              const PassDesc& pd, double* partials, DevState* st, hipStream_t s,
+                              int* nblocks_out) {
+  const Shape sh{tz, by, ry};
+  const int ty = by * ry;
+  const int nblocks = (N / tz) * (N / ty) * (N / xc);
+  if (nblocks_out) *nblocks_out = nblocks;
+  const int swz = (swizzle && (nblocks % 8 == 0)) ? 1 : 0;
+  auto fill = [&](auto& A, auto* tag) {
+    using TT = std::remove_pointer_t<decltype(tag)>;
+    for (int i = 0; i < 4; ++i) {
+      A.src[i] = static_cast<const TT*>(src[i]);
+      A.dst[i] = static_cast<TT*>(dst[i]);
+    }
+    A.N = N;
+    A.XC = xc;
+    A.swizzle = swz;
+    A.dx = phys[0];
+    A.alpha = phys[1];
+    A.fmp2 = phys[2];
+    A.m2_0 = phys[3];
+    A.m2_1 = phys[4];
+    A.lam = phys[5];
+    A.q = phys[6];
+    A.h = phys[7];
+    A.expand = expand;
+    A.pd = pd;
+    A.partials = partials;
+    A.st = st;
+  };
+  if (fp32) {
+    ScalarArgs<float> A;
+    fill(A, (float*)nullptr);
+    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s) : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s);
+  } else {
+    ScalarArgs<double> A;
+    fill(A, (double*)nullptr);
+    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s) : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s);
+  }
+}
+
+}  // namespace cl

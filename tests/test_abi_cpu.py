@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/cosmolat.h declares, and validates parameters."""
+import os
+import re
+
+import pytest
+
+from paper_2006_15122_amd import lattice, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cosmolat.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(lattice_\w+)\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lattice.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lattice.EXPORTS) == names
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    import ctypes
+    import subprocess
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "%s"\n'
+        'int main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu\\n", sizeof(lattice_params),'
+        ' sizeof(lattice_scalars), sizeof(lattice_obs), offsetof(lattice_params, seed),'
+        ' offsetof(lattice_params, kcut), offsetof(lattice_obs, gauss), offsetof(lattice_obs, step));'
+        ' return 0;}\n' % os.path.join(ROOT, "include", "cosmolat.h"))
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(lattice.Params), ctypes.sizeof(lattice.Scalars), ctypes.sizeof(lattice.Obs),
+            lattice.Params.seed.offset, lattice.Params.kcut.offset, lattice.Obs.gauss.offset,
+            lattice.Obs.step.offset]
+    assert got == want
+
+
+def test_workspace_size_covers_state():
+    c32 = synth.small(synth.config2(), 32)
+    c64 = synth.small(synth.config2(), 64)
+    s32, s64 = lattice.workspace_size(c32), lattice.workspace_size(c64)
+    assert s64 > s32
+    # two ping-pong copies of 4 FP32 arrays plus complex FP64 FFT scratch at least
+    assert s64 >= 2 * 4 * 4 * 64 ** 3 + 16 * 64 ** 3
+    c1 = synth.config1()
+    assert lattice.workspace_size(c1) >= 2 * 2 * 8 * 32 ** 3 + 16 * 32 ** 3
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(N=48), "LAT_EINVAL"),            # not a multiple of 32
+    (dict(N=16), "LAT_EINVAL"),
+    (dict(dt=1.0), "LAT_EINVAL"),          # above the Courant bound dx/sqrt(3)
+    (dict(nf=3), "LAT_EINVAL"),
+    (dict(kIR=-1.0), "LAT_EINVAL"),
+])
+def test_invalid_parameters_rejected(bad, code):
+    cfg = dict(synth.small(synth.config2(), 64), **bad)
+    with pytest.raises(lattice.LatticeError) as e:
+        lattice.workspace_size(cfg)
+    assert code in str(e.value)
+    assert lattice.lib().lattice_last_error().decode() != ""
+
+
+def test_courant_bound_edge():
+    cfg = synth.small(synth.config2(), 64)
+    import math
+    dx = 2 * math.pi / (cfg["kIR"] * 64)
+    lattice.workspace_size(dict(cfg, dt=dx / math.sqrt(3) * 0.999))
+    with pytest.raises(lattice.LatticeError):
+        lattice.workspace_size(dict(cfg, dt=dx / math.sqrt(3) * 1.001))
