@@ -1,0 +1,169 @@
+"""Benchmark of the lattice hot path on one MI355X.
+
+A step is one full velocity-Verlet (VV2) time step of the two-field model
+V = phi^4/4 + q phi^2 chi^2/2 on a 256^3 lattice (FP32 fields and momenta,
+FP64 volume averages, self-consistent expansion): drift, stencil kick,
+energy reductions and scale-factor update, all in the fused HIP pass.
+Inputs are the seeded vacuum initial conditions built on the device.
+
+Prints one JSON line.  value = lattice site-updates per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+BYTES_PER_SITE_VV2_NF2_FP32 = 32  # read phi, chi, pi_phi, pi_chi; write the same (FP32)
+
+
+def _kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("scalar.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2006_15122_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(per_launch_sites: int):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    counts, if they were taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "scalar_pass_256_vv2_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != _kernel_hash() or d.get("sites") != per_launch_sites:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_lattice(cfg: dict, steps: int, warmup: int):
+    import torch
+
+    from paper_2006_15122_amd.lattice import Lattice
+
+    lat = Lattice(cfg, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    obs = lat.energies()
+    tile = lat.tiling()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return ms, wall, obs, tile
+
+
+def cpu_baseline(cfg: dict, nsteps: int) -> dict:
+    import oracle
+
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    phi, pi = st["phi"], st["pi"]
+    t0 = time.perf_counter()
+    oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], cfg["integrator"], nsteps, omp=True)
+    dt = time.perf_counter() - t0
+    N = cfg["N"]
+    return {"value": N ** 3 * nsteps / dt, "unit": "site-updates/s", "cores": int(oracle.lib(True).orc_num_threads()),
+            "kind": "oracle",
+            "sample": f"FP64 oracle (C, OpenMP over x-planes), {cfg['integrator'].upper()}, {N}^3, two fields, "
+                      f"{nsteps} steps from the seeded initial state, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy, the reference for HBM counter scaling")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs the lattice on a single MI355X "
+              f"(--gpus {args.gpus} is not supported; multi-GPU sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2006_15122_amd import synth
+
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cfg = synth.config2(q=100.0, integrator="vv2")
+    N = cfg["N"]
+    ms, wall, obs, tile = time_lattice(cfg, args.steps, args.warmup)
+    sites = N ** 3
+    # one call of lattice_step(K) issues K fused passes plus one opening half-kick pass
+    passes = args.steps + 1
+    ms_per_pass = ms / passes
+    value = sites * args.steps / (ms / 1e3)
+    achieved = sites * BYTES_PER_SITE_VV2_NF2_FP32 / (ms_per_pass / 1e3) / 1e9
+    out = {
+        "metric": "lattice site-updates/s per GPU (two-field VV2, 256^3, FP32 fields / FP64 sums)",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded vacuum fluctuations, device Philox)",
+        "config": {"workload": "two-field preheating phi^4/4 + q phi^2 chi^2/2, q=100, N=256^3, kIR=0.6, "
+                               "dt=0.005, velocity Verlet, self-consistent expansion",
+                   "N": N, "integrator": "vv2", "nfields": 2, "storage": "fp32", "sums": "fp64",
+                   "tile": {"tz": tile[0], "by": tile[1], "ry": tile[2], "xc": tile[3]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(sites),
+                     "kernel": "scalar_pass_kernel<float,2,...>", "ms_per_launch": ms_per_pass,
+                     "bytes_per_launch": sites * BYTES_PER_SITE_VV2_NF2_FP32},
+        "wall_s": wall,
+        "final_obs": {k: obs[k] for k in ("a", "b", "EK", "EG", "EV", "hc")},
+    }
+    if not args.no_extras:
+        extras = {}
+        for name, c, st in (("vv4_256", synth.config2(q=100.0, integrator="vv4"), max(args.steps // 4, 10)),
+                            ("vv2_512", dict(synth.config2(q=100.0, N=512), omega_over_f=1e-2), max(args.steps // 8, 10))):
+            ms2, _, _, t2 = time_lattice(c, st, 10)
+            n3 = c["N"] ** 3
+            s_per_site = {"vv2": 1, "vv4": 3}[c["integrator"]]
+            npass = st * s_per_site + 1
+            extras[name] = {"site_updates_per_s": n3 * st / (ms2 / 1e3),
+                            "hbm_frac": n3 * 32 / (ms2 / npass / 1e3) / 1e9 / HBM_PEAK_GBS,
+                            "tile": t2, "steps": st}
+        out["extras"] = extras
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,7 +47,7 @@ int upload_components(lattice* h, const double* const* comps, int n);
 int download_components(lattice* h, double* const* comps, int n);
 int upload_scalars(lattice* h, double a, double b, double eta);
 int init_state(lattice* h);
-int scalar_pass(lattice* h, const PassDesc& pd);
+int scalar_pass(lattice* h, const PassDesc& pd, bool full = false);
 int scalar_step(lattice* h, int64_t n);
 int scalar_energies(lattice* h);
 int u1_step(lattice* h, int64_t n);
@@ -58,10 +58,10 @@ bool tiling_ok(const lattice* h, const Tiling& t);
 void default_tiling(lattice* h);
 int autotune(lattice* h);
 
-int num_shapes();
-void get_shape(int i, int* tz, int* by, int* ry);
+int num_shapes(int fp32, int nf);
+void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,
                               int ry, int xc, int swizzle, const double* phys, int expand, const PassDesc& pd,
-                              double* partials, DevState* st, hipStream_t s, int* nblocks_out);
+                              double* partials, DevState* st, hipStream_t s, int* nblocks_out, int full);
 
 }  // namespace cl

@@ -332,7 +332,7 @@ static void phys_of(const lattice* h, double* phys) {
   phys[7] = h->p.dt;
 }
 
-int scalar_pass(lattice* h, const PassDesc& pd) {
+int scalar_pass(lattice* h, const PassDesc& pd, bool full) {
   double phys[8];
   phys_of(h, phys);
   const int nf = h->p.nf;
@@ -349,7 +349,7 @@ int scalar_pass(lattice* h, const PassDesc& pd) {
   int nb = 0;
   hipError_t e = launch_scalar_pass(h->p.precision == LAT_FP32, nf, src, dst, h->p.N, h->tile.tz, h->tile.by,
                                     h->tile.ry, h->tile.xc, 1, phys, h->p.expansion, pd, h->partials, h->st,
-                                    h->stream, &nb);
+                                    h->stream, &nb, full ? 1 : 0);
   if (e != hipSuccess) {
     set_error(std::string("scalar pass launch: ") + hipGetErrorString(e));
     return LAT_EHIP;
@@ -408,8 +408,8 @@ int scalar_step(lattice* h, int64_t n) {
 }
 
 int scalar_energies(lattice* h) {
-  if (h->p.integrator == LAT_LF2 && h->staggered) return scalar_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 0, 0));
-  return scalar_pass(h, pass(0.0, 0.0, 0.0, MODE_VV, 0, 0));
+  if (h->p.integrator == LAT_LF2 && h->staggered) return scalar_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 0, 0), true);
+  return scalar_pass(h, pass(0.0, 0.0, 0.0, MODE_VV, 0, 0), true);
 }
 
 // ---------------------------------------------------------------------------
@@ -417,9 +417,10 @@ int scalar_energies(lattice* h) {
 // ---------------------------------------------------------------------------
 bool tiling_ok(const lattice* h, const Tiling& t) {
   bool compiled = false;
-  for (int i = 0; i < num_shapes(); ++i) {
+  const int fp32 = h->p.precision == LAT_FP32;
+  for (int i = 0; i < num_shapes(fp32, h->p.nf); ++i) {
     int tz, by, ry;
-    get_shape(i, &tz, &by, &ry);
+    get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
     if (tz == t.tz && by == t.by && ry == t.ry) compiled = true;
   }
   if (!compiled) return false;
@@ -432,7 +433,7 @@ bool tiling_ok(const lattice* h, const Tiling& t) {
 
 void default_tiling(lattice* h) {
   const int N = h->p.N;
-  Tiling cands[] = {{64, 4, 4, 16}, {64, 4, 2, 8}, {32, 8, 2, 8}, {32, 4, 4, 4}};
+  Tiling cands[] = {{64, 4, 4, 16}, {64, 4, 2, 16}, {32, 8, 2, 8}, {32, 4, 4, 4}};
   for (const Tiling& t : cands)
     if (tiling_ok(h, t)) { h->tile = t; return; }
   h->tile = Tiling{32, 4, 4, 4};
@@ -447,13 +448,14 @@ int autotune(lattice* h) {
   hipEvent_t e0, e1;
   CL_HIP(hipEventCreate(&e0));
   CL_HIP(hipEventCreate(&e1));
-  const int xcs[] = {4, 8, 16, 32};
+  const int xcs[] = {8, 16, 32, 64};
   float best = 1e30f;
   Tiling bt = h->tile;
   const int saved_cur = h->cur;
-  for (int i = 0; i < num_shapes(); ++i) {
+  const int fp32 = h->p.precision == LAT_FP32;
+  for (int i = 0; i < num_shapes(fp32, h->p.nf); ++i) {
     int tz, by, ry;
-    get_shape(i, &tz, &by, &ry);
+    get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
     for (int xc : xcs) {
       Tiling t{tz, by, ry, xc};
       if (!tiling_ok(h, t)) continue;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -38,9 +39,13 @@ struct ScalarArgs {
   DevState* st;
 };
 
-template <int NF>
+// Accumulators of one pass.  FULL (observation passes): per field
+// <pi_in^2>, <pi_E^2>, <grad^2>, <phi>, <phi^2>, then the three potential
+// terms.  Stepping passes keep only what the scale-factor kernel needs:
+// sum_f <pi_in^2>, sum_f <pi_E^2>, sum_f <grad^2>, <V>.
+template <int NF, bool FULL>
 struct Acc {
-  static constexpr int N = 5 * NF + 3;
+  static constexpr int N = FULL ? 5 * NF + 3 : 4;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -61,16 +66,15 @@ __device__ __forceinline__ T dpot(int f, const T (&p)[NF], T m2_0, T m2_1, T lam
   }
 }
 
-// Reduce the per-thread accumulators of a block into partials[blockIdx.x];
-// the last block to arrive combines all partials in block order and
-// performs the FP64 scale-factor update.
-template <typename T, int NF, int NT>
-__device__ void finish_pass(const ScalarArgs<T>& A, double (&acc)[Acc<NF>::N], double anew,
-                            double a_in, double b_in) {
-  constexpr int NACC = Acc<NF>::N;
+// Reduce the per-thread accumulators of a block into partials[blockIdx.x]
+// (wave shuffles, then the waves in order).  No fence or atomic here: the
+// cross-block combination happens in scalar_finish_kernel, after the kernel
+// boundary has made every block's partials visible to every XCD.
+template <typename T, int NF, bool FULL, int NT>
+__device__ void block_partials(const ScalarArgs<T>& A, double (&acc)[Acc<NF, FULL>::N]) {
+  constexpr int NACC = Acc<NF, FULL>::N;
   constexpr int NW = NT / 64;
   __shared__ double red[NW][NACC];
-  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
@@ -83,24 +87,26 @@ __device__ void finish_pass(const ScalarArgs<T>& A, double (&acc)[Acc<NF>::N], d
     for (int w = 0; w < NW; ++w) s += red[w][tid];
     A.partials[(size_t)blockIdx.x * NACC + tid] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(&A.st->counter, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
+}
+
+// One block: combine the partials of all nblocks blocks in block order
+// (thread t takes blocks t, t+256, ...; then shuffles and waves in order),
+// form the volume averages (Sec. 4.3/4.5) and advance b in FP64,
+//   b_out = b_in + (wk1 + wk2) h K_a(a', E),
+//   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].
+template <typename T, int NF, bool FULL>
+__global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks) {
+  constexpr int NACC = Acc<NF, FULL>::N;
+  constexpr int NT = 1024, NW = NT / 64;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double tot[NACC];
 #pragma unroll
   for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
-  for (int b = tid; b < nb; b += NT) {
+  for (int b = tid; b < nblocks; b += NT) {
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) tot[k] += __builtin_nontemporal_load(&A.partials[(size_t)b * NACC + k]);
+    for (int k = 0; k < NACC; ++k) tot[k] += A.partials[(size_t)b * NACC + k];
   }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
     const double s = wave_sum(tot[k]);
@@ -114,30 +120,40 @@ __device__ void finish_pass(const ScalarArgs<T>& A, double (&acc)[Acc<NF>::N], d
     for (int w = 0; w < NW; ++w) s += red[w][k];
     S[k] = s;
   }
+  const double a_in = A.st->a, b_in = A.st->b;
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double V = (double)A.N * (double)A.N * (double)A.N;
   const double al = A.alpha;
   const double a6 = pow(anew, 6.0), a2 = anew * anew, dx2 = A.dx * A.dx;
   lattice_obs o;
-  // obs is a plain struct; zero-fill the fields this model does not use
   o.EK = o.EG = 0.0;
   o.EK_f[0] = o.EK_f[1] = o.EG_f[0] = o.EG_f[1] = 0.0;
   o.mean_f[0] = o.mean_f[1] = o.meansq_f[0] = o.meansq_f[1] = 0.0;
   bool bad = false;
-  for (int f = 0; f < NF; ++f) {
-    const double k1 = S[5 * f + 0] / V, k2 = S[5 * f + 1] / V;
-    const double ek = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
-    const double eg = S[5 * f + 2] / V / (2.0 * a2 * dx2);
-    o.EK_f[f] = ek;
-    o.EG_f[f] = eg;
-    o.mean_f[f] = S[5 * f + 3] / V;
-    o.meansq_f[f] = S[5 * f + 4] / V;
-    o.EK += ek;
-    o.EG += eg;
+  if constexpr (FULL) {
+    for (int f = 0; f < NF; ++f) {
+      const double k1 = S[5 * f + 0] / V, k2 = S[5 * f + 1] / V;
+      const double ek = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+      const double eg = S[5 * f + 2] / V / (2.0 * a2 * dx2);
+      o.EK_f[f] = ek;
+      o.EG_f[f] = eg;
+      o.mean_f[f] = S[5 * f + 3] / V;
+      o.meansq_f[f] = S[5 * f + 4] / V;
+      o.EK += ek;
+      o.EG += eg;
+    }
+    o.EV_term[0] = S[5 * NF + 0] / V;
+    o.EV_term[1] = S[5 * NF + 1] / V;
+    o.EV_term[2] = S[5 * NF + 2] / V;
+    o.EV = o.EV_term[0] + o.EV_term[1] + o.EV_term[2];
+  } else {
+    const double k1 = S[0] / V, k2 = S[1] / V;
+    o.EK = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+    o.EG = S[2] / V / (2.0 * a2 * dx2);
+    o.EV = S[3] / V;
+    o.EV_term[0] = o.EV_term[1] = o.EV_term[2] = NAN;
+    for (int f = 0; f < 2; ++f) o.EK_f[f] = o.EG_f[f] = o.mean_f[f] = o.meansq_f[f] = NAN;
   }
-  o.EV_term[0] = S[5 * NF + 0] / V;
-  o.EV_term[1] = S[5 * NF + 1] / V;
-  o.EV_term[2] = S[5 * NF + 2] / V;
-  o.EV = o.EV_term[0] + o.EV_term[1] + o.EV_term[2];
   for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
   const double rho = o.EK + o.EG + o.EV;
   double b_out = b_in, b_sync = b_in, hc = 0.0;
@@ -170,16 +186,14 @@ __device__ void finish_pass(const ScalarArgs<T>& A, double (&acc)[Acc<NF>::N], d
     A.st->b = b_out;
     A.st->eta = eta_new;
   }
-  (void)a_in;
-  A.st->counter = 0u;
 }
 
-template <typename T, int NF, int TZ, int BY, int RY>
+template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
 __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
   constexpr int TY = BY * RY;
   constexpr int NT = TZ * BY;
   constexpr int LZ = TZ + 2;
-  constexpr int NACC = Acc<NF>::N;
+  constexpr int NACC = Acc<NF, FULL>::N;
   __shared__ T lds[NF][TY + 2][LZ];
 
   const int N = A.N;
@@ -206,13 +220,16 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
   const T cE = (T)((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
   const T m2_0 = (T)A.m2_0, m2_1 = (T)A.m2_1, lam = (T)A.lam, q = (T)A.q;
   const T half = T(0.5), quarter = T(0.25);
+  const bool lf = A.pd.mode == MODE_LF;
 
   double acc[NACC];
 #pragma unroll
   for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
 
   const int z = z0 + tz;
-  T pm[NF][RY], pc[NF][RY], pn[NF][RY], qc[NF][RY], qn[NF][RY];
+  // register planes: pm = drifted x-1, pc = drifted x, (pn, qn) = raw x+1,
+  // (pf, qf) = raw x+2 in flight; qc = momentum at x
+  T pm[NF][RY], pc[NF][RY], qc[NF][RY], pn[NF][RY], qn[NF][RY], pf[NF][RY], qf[NF][RY];
 
   // halo item owned by this thread (at most one: 2 TZ + 2 TY <= NT)
   constexpr int NH = 2 * TZ + 2 * TY;
@@ -225,11 +242,11 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
     else if (tid < 2 * TZ + TY) { hly = 1 + tid - 2 * TZ; hlz = 0; hy = y0 + tid - 2 * TZ; hz = (z0 - 1 + N) % N; }
     else { hly = 1 + tid - 2 * TZ - TY; hlz = TZ + 1; hy = y0 + tid - 2 * TZ - TY; hz = (z0 + TZ) % N; }
   }
-  T hp[NF], hq[NF];
+  T hp1[NF], hq1[NF], hp2[NF], hq2[NF];
 
   auto row_off = [&](int x, int y) -> size_t { return (size_t)x * NN + (size_t)y * N; };
 
-  // load own columns of plane x (raw phi and pi)
+  // raw phi and pi of the own columns of plane x
   auto load_own = [&](int x, T (&p)[NF][RY], T (&pq)[NF][RY]) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -241,17 +258,18 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
       }
     }
   };
-  auto load_halo = [&](int x) {
+  auto load_halo = [&](int x, T (&p)[NF], T (&pq)[NF]) {
     if (has_halo) {
       const size_t o = row_off(x, hy) + hz;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        hp[f] = A.src[f][o];
-        hq[f] = A.src[2 + f][o];
+        p[f] = A.src[f][o];
+        pq[f] = A.src[2 + f][o];
       }
     }
   };
-  auto store_lds = [&](const T (&p)[NF][RY]) {
+  // drifted plane into LDS: own columns from registers, halo drifted here
+  auto store_lds = [&](const T (&p)[NF][RY], const T (&hp)[NF], const T (&hq)[NF]) {
 #pragma unroll
     for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -262,30 +280,33 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
     }
   };
 
-  // prologue: plane x0-1 (own columns, drifted) and plane x0
+  // prologue: planes x0-1 (drifted), x0 (drifted, into LDS), x0+1 (raw, in flight)
   {
     const int xm = (x0 - 1 + N) % N;
-    load_own(xm, pm, qn);
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int r = 0; r < RY; ++r) pm[f][r] = pm[f][r] + cdrift * qn[f][r];
+    load_own(xm, pm, qf);  // qf: momentum of plane x0-1, only needed for its drift
     load_own(x0, pc, qc);
-    load_halo(x0);
+    load_halo(x0, hp1, hq1);
+    load_own((x0 + 1) % N, pn, qn);
+    if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int r = 0; r < RY; ++r) pc[f][r] = pc[f][r] + cdrift * qc[f][r];
-    store_lds(pc);
+      for (int r = 0; r < RY; ++r) {
+        pm[f][r] = pm[f][r] + cdrift * qf[f][r];
+        pc[f][r] = pc[f][r] + cdrift * qc[f][r];
+      }
+    store_lds(pc, hp1, hq1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
   }
 
   for (int i = 0; i < A.XC; ++i) {
     const int x = x0 + i;
-    const int xp = (x + 1) % N;
-    // issue loads of plane x+1 before the stencil of plane x
-    load_own(xp, pn, qn);
-    const bool more = (i + 1 < A.XC);
-    if (more) load_halo(xp);
+    // issue loads of plane x+2, two planes ahead of the stencil
+    if (i + 1 < A.XC) {
+      load_own((x + 2) % N, pf, qf);
+      if (i + 2 < A.XC) load_halo((x + 2) % N, hp2, hq2);
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -305,28 +326,45 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
         const T pout = pin + ckick * K;
         const T pe = pin + cE * K;
         if (A.pd.write) {
-          A.dst[f][o] = cur[f];
-          A.dst[2 + f][o] = pout;
+          // streaming stores: the new state is read again only by the next
+          // pass, so keep it from evicting the halo rows other tiles still need
+          __builtin_nontemporal_store(cur[f], &A.dst[f][o]);
+          __builtin_nontemporal_store(pout, &A.dst[2 + f][o]);
         }
         const T gx = pnext - cur[f], gy = yp - cur[f], gz = zp - cur[f];
-        acc[5 * f + 0] += (double)(pin * pin);
-        acc[5 * f + 1] += (double)(pe * pe);
-        acc[5 * f + 2] += (double)(gx * gx + gy * gy + gz * gz);
-        acc[5 * f + 3] += (double)cur[f];
-        acc[5 * f + 4] += (double)(cur[f] * cur[f]);
+        if constexpr (FULL) {
+          acc[5 * f + 0] += (double)(pin * pin);
+          acc[5 * f + 1] += (double)(pe * pe);
+          acc[5 * f + 2] += (double)(gx * gx + gy * gy + gz * gz);
+          acc[5 * f + 3] += (double)cur[f];
+          acc[5 * f + 4] += (double)(cur[f] * cur[f]);
+        } else {
+          if (lf) acc[0] += (double)(pin * pin);
+          acc[1] += (double)(pe * pe);
+          acc[2] += (double)(gx * gx + gy * gy + gz * gz);
+        }
       }
       const T p2 = cur[0] * cur[0];
-      if constexpr (NF > 1) {
-        const T c2 = cur[1] * cur[1];
-        acc[5 * NF + 0] += (double)(half * (m2_0 * p2 + m2_1 * c2));
-        acc[5 * NF + 2] += (double)(half * q * p2 * c2);
+      if constexpr (FULL) {
+        if constexpr (NF > 1) {
+          const T c2 = cur[1] * cur[1];
+          acc[5 * NF + 0] += (double)(half * (m2_0 * p2 + m2_1 * c2));
+          acc[5 * NF + 2] += (double)(half * q * p2 * c2);
+        } else {
+          acc[5 * NF + 0] += (double)(half * m2_0 * p2);
+        }
+        acc[5 * NF + 1] += (double)(quarter * lam * p2 * p2);
       } else {
-        acc[5 * NF + 0] += (double)(half * m2_0 * p2);
+        T v = half * m2_0 * p2 + quarter * lam * p2 * p2;
+        if constexpr (NF > 1) {
+          const T c2 = cur[1] * cur[1];
+          v += half * (m2_1 * c2 + q * p2 * c2);
+        }
+        acc[3] += (double)v;
       }
-      acc[5 * NF + 1] += (double)(quarter * lam * p2 * p2);
     }
     __syncthreads();
-    // shift registers: plane x+1 becomes current
+    // shift: plane x+1 becomes current, x+2 becomes next
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -334,10 +372,16 @@ __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
         pm[f][r] = pc[f][r];
         pc[f][r] = pn[f][r] + cdrift * qn[f][r];
         qc[f][r] = qn[f][r];
+        pn[f][r] = pf[f][r];
+        qn[f][r] = qf[f][r];
       }
-    if (more) store_lds(pc);
+    if (i + 1 < A.XC) {
+      store_lds(pc, hp1, hq1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
+    }
   }
-  finish_pass<T, NF, NT>(A, acc, anew, a_in, b_in);
+  block_partials<T, NF, FULL, NT>(A, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,48 +391,74 @@ struct Shape {
   int tz, by, ry;
 };
 
-template <typename T, int NF, int TZ, int BY, int RY>
+template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
 hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((scalar_pass_kernel<T, NF, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
+  hipLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(1024), 0, s, A, nblocks);
   return hipGetLastError();
 }
 
-#define CL_SHAPES(X, T, NF) \
-  X(T, NF, 64, 4, 4)        \
-  X(T, NF, 64, 4, 2)        \
-  X(T, NF, 64, 8, 2)        \
-  X(T, NF, 64, 4, 8)        \
-  X(T, NF, 32, 8, 2)        \
-  X(T, NF, 32, 4, 4)        \
+// Stepping passes: every compiled tile shape (FP32 two-field is the
+// production case; the other storage/field combinations get a subset).
+#define CL_SHAPES_MAIN(X, T, NF) \
+  X(T, NF, 64, 4, 4)             \
+  X(T, NF, 64, 4, 2)             \
+  X(T, NF, 64, 8, 2)             \
+  X(T, NF, 64, 4, 8)             \
+  X(T, NF, 32, 8, 2)             \
+  X(T, NF, 32, 4, 4)             \
   X(T, NF, 32, 8, 4)
+#define CL_SHAPES_SMALL(X, T, NF) \
+  X(T, NF, 64, 4, 2)              \
+  X(T, NF, 32, 8, 2)              \
+  X(T, NF, 32, 4, 4)
 
-static const Shape kShapes[] = {{64, 4, 4}, {64, 4, 2}, {64, 8, 2}, {64, 4, 8},
-                                {32, 8, 2}, {32, 4, 4}, {32, 8, 4}};
-static const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+static const Shape kShapesMain[] = {{64, 4, 4}, {64, 4, 2}, {64, 8, 2}, {64, 4, 8},
+                                    {32, 8, 2}, {32, 4, 4}, {32, 8, 4}};
+static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
+
+// Observation passes always use the 32 x 16 tile with 8 planes, which
+// divides every supported N.
+static const int kObsTz = 32, kObsBy = 8, kObsRy = 2, kObsXc = 8;
 
 template <typename T, int NF>
-hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s) {
+hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s, bool full) {
+  if (full) return launch_shape<T, NF, true, 32, 8, 2>(A, nblocks, s);
 #define X(TT, NFF, a, b, c) \
-  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, a, b, c>(A, nblocks, s);
-  CL_SHAPES(X, T, NF)
+  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s);
+  if constexpr (std::is_same<T, float>::value && NF == 2) {
+    CL_SHAPES_MAIN(X, T, NF)
+  } else {
+    CL_SHAPES_SMALL(X, T, NF)
+  }
 #undef X
   return hipErrorInvalidValue;
 }
 
-int num_shapes() { return kNumShapes; }
-void get_shape(int i, int* tz, int* by, int* ry) {
-  *tz = kShapes[i].tz;
-  *by = kShapes[i].by;
-  *ry = kShapes[i].ry;
+int num_shapes(int fp32, int nf) {
+  return (fp32 && nf == 2) ? (int)(sizeof(kShapesMain) / sizeof(Shape)) : (int)(sizeof(kShapesSmall) / sizeof(Shape));
+}
+void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry) {
+  const Shape& sh = (fp32 && nf == 2) ? kShapesMain[i] : kShapesSmall[i];
+  *tz = sh.tz;
+  *by = sh.by;
+  *ry = sh.ry;
 }
 
-int nacc_for(int nf) { return 5 * nf + 3; }
 
 // Launch one pass.  buffers: src/dst arrays [4] in storage precision.
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz,
                               int by, int ry, int xc, int swizzle, const double* phys, int expand,
                               const PassDesc& pd, double* partials, DevState* st, hipStream_t s,
-                              int* nblocks_out) {
+                              int* nblocks_out, int full) {
+  if (full) {
+    tz = kObsTz;
+    by = kObsBy;
+    ry = kObsRy;
+    xc = kObsXc;
+  }
   const Shape sh{tz, by, ry};
   const int ty = by * ry;
   const int nblocks = (N / tz) * (N / ty) * (N / xc);
@@ -419,11 +489,11 @@ hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* co
   if (fp32) {
     ScalarArgs<float> A;
     fill(A, (float*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s) : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s);
+    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s, full) : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s, full);
   } else {
     ScalarArgs<double> A;
     fill(A, (double*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s) : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s);
+    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s, full) : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s, full);
   }
 }
 

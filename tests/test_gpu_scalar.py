@@ -149,7 +149,7 @@ def test_full_size_256_vv2_sampled_sites():
     compare_obs(lat.energies(), oracle.sync_observe(m, phi, pi, a, b), 2, 1e-5, "256^3")
     s = lat.get_state()
     rng = np.random.default_rng(0)
-    idx = tuple(rng.integers(0, 256, size=(4, 4096)))
+    idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 256, size=(3, 4096)))
     for arr, ref in ((s["phi"], phi), (s["pi"], pi)):
         d = np.abs(arr[idx] - ref[idx])
         assert np.max(d) < 1e-5 * np.max(np.abs(ref[idx])), np.max(d)
@@ -223,7 +223,9 @@ def test_zero_steps_and_energies_idempotent():
     lat.step(0)
     e1, e2 = lat.energies(), lat.energies()
     s1 = lat.get_state()
-    assert e1 == e2
+    assert set(e1) == set(e2)
+    for k in e1:
+        assert e1[k] == e2[k] or (isinstance(e1[k], float) and math.isnan(e1[k]) and math.isnan(e2[k])), k
     assert np.array_equal(s0["phi"], s1["phi"])
 
 
