@@ -382,3 +382,165 @@ def spectrum(f: np.ndarray, kIR: float) -> dict:
     delta[1:] = (kIR * bb[1:]) ** 3 * norm * S[1:] / (4.0 * math.pi * bb[1:] ** 2)
     delta_avg = np.where(cnt > 0, kbar ** 3 * norm * S / np.maximum(cnt, 1), 0.0)
     return {"count": cnt, "S": S, "k": kbar, "delta": delta, "delta_avg": delta_avg}
+
+
+# ---------------------------------------------------------------------------
+# Complex scalar with compact U(1) links (Sec. 5.1, 5.3, 5.4; ICs Sec. 7.2)
+# ---------------------------------------------------------------------------
+class U1(ctypes.Structure):
+    """Parameters of the compact Abelian-Higgs model."""
+    _fields_ = [("N", ctypes.c_int32), ("expand", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("pad1", ctypes.c_int32), ("dx", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("fmp2", ctypes.c_double), ("lam", ctypes.c_double), ("m2", ctypes.c_double),
+                ("e", ctypes.c_double), ("wf2", ctypes.c_double)]
+
+
+def u1_model(cfg: dict) -> U1:
+    m = U1()
+    m.N = int(cfg["N"])
+    m.expand = 1 if cfg.get("expansion", True) else 0
+    m.dx = lattice_dx(m.N, cfg["kIR"])
+    m.alpha = float(cfg.get("alpha", 1.0))
+    m.fmp2 = float(cfg.get("fstar_over_mp", 1.0)) ** 2
+    m.lam = float(cfg.get("lam", 0.0))
+    m.m2 = float(list(cfg.get("m2", (0.0, 0.0)))[0])
+    m.e = float(cfg["e"])
+    m.wf2 = float(cfg.get("omega_over_f", 1.0)) ** 2
+    return m
+
+
+def u1_kernels(m: U1, a, phi, links):
+    Kp = np.empty_like(phi)
+    KA = np.empty((3,) + phi.shape[1:])
+    lib().orc_u1_kernels(ctypes.byref(m), ctypes.c_double(a), _p(_f64(phi)), _p(_f64(links)), _p(Kp), _p(KA))
+    return Kp, KA
+
+
+def u1_lf_startup(m: U1, st: dict, h: float):
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib().orc_u1_lf_startup(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["piA"]),
+                            ctypes.byref(ca), ctypes.byref(cb), ctypes.c_double(h))
+    st["a"], st["b"] = ca.value, cb.value
+
+
+def u1_lf_steps(m: U1, st: dict, h: float, nsteps: int, omp: bool = False):
+    """nsteps compact staggered-leapfrog steps (Sec. 5.3.1), in place on st."""
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib(omp).orc_u1_lf_steps(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["piA"]),
+                             ctypes.byref(ca), ctypes.byref(cb), ctypes.c_double(h), ctypes.c_int64(nsteps))
+    st["a"], st["b"] = ca.value, cb.value
+
+
+def _u1_obs(e, a):
+    d = {"a": a, "EK": e[0], "EG": e[1], "EV": e[2], "EK_A": e[3], "EG_A": e[4], "EV_quartic": e[5],
+         "EV_mass": e[6], "b": e[7], "hc": e[8], "gauss": e[9], "mean0": e[10], "mean1": e[11],
+         "meansq": e[12]}
+    d["rho"] = e[0] + e[1] + e[2] + e[3] + e[4]
+    d["p"] = e[0] - e[1] / 3.0 - e[2] + (e[3] + e[4]) / 3.0
+    d["w"] = d["p"] / d["rho"] if d["rho"] != 0 else 0.0
+    return d
+
+
+def u1_lf_observe(m: U1, st: dict, h: float) -> dict:
+    e = np.zeros(13)
+    lib().orc_u1_lf_observe(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["piA"]),
+                            ctypes.c_double(st["a"]), ctypes.c_double(st["b"]), ctypes.c_double(h), _p(e))
+    return _u1_obs(e, st["a"])
+
+
+def u1_sync_observe(m: U1, st: dict) -> dict:
+    e = np.zeros(13)
+    lib().orc_u1_sync_observe(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["piA"]),
+                              ctypes.c_double(st["a"]), ctypes.c_double(st["b"]), _p(e))
+    return _u1_obs(e, st["a"])
+
+
+def u1_gauss(m: U1, st: dict) -> np.ndarray:
+    out = np.zeros(4)
+    lib().orc_u1_gauss(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["piA"]), _p(out))
+    return out
+
+
+def u1_potential(cfg, phibar) -> float:
+    """V = lambda |phi|^4 + m2 |phi|^2 with |phi|^2 = (phi_0^2 + phi_1^2)/2."""
+    r2 = 0.5 * (phibar[0] ** 2 + phibar[1] ** 2)
+    return float(cfg.get("lam", 0.0)) * r2 * r2 + float(list(cfg.get("m2", (0.0, 0.0)))[0]) * r2
+
+
+def u1_vacuum_ic(cfg: dict) -> dict:
+    """Initial state of the compact U(1) model (Sec. 7.2).
+
+    Real components phi_0, phi_1 of phi = (phi_0 + i phi_1)/sqrt 2 get the
+    vacuum modes of Sec. 7.1 with the constraints that remove the zero mode of
+    the charge: |l_n| = |r_n| and th_1^r = th_0^r + th_1^l - th_0^l.  Random
+    numbers: Philox(counter=(lin, n, 0), key=seed); u0 -> |l_n|, u2 -> th_n^l,
+    u3 of component 0 -> th_0^r.  Links V = 1 (A = 0); the link momenta solve
+    the discrete Gauss law sum_i Delta^-_i piA_i = rho in Fourier space with
+    the minimum-norm solution E_i = conj(s_i) rho / sum_j |s_j|^2,
+    s_j = (1 - exp(+2 pi i n~_j / N)) / dx; b_0 from the Hubble constraint.
+    """
+    N = int(cfg["N"])
+    kIR = float(cfg["kIR"])
+    dx = lattice_dx(N, kIR)
+    alpha = float(cfg.get("alpha", 1.0))
+    a = float(cfg.get("a0", 1.0))
+    w2 = float(cfg.get("omega_over_f", 1.0)) ** 2
+    e = float(cfg["e"])
+    lam = float(cfg.get("lam", 0.0))
+    m2 = float(list(cfg.get("m2", (0.0, 0.0)))[0])
+    fmp2 = float(cfg.get("fstar_over_mp", 1.0)) ** 2
+    expand = bool(cfg.get("expansion", True))
+    pb = list(cfg.get("phi0", (1.0, 0.0)))[:2]
+    db = list(cfg.get("dphi0", (0.0, 0.0)))[:2]
+    rho_hom = (db[0] ** 2 + db[1] ** 2) / (2.0 * a ** (2 * alpha)) + u1_potential(cfg, pb)
+    Hh = math.sqrt(fmp2 / 3.0 * a ** (2 * (alpha + 1)) * rho_hom) / a if expand else 0.0
+    s = pb[0] ** 2 + pb[1] ** 2
+    m2eff = [lam * (s + 2.0 * pb[n] ** 2) + m2 for n in range(2)]
+    n1, n2, n3, nabs = reciprocal(N)
+    k = kIR * nabs
+    lin, par = conjugate_partner(N)
+    rep = lin < par
+    kcut = float(cfg.get("kcut", 0.0) or 0.0)
+    two32 = 4294967296.0
+    U = [philox(int(cfg["seed"]), n, 0, N ** 3).reshape(N, N, N, 4).astype(np.float64) for n in range(2)]
+    th_l = [2.0 * math.pi * (U[n][..., 2] + 0.5) / two32 for n in range(2)]
+    th0r = 2.0 * math.pi * (U[0][..., 3] + 0.5) / two32
+    th_r = [th0r, th0r + th_l[1] - th_l[0]]
+    fields, derivs = [], []
+    for n in range(2):
+        om2 = k * k + a * a * m2eff[n]
+        ok = rep & (om2 > 0)
+        if kcut > 0:
+            ok &= k <= kcut
+        om = np.sqrt(np.where(ok, om2, 1.0))
+        P = np.where(ok, w2 * (N / dx) ** 3 / (2.0 * a * a * om), 0.0)
+        R = np.sqrt(-P * np.log((U[n][..., 0] + 0.5) / two32))
+        L = R * np.exp(1j * th_l[n])
+        Rt = R * np.exp(1j * th_r[n])
+        F = np.where(ok, (L + Rt) / math.sqrt(2.0), 0.0).ravel()
+        Fd = np.where(ok, a ** (-(1.0 - alpha)) * 1j * om * (L - Rt) / math.sqrt(2.0)
+                      - Hh * (L + Rt) / math.sqrt(2.0), 0.0).ravel()
+        okf, linf, parf = ok.ravel(), lin.ravel(), par.ravel()
+        F[parf[okf]] = np.conj(F[linf[okf]])
+        Fd[parf[okf]] = np.conj(Fd[linf[okf]])
+        fields.append(pb[n] + paper_idft(F.reshape(N, N, N)).real)
+        derivs.append(db[n] + paper_idft(Fd.reshape(N, N, N)).real)
+    r2 = 1.0 / math.sqrt(2.0)
+    phi = np.stack([fields[0] * r2, fields[1] * r2])
+    pi = a ** (3.0 - alpha) * np.stack([derivs[0] * r2, derivs[1] * r2])
+    rho = 2.0 * e / w2 * (phi[0] * pi[1] - phi[1] * pi[0])
+    Rh = paper_dft(rho)
+    sj = [(1.0 - np.exp(2j * math.pi * nn / N)) / dx for nn in (n1, n2, n3)]
+    den = sum(np.abs(x) ** 2 for x in sj)
+    zero = den == 0
+    piA = np.stack([a ** (1.0 - alpha) * paper_idft(np.where(zero, 0.0, np.conj(x) * Rh / np.where(zero, 1.0, den))).real
+                    for x in sj])
+    links = np.zeros((3, 2, N, N, N))
+    links[:, 0] = 1.0
+    st = {"phi": phi, "pi": pi, "links": links, "piA": piA, "a": a, "b": 1.0}
+    if expand:
+        o = u1_sync_observe(u1_model(cfg), st)
+        st["b"] = math.sqrt(fmp2 / 3.0 * a ** (2 * (alpha + 1)) * o["rho"])
+    else:
+        st["b"] = 0.0
+    return st

@@ -378,3 +378,313 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Complex scalar with compact U(1) links (Sec. 5.1, 5.3; toolkit of   */
+/* Sec. 3.2.2).  phi = (phi_0 + i phi_1)/sqrt 2 is stored as (Re, Im);  */
+/* link V_i(n) = exp(-i e dx A_i) lives on n + i/2, stored (Re, Im);    */
+/* pi_A,i is one real per link.  Plaquette                              */
+/*   V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n).               */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t N, expand, pad0, pad1;
+  double dx, alpha, fmp2;
+  double lambda;   /* V = lambda |phi|^4 + m2 |phi|^2 */
+  double m2;
+  double e;        /* gauge coupling g_A Q_A */
+  double wf2;      /* (w_star/f_star)^2 */
+} orc_u1;
+
+typedef struct { double re, im; } cpx;
+static inline cpx cmk(double r, double i) { cpx c = {r, i}; return c; }
+static inline cpx cmul_(cpx a, cpx b) { return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+static inline cpx cconj_(cpx a) { return cmk(a.re, -a.im); }
+
+/* array views: phi[c*V + s] (c = 0 Re, 1 Im); links[(2*i + c)*V + s] */
+static inline cpx phi_at(const double* phi, int64_t V, int64_t s) { return cmk(phi[s], phi[V + s]); }
+static inline cpx link_at(const double* L, int64_t V, int i, int64_t s) { return cmk(L[(2 * i) * V + s], L[(2 * i + 1) * V + s]); }
+
+static int64_t shift(int N, int64_t s, int dir, int step) {
+  int x = (int)(s / ((int64_t)N * N)), y = (int)((s / N) % N), z = (int)(s % N);
+  if (dir == 0) x += step; else if (dir == 1) y += step; else z += step;
+  return site(N, x, y, z);
+}
+
+static cpx plaquette(const orc_u1* m, const double* L, int i, int j, int64_t s) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const cpx a = link_at(L, V, i, s);
+  const cpx b = link_at(L, V, j, shift(N, s, i, 1));
+  const cpx c = cconj_(link_at(L, V, i, shift(N, s, j, 1)));
+  const cpx d = cconj_(link_at(L, V, j, s));
+  return cmul_(cmul_(a, b), cmul_(c, d));
+}
+
+/* Kernels of the compact U(1) scheme (Sec. 5.1 kernels, Sec. 5.3 gauge kernel):
+   K_phi   = -a^{3+alpha} (2 lambda |phi|^2 + m2) phi
+             + a^{1+alpha} sum_i (V_i phi_{+i} - 2 phi + conj V_i(n-i) phi_{-i}) / dx^2
+   K_{A,i} = a^{1+alpha} (2 e / dx) (f_star/w_star)^2 Im[conj phi V_i phi_{+i}]
+             + a^{alpha-1} / (e dx^3) sum_{j != i} (Im V_ij(n) - Im V_ij(n-j))          */
+void orc_u1_kernels(const orc_u1* m, double a, const double* phi, const double* L, double* Kphi, double* KA) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const double cl = pow(a, 1.0 + m->alpha) / (m->dx * m->dx);
+  const double cp = pow(a, 3.0 + m->alpha);
+  const double cj = pow(a, 1.0 + m->alpha) * 2.0 * m->e / m->dx / m->wf2;
+  const double cb = pow(a, m->alpha - 1.0) / (m->e * m->dx * m->dx * m->dx);
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < N; ++x)
+    for (int y = 0; y < N; ++y)
+      for (int z = 0; z < N; ++z) {
+        const int64_t s = site(N, x, y, z);
+        const cpx p = phi_at(phi, V, s);
+        cpx lap = cmk(-6.0 * p.re, -6.0 * p.im);
+        for (int i = 0; i < 3; ++i) {
+          const int64_t sp = shift(N, s, i, 1), sm = shift(N, s, i, -1);
+          const cpx f = cmul_(link_at(L, V, i, s), phi_at(phi, V, sp));
+          const cpx b = cmul_(cconj_(link_at(L, V, i, sm)), phi_at(phi, V, sm));
+          lap.re += f.re + b.re;
+          lap.im += f.im + b.im;
+        }
+        const double r2 = p.re * p.re + p.im * p.im;
+        const double dv = 2.0 * m->lambda * r2 + m->m2;
+        Kphi[s] = cl * lap.re - cp * dv * p.re;
+        Kphi[V + s] = cl * lap.im - cp * dv * p.im;
+        for (int i = 0; i < 3; ++i) {
+          const cpx cur = cmul_(cconj_(p), cmul_(link_at(L, V, i, s), phi_at(phi, V, shift(N, s, i, 1))));
+          double mag = 0.0;
+          for (int j = 0; j < 3; ++j) {
+            if (j == i) continue;
+            mag += plaquette(m, L, i, j, s).im - plaquette(m, L, i, j, shift(N, s, j, -1)).im;
+          }
+          KA[i * V + s] = cj * cur.im + cb * mag;
+        }
+      }
+}
+
+/* Raw volume averages (Sec. 5.4): out[0] = <|pi|^2>, out[1] = <sum_i |V_i phi_{+i} - phi|^2>
+   (no 1/dx^2), out[2] = <lambda |phi|^4>, out[3] = <m2 |phi|^2>, out[4] = <sum_i piA_i^2>,
+   out[5] = <sum_{i<j} (1 - Re V_ij)>, out[6] = <Re phi>, out[7] = <Im phi>, out[8] = <|phi|^2>. */
+void orc_u1_sums(const orc_u1* m, const double* phi, const double* pi, const double* L, const double* piA,
+                 double* out) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const int nacc = 9;
+  double* part = (double*)calloc((size_t)N * nacc, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < N; ++x) {
+    double* acc = part + (size_t)x * nacc;
+    for (int y = 0; y < N; ++y)
+      for (int z = 0; z < N; ++z) {
+        const int64_t s = site(N, x, y, z);
+        const cpx p = phi_at(phi, V, s);
+        if (pi) acc[0] += pi[s] * pi[s] + pi[V + s] * pi[V + s];
+        for (int i = 0; i < 3; ++i) {
+          const cpx f = cmul_(link_at(L, V, i, s), phi_at(phi, V, shift(N, s, i, 1)));
+          acc[1] += (f.re - p.re) * (f.re - p.re) + (f.im - p.im) * (f.im - p.im);
+          if (piA) acc[4] += piA[i * V + s] * piA[i * V + s];
+        }
+        const double r2 = p.re * p.re + p.im * p.im;
+        acc[2] += m->lambda * r2 * r2;
+        acc[3] += m->m2 * r2;
+        for (int i = 0; i < 3; ++i)
+          for (int j = i + 1; j < 3; ++j) acc[5] += 1.0 - plaquette(m, L, i, j, s).re;
+        acc[6] += p.re;
+        acc[7] += p.im;
+        acc[8] += r2;
+      }
+  }
+  for (int k = 0; k < nacc; ++k) {
+    double sacc = 0.0;
+    for (int x = 0; x < N; ++x) sacc += part[(size_t)x * nacc + k];
+    out[k] = sacc / (double)V;
+  }
+  free(part);
+}
+
+/* Energies (Sec. 5.4.1): e[0] = E_K^phi = <|pi|^2>/a^6, e[1] = E_G^phi = <sum|D+phi|^2>/a^2,
+   e[2] = E_V, e[3] = E_K^A = (w_star/f_star)^2 sum <piA^2>/(2 a^4),
+   e[4] = E_G^A = (w_star/f_star)^2 /(a^4 dx^4 e^2) sum_{i<j} <1 - Re V_ij>,
+   e[5] = <lambda|phi|^4>, e[6] = <m2|phi|^2>.  kin_phi / kin_A override the kinetic
+   averages when >= 0 (staggered averages). */
+static void u1_energies(const orc_u1* m, double a, const double* s, double kin_phi, double kin_A, double* e) {
+  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = m->dx * m->dx;
+  e[0] = (kin_phi >= 0.0 ? kin_phi : s[0]) / a6;
+  e[1] = s[1] / (a2 * dx2);
+  e[2] = s[2] + s[3];
+  e[3] = m->wf2 * (kin_A >= 0.0 ? kin_A : s[4]) / (2.0 * a4);
+  e[4] = m->wf2 * s[5] / (a4 * dx2 * dx2 * m->e * m->e);
+  e[5] = s[2];
+  e[6] = s[3];
+}
+
+/* Scale-factor kernel with the gauge term (Sec. 5.1):
+   K_a = (1/3)(f/m_p)^2 a^{1+2 alpha} [(alpha-2) E_K^phi + alpha E_G^phi + (alpha+1) E_V
+                                        + (alpha-1)(E_K^A + E_G^A)] */
+double orc_u1_Ka(const orc_u1* m, double a, const double* e) {
+  const double al = m->alpha;
+  return m->fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+         ((al - 2.0) * e[0] + al * e[1] + (al + 1.0) * e[2] + (al - 1.0) * (e[3] + e[4]));
+}
+
+/* Cayley link drift (Sec. 5.3, drift from momenta, exact form):
+   V <- (1 - i u)/(1 + i u) V,  u = e h dx piA / (2 a_mid^{1-alpha}). */
+static void u1_link_drift(const orc_u1* m, double* L, const double* piA, double h, double amid) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  const double c = m->e * h * m->dx / (2.0 * pow(amid, 1.0 - m->alpha));
+  for (int i = 0; i < 3; ++i)
+    for (int64_t s = 0; s < V; ++s) {
+      const double u = c * piA[i * V + s];
+      const double d = 1.0 + u * u;
+      const cpx r = cmk((1.0 - u * u) / d, -2.0 * u / d);
+      const cpx v = cmul_(r, link_at(L, V, i, s));
+      L[(2 * i) * V + s] = v.re;
+      L[(2 * i + 1) * V + s] = v.im;
+    }
+}
+
+static double sum_sq(const double* x, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += x[i] * x[i];
+  return s;
+}
+
+/* Start-up of the staggered leapfrog from a synchronised state:
+   pi_{-1/2} = pi_0 - (h/2) K_phi, piA_{-1/2} = piA_0 - (h/2) K_A,
+   b_{-1/2} = b_0 - (h/2) K_a[a_0, E(synchronised)]. */
+void orc_u1_lf_startup(const orc_u1* m, double* phi, double* pi, double* L, double* piA, double* a, double* b,
+                       double h) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 2 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double s[9], e[7];
+  if (m->expand) {
+    orc_u1_sums(m, phi, pi, L, piA, s);
+    u1_energies(m, *a, s, -1.0, -1.0, e);
+    *b = *b - 0.5 * h * orc_u1_Ka(m, *a, e);
+  }
+  orc_u1_kernels(m, *a, phi, L, Kp, KA);
+  for (int64_t i = 0; i < 2 * V; ++i) pi[i] -= 0.5 * h * Kp[i];
+  for (int64_t i = 0; i < 3 * V; ++i) piA[i] -= 0.5 * h * KA[i];
+  free(Kp);
+  free(KA);
+}
+
+/* Compact staggered leapfrog (Sec. 5.3.1), per step:
+     pi_{+1/2}  = pi_{-1/2} + h K_phi[a, phi, V]
+     piA_{+1/2} = piA_{-1/2} + h K_A[a, phi, V]
+     b_{+1/2}   = b_{-1/2} + h K_a[a, avg E_K^phi, E_G^phi, E_V, avg E_K^A, E_G^A]
+     a_{+1}     = a + h b_{+1/2}
+     phi_{+1}   = phi + h pi_{+1/2} / a_{+1/2}^{3-alpha}
+     V_{+1}     = Cayley(piA_{+1/2}) V
+   The kinetic averages take both staggered momenta with the scale factor at n. */
+void orc_u1_lf_steps(const orc_u1* m, double* phi, double* pi, double* L, double* piA, double* a, double* b,
+                     double h, int64_t nsteps) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 2 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double s[9], e[7];
+  for (int64_t it = 0; it < nsteps; ++it) {
+    orc_u1_kernels(m, *a, phi, L, Kp, KA);
+    const double kp0 = sum_sq(pi, 2 * V), ka0 = sum_sq(piA, 3 * V);
+    for (int64_t i = 0; i < 2 * V; ++i) pi[i] += h * Kp[i];
+    for (int64_t i = 0; i < 3 * V; ++i) piA[i] += h * KA[i];
+    double anew = *a, amid = *a;
+    if (m->expand) {
+      const double kp1 = sum_sq(pi, 2 * V), ka1 = sum_sq(piA, 3 * V);
+      orc_u1_sums(m, phi, NULL, L, NULL, s);
+      u1_energies(m, *a, s, 0.5 * (kp0 + kp1) / (double)V, 0.5 * (ka0 + ka1) / (double)V, e);
+      *b = *b + h * orc_u1_Ka(m, *a, e);
+      anew = *a + h * (*b);
+      amid = 0.5 * (*a + anew);
+    }
+    const double cd = h * pow(amid, -(3.0 - m->alpha));
+    for (int64_t i = 0; i < 2 * V; ++i) phi[i] += cd * pi[i];
+    u1_link_drift(m, L, piA, h, amid);
+    *a = anew;
+  }
+  free(Kp);
+  free(KA);
+}
+
+/* Gauss-law residual (Sec. 5.2 discrete Gauss law, sign fixed by the kick):
+   G(n) = sum_i (piA_i(n) - piA_i(n-i))/dx - 2 e (f_star/w_star)^2 Im[conj phi(n) pi(n)];
+   out[0] = sum G^2, out[1] = sum (div piA)^2, out[2] = sum rho^2, out[3] = sum rho. */
+void orc_u1_gauss(const orc_u1* m, const double* phi, const double* pi, const double* piA, double* out) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  double g2 = 0.0, d2 = 0.0, r2 = 0.0, rs = 0.0;
+  for (int64_t s = 0; s < V; ++s) {
+    double div = 0.0;
+    for (int i = 0; i < 3; ++i) div += (piA[i * V + s] - piA[i * V + shift(N, s, i, -1)]) / m->dx;
+    const double rho = 2.0 * m->e / m->wf2 * (phi[s] * pi[V + s] - phi[V + s] * pi[s]);
+    g2 += (div - rho) * (div - rho);
+    d2 += div * div;
+    r2 += rho * rho;
+    rs += rho;
+  }
+  out[0] = g2;
+  out[1] = d2;
+  out[2] = r2;
+  out[3] = rs;
+}
+
+/* Observables of a staggered state (phi_n, V_n, a_n; pi_{n-1/2}, piA_{n-1/2}, b_{n-1/2}):
+   e[0..6] as u1_energies with the averaged kinetic terms, e[7] = b_n (mean of the two
+   half-step values), e[8] = Hubble-constraint residual, e[9] = Gauss residual
+   ||G|| / (||div piA|| + ||rho||) of the stored half-step momenta,
+   e[10..12] = <Re phi>, <Im phi>, <|phi|^2>. */
+void orc_u1_lf_observe(const orc_u1* m, const double* phi, const double* pi, const double* L, const double* piA,
+                       double a, double b, double h, double* e) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 2 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  orc_u1_kernels(m, a, phi, L, Kp, KA);
+  double kp1 = 0.0, ka1 = 0.0;
+  for (int64_t i = 0; i < 2 * V; ++i) { const double v = pi[i] + h * Kp[i]; kp1 += v * v; }
+  for (int64_t i = 0; i < 3 * V; ++i) { const double v = piA[i] + h * KA[i]; ka1 += v * v; }
+  const double kp0 = sum_sq(pi, 2 * V), ka0 = sum_sq(piA, 3 * V);
+  double s[9];
+  orc_u1_sums(m, phi, NULL, L, NULL, s);
+  u1_energies(m, a, s, 0.5 * (kp0 + kp1) / (double)V, 0.5 * (ka0 + ka1) / (double)V, e);
+  double bn = b, hc = 0.0;
+  if (m->expand) {
+    const double bp = b + h * orc_u1_Ka(m, a, e);
+    bn = 0.5 * (b + bp);
+    const double rho = e[0] + e[1] + e[2] + e[3] + e[4];
+    const double rhs = m->fmp2 / 3.0 * pow(a, 2.0 * (m->alpha + 1.0)) * rho;
+    hc = fabs(bn * bn - rhs) / (bn * bn);
+  }
+  double g[4];
+  orc_u1_gauss(m, phi, pi, piA, g);
+  e[7] = bn;
+  e[8] = hc;
+  e[9] = sqrt(g[0]) / (sqrt(g[1]) + sqrt(g[2]));
+  e[10] = s[6];
+  e[11] = s[7];
+  e[12] = s[8];
+  free(Kp);
+  free(KA);
+}
+
+/* Observables of a synchronised state; same layout as orc_u1_lf_observe. */
+void orc_u1_sync_observe(const orc_u1* m, const double* phi, const double* pi, const double* L,
+                         const double* piA, double a, double b, double* e) {
+  double s[9];
+  orc_u1_sums(m, phi, pi, L, piA, s);
+  u1_energies(m, a, s, -1.0, -1.0, e);
+  double hc = 0.0;
+  if (m->expand) {
+    const double rho = e[0] + e[1] + e[2] + e[3] + e[4];
+    const double rhs = m->fmp2 / 3.0 * pow(a, 2.0 * (m->alpha + 1.0)) * rho;
+    hc = fabs(b * b - rhs) / (b * b);
+  }
+  double g[4];
+  orc_u1_gauss(m, phi, pi, piA, g);
+  e[7] = b;
+  e[8] = hc;
+  e[9] = sqrt(g[0]) / (sqrt(g[1]) + sqrt(g[2]));
+  e[10] = s[6];
+  e[11] = s[7];
+  e[12] = s[8];
+}

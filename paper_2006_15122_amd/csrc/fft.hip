@@ -331,7 +331,6 @@ int init_state(lattice* h) {
   const double fmp2 = p.fstar_over_mp * p.fstar_over_mp;
   double rho_hom = 0.0;
   for (int f = 0; f < nfield; ++f) rho_hom += p.dphi0[f] * p.dphi0[f] / (2.0 * std::pow(a, 2.0 * al));
-  if (p.model == LAT_MODEL_U1) rho_hom *= 0.5;  // |phi'|^2 with the 1/sqrt 2 of each component
   rho_hom += potential_host(p, p.phi0);
   const double Hhom = p.expansion ? std::sqrt(fmp2 / 3.0 * std::pow(a, 2.0 * (al + 1.0)) * rho_hom) / a : 0.0;
   const int threads = 256;
