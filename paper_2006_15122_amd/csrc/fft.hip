@@ -323,6 +323,7 @@ int run_fft3d(lattice* h, int sign, double scale) {
 // model, then b from the Hubble constraint with the full-lattice energies.
 int init_state(lattice* h) {
   const lattice_params& p = h->p;
+  if (p.model == LAT_MODEL_U1) return u1_init_state(h);
   const int N = p.N;
   const int64_t V = (int64_t)N * N * N;
   const double a = p.a0, al = p.alpha;
@@ -369,10 +370,6 @@ int init_state(lattice* h) {
                            V, base, 1.0 / (double)V, scale, fluct ? 1 : 0);
       CL_HIP(hipGetLastError());
     }
-  }
-  if (p.model == LAT_MODEL_U1) {
-    int rc = u1_init_gauge(h, Hhom);
-    if (rc) return rc;
   }
   int rc = upload_scalars(h, a, 0.0, 0.0);
   if (rc) return rc;

@@ -52,7 +52,8 @@ int scalar_step(lattice* h, int64_t n);
 int scalar_energies(lattice* h);
 int u1_step(lattice* h, int64_t n);
 int u1_energies(lattice* h);
-int u1_init_gauge(lattice* h, double Hhom);
+int u1_init_state(lattice* h);
+int u1_gauss(lattice* h);
 int run_fft3d(lattice* h, int sign, double scale);
 bool tiling_ok(const lattice* h, const Tiling& t);
 void default_tiling(lattice* h);

@@ -1,21 +1,620 @@
-// Compact U(1) gauge sector (Sec. 5.3): placeholder entry points until the
-// U(1) kernels land.
+// Complex scalar with compact U(1) links on gfx950 (Sec. 5.3, compact
+// staggered leapfrog).  One step = kick (in place) -> FP64 finish -> drift
+// (in place).  The kick of pi at n reads only phi and links, and the drift of
+// phi and V at n reads only pi and piA at n, so no state buffer is doubled.
+//
+// Components (storage precision, N^3 each): 0,1 = Re, Im phi; 2,3 = Re, Im
+// pi; 4 + 2i + c = (Re, Im) of the link V_i; 10 + i = piA_i.
+//
+// Kernels (Sec. 5.1, 5.3):
+//   K_phi   = -a^{3+alpha}(2 lambda |phi|^2 + m2) phi
+//             + a^{1+alpha} sum_i (V_i phi_{+i} - 2 phi + conj V_i(n-i) phi_{-i}) / dx^2
+//   K_{A,i} = a^{1+alpha}(2 e/dx)(f/w)^2 Im[conj phi V_i phi_{+i}]
+//             + a^{alpha-1}/(e dx^3) sum_{j!=i} (Im V_ij(n) - Im V_ij(n-j)),
+//   V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace cl {
 
-int u1_step(lattice*, int64_t) {
-  set_error("U(1) model not built yet");
-  return LAT_EINVAL;
+template <typename T>
+struct C2 {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ C2<T> cm(C2<T> a, C2<T> b) {
+  return C2<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-int u1_energies(lattice*) {
-  set_error("U(1) model not built yet");
-  return LAT_EINVAL;
+template <typename T>
+__device__ __forceinline__ C2<T> cc(C2<T> a) {
+  return C2<T>{a.x, -a.y};
 }
-int u1_init_gauge(lattice*, double) {
-  set_error("U(1) model not built yet");
-  return LAT_EINVAL;
+
+template <typename T>
+struct U1Args {
+  T* c[13];
+  int N;
+  double dx, alpha, fmp2, lam, m2, e, wf2, h;
+  int expand;
+  // kick: pi += ck h K (ck = 1 LF step, -1/2 start-up, 0 observation);
+  // mode LF: E_K from the mean of <pi_in^2> and <pi_out^2>, VV: from pi_in
+  double ck;
+  int mode;
+  int write;
+  int advance;  // finish: after the kick, a' = a + h b_out and a_mid for the drift
+  double* partials;
+  DevState* st;
+};
+
+constexpr int kU1Acc = 11;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NACC>
+__device__ void u1_block_partials(double (&acc)[NACC], double* partials) {
+  __shared__ double red[4][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wsum(acc[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid < NACC) partials[(size_t)blockIdx.x * NACC + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
+  return C2<T>{re[i], im[i]};
+}
+
+// one thread per site; neighbours come through the cache hierarchy
+template <typename T>
+__global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
+  const int N = A.N;
+  const size_t NN = (size_t)N * N;
+  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int x = (int)(s / NN), y = (int)((s / N) % N), z = (int)(s % N);
+  auto at = [&](int dx_, int dy_, int dz_) -> size_t {
+    const int xx = (x + dx_ + N) % N, yy = (y + dy_ + N) % N, zz = (z + dz_ + N) % N;
+    return (size_t)xx * NN + (size_t)yy * N + zz;
+  };
+  auto off = [&](int dir, int step, int dir2, int step2) -> size_t {
+    int d[3] = {0, 0, 0};
+    d[dir] += step;
+    d[dir2] += step2;
+    return at(d[0], d[1], d[2]);
+  };
+  auto link = [&](int i, size_t site) -> C2<T> { return ld(A.c[4 + 2 * i], A.c[5 + 2 * i], site); };
+  auto phi = [&](size_t site) -> C2<T> { return ld(A.c[0], A.c[1], site); };
+
+  const double a_in = A.st->a;
+  const T cl = (T)(pow(a_in, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cp = (T)pow(a_in, 3.0 + A.alpha);
+  const T cj = (T)(pow(a_in, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+  const T cb = (T)(pow(a_in, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+  const T ck = (T)(A.ck * A.h);
+  const T lam = (T)A.lam, m2 = (T)A.m2;
+
+  const C2<T> p = phi(s);
+  C2<T> lap{T(-6) * p.x, T(-6) * p.y};
+  double grad = 0.0;
+  C2<T> Vs[3];
+  T Kcur[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Vs[i] = link(i, s);
+    const size_t sp = off(i, 1, i, 0), sm = off(i, -1, i, 0);
+    const C2<T> f = cm(Vs[i], phi(sp));
+    const C2<T> b = cm(cc(link(i, sm)), phi(sm));
+    lap.x += f.x + b.x;
+    lap.y += f.y + b.y;
+    const T gx = f.x - p.x, gy = f.y - p.y;
+    grad += (double)(gx * gx + gy * gy);
+    Kcur[i] = cj * (p.x * f.y - p.y * f.x);  // Im(conj p * f)
+  }
+  const T r2 = p.x * p.x + p.y * p.y;
+  const T dv = T(2) * lam * r2 + m2;
+  const C2<T> Kp{cl * lap.x - cp * dv * p.x, cl * lap.y - cp * dv * p.y};
+
+  double mag = 0.0;
+  T KA[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T curl = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (j == i) continue;
+      // V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n)
+      const C2<T> P0 = cm(cm(Vs[i], link(j, off(i, 1, j, 0))), cm(cc(link(i, off(j, 1, i, 0))), cc(Vs[j])));
+      // V_ij(n-j) = V_i(n-j) V_j(n-j+i) conj V_i(n) conj V_j(n-j)
+      const size_t smj = off(j, -1, j, 0);
+      const C2<T> P1 = cm(cm(link(i, smj), link(j, off(j, -1, i, 1))), cm(cc(Vs[i]), cc(link(j, smj))));
+      curl += P0.y - P1.y;
+      if (j > i) mag += (double)(T(1) - P0.x);
+    }
+    KA[i] = Kcur[i] + cb * curl;
+  }
+
+  const C2<T> pin = ld(A.c[2], A.c[3], s);
+  const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
+  const bool lf = A.mode == MODE_LF;
+  double acc[kU1Acc];
+  acc[0] = (double)(pin.x * pin.x + pin.y * pin.y);
+  acc[1] = lf ? (double)(pout.x * pout.x + pout.y * pout.y) : acc[0];
+  acc[2] = grad;
+  acc[3] = (double)(lam * r2 * r2);
+  acc[4] = (double)(m2 * r2);
+  double ka0 = 0.0, ka1 = 0.0;
+  T aout[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T ain = A.c[10 + i][s];
+    aout[i] = ain + ck * KA[i];
+    ka0 += (double)(ain * ain);
+    ka1 += (double)(aout[i] * aout[i]);
+  }
+  acc[5] = ka0;
+  acc[6] = lf ? ka1 : ka0;
+  acc[7] = mag;
+  acc[8] = (double)p.x;
+  acc[9] = (double)p.y;
+  acc[10] = (double)r2;
+  if (A.write) {
+    A.c[2][s] = pout.x;
+    A.c[3][s] = pout.y;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A.c[10 + i][s] = aout[i];
+  }
+  u1_block_partials<kU1Acc>(acc, A.partials);
+}
+
+// Combine the partials in block order; energies of Sec. 5.4.1 and the scale-
+// factor kernel with the gauge term (Sec. 5.1):
+//   K_a = (1/3)(f/m_p)^2 a^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V
+//                                       + (alpha-1)(E_K^A + E_G^A)].
+template <typename T>
+__global__ __launch_bounds__(1024) void u1_finish_kernel(U1Args<T> A, int nblocks) {
+  constexpr int NACC = kU1Acc, NW = 16;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double tot[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
+  for (int b = tid; b < nblocks; b += 1024) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) tot[k] += A.partials[(size_t)b * NACC + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wsum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double S[NACC];
+  for (int k = 0; k < NACC; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][k];
+    S[k] = s;
+  }
+  const double V = (double)A.N * A.N * A.N;
+  const double a = A.st->a, b_in = A.st->b, al = A.alpha;
+  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = A.dx * A.dx;
+  lattice_obs o;
+  o.EK = 0.5 * (S[0] + S[1]) / V / a6;
+  o.EG = S[2] / V / (a2 * dx2);
+  o.EV_term[0] = S[4] / V;
+  o.EV_term[1] = S[3] / V;
+  o.EV_term[2] = 0.0;
+  o.EV = o.EV_term[0] + o.EV_term[1];
+  o.EK_A = A.wf2 * 0.5 * (S[5] + S[6]) / V / (2.0 * a4);
+  o.EG_A = A.wf2 * S[7] / V / (a4 * dx2 * dx2 * A.e * A.e);
+  o.EK_f[0] = o.EK;
+  o.EK_f[1] = 0.0;
+  o.EG_f[0] = o.EG;
+  o.EG_f[1] = 0.0;
+  o.mean_f[0] = S[8] / V;
+  o.mean_f[1] = S[9] / V;
+  o.meansq_f[0] = S[10] / V;
+  o.meansq_f[1] = 0.0;
+  bool bad = false;
+  for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
+  const double rho = o.EK + o.EG + o.EV + o.EK_A + o.EG_A;
+  double b_out = b_in, b_sync = b_in, hc = 0.0, anext = a;
+  if (A.expand) {
+    const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+                      ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * (o.EK_A + o.EG_A));
+    b_out = b_in + A.ck * A.h * Ka;
+    b_sync = (A.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in;
+    const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
+    hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
+    if (A.advance) anext = a + A.h * b_out;
+  }
+  o.eta = A.st->eta;
+  o.a = a;
+  o.b = b_sync;
+  o.H = b_sync / a;
+  o.rho = rho;
+  o.p = o.EK - o.EG / 3.0 - o.EV + (o.EK_A + o.EG_A) / 3.0;
+  o.w = rho != 0.0 ? o.p / rho : 0.0;
+  o.hc = hc;
+  o.gauss = A.st->obs.gauss;
+  o.step = 0;
+  o.staggered = (A.mode == MODE_LF) ? 1 : 0;
+  o.reserved = 0;
+  A.st->obs = o;
+  if (bad) A.st->nonfinite = 1;
+  if (A.write) {
+    A.st->b = b_out;
+    if (A.advance) {
+      A.st->aux[0] = 0.5 * (a + anext);  // a_{n+1/2} for the drift
+      A.st->a = anext;
+      A.st->eta = A.st->eta + A.h;
+    }
+  }
+}
+
+// phi <- phi + h pi / a_mid^{3-alpha};  V_i <- (1 - i u)/(1 + i u) V_i,
+// u = e h dx piA_i / (2 a_mid^{1-alpha})  (Sec. 5.3, drift from momenta).
+template <typename T>
+__global__ __launch_bounds__(256) void u1_drift_kernel(U1Args<T> A) {
+  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const double amid = A.expand ? A.st->aux[0] : A.st->a;
+  const T cd = (T)(A.h * pow(amid, -(3.0 - A.alpha)));
+  const T cu = (T)(A.e * A.h * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
+  A.c[0][s] = A.c[0][s] + cd * A.c[2][s];
+  A.c[1][s] = A.c[1][s] + cd * A.c[3][s];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T u = cu * A.c[10 + i][s];
+    const T d = T(1) / (T(1) + u * u);
+    const C2<T> r{(T(1) - u * u) * d, T(-2) * u * d};
+    const C2<T> v = cm(r, C2<T>{A.c[4 + 2 * i][s], A.c[5 + 2 * i][s]});
+    A.c[4 + 2 * i][s] = v.x;
+    A.c[5 + 2 * i][s] = v.y;
+  }
+}
+
+// Gauss residual G(n) = sum_i (piA_i(n) - piA_i(n-i))/dx - 2e (f/w)^2 Im[conj phi pi]
+template <typename T>
+__global__ __launch_bounds__(256) void u1_gauss_kernel(U1Args<T> A) {
+  const int N = A.N;
+  const size_t NN = (size_t)N * N;
+  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int x = (int)(s / NN), y = (int)((s / N) % N), z = (int)(s % N);
+  const size_t sm[3] = {(size_t)((x - 1 + N) % N) * NN + (size_t)y * N + z,
+                        (size_t)x * NN + (size_t)((y - 1 + N) % N) * N + z,
+                        (size_t)x * NN + (size_t)y * N + (z - 1 + N) % N};
+  double div = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) div += ((double)A.c[10 + i][s] - (double)A.c[10 + i][sm[i]]) / A.dx;
+  const double rho = 2.0 * A.e / A.wf2 *
+                     ((double)A.c[0][s] * (double)A.c[3][s] - (double)A.c[1][s] * (double)A.c[2][s]);
+  double acc[4] = {(div - rho) * (div - rho), div * div, rho * rho, rho};
+  u1_block_partials<4>(acc, A.partials);
+}
+
+__global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* partials, int nblocks, DevState* st) {
+  __shared__ double red[16][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < nblocks; b += 1024)
+    for (int k = 0; k < 4; ++k) tot[k] += partials[(size_t)b * 4 + k];
+  for (int k = 0; k < 4; ++k) {
+    const double s = wsum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double S[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k)
+    for (int w = 0; w < 16; ++w) S[k] += red[w][k];
+  const double den = sqrt(S[1]) + sqrt(S[2]);
+  st->obs.gauss = den > 0.0 ? sqrt(S[0]) / den : 0.0;
+}
+
+template <typename T>
+static void fill_args(lattice* h, U1Args<T>& A) {
+  for (int c = 0; c < 13; ++c) A.c[c] = static_cast<T*>(h->buf[h->cur][c]);
+  A.N = h->p.N;
+  A.dx = h->dx;
+  A.alpha = h->p.alpha;
+  A.fmp2 = h->p.fstar_over_mp * h->p.fstar_over_mp;
+  A.lam = h->p.lambda;
+  A.m2 = h->p.m2[0];
+  A.e = h->p.e;
+  A.wf2 = h->p.omega_over_f * h->p.omega_over_f;
+  A.h = h->p.dt;
+  A.expand = h->p.expansion;
+  A.partials = h->partials;
+  A.st = h->st;
+}
+
+template <typename T>
+static int u1_kick_t(lattice* h, double ck, int mode, int write, int advance) {
+  U1Args<T> A;
+  fill_args(h, A);
+  A.ck = ck;
+  A.mode = mode;
+  A.write = write;
+  A.advance = advance;
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const int nb = (int)(V / 256);
+  hipLaunchKernelGGL(u1_kick_kernel<T>, dim3(nb), dim3(256), 0, h->stream, A);
+  CL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(u1_finish_kernel<T>, dim3(1), dim3(1024), 0, h->stream, A, nb);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+template <typename T>
+static int u1_drift_t(lattice* h) {
+  U1Args<T> A;
+  fill_args(h, A);
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  hipLaunchKernelGGL(u1_drift_kernel<T>, dim3((int)(V / 256)), dim3(256), 0, h->stream, A);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+template <typename T>
+static int u1_gauss_t(lattice* h) {
+  U1Args<T> A;
+  fill_args(h, A);
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  const int nb = (int)(V / 256);
+  hipLaunchKernelGGL(u1_gauss_kernel<T>, dim3(nb), dim3(256), 0, h->stream, A);
+  CL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(u1_gauss_finish_kernel, dim3(1), dim3(1024), 0, h->stream, h->partials, nb, h->st);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+static int u1_kick(lattice* h, double ck, int mode, int write, int advance) {
+  return h->p.precision == LAT_FP32 ? u1_kick_t<float>(h, ck, mode, write, advance)
+                                    : u1_kick_t<double>(h, ck, mode, write, advance);
+}
+static int u1_drift(lattice* h) {
+  return h->p.precision == LAT_FP32 ? u1_drift_t<float>(h) : u1_drift_t<double>(h);
+}
+int u1_gauss(lattice* h) { return h->p.precision == LAT_FP32 ? u1_gauss_t<float>(h) : u1_gauss_t<double>(h); }
+
+int u1_step(lattice* h, int64_t n) {
+  int rc;
+  if (!h->staggered) {
+    // pi_{-1/2} = pi_0 - (h/2) K, piA likewise, b_{-1/2} = b_0 - (h/2) K_a(synchronised E)
+    rc = u1_kick(h, -0.5, MODE_VV, 1, 0);
+    if (rc) return rc;
+    h->staggered = 1;
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    rc = u1_kick(h, 1.0, MODE_LF, 1, 1);
+    if (rc) return rc;
+    rc = u1_drift(h);
+    if (rc) return rc;
+  }
+  h->step += n;
+  return LAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// initial state (Sec. 7.2)
+// ---------------------------------------------------------------------------
+struct U1ModeArgs {
+  int N, comp, deriv;
+  uint64_t seed;
+  double kIR, P0, a, alpha, m2eff, Hhom, kcut;
+};
+
+__device__ __forceinline__ int wrapk_u1(int i, int N) { return i <= N / 2 ? i : i - N; }
+
+// Modes of the real component `comp` of phi = (phi_0 + i phi_1)/sqrt 2 with the
+// zero-charge constraints |l_n| = |r_n|, th_1^r = th_0^r + th_1^l - th_0^l.
+// Philox(counter = (lin, n, 0), key = seed): u0 -> |l_n| (Rayleigh, E|.|^2 = P),
+// u2 -> th_n^l, u3 of component 0 -> th_0^r.
+__global__ void u1_modes_kernel(double2* F, U1ModeArgs M) {
+  const int64_t V = (int64_t)M.N * M.N * M.N;
+  const int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (lin >= V) return;
+  const int N = M.N;
+  const int i3 = (int)(lin % N), i2 = (int)((lin / N) % N), i1 = (int)(lin / ((int64_t)N * N));
+  const int64_t par = ((int64_t)((N - i1) % N) * N + (N - i2) % N) * N + (N - i3) % N;
+  if (lin > par) return;
+  if (lin == par) { F[lin] = make_double2(0.0, 0.0); return; }
+  const int n1 = wrapk_u1(i1, N), n2 = wrapk_u1(i2, N), n3 = wrapk_u1(i3, N);
+  const double k = M.kIR * sqrt((double)n1 * n1 + (double)n2 * n2 + (double)n3 * n3);
+  const double om2 = k * k + M.a * M.a * M.m2eff;
+  if (!(om2 > 0.0) || (M.kcut > 0.0 && k > M.kcut)) {
+    F[lin] = make_double2(0.0, 0.0);
+    F[par] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double om = sqrt(om2), P = M.P0 / (2.0 * M.a * M.a * om);
+  const uint32_t k0 = (uint32_t)M.seed, k1 = (uint32_t)(M.seed >> 32);
+  const uint32_t c0 = (uint32_t)lin, c1 = (uint32_t)((uint64_t)lin >> 32);
+  const Philox4 un = philox4x32_10(c0, c1, (uint32_t)M.comp, 0u, k0, k1);
+  const Philox4 u0 = philox4x32_10(c0, c1, 0u, 0u, k0, k1);
+  const double two32 = 4294967296.0, twopi = 6.283185307179586476925286766559;
+  const double R = sqrt(-P * log(((double)un.v[0] + 0.5) / two32));
+  const double thl = twopi * ((double)un.v[2] + 0.5) / two32;
+  const double th0l = twopi * ((double)u0.v[2] + 0.5) / two32;
+  const double th0r = twopi * ((double)u0.v[3] + 0.5) / two32;
+  const double thr = M.comp == 0 ? th0r : th0r + thl - th0l;
+  double sl, cl_, sr, cr;
+  sincos(thl, &sl, &cl_);
+  sincos(thr, &sr, &cr);
+  const double Lx = R * cl_, Ly = R * sl, Rx = R * cr, Ry = R * sr;
+  const double is2 = 0.70710678118654752440084436210485;
+  double2 v;
+  if (!M.deriv) {
+    v = make_double2((Lx + Rx) * is2, (Ly + Ry) * is2);
+  } else {
+    const double c = pow(M.a, -(1.0 - M.alpha)) * om * is2;
+    v = make_double2(-c * (Ly - Ry) - M.Hhom * (Lx + Rx) * is2, c * (Lx - Rx) - M.Hhom * (Ly + Ry) * is2);
+  }
+  F[lin] = v;
+  F[par] = make_double2(v.x, -v.y);
+}
+
+__global__ void u1_take_real_kernel(const double2* F, double* out, int64_t V, double base, double invV) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < V) out[i] = base + F[i].x * invV;
+}
+
+// phi = (phi_0 + i phi_1)/sqrt 2, pi = a^{3-alpha}(phi_0' + i phi_1')/sqrt 2, and the
+// charge density rho = 2e (f/w)^2 Im[conj phi pi] (FP64, from the unrounded values)
+template <typename T>
+__global__ void u1_store_kernel(const double* f0, const double* f1, const double* d0, const double* d1, T* pr,
+                                T* pim, T* qr, T* qim, double2* rho, int64_t V, double cpi, double cq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  const double is2 = 0.70710678118654752440084436210485;
+  const double a = f0[i] * is2, b = f1[i] * is2, c = cpi * d0[i] * is2, d = cpi * d1[i] * is2;
+  pr[i] = (T)a;
+  pim[i] = (T)b;
+  qr[i] = (T)c;
+  qim[i] = (T)d;
+  rho[i] = make_double2(cq * (a * d - b * c), 0.0);
+}
+
+// Minimum-norm solution of sum_i s_i E_i = rho^ with s_i = (1 - e^{+2 pi i n_i/N})/dx:
+// E_i = conj(s_i) rho^ / sum_j |s_j|^2, E(0) = 0.
+__global__ void u1_gauss_solve_kernel(const double2* R, double2* F, int N, int dir, double dx) {
+  const int64_t V = (int64_t)N * N * N;
+  const int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (lin >= V) return;
+  const int idx[3] = {(int)(lin / ((int64_t)N * N)), (int)((lin / N) % N), (int)(lin % N)};
+  const double twopi = 6.283185307179586476925286766559;
+  double den = 0.0, sr = 0.0, si = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    double sn, cs;
+    sincos(twopi * (double)idx[j] / (double)N, &sn, &cs);
+    const double xr = (1.0 - cs) / dx, xi = -sn / dx;
+    den += xr * xr + xi * xi;
+    if (j == dir) { sr = xr; si = xi; }
+  }
+  if (den == 0.0) { F[lin] = make_double2(0.0, 0.0); return; }
+  const double2 r = R[lin];
+  // conj(s) * r = (sr - i si)(r.x + i r.y)
+  F[lin] = make_double2((sr * r.x + si * r.y) / den, (sr * r.y - si * r.x) / den);
+}
+
+template <typename T>
+__global__ void u1_store_link_momentum_kernel(const double2* F, T* out, int64_t V, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < V) out[i] = (T)(scale * F[i].x);
+}
+
+template <typename T>
+__global__ void u1_unit_links_kernel(T* re0, T* im0, T* re1, T* im1, T* re2, T* im2, int64_t V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  re0[i] = re1[i] = re2[i] = T(1);
+  im0[i] = im1[i] = im2[i] = T(0);
+}
+
+template <typename T>
+static int u1_init_state_t(lattice* h) {
+  const lattice_params& p = h->p;
+  const int N = p.N;
+  const int64_t V = (int64_t)N * N * N;
+  const double a = p.a0, al = p.alpha, fmp2 = p.fstar_over_mp * p.fstar_over_mp;
+  const double r2 = 0.5 * (p.phi0[0] * p.phi0[0] + p.phi0[1] * p.phi0[1]);
+  const double rho_hom = (p.dphi0[0] * p.dphi0[0] + p.dphi0[1] * p.dphi0[1]) / (2.0 * std::pow(a, 2.0 * al)) +
+                         p.lambda * r2 * r2 + p.m2[0] * r2;
+  const double Hhom = p.expansion ? std::sqrt(fmp2 / 3.0 * std::pow(a, 2.0 * (al + 1.0)) * rho_hom) / a : 0.0;
+  const double s = p.phi0[0] * p.phi0[0] + p.phi0[1] * p.phi0[1];
+  double2* F = reinterpret_cast<double2*>(h->fft);
+  double* scratch = reinterpret_cast<double*>(h->buf[1 - h->cur][0]);  // 4 V doubles, then rho^
+  double* full[4] = {scratch, scratch + V, scratch + 2 * V, scratch + 3 * V};
+  const int thr = 256;
+  const int blk = (int)((V + thr - 1) / thr);
+  for (int n = 0; n < 2; ++n) {
+    for (int deriv = 0; deriv < 2; ++deriv) {
+      double* out = full[deriv ? 2 + n : n];
+      const double base = deriv ? p.dphi0[n] : p.phi0[n];
+      if (p.ic == LAT_IC_VACUUM) {
+        U1ModeArgs M;
+        M.N = N;
+        M.comp = n;
+        M.deriv = deriv;
+        M.seed = p.seed;
+        M.kIR = p.kIR;
+        M.P0 = p.omega_over_f * p.omega_over_f * std::pow((double)N / h->dx, 3.0);
+        M.a = a;
+        M.alpha = al;
+        M.m2eff = p.lambda * (s + 2.0 * p.phi0[n] * p.phi0[n]) + p.m2[0];
+        M.Hhom = Hhom;
+        M.kcut = p.kcut;
+        hipLaunchKernelGGL(u1_modes_kernel, dim3(blk), dim3(thr), 0, h->stream, F, M);
+        CL_HIP(hipGetLastError());
+        int rc = run_fft3d(h, -1, 1.0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(u1_take_real_kernel, dim3(blk), dim3(thr), 0, h->stream, F, out, V, base,
+                           1.0 / (double)V);
+      } else {
+        hipLaunchKernelGGL(u1_take_real_kernel, dim3(blk), dim3(thr), 0, h->stream, F, out, V, base, 0.0);
+      }
+      CL_HIP(hipGetLastError());
+    }
+  }
+  T* c[13];
+  for (int k = 0; k < 13; ++k) c[k] = static_cast<T*>(h->buf[h->cur][k]);
+  const double cq = 2.0 * p.e / (p.omega_over_f * p.omega_over_f);
+  hipLaunchKernelGGL(u1_store_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, full[0], full[1], full[2], full[3],
+                     c[0], c[1], c[2], c[3], F, V, std::pow(a, 3.0 - al), cq);
+  CL_HIP(hipGetLastError());
+  int rc = run_fft3d(h, +1, 1.0);
+  if (rc) return rc;
+  double2* R = reinterpret_cast<double2*>(scratch);
+  CL_HIP(hipMemcpyAsync(R, F, (size_t)V * sizeof(double2), hipMemcpyDeviceToDevice, h->stream));
+  for (int i = 0; i < 3; ++i) {
+    hipLaunchKernelGGL(u1_gauss_solve_kernel, dim3(blk), dim3(thr), 0, h->stream, R, F, N, i, h->dx);
+    CL_HIP(hipGetLastError());
+    rc = run_fft3d(h, -1, 1.0);
+    if (rc) return rc;
+    hipLaunchKernelGGL(u1_store_link_momentum_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, F, c[10 + i], V,
+                       std::pow(a, 1.0 - al) / (double)V);
+    CL_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(u1_unit_links_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, c[4], c[5], c[6], c[7], c[8],
+                     c[9], V);
+  CL_HIP(hipGetLastError());
+  rc = upload_scalars(h, a, 0.0, 0.0);
+  if (rc) return rc;
+  h->staggered = 0;
+  h->step = 0;
+  if (p.expansion) {
+    rc = u1_energies(h);
+    if (rc) return rc;
+    DevState d;
+    CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    CL_HIP(hipStreamSynchronize(h->stream));
+    const double b0 = std::sqrt(fmp2 / 3.0 * std::pow(a, 2.0 * (al + 1.0)) * d.obs.rho);
+    rc = upload_scalars(h, a, b0, 0.0);
+    if (rc) return rc;
+  }
+  return LAT_OK;
+}
+
+int u1_init_state(lattice* h) {
+  return h->p.precision == LAT_FP32 ? u1_init_state_t<float>(h) : u1_init_state_t<double>(h);
+}
+
+int u1_energies(lattice* h) {
+  int rc = u1_gauss(h);
+  if (rc) return rc;
+  if (h->staggered) return u1_kick(h, 1.0, MODE_LF, 0, 0);
+  return u1_kick(h, 0.0, MODE_VV, 0, 0);
 }
 
 }  // namespace cl

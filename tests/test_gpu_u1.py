@@ -1,0 +1,143 @@
+"""GPU parity of the compact U(1) path (Sec. 5.3) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_15122_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("a", "b", "EK", "EG", "EV", "EK_A", "EG_A", "EV_quartic")
+
+
+def _lattice(cfg):
+    from paper_2006_15122_amd.lattice import Lattice
+
+    return Lattice(cfg, device="cuda:0")
+
+
+def _cfg(N, precision="fp32", **kw):
+    c = dict(synth.config3(N=N), precision=precision)
+    c.update(kw)
+    return c
+
+
+def _state_for_gpu(st):
+    return dict(phi=st["phi"], pi=st["pi"], links=st["links"], piA=st["piA"])
+
+
+def compare(g, o, tol, what):
+    bad = {}
+    for k in KEYS:
+        if o[k] == 0.0:
+            continue
+        r = abs(g[k] - o[k]) / abs(o[k])
+        if not r <= tol:
+            bad[k] = r
+    sc = math.sqrt(o["meansq"])
+    for gk, ok in (("mean0", "mean0"), ("mean1", "mean1")):
+        r = abs(g[gk] - o[ok]) / sc
+        if not r <= tol:
+            bad[gk] = r
+    r = abs(g["meansq0"] - o["meansq"]) / o["meansq"]
+    if not r <= tol:
+        bad["meansq"] = r
+    assert not bad, (what, bad)
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_u1_initial_state_matches_oracle_fp64(N):
+    cfg = _cfg(N, "fp64")
+    lat = _lattice(cfg)
+    st = oracle.u1_vacuum_ic(cfg)
+    s = lat.get_state()
+    for key in ("phi", "pi", "links", "piA"):
+        ref = st[key]
+        assert np.max(np.abs(s[key] - ref)) < 1e-12 * max(np.max(np.abs(ref)), 1e-30), key
+    assert abs(s["b"] - st["b"]) < 1e-12 * st["b"]
+    e = lat.energies()
+    assert e["gauss"] < 1e-12
+
+
+def test_u1_fp64_parity_and_gauss_200_steps():
+    cfg = _cfg(32, "fp64")
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    h = cfg["dt"]
+    oracle.u1_lf_startup(m, st, h)
+    for k in range(4):
+        lat.step(50)
+        oracle.u1_lf_steps(m, st, h, 50)
+        o = oracle.u1_lf_observe(m, st, h)
+        g = lat.energies()
+        compare(g, o, 1e-10, f"fp64 step {50 * (k + 1)}")
+        assert g["gauss"] < 1e-12 and o["gauss"] < 1e-12
+    s = lat.get_state()
+    assert s["staggered"] and s["step"] == 200
+    for key in ("phi", "pi", "links", "piA"):
+        assert np.max(np.abs(s[key] - st[key])) < 1e-10 * np.max(np.abs(st[key])), key
+
+
+def test_u1_fp32_parity_64_400_steps():
+    cfg = _cfg(64, "fp32")
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    h = cfg["dt"]
+    oracle.u1_lf_startup(m, st, h)
+    for k in range(4):
+        lat.step(100)
+        oracle.u1_lf_steps(m, st, h, 100, omp=True)
+        o = oracle.u1_lf_observe(m, st, h)
+        g = lat.energies()
+        compare(g, o, 1e-5, f"fp32 step {100 * (k + 1)}")
+        assert g["gauss"] < 1e-5, g["gauss"]
+
+
+def test_u1_full_size_192_sampled_sites():
+    cfg = _cfg(192, "fp32")
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    h = cfg["dt"]
+    lat.step(3)
+    oracle.u1_lf_startup(m, st, h)
+    oracle.u1_lf_steps(m, st, h, 3, omp=True)
+    o = oracle.u1_lf_observe(m, st, h)
+    g = lat.energies()
+    compare(g, o, 1e-5, "192^3")
+    assert g["gauss"] < 1e-5
+    s = lat.get_state()
+    rng = np.random.default_rng(1)
+    for key, nc in (("phi", 2), ("pi", 2), ("piA", 3)):
+        idx = (rng.integers(0, nc, 4096),) + tuple(rng.integers(0, 192, (3, 4096)))
+        d = np.abs(s[key][idx] - st[key][idx])
+        assert np.max(d) < 2e-5 * np.max(np.abs(st[key][idx])), key
+
+
+def test_u1_device_init_fp32_gauss_and_energy_budget():
+    cfg = _cfg(96, "fp32")
+    lat = _lattice(cfg)
+    e = lat.energies()
+    assert e["gauss"] < 1e-5
+    assert e["EG_A"] == 0.0 and e["EK_A"] > 0.0
+    lat.step(20)
+    e2 = lat.energies()
+    assert e2["gauss"] < 1e-5 and e2["EG_A"] > 0.0
+
+
+def test_u1_spectrum_matches_oracle():
+    cfg = _cfg(32, "fp64")
+    lat = _lattice(cfg)
+    s = lat.get_state()
+    for which, arr in ((0, s["phi"][0]), (1, s["phi"][1]), (16, s["pi"][0])):
+        g = lat.spectrum(which)
+        o = oracle.spectrum(arr, cfg["kIR"])
+        assert np.array_equal(g["count"], o["count"])
+        assert np.max(np.abs(g["S"] - o["S"])) < 1e-10 * np.max(o["S"])
