@@ -159,6 +159,15 @@ def main():
             extras[name] = {"site_updates_per_s": n3 * st / (ms2 / 1e3),
                             "hbm_frac": n3 * 32 / (ms2 / npass / 1e3) / 1e9 / HBM_PEAK_GBS,
                             "tile": t2, "steps": st}
+        # compact U(1) Abelian-Higgs, 192^3, FP32, staggered leapfrog; state per site: phi (2),
+        # pi (2), link phases (3), link momenta (3) = 10 FP32, read and written once per step
+        c3 = synth.config3()
+        st3 = max(args.steps // 10, 10)
+        ms3, _, obs3, _ = time_lattice(c3, st3, 5)
+        n3 = c3["N"] ** 3
+        extras["u1_192_lf2"] = {"site_updates_per_s": n3 * st3 / (ms3 / 1e3),
+                                "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                "bytes_per_site_update": 80, "steps": st3, "gauss": obs3["gauss"]}
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

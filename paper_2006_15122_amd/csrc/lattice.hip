@@ -80,7 +80,7 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, 
 }
 
 int ncomponents(const lattice_params* p) {
-  if (p->model == LAT_MODEL_U1) return 13;  // phi (2), pi (2), links (3x2), piA (3)
+  if (p->model == LAT_MODEL_U1) return 10;  // phi (2), pi (2), link phases (3), piA (3)
   return 2 * p->nf;
 }
 
@@ -192,8 +192,17 @@ int lattice_set_state(lattice_t* h, const double* fields, const double* momenta,
   std::vector<const double*> comps;
   for (int f = 0; f < nf; ++f) comps.push_back(fields + f * V);
   for (int f = 0; f < nf; ++f) comps.push_back(momenta + f * V);
+  std::vector<double> phases;
   if (u1) {
-    for (int c = 0; c < 6; ++c) comps.push_back(links + c * V);
+    // a unit link (Re, Im) is stored by its phase
+    phases.resize((size_t)3 * V);
+    for (int i = 0; i < 3; ++i)
+      for (int64_t k = 0; k < V; ++k) {
+        const double re = links[(2 * i) * V + k], im = links[(2 * i + 1) * V + k];
+        if (!std::isfinite(re) || !std::isfinite(im)) { set_error("non-finite link"); return LAT_ENONFINITE; }
+        phases[(size_t)i * V + k] = std::atan2(im, re);
+      }
+    for (int i = 0; i < 3; ++i) comps.push_back(phases.data() + (size_t)i * V);
     for (int c = 0; c < 3; ++c) comps.push_back(link_momenta + c * V);
   }
   for (size_t c = 0; c < comps.size(); ++c)
@@ -219,12 +228,24 @@ int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* lin
     if (fields) comps[f] = fields + f * V;
     if (momenta) comps[nf + f] = momenta + f * V;
   }
+  std::vector<double> phases;
   if (u1) {
-    for (int c = 0; c < 6; ++c) if (links) comps[4 + c] = links + c * V;
-    for (int c = 0; c < 3; ++c) if (link_momenta) comps[10 + c] = link_momenta + c * V;
+    if (links) {
+      phases.resize((size_t)3 * V);
+      for (int i = 0; i < 3; ++i) comps[4 + i] = phases.data() + (size_t)i * V;
+    }
+    for (int c = 0; c < 3; ++c) if (link_momenta) comps[7 + c] = link_momenta + c * V;
   }
   int rc = download_components(h, comps.data(), (int)comps.size());
   if (rc) return rc;
+  if (u1 && links) {
+    for (int i = 0; i < 3; ++i)
+      for (int64_t k = 0; k < V; ++k) {
+        const double t = phases[(size_t)i * V + k];
+        links[(2 * i) * V + k] = std::cos(t);
+        links[(2 * i + 1) * V + k] = std::sin(t);
+      }
+  }
   if (s) {
     DevState d;
     CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));

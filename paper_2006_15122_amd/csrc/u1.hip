@@ -4,7 +4,11 @@
 // phi and V at n reads only pi and piA at n, so no state buffer is doubled.
 //
 // Components (storage precision, N^3 each): 0,1 = Re, Im phi; 2,3 = Re, Im
-// pi; 4 + 2i + c = (Re, Im) of the link V_i; 10 + i = piA_i.
+// pi; 4 + i = phase th_i of the link V_i = exp(i th_i); 7 + i = piA_i.
+// A compact U(1) link is a point on the unit circle, so its phase is an exact
+// coordinate: plaquettes are V_ij = exp(i Phi_ij) with
+// Phi_ij(n) = th_i(n) + th_j(n+i) - th_i(n+j) - th_j(n), 1 - Re V_ij =
+// 2 sin^2(Phi_ij/2) without cancellation, and |V| = 1 holds exactly in FP32.
 //
 // Kernels (Sec. 5.1, 5.3):
 //   K_phi   = -a^{3+alpha}(2 lambda |phi|^2 + m2) phi
@@ -36,7 +40,7 @@ __device__ __forceinline__ C2<T> cc(C2<T> a) {
 
 template <typename T>
 struct U1Args {
-  T* c[13];
+  T* c[10];
   int N;
   double dx, alpha, fmp2, lam, m2, e, wf2, h;
   int expand;
@@ -71,6 +75,13 @@ __device__ void u1_block_partials(double (&acc)[NACC], double* partials) {
   if (tid < NACC) partials[(size_t)blockIdx.x * NACC + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
+__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
+__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+__device__ __forceinline__ float atan_t(float x) { return atanf(x); }
+__device__ __forceinline__ double atan_t(double x) { return atan(x); }
+
 template <typename T>
 __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
   return C2<T>{re[i], im[i]};
@@ -93,7 +104,12 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
     d[dir2] += step2;
     return at(d[0], d[1], d[2]);
   };
-  auto link = [&](int i, size_t site) -> C2<T> { return ld(A.c[4 + 2 * i], A.c[5 + 2 * i], site); };
+  auto theta = [&](int i, size_t site) -> T { return A.c[4 + i][site]; };
+  auto link = [&](int i, size_t site) -> C2<T> {
+    T sn, cs;
+    sincos_t(theta(i, site), &sn, &cs);
+    return C2<T>{cs, sn};
+  };
   auto phi = [&](size_t site) -> C2<T> { return ld(A.c[0], A.c[1], site); };
 
   const double a_in = A.st->a;
@@ -107,13 +123,15 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
   const C2<T> p = phi(s);
   C2<T> lap{T(-6) * p.x, T(-6) * p.y};
   double grad = 0.0;
-  C2<T> Vs[3];
+  T th[3];
   T Kcur[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    Vs[i] = link(i, s);
+    th[i] = theta(i, s);
+    T sn, cs;
+    sincos_t(th[i], &sn, &cs);
     const size_t sp = off(i, 1, i, 0), sm = off(i, -1, i, 0);
-    const C2<T> f = cm(Vs[i], phi(sp));
+    const C2<T> f = cm(C2<T>{cs, sn}, phi(sp));
     const C2<T> b = cm(cc(link(i, sm)), phi(sm));
     lap.x += f.x + b.x;
     lap.y += f.y + b.y;
@@ -125,6 +143,7 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
   const T dv = T(2) * lam * r2 + m2;
   const C2<T> Kp{cl * lap.x - cp * dv * p.x, cl * lap.y - cp * dv * p.y};
 
+  // plaquette phases: Phi_ij(n) = th_i(n) + th_j(n+i) - th_i(n+j) - th_j(n)
   double mag = 0.0;
   T KA[3];
 #pragma unroll
@@ -133,13 +152,15 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (j == i) continue;
-      // V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n)
-      const C2<T> P0 = cm(cm(Vs[i], link(j, off(i, 1, j, 0))), cm(cc(link(i, off(j, 1, i, 0))), cc(Vs[j])));
-      // V_ij(n-j) = V_i(n-j) V_j(n-j+i) conj V_i(n) conj V_j(n-j)
+      const T ph0 = (th[i] + theta(j, off(i, 1, j, 0))) - (theta(i, off(j, 1, i, 0)) + th[j]);
       const size_t smj = off(j, -1, j, 0);
-      const C2<T> P1 = cm(cm(link(i, smj), link(j, off(j, -1, i, 1))), cm(cc(Vs[i]), cc(link(j, smj))));
-      curl += P0.y - P1.y;
-      if (j > i) mag += (double)(T(1) - P0.x);
+      // Phi_ij(n-j) = th_i(n-j) + th_j(n-j+i) - th_i(n) - th_j(n-j)
+      const T ph1 = (theta(i, smj) + theta(j, off(j, -1, i, 1))) - (th[i] + theta(j, smj));
+      curl += sin_t(ph0) - sin_t(ph1);
+      if (j > i) {
+        const T sh = sin_t(T(0.5) * ph0);
+        mag += (double)(T(2) * sh * sh);
+      }
     }
     KA[i] = Kcur[i] + cb * curl;
   }
@@ -157,7 +178,7 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
   T aout[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T ain = A.c[10 + i][s];
+    const T ain = A.c[7 + i][s];
     aout[i] = ain + ck * KA[i];
     ka0 += (double)(ain * ain);
     ka1 += (double)(aout[i] * aout[i]);
@@ -172,7 +193,7 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
     A.c[2][s] = pout.x;
     A.c[3][s] = pout.y;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) A.c[10 + i][s] = aout[i];
+    for (int i = 0; i < 3; ++i) A.c[7 + i][s] = aout[i];
   }
   u1_block_partials<kU1Acc>(acc, A.partials);
 }
@@ -265,6 +286,7 @@ __global__ __launch_bounds__(1024) void u1_finish_kernel(U1Args<T> A, int nblock
 
 // phi <- phi + h pi / a_mid^{3-alpha};  V_i <- (1 - i u)/(1 + i u) V_i,
 // u = e h dx piA_i / (2 a_mid^{1-alpha})  (Sec. 5.3, drift from momenta).
+// (1 - i u)/(1 + i u) = exp(-2 i atan u), so th_i <- th_i - 2 atan u, kept in (-pi, pi].
 template <typename T>
 __global__ __launch_bounds__(256) void u1_drift_kernel(U1Args<T> A) {
   const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -273,14 +295,13 @@ __global__ __launch_bounds__(256) void u1_drift_kernel(U1Args<T> A) {
   const T cu = (T)(A.e * A.h * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
   A.c[0][s] = A.c[0][s] + cd * A.c[2][s];
   A.c[1][s] = A.c[1][s] + cd * A.c[3][s];
+  const T twopi = (T)6.283185307179586476925286766559;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T u = cu * A.c[10 + i][s];
-    const T d = T(1) / (T(1) + u * u);
-    const C2<T> r{(T(1) - u * u) * d, T(-2) * u * d};
-    const C2<T> v = cm(r, C2<T>{A.c[4 + 2 * i][s], A.c[5 + 2 * i][s]});
-    A.c[4 + 2 * i][s] = v.x;
-    A.c[5 + 2 * i][s] = v.y;
+    const T u = cu * A.c[7 + i][s];
+    T t = A.c[4 + i][s] - T(2) * atan_t(u);
+    t -= twopi * rint(t / twopi);
+    A.c[4 + i][s] = t;
   }
 }
 
@@ -296,7 +317,7 @@ __global__ __launch_bounds__(256) void u1_gauss_kernel(U1Args<T> A) {
                         (size_t)x * NN + (size_t)y * N + (z - 1 + N) % N};
   double div = 0.0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) div += ((double)A.c[10 + i][s] - (double)A.c[10 + i][sm[i]]) / A.dx;
+  for (int i = 0; i < 3; ++i) div += ((double)A.c[7 + i][s] - (double)A.c[7 + i][sm[i]]) / A.dx;
   const double rho = 2.0 * A.e / A.wf2 *
                      ((double)A.c[0][s] * (double)A.c[3][s] - (double)A.c[1][s] * (double)A.c[2][s]);
   double acc[4] = {(div - rho) * (div - rho), div * div, rho * rho, rho};
@@ -324,7 +345,7 @@ __global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* par
 
 template <typename T>
 static void fill_args(lattice* h, U1Args<T>& A) {
-  for (int c = 0; c < 13; ++c) A.c[c] = static_cast<T*>(h->buf[h->cur][c]);
+  for (int c = 0; c < 10; ++c) A.c[c] = static_cast<T*>(h->buf[h->cur][c]);
   A.N = h->p.N;
   A.dx = h->dx;
   A.alpha = h->p.alpha;
@@ -515,11 +536,10 @@ __global__ void u1_store_link_momentum_kernel(const double2* F, T* out, int64_t 
 }
 
 template <typename T>
-__global__ void u1_unit_links_kernel(T* re0, T* im0, T* re1, T* im1, T* re2, T* im2, int64_t V) {
+__global__ void u1_zero_phases_kernel(T* t0, T* t1, T* t2, int64_t V) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V) return;
-  re0[i] = re1[i] = re2[i] = T(1);
-  im0[i] = im1[i] = im2[i] = T(0);
+  t0[i] = t1[i] = t2[i] = T(0);
 }
 
 template <typename T>
@@ -567,8 +587,8 @@ static int u1_init_state_t(lattice* h) {
       CL_HIP(hipGetLastError());
     }
   }
-  T* c[13];
-  for (int k = 0; k < 13; ++k) c[k] = static_cast<T*>(h->buf[h->cur][k]);
+  T* c[10];
+  for (int k = 0; k < 10; ++k) c[k] = static_cast<T*>(h->buf[h->cur][k]);
   const double cq = 2.0 * p.e / (p.omega_over_f * p.omega_over_f);
   hipLaunchKernelGGL(u1_store_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, full[0], full[1], full[2], full[3],
                      c[0], c[1], c[2], c[3], F, V, std::pow(a, 3.0 - al), cq);
@@ -582,12 +602,11 @@ static int u1_init_state_t(lattice* h) {
     CL_HIP(hipGetLastError());
     rc = run_fft3d(h, -1, 1.0);
     if (rc) return rc;
-    hipLaunchKernelGGL(u1_store_link_momentum_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, F, c[10 + i], V,
+    hipLaunchKernelGGL(u1_store_link_momentum_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, F, c[7 + i], V,
                        std::pow(a, 1.0 - al) / (double)V);
     CL_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(u1_unit_links_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, c[4], c[5], c[6], c[7], c[8],
-                     c[9], V);
+  hipLaunchKernelGGL(u1_zero_phases_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, c[4], c[5], c[6], V);
   CL_HIP(hipGetLastError());
   rc = upload_scalars(h, a, 0.0, 0.0);
   if (rc) return rc;
