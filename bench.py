@@ -70,6 +70,49 @@ def time_lattice(cfg: dict, steps: int, warmup: int):
     return ms, wall, obs, tile
 
 
+def time_batch(steps: int) -> dict:
+    """96 two-field VV2 runs (32 each of 32^3, 64^3, 96^3, q log-uniform in
+    [10, 1e4]): one batched kernel per pass replayed from a HIP graph, against
+    the same runs stepped one after another with the single-lattice kernels."""
+    import torch
+
+    from paper_2006_15122_amd import synth
+    from paper_2006_15122_amd.lattice import Batch
+
+    runs = synth.config4_runs()
+    B = Batch(runs)
+    sites = sum(c["N"] ** 3 for c in runs)
+    B.step(steps)                      # captures the graph
+    B.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    B.step(steps)                      # replay
+    e1.record(B.stream)
+    B.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    seq_steps = max(steps // 5, 4)
+    with torch.cuda.stream(B.stream):
+        for r in B.runs:               # warm the single-lattice kernels
+            r.step(1)
+        B.synchronize()
+        e0.record(B.stream)
+        for r in B.runs:
+            r.step(seq_steps)
+        e1.record(B.stream)
+        B.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    tile = B.tiling()
+    B.close()
+    torch.cuda.empty_cache()
+    batched = sites * steps / (ms_b / 1e3)
+    seq = sites * seq_steps / (ms_s / 1e3)
+    return {"runs": len(runs), "sites": sites, "batched_site_updates_per_s": batched,
+            "sequential_site_updates_per_s": seq, "batched_over_sequential": batched / seq,
+            "batched_hbm_frac": sites * 32 * (steps + 1) / steps * steps / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "steps_batched": steps, "steps_sequential": seq_steps, "tile": tile}
+
+
 def cpu_baseline(cfg: dict, nsteps: int) -> dict:
     import oracle
 
@@ -168,6 +211,7 @@ def main():
         extras["u1_192_lf2"] = {"site_updates_per_s": n3 * st3 / (ms3 / 1e3),
                                 "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
                                 "bytes_per_site_update": 80, "steps": st3, "gauss": obs3["gauss"]}
+        extras["batch_96"] = time_batch(max(args.steps // 10, 20))
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

@@ -188,6 +188,50 @@ int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t
    and the storage element size in bytes; for zero-copy consumers. */
 int lattice_field_device_ptr(lattice_t* h, int c, void** ptr, int32_t* elem_bytes);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles: nruns independent scalar lattices advanced together,
+ * one batched kernel per pass over the tiles of every run plus one FP64
+ * finish block per run; a whole lattice_batch_step call is captured in a
+ * HIP graph and launched once.  All runs share model (LAT_MODEL_SCALAR), nf,
+ * integrator (LAT_VV2 or LAT_VV4), precision and dt; N (multiple of 32),
+ * couplings, kIR and seed may differ per run.
+ * ------------------------------------------------------------------------ */
+typedef struct lattice_batch lattice_batch_t;
+
+/* Device bytes for the batch (ps: array of nruns parameter sets).
+   Errors: LAT_EINVAL. */
+int lattice_batch_workspace_size(const lattice_params* ps, int nruns, size_t* bytes);
+
+/* Build every run (its initial state as in lattice_init) inside dev_ws and
+   pick a tile shape common to all runs with the autotuner.  hip_stream must
+   be a created stream (not NULL) for graph capture.  Errors: LAT_EINVAL
+   (mismatched shared parameters), LAT_ENOMEM, LAT_EHIP. */
+int lattice_batch_init(const lattice_params* ps, int nruns, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                       lattice_batch_t** out);
+
+/* Advance every run by nsteps full steps (synchronised at the end).
+   Asynchronous on the stream.  Errors: LAT_EINVAL, LAT_EHIP. */
+int lattice_batch_step(lattice_batch_t* b, int64_t nsteps);
+
+/* Observables of every run into out[0 .. nruns-1].  Synchronises.
+   Errors: LAT_ENONFINITE, LAT_EHIP. */
+int lattice_batch_energies(lattice_batch_t* b, lattice_obs* out);
+
+/* Handle of one run, owned by the batch (valid until lattice_batch_destroy):
+   use it for lattice_set_state / get_state / energies / spectrum, or with
+   lattice_step to advance that run alone with the single-lattice kernels.
+   Errors: LAT_EINVAL. */
+int lattice_batch_run(lattice_batch_t* b, int run, lattice_t** out);
+
+/* Tile shape shared by the batched pass (see lattice_set_tiling), and graph
+   capture on/off (default on).  Errors: LAT_EINVAL. */
+int lattice_batch_get_tiling(lattice_batch_t* b, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc);
+int lattice_batch_set_tiling(lattice_batch_t* b, int32_t tz, int32_t by, int32_t ry, int32_t xc);
+int lattice_batch_use_graph(lattice_batch_t* b, int on);
+
+/* Release the batch and its run handles (not the workspace). */
+int lattice_batch_destroy(lattice_batch_t* b);
+
 #ifdef __cplusplus
 }
 #endif

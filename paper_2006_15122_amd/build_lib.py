@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lattice.hip", "scalar.hip", "fft.hip", "u1.hip"]
+SOURCES = ["lattice.hip", "scalar.hip", "fft.hip", "u1.hip", "batch.hip"]
 OUT = os.path.join(HERE, "libcosmolat.so")
 
 FLAGS = [

@@ -42,6 +42,10 @@ struct lattice {
 namespace cl {
 
 int ncomponents(const lattice_params* p);
+int validate(const lattice_params* p);
+PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update);
+std::vector<PassDesc> pass_schedule(int integrator, const std::vector<double>& w, int* staggered, int64_t n);
+void phys_of(const lattice* h, double* phys);
 std::vector<double> vv_weights(int integrator);
 int upload_components(lattice* h, const double* const* comps, int n);
 int download_components(lattice* h, double* const* comps, int n);

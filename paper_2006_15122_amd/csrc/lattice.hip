@@ -31,7 +31,7 @@ std::vector<double> vv_weights(int integrator) {
   return {1.0};
 }
 
-static int validate(const lattice_params* p) {
+int validate(const lattice_params* p) {
   if (!p) { set_error("params is NULL"); return LAT_EINVAL; }
   if (p->model != LAT_MODEL_SCALAR && p->model != LAT_MODEL_U1) { set_error("unknown model"); return LAT_EINVAL; }
   if (p->model == LAT_MODEL_SCALAR && (p->nf < 1 || p->nf > 2)) { set_error("scalar model needs nf = 1 or 2"); return LAT_EINVAL; }
@@ -93,7 +93,7 @@ extern "C" {
 const char* lattice_last_error(void) { return g_err.c_str(); }
 
 int lattice_workspace_size(const lattice_params* p, size_t* bytes) {
-  const int rc = validate(p);
+  const int rc = cl::validate(p);
   if (rc) return rc;
   if (!bytes) { set_error("bytes is NULL"); return LAT_EINVAL; }
   size_t a, b, c, d, e, t, cb;
@@ -342,7 +342,7 @@ int upload_scalars(lattice* h, double a, double b, double eta) {
 // ---------------------------------------------------------------------------
 // scalar passes
 // ---------------------------------------------------------------------------
-static void phys_of(const lattice* h, double* phys) {
+void phys_of(const lattice* h, double* phys) {
   phys[0] = h->dx;
   phys[1] = h->p.alpha;
   phys[2] = h->p.fstar_over_mp * h->p.fstar_over_mp;
@@ -379,7 +379,7 @@ int scalar_pass(lattice* h, const PassDesc& pd, bool full) {
   return LAT_OK;
 }
 
-static PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update) {
+PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update) {
   PassDesc p;
   p.wd = wd;
   p.wk1 = wk1;
@@ -390,39 +390,39 @@ static PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int
   return p;
 }
 
-int scalar_step(lattice* h, int64_t n) {
-  int rc;
-  if (h->p.integrator == LAT_LF2) {
-    if (!h->staggered) {
+// Passes of one lattice_step(n) call (Sec. 3.4/4.4 with merged kicks; Sec.
+// 4.2.1).  staggered is updated for leapfrog.
+std::vector<PassDesc> pass_schedule(int integrator, const std::vector<double>& w, int* staggered, int64_t n) {
+  std::vector<PassDesc> out;
+  if (integrator == LAT_LF2) {
+    if (!*staggered) {
       // pi_{-1/2} = pi_0 - (h/2) K, b_{-1/2} = b_0 - (h/2) K_a
-      rc = scalar_pass(h, pass(0.0, 0.0, -0.5, MODE_VV, 1, 1));
-      if (rc) return rc;
-      h->staggered = 1;
+      out.push_back(pass(0.0, 0.0, -0.5, MODE_VV, 1, 1));
+      *staggered = 1;
     }
-    if (n == 0) return LAT_OK;
-    rc = scalar_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 1, 1));  // kick at phi_n
-    if (rc) return rc;
-    for (int64_t j = 1; j < n; ++j) {
-      rc = scalar_pass(h, pass(1.0, 0.0, 1.0, MODE_LF, 1, 1));  // drift, then kick
-      if (rc) return rc;
-    }
-    rc = scalar_pass(h, pass(1.0, 0.0, 0.0, MODE_LF, 1, 1));  // closing drift
-    if (rc) return rc;
-    h->step += n;
-    return LAT_OK;
+    if (n == 0) return out;
+    out.push_back(pass(0.0, 0.0, 1.0, MODE_LF, 1, 1));                       // kick at phi_n
+    for (int64_t j = 1; j < n; ++j) out.push_back(pass(1.0, 0.0, 1.0, MODE_LF, 1, 1));  // drift, kick
+    out.push_back(pass(1.0, 0.0, 0.0, MODE_LF, 1, 1));                       // closing drift
+    return out;
   }
-  if (n == 0) return LAT_OK;
-  const std::vector<double>& w = h->weights;
+  if (n == 0) return out;
   const int s = (int)w.size();
-  rc = scalar_pass(h, pass(0.0, 0.0, 0.5 * w[0], MODE_VV, 1, 1));  // opening half kick
-  if (rc) return rc;
-  for (int64_t it = 0; it < n; ++it) {
+  out.push_back(pass(0.0, 0.0, 0.5 * w[0], MODE_VV, 1, 1));  // opening half kick
+  for (int64_t it = 0; it < n; ++it)
     for (int p = 0; p < s; ++p) {
       const bool last = (it == n - 1) && (p == s - 1);
       const double nxt = last ? 0.0 : w[(p + 1) % s];
-      rc = scalar_pass(h, pass(w[p], 0.5 * w[p], 0.5 * nxt, MODE_VV, 1, 1));
-      if (rc) return rc;
+      out.push_back(pass(w[p], 0.5 * w[p], 0.5 * nxt, MODE_VV, 1, 1));
     }
+  return out;
+}
+
+int scalar_step(lattice* h, int64_t n) {
+  const std::vector<PassDesc> sched = pass_schedule(h->p.integrator, h->weights, &h->staggered, n);
+  for (const PassDesc& pd : sched) {
+    const int rc = scalar_pass(h, pd);
+    if (rc) return rc;
   }
   h->step += n;
   return LAT_OK;

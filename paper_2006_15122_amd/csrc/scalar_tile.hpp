@@ -1,0 +1,402 @@
+// Device code of the fused scalar pass, shared by the single-lattice and the
+// batched launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace cl {
+
+
+template <typename T>
+struct ScalarArgs {
+  const T* src[4];   // phi_0, phi_1, pi_0, pi_1 (nf = 1 uses entries 0 and 2)
+  T* dst[4];
+  int N;
+  int XC;            // x-planes per block
+  int swizzle;       // map consecutive blocks of one XCD to neighbouring tiles
+  double dx, alpha, fmp2, m2_0, m2_1, lam, q, h;
+  int expand;
+  PassDesc pd;
+  double* partials;  // [gridDim.x][NACC]
+  DevState* st;
+};
+
+// Accumulators of one pass.  FULL (observation passes): per field
+// <pi_in^2>, <pi_E^2>, <grad^2>, <phi>, <phi^2>, then the three potential
+// terms.  Stepping passes keep only what the scale-factor kernel needs:
+// sum_f <pi_in^2>, sum_f <pi_E^2>, sum_f <grad^2>, <V>.
+template <int NF, bool FULL>
+struct Acc {
+  static constexpr int N = FULL ? 5 * NF + 3 : 4;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, int NF>
+__device__ __forceinline__ T dpot(int f, const T (&p)[NF], T m2_0, T m2_1, T lam, T q) {
+  if (f == 0) {
+    T d = m2_0 * p[0] + lam * p[0] * p[0] * p[0];
+    if constexpr (NF > 1) d += q * p[1] * p[1] * p[0];
+    return d;
+  } else {
+    if constexpr (NF > 1) return m2_1 * p[1] + q * p[0] * p[0] * p[1];
+    return T(0);
+  }
+}
+
+// Reduce the per-thread accumulators of a block into partials[blockIdx.x]
+// (wave shuffles, then the waves in order).  No fence or atomic here: the
+// cross-block combination happens in scalar_finish_kernel, after the kernel
+// boundary has made every block's partials visible to every XCD.
+template <typename T, int NF, bool FULL, int NT>
+__device__ void block_partials(const ScalarArgs<T>& A, double (&acc)[Acc<NF, FULL>::N], int pidx) {
+  constexpr int NACC = Acc<NF, FULL>::N;
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid < NACC) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][tid];
+    A.partials[(size_t)pidx * NACC + tid] = s;
+  }
+}
+
+// One block: combine the partials of all nblocks blocks in block order
+// (thread t takes blocks t, t+256, ...; then shuffles and waves in order),
+// form the volume averages (Sec. 4.3/4.5) and advance b in FP64,
+//   b_out = b_in + (wk1 + wk2) h K_a(a', E),
+//   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].
+// Sum NB consecutive partial records (starting at `first`) in a fixed order
+// with one block of NT threads; thread 0 returns the totals in S.
+template <int NACC, int NT>
+__device__ bool reduce_partials(const double* partials, int first, int nb, double (&S)[NACC]) {
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double tot[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
+  for (int b = tid; b < nb; b += NT) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) tot[k] += partials[(size_t)(first + b) * NACC + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wave_sum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return false;
+  for (int k = 0; k < NACC; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][k];
+    S[k] = s;
+  }
+  return true;
+}
+
+// From the lattice sums S of one pass: the volume averages (Sec. 4.3/4.5) and
+// the FP64 advance of b,
+//   b_out = b_in + (wk1 + wk2) h K_a(a', E),
+//   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].
+template <typename T, int NF, bool FULL>
+__device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<NF, FULL>::N]) {
+  constexpr int NACC = Acc<NF, FULL>::N;
+  const double a_in = A.st->a, b_in = A.st->b;
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double V = (double)A.N * (double)A.N * (double)A.N;
+  const double al = A.alpha;
+  const double a6 = pow(anew, 6.0), a2 = anew * anew, dx2 = A.dx * A.dx;
+  lattice_obs o;
+  o.EK = o.EG = 0.0;
+  o.EK_f[0] = o.EK_f[1] = o.EG_f[0] = o.EG_f[1] = 0.0;
+  o.mean_f[0] = o.mean_f[1] = o.meansq_f[0] = o.meansq_f[1] = 0.0;
+  bool bad = false;
+  if constexpr (FULL) {
+    for (int f = 0; f < NF; ++f) {
+      const double k1 = S[5 * f + 0] / V, k2 = S[5 * f + 1] / V;
+      const double ek = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+      const double eg = S[5 * f + 2] / V / (2.0 * a2 * dx2);
+      o.EK_f[f] = ek;
+      o.EG_f[f] = eg;
+      o.mean_f[f] = S[5 * f + 3] / V;
+      o.meansq_f[f] = S[5 * f + 4] / V;
+      o.EK += ek;
+      o.EG += eg;
+    }
+    o.EV_term[0] = S[5 * NF + 0] / V;
+    o.EV_term[1] = S[5 * NF + 1] / V;
+    o.EV_term[2] = S[5 * NF + 2] / V;
+    o.EV = o.EV_term[0] + o.EV_term[1] + o.EV_term[2];
+  } else {
+    const double k1 = S[0] / V, k2 = S[1] / V;
+    o.EK = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+    o.EG = S[2] / V / (2.0 * a2 * dx2);
+    o.EV = S[3] / V;
+    o.EV_term[0] = o.EV_term[1] = o.EV_term[2] = NAN;
+    for (int f = 0; f < 2; ++f) o.EK_f[f] = o.EG_f[f] = o.mean_f[f] = o.meansq_f[f] = NAN;
+  }
+  for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
+  const double rho = o.EK + o.EG + o.EV;
+  double b_out = b_in, b_sync = b_in, hc = 0.0;
+  if (A.expand) {
+    const double Ka = A.fmp2 / 3.0 * pow(anew, 1.0 + 2.0 * al) *
+                      ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV);
+    b_out = b_in + (A.pd.wk1 + A.pd.wk2) * A.h * Ka;
+    b_sync = (A.pd.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in + A.pd.wk1 * A.h * Ka;
+    const double rhs = A.fmp2 / 3.0 * pow(anew, 2.0 * (al + 1.0)) * rho;
+    hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
+  }
+  const double eta_new = A.st->eta + A.pd.wd * A.h;
+  o.eta = eta_new;
+  o.a = anew;
+  o.b = b_sync;
+  o.H = b_sync / anew;
+  o.EK_A = o.EG_A = 0.0;
+  o.rho = rho;
+  o.p = o.EK - o.EG / 3.0 - o.EV;
+  o.w = rho != 0.0 ? o.p / rho : 0.0;
+  o.hc = hc;
+  o.gauss = NAN;
+  o.step = 0;
+  o.staggered = (A.pd.mode == MODE_LF) ? 1 : 0;
+  o.reserved = 0;
+  A.st->obs = o;
+  if (bad) A.st->nonfinite = 1;
+  if (A.pd.update) {
+    A.st->a = anew;
+    A.st->b = b_out;
+    A.st->eta = eta_new;
+  }
+}
+
+// One block: combine the partials of all nblocks tiles in block order and
+// update the homogeneous state.
+template <typename T, int NF, bool FULL>
+__global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks) {
+  double S[Acc<NF, FULL>::N];
+  if (!reduce_partials<Acc<NF, FULL>::N, 1024>(A.partials, 0, nblocks, S)) return;
+  finish_from_sums<T, NF, FULL>(A, S);
+}
+
+// One tile (index `tile` in the order z-tile fastest, then y-tile, then
+// x-chunk) of one lattice; its sums go to partial record `pidx`.
+template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
+__device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, int pidx) {
+  constexpr int TY = BY * RY;
+  constexpr int NT = TZ * BY;
+  constexpr int LZ = TZ + 2;
+  constexpr int NACC = Acc<NF, FULL>::N;
+  __shared__ T lds[NF][TY + 2][LZ];
+
+  const int N = A.N;
+  const int tid = threadIdx.x;
+  const int tz = tid % TZ, ty = tid / TZ;
+  const int nzt = N / TZ, nyt = N / TY;
+  int bid = tile;
+  const int zt = bid % nzt;
+  bid /= nzt;
+  const int yt = bid % nyt;
+  const int xcI = bid / nyt;
+  const int z0 = zt * TZ, y0 = yt * TY, x0 = xcI * A.XC;
+  const size_t NN = (size_t)N * N;
+
+  // homogeneous coefficients (FP64, identical in every block)
+  const double a_in = A.st->a, b_in = A.st->b;
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double amid = 0.5 * (a_in + anew);
+  const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
+  const T clap = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cpot = (T)pow(anew, 3.0 + A.alpha);
+  const T ckick = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
+  const T cE = (T)((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
+  const T m2_0 = (T)A.m2_0, m2_1 = (T)A.m2_1, lam = (T)A.lam, q = (T)A.q;
+  const T half = T(0.5), quarter = T(0.25);
+  const bool lf = A.pd.mode == MODE_LF;
+
+  double acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+
+  const int z = z0 + tz;
+  // register planes: pm = drifted x-1, pc = drifted x, (pn, qn) = raw x+1,
+  // (pf, qf) = raw x+2 in flight; qc = momentum at x
+  T pm[NF][RY], pc[NF][RY], qc[NF][RY], pn[NF][RY], qn[NF][RY], pf[NF][RY], qf[NF][RY];
+
+  // halo item owned by this thread (at most one: 2 TZ + 2 TY <= NT)
+  constexpr int NH = 2 * TZ + 2 * TY;
+  static_assert(NH <= NT, "halo larger than block");
+  int hy = 0, hz = 0, hly = 0, hlz = 0;
+  const bool has_halo = tid < NH;
+  if (has_halo) {
+    if (tid < TZ) { hly = 0; hlz = 1 + tid; hy = (y0 - 1 + N) % N; hz = z0 + tid; }
+    else if (tid < 2 * TZ) { hly = TY + 1; hlz = 1 + tid - TZ; hy = (y0 + TY) % N; hz = z0 + tid - TZ; }
+    else if (tid < 2 * TZ + TY) { hly = 1 + tid - 2 * TZ; hlz = 0; hy = y0 + tid - 2 * TZ; hz = (z0 - 1 + N) % N; }
+    else { hly = 1 + tid - 2 * TZ - TY; hlz = TZ + 1; hy = y0 + tid - 2 * TZ - TY; hz = (z0 + TZ) % N; }
+  }
+  T hp1[NF], hq1[NF], hp2[NF], hq2[NF];
+
+  auto row_off = [&](int x, int y) -> size_t { return (size_t)x * NN + (size_t)y * N; };
+
+  // raw phi and pi of the own columns of plane x
+  auto load_own = [&](int x, T (&p)[NF][RY], T (&pq)[NF][RY]) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const size_t o = row_off(x, y0 + r * BY + ty) + z;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        p[f][r] = A.src[f][o];
+        pq[f][r] = A.src[2 + f][o];
+      }
+    }
+  };
+  auto load_halo = [&](int x, T (&p)[NF], T (&pq)[NF]) {
+    if (has_halo) {
+      const size_t o = row_off(x, hy) + hz;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        p[f] = A.src[f][o];
+        pq[f] = A.src[2 + f][o];
+      }
+    }
+  };
+  // drifted plane into LDS: own columns from registers, halo drifted here
+  auto store_lds = [&](const T (&p)[NF][RY], const T (&hp)[NF], const T (&hq)[NF]) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) lds[f][1 + r * BY + ty][1 + tz] = p[f][r];
+    if (has_halo) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) lds[f][hly][hlz] = hp[f] + cdrift * hq[f];
+    }
+  };
+
+  // prologue: planes x0-1 (drifted), x0 (drifted, into LDS), x0+1 (raw, in flight)
+  {
+    const int xm = (x0 - 1 + N) % N;
+    load_own(xm, pm, qf);  // qf: momentum of plane x0-1, only needed for its drift
+    load_own(x0, pc, qc);
+    load_halo(x0, hp1, hq1);
+    load_own((x0 + 1) % N, pn, qn);
+    if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        pm[f][r] = pm[f][r] + cdrift * qf[f][r];
+        pc[f][r] = pc[f][r] + cdrift * qc[f][r];
+      }
+    store_lds(pc, hp1, hq1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
+  }
+
+  for (int i = 0; i < A.XC; ++i) {
+    const int x = x0 + i;
+    // issue loads of plane x+2, two planes ahead of the stencil
+    if (i + 1 < A.XC) {
+      load_own((x + 2) % N, pf, qf);
+      if (i + 2 < A.XC) load_halo((x + 2) % N, hp2, hq2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 1 + r * BY + ty;
+      T cur[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cur[f] = pc[f][r];
+      const size_t o = row_off(x, y0 + r * BY + ty) + z;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const T pnext = pn[f][r] + cdrift * qn[f][r];
+        const T yp = lds[f][ly + 1][1 + tz], ym = lds[f][ly - 1][1 + tz];
+        const T zp = lds[f][ly][2 + tz], zm = lds[f][ly][tz];
+        const T lap = (pm[f][r] + pnext) + (yp + ym) + (zp + zm) - T(6) * cur[f];
+        const T K = clap * lap - cpot * dpot<T, NF>(f, cur, m2_0, m2_1, lam, q);
+        const T pin = qc[f][r];
+        const T pout = pin + ckick * K;
+        const T pe = pin + cE * K;
+        if (A.pd.write) {
+          // streaming stores: the new state is read again only by the next
+          // pass, so keep it from evicting the halo rows other tiles still need
+          __builtin_nontemporal_store(cur[f], &A.dst[f][o]);
+          __builtin_nontemporal_store(pout, &A.dst[2 + f][o]);
+        }
+        const T gx = pnext - cur[f], gy = yp - cur[f], gz = zp - cur[f];
+        if constexpr (FULL) {
+          acc[5 * f + 0] += (double)(pin * pin);
+          acc[5 * f + 1] += (double)(pe * pe);
+          acc[5 * f + 2] += (double)(gx * gx + gy * gy + gz * gz);
+          acc[5 * f + 3] += (double)cur[f];
+          acc[5 * f + 4] += (double)(cur[f] * cur[f]);
+        } else {
+          if (lf) acc[0] += (double)(pin * pin);
+          acc[1] += (double)(pe * pe);
+          acc[2] += (double)(gx * gx + gy * gy + gz * gz);
+        }
+      }
+      const T p2 = cur[0] * cur[0];
+      if constexpr (FULL) {
+        if constexpr (NF > 1) {
+          const T c2 = cur[1] * cur[1];
+          acc[5 * NF + 0] += (double)(half * (m2_0 * p2 + m2_1 * c2));
+          acc[5 * NF + 2] += (double)(half * q * p2 * c2);
+        } else {
+          acc[5 * NF + 0] += (double)(half * m2_0 * p2);
+        }
+        acc[5 * NF + 1] += (double)(quarter * lam * p2 * p2);
+      } else {
+        T v = half * m2_0 * p2 + quarter * lam * p2 * p2;
+        if constexpr (NF > 1) {
+          const T c2 = cur[1] * cur[1];
+          v += half * (m2_1 * c2 + q * p2 * c2);
+        }
+        acc[3] += (double)v;
+      }
+    }
+    __syncthreads();
+    // shift: plane x+1 becomes current, x+2 becomes next
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        pm[f][r] = pc[f][r];
+        pc[f][r] = pn[f][r] + cdrift * qn[f][r];
+        qc[f][r] = qn[f][r];
+        pn[f][r] = pf[f][r];
+        qn[f][r] = qf[f][r];
+      }
+    if (i + 1 < A.XC) {
+      store_lds(pc, hp1, hq1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
+    }
+  }
+  block_partials<T, NF, FULL, NT>(A, acc, pidx);
+}
+
+template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
+__global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
+  int bid = blockIdx.x;
+  if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  scalar_tile<T, NF, FULL, TZ, BY, RY>(A, bid, blockIdx.x);
+}
+
+
+}  // namespace cl

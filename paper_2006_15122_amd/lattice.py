@@ -25,7 +25,10 @@ ERRORS = {-1: "LAT_EINVAL", -2: "LAT_ENOMEM", -3: "LAT_EHIP", -4: "LAT_ENONFINIT
 EXPORTS = ["lattice_workspace_size", "lattice_init", "lattice_set_state", "lattice_get_state",
            "lattice_step", "lattice_energies", "lattice_spectrum", "lattice_destroy",
            "lattice_last_error", "lattice_get_tiling", "lattice_set_tiling",
-           "lattice_field_device_ptr"]
+           "lattice_field_device_ptr", "lattice_batch_workspace_size", "lattice_batch_init",
+           "lattice_batch_step", "lattice_batch_energies", "lattice_batch_run",
+           "lattice_batch_get_tiling", "lattice_batch_set_tiling", "lattice_batch_use_graph",
+           "lattice_batch_destroy"]
 
 
 class LatticeError(RuntimeError):
@@ -137,13 +140,20 @@ def obs_dict(o: Obs, nf: int) -> dict:
 class Lattice:
     """One lattice on one GPU.  cfg: a workload dict (see synth.py)."""
 
-    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
-        import torch
-
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, _handle=None, _owner=None):
         self.cfg = dict(cfg)
         self.p = params(cfg)
         self.nf = self.p.nf
         self.N = self.p.N
+        if _handle is not None:
+            # a run owned by a Batch: no workspace of its own
+            self.h = _handle
+            self._owner = _owner
+            self._borrowed = True
+            return
+        import torch
+
+        self._borrowed = False
         nbytes = workspace_size(cfg)
         self.device = torch.device(device)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -213,8 +223,75 @@ class Lattice:
         _check(lib().lattice_set_tiling(self.h, tz, by, ry, xc))
 
     def close(self):
-        if self.h:
+        if self.h and not self._borrowed:
             lib().lattice_destroy(self.h)
+        self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """An ensemble of independent scalar lattices stepped together (one batched
+    kernel per pass, whole step calls replayed from a HIP graph).  cfgs: list of
+    workload dicts sharing nf, integrator, precision and dt."""
+
+    def __init__(self, cfgs, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.cfgs = [dict(c) for c in cfgs]
+        n = len(cfgs)
+        P = (Params * n)(*[params(c) for c in cfgs])
+        self._P = P
+        nb = ctypes.c_size_t()
+        _check(lib().lattice_batch_workspace_size(P, ctypes.c_int(n), ctypes.byref(nb)))
+        self.device = torch.device(device)
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        # graph capture needs a created (non-default) stream; default priority
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        torch.cuda.synchronize(self.device)
+        self.h = ctypes.c_void_p()
+        _check(lib().lattice_batch_init(P, ctypes.c_int(n), ctypes.c_void_p(base + off), ctypes.c_size_t(nb.value),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.h)))
+        self.nruns = n
+        self.runs = []
+        for r in range(n):
+            hr = ctypes.c_void_p()
+            _check(lib().lattice_batch_run(self.h, ctypes.c_int(r), ctypes.byref(hr)))
+            self.runs.append(Lattice(cfgs[r], _handle=hr, _owner=self))
+
+    def step(self, nsteps: int = 1):
+        _check(lib().lattice_batch_step(self.h, ctypes.c_int64(int(nsteps))))
+
+    def energies(self) -> list:
+        out = (Obs * self.nruns)()
+        _check(lib().lattice_batch_energies(self.h, out))
+        return [obs_dict(out[r], self.runs[r].nf) for r in range(self.nruns)]
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def tiling(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().lattice_batch_get_tiling(self.h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def set_tiling(self, tz, by, ry, xc):
+        _check(lib().lattice_batch_set_tiling(self.h, tz, by, ry, xc))
+
+    def use_graph(self, on: bool):
+        _check(lib().lattice_batch_use_graph(self.h, 1 if on else 0))
+
+    def close(self):
+        if self.h:
+            for r in self.runs:
+                r.h = ctypes.c_void_p()
+            lib().lattice_batch_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

@@ -76,3 +76,19 @@ def test_courant_bound_edge():
     lattice.workspace_size(dict(cfg, dt=dx / math.sqrt(3) * 0.999))
     with pytest.raises(lattice.LatticeError):
         lattice.workspace_size(dict(cfg, dt=dx / math.sqrt(3) * 1.001))
+
+
+def test_batch_parameter_checks():
+    import ctypes
+    cfgs = [synth.small(synth.config2(), 32), synth.small(synth.config2(), 64)]
+    P = (lattice.Params * 2)(*[lattice.params(c) for c in cfgs])
+    n = ctypes.c_size_t()
+    assert lattice.lib().lattice_batch_workspace_size(P, 2, ctypes.byref(n)) == 0
+    assert n.value > lattice.workspace_size(cfgs[0]) + lattice.workspace_size(cfgs[1])
+    bad = [cfgs[0], dict(cfgs[1], dt=0.004)]
+    P2 = (lattice.Params * 2)(*[lattice.params(c) for c in bad])
+    assert lattice.lib().lattice_batch_workspace_size(P2, 2, ctypes.byref(n)) == -1
+    assert "share" in lattice.lib().lattice_last_error().decode()
+    lf = [dict(cfgs[0], integrator="lf2")]
+    P3 = (lattice.Params * 1)(*[lattice.params(c) for c in lf])
+    assert lattice.lib().lattice_batch_workspace_size(P3, 1, ctypes.byref(n)) == -1
