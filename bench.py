@@ -27,7 +27,7 @@ BYTES_PER_SITE_VV2_NF2_FP32 = 32  # read phi, chi, pi_phi, pi_chi; write the sam
 
 def _kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("scalar.hip", "common.hpp"):
+    for f in ("scalar.hip", "scalar_tile.hpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2006_15122_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -44,15 +44,20 @@ def _traffic(per_launch_sites: int):
     return d.get("bytes_per_launch")
 
 
-def time_lattice(cfg: dict, steps: int, warmup: int):
+def time_lattice(cfg: dict, steps: int, warmup: int, passes: int = 0):
+    """Time `steps` steps on the lattice's stream (HIP events).  With passes > 0
+    the first `passes` fused-pass kernels of the timed region also carry
+    their own device start/stop timestamps; returns their mean duration."""
     import torch
 
     from paper_2006_15122_amd.lattice import Lattice
 
     lat = Lattice(cfg, device="cuda:0")
-    stream = torch.cuda.current_stream()
+    stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
+    if passes:
+        lat.pass_timer(passes)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -62,12 +67,17 @@ def time_lattice(cfg: dict, steps: int, warmup: int):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    kernel_ms = None
+    if passes:
+        kt, kn = lat.pass_timer_read()
+        kernel_ms = kt / kn if kn else None
+        lat.pass_timer(0)
     obs = lat.energies()
     tile = lat.tiling()
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    return ms, wall, obs, tile
+    return ms, wall, obs, tile, kernel_ms
 
 
 def time_batch(steps: int) -> dict:
@@ -136,7 +146,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy, the reference for HBM counter scaling")
     args = ap.parse_args()
@@ -160,13 +170,13 @@ def main():
 
     cfg = synth.config2(q=100.0, integrator="vv2")
     N = cfg["N"]
-    ms, wall, obs, tile = time_lattice(cfg, args.steps, args.warmup)
-    sites = N ** 3
     # one call of lattice_step(K) issues K fused passes plus one opening half-kick pass
     passes = args.steps + 1
+    ms, wall, obs, tile, kernel_ms = time_lattice(cfg, args.steps, args.warmup, passes)
+    sites = N ** 3
     ms_per_pass = ms / passes
     value = sites * args.steps / (ms / 1e3)
-    achieved = sites * BYTES_PER_SITE_VV2_NF2_FP32 / (ms_per_pass / 1e3) / 1e9
+    achieved = sites * BYTES_PER_SITE_VV2_NF2_FP32 / (kernel_ms / 1e3) / 1e9
     out = {
         "metric": "lattice site-updates/s per GPU (two-field VV2, 256^3, FP32 fields / FP64 sums)",
         "value": value,
@@ -186,7 +196,8 @@ def main():
                    "tile": {"tz": tile[0], "by": tile[1], "ry": tile[2], "xc": tile[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(sites),
-                     "kernel": "scalar_pass_kernel<float,2,...>", "ms_per_launch": ms_per_pass,
+                     "kernel": "scalar_pass_kernel<float, 2, false, %d, %d, %d>" % tile[:3],
+                     "ms_per_launch": kernel_ms, "launches": passes, "step_ms_per_pass": ms_per_pass,
                      "bytes_per_launch": sites * BYTES_PER_SITE_VV2_NF2_FP32},
         "wall_s": wall,
         "final_obs": {k: obs[k] for k in ("a", "b", "EK", "EG", "EV", "hc")},
@@ -195,18 +206,18 @@ def main():
         extras = {}
         for name, c, st in (("vv4_256", synth.config2(q=100.0, integrator="vv4"), max(args.steps // 4, 10)),
                             ("vv2_512", dict(synth.config2(q=100.0, N=512), omega_over_f=1e-2), max(args.steps // 8, 10))):
-            ms2, _, _, t2 = time_lattice(c, st, 10)
-            n3 = c["N"] ** 3
             s_per_site = {"vv2": 1, "vv4": 3}[c["integrator"]]
             npass = st * s_per_site + 1
+            ms2, _, _, t2, k2 = time_lattice(c, st, 10, npass)
+            n3 = c["N"] ** 3
             extras[name] = {"site_updates_per_s": n3 * st / (ms2 / 1e3),
-                            "hbm_frac": n3 * 32 / (ms2 / npass / 1e3) / 1e9 / HBM_PEAK_GBS,
-                            "tile": t2, "steps": st}
+                            "hbm_frac": n3 * 32 / (k2 / 1e3) / 1e9 / HBM_PEAK_GBS,
+                            "kernel_ms": k2, "step_ms_per_pass": ms2 / npass, "tile": t2, "steps": st}
         # compact U(1) Abelian-Higgs, 192^3, FP32, staggered leapfrog; state per site: phi (2),
         # pi (2), link phases (3), link momenta (3) = 10 FP32, read and written once per step
         c3 = synth.config3()
         st3 = max(args.steps // 10, 10)
-        ms3, _, obs3, _ = time_lattice(c3, st3, 5)
+        ms3, _, obs3, _, _ = time_lattice(c3, st3, 5)
         n3 = c3["N"] ** 3
         extras["u1_192_lf2"] = {"site_updates_per_s": n3 * st3 / (ms3 / 1e3),
                                 "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,

@@ -46,7 +46,7 @@ extern "C" {
 #define LAT_MODEL_U1 1      /* complex scalar with compact U(1) links (Sec. 5.3):
                                V = lambda |phi|^4 + m2[0] |phi|^2            */
 
-/* Integrators (Sec. 3.3-3.5, 4.2-4.4) */
+/* Integrators (Sec. 3.3-3.4, 4.2-4.3) */
 #define LAT_LF2 0   /* staggered leapfrog, scheme III (pi = a^{3-alpha} phi')    */
 #define LAT_VV2 1   /* velocity Verlet                                          */
 #define LAT_VV4 2   /* Yoshida composition of VV2, 3 sub-steps                  */
@@ -96,7 +96,7 @@ typedef struct lattice_scalars {
   int32_t reserved;
 } lattice_scalars;
 
-/* Observables (Sec. 4.5, 5.4), all FP64 volume averages in program units. */
+/* Observables (Sec. 4.4, 5.4), all FP64 volume averages in program units. */
 typedef struct lattice_obs {
   double eta, a, b;    /* b at the same time as a (LF2: mean of the two    */
                        /* neighbouring half-step values)                   */
@@ -158,7 +158,7 @@ int lattice_step(lattice_t* h, int64_t nsteps);
 int lattice_energies(lattice_t* h, lattice_obs* out);
 
 /* Radially binned power spectrum of one field component (Sec. 3.1, eq. of
-   the discrete spectrum; Sec. 4.5.2, 5.4.2).  Shell b holds the modes with
+   the discrete spectrum; Sec. 4.4.2, 5.4.2).  Shell b holds the modes with
    floor(|n~|) = b, b = 0 .. floor(sqrt(3) N / 2).  Per shell: k[b] = mean
    k_IR |n~|, sum_sq[b] = sum |f(n~)|^2 with f(n~) = sum_n e^{+2 pi i n~.n/N}
    f(n), counts[b], and delta[b] = (k_IR b)^3/(2 pi^2) (dx/N)^3 sum_sq[b] /
@@ -168,6 +168,18 @@ int lattice_energies(lattice_t* h, lattice_obs* out);
    Errors: LAT_EINVAL (which), LAT_ENOMEM (nbins_cap too small), LAT_EHIP. */
 int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* k, double* delta,
                      double* sum_sq, int64_t* counts, int* nbins);
+
+/* The same spectrum reduced on the device to nk values, for training sets
+   built without host round trips: log10 of the mode-averaged spectrum
+   kbar_b^3/(2 pi^2) (dx/N)^3 sum_sq[b] / counts[b] (Sec. 3.1 with the
+   average over the modes of each shell) at nk wavenumbers
+   k_j = k_IR (b_max)^(j/(nk-1)), b_max = floor(sqrt(3) N / 2), linear in
+   log10 k between the centres (mean k) of the shells b >= 1 that hold modes
+   and positive power, constant beyond the first and last such shell
+   (-inf if there is none).  dev_out: caller-owned device array of nk FP32.
+   Asynchronous on the stream.  Errors: LAT_EINVAL (which, nk outside
+   [2, 4096], NULL), LAT_EHIP. */
+int lattice_spectrum_logk(lattice_t* h, int which, int nk, float* dev_out);
 
 /* Release the handle (not the workspace).  Synchronises the stream. */
 int lattice_destroy(lattice_t* h);
@@ -183,6 +195,17 @@ int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int3
 /* Force a tile shape (for the autotuner and tests).  Errors: LAT_EINVAL if
    the shape is not compiled or does not divide N. */
 int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t xc);
+
+/* Kernel timing of the fused scalar pass.  After lattice_pass_timer(h, n),
+   the next n stepping-pass launches of lattice_step carry the device's own
+   start and stop timestamps of their dispatch (the launch is otherwise the
+   same; no work is added or skipped).  lattice_pass_timer_read synchronises
+   the stream and returns the summed kernel time of the recorded launches
+   and their number, then starts a new count with the same events.
+   n = 0 releases the events.  Scalar models only.
+   Errors: LAT_EINVAL, LAT_EHIP. */
+int lattice_pass_timer(lattice_t* h, int32_t max_launches);
+int lattice_pass_timer_read(lattice_t* h, double* total_ms, int64_t* launches);
 
 /* Device pointer to component c of the current fields (storage precision),
    and the storage element size in bytes; for zero-copy consumers. */

@@ -7,7 +7,7 @@ code with the HIP library and never calls it.
 
 The time-stepping loops live in ``oracle.c`` (plain loops, one pass per line of
 the paper's schemes); this module wraps them and adds, in numpy, the initial
-conditions (Sec. 7.1) and power spectra (Sec. 3.1, Sec. 4.5.2).  numpy's FFT is
+conditions (Sec. 7.1) and power spectra (Sec. 3.1, Sec. 4.4.2).  numpy's FFT is
 used as a library primitive for the discrete Fourier transform.
 
 Parity status per function is stated in the docstrings; every function here is
@@ -126,7 +126,7 @@ def kernel(m: Scalar, a: float, phi: np.ndarray) -> np.ndarray:
 
 
 def vv_steps(m: Scalar, phi, pi, a, b, h, integrator="vv2", nsteps=1, omp=False):
-    """nsteps velocity-Verlet (VV2) or Yoshida (VV4) steps, in place (Sec. 4.4)."""
+    """nsteps velocity-Verlet (VV2) or Yoshida (VV4) steps, in place (Sec. 4.3.2)."""
     w = np.array(VV_WEIGHTS[integrator], dtype=np.float64)
     ca, cb = ctypes.c_double(a), ctypes.c_double(b)
     lib(omp).orc_vv_steps(ctypes.byref(m), _p(phi), _p(pi), ctypes.byref(ca), ctypes.byref(cb),
@@ -352,7 +352,7 @@ def vacuum_ic(cfg: dict) -> dict:
 
 
 # ---------------------------------------------------------------------------
-# Power spectrum (Sec. 3.1 discrete spectrum; Sec. 4.5.2)
+# Power spectrum (Sec. 3.1 discrete spectrum; Sec. 4.4.2)
 # ---------------------------------------------------------------------------
 def spectrum(f: np.ndarray, kIR: float) -> dict:
     """Radially binned spectrum of a real lattice field.
@@ -382,6 +382,47 @@ def spectrum(f: np.ndarray, kIR: float) -> dict:
     delta[1:] = (kIR * bb[1:]) ** 3 * norm * S[1:] / (4.0 * math.pi * bb[1:] ** 2)
     delta_avg = np.where(cnt > 0, kbar ** 3 * norm * S / np.maximum(cnt, 1), 0.0)
     return {"count": cnt, "S": S, "k": kbar, "delta": delta, "delta_avg": delta_avg}
+
+
+def logk_grid(N: int, kIR: float, nk: int = 64) -> np.ndarray:
+    """nk log-spaced wavenumbers from kIR to kIR floor(sqrt(3) N / 2), the
+    lowest and highest shells of the lattice (Sec. 3.1 binning)."""
+    kmax = kIR * math.floor(math.sqrt(3.0) * N / 2.0)
+    return kIR * (kmax / kIR) ** (np.arange(nk, dtype=np.float64) / (nk - 1))
+
+
+def log_interp(kbar: np.ndarray, value: np.ndarray, valid: np.ndarray, kq: np.ndarray) -> np.ndarray:
+    """log10(value) interpolated linearly in log10 k between the valid shell
+    centres kbar, held constant beyond the first and last valid shell."""
+    xs, ys = [], []
+    for b in range(len(kbar)):
+        if valid[b]:
+            xs.append(math.log10(kbar[b]))
+            ys.append(math.log10(value[b]))
+    out = np.empty(len(kq))
+    for j, k in enumerate(kq):
+        x = math.log10(k)
+        if x <= xs[0]:
+            out[j] = ys[0]
+        elif x >= xs[-1]:
+            out[j] = ys[-1]
+        else:
+            i = 0
+            while xs[i + 1] < x:
+                i += 1
+            t = (x - xs[i]) / (xs[i + 1] - xs[i])
+            out[j] = ys[i] + t * (ys[i + 1] - ys[i])
+    return out
+
+
+def spectrum_logk(f: np.ndarray, kIR: float, nk: int = 64) -> np.ndarray:
+    """The surrogate's target: log10 of the mode-averaged spectrum
+    delta_avg (shells b >= 1 with modes and positive power) at the nk
+    wavenumbers of logk_grid."""
+    s = spectrum(f, kIR)
+    b = np.arange(len(s["count"]))
+    valid = (b >= 1) & (s["count"] > 0) & (s["delta_avg"] > 0)
+    return log_interp(s["k"], s["delta_avg"], valid, logk_grid(f.shape[0], kIR, nk))
 
 
 # ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ Biases, pre-activations, the layer-1 product (K = 2) and the gradients of
 W1, b1 stay in full precision.
 
 The network is not a step of the paper's method; it is the learned add-on
-whose targets are the lattice spectra of Sec. 3.1 / 4.5.2.
+whose targets are the lattice spectra of Sec. 3.1 / 4.4.2.
 """
 from __future__ import annotations
 
@@ -47,18 +47,6 @@ def gelu(x):
 def gelu_grad(x):
     """d/dx GELU = Phi(x) + x phi(x)."""
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
-
-
-def init_params(seed: int) -> dict:
-    """Glorot-uniform weights, zero biases (any initial values work for the tests)."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for l in range(4):
-        fi, fo = SIZES[l], SIZES[l + 1]
-        lim = math.sqrt(6.0 / (fi + fo))
-        p[f"W{l + 1}"] = rng.uniform(-lim, lim, (fo, fi))
-        p[f"b{l + 1}"] = np.zeros(fo)
-    return p
 
 
 def forward(p: dict, x: np.ndarray, bf16: bool = False) -> tuple:

@@ -81,7 +81,7 @@ static inline int64_t site(int N, int x, int y, int z) {
   return ((int64_t)x * N + y) * N + z;
 }
 
-/* Program potential and its terms (Sec. 4.5.1: E_V and E_{V_a}). */
+/* Program potential and its terms (Sec. 4.4.1: E_V and E_{V_a}). */
 static double pot_terms(const orc_scalar* m, double phi, double chi, double t[3]) {
   t[0] = 0.5 * m->m2[0] * phi * phi + (m->nf > 1 ? 0.5 * m->m2[1] * chi * chi : 0.0);
   t[1] = 0.25 * m->lambda * phi * phi * phi * phi;
@@ -99,7 +99,7 @@ static double dpot(const orc_scalar* m, int f, double phi, double chi) {
   return m->m2[1] * chi + m->q * phi * phi * chi;
 }
 
-/* Field kernel of the scalar Verlet schemes (Sec. 4.3, Hamiltonian form):
+/* Field kernel of the scalar Verlet schemes (Sec. 4.2.3, Hamiltonian form):
    K_f = a^{1+alpha} sum_k Delta^-_k Delta^+_k phi_f - a^{3+alpha} V_{,phi_f}. */
 void orc_scalar_kernel(const orc_scalar* m, double a, const double* phi, double* K) {
   const int N = m->N;
@@ -123,7 +123,7 @@ void orc_scalar_kernel(const orc_scalar* m, double a, const double* phi, double*
   }
 }
 
-/* Raw volume averages needed by the energies (Sec. 4.5), per field f:
+/* Raw volume averages needed by the energies (Sec. 4.4), per field f:
    out[4f+0] = <pi_f^2>, out[4f+1] = <sum_k (phi_f(n+k) - phi_f(n))^2> (no 1/dx^2),
    out[4f+2] = <phi_f>,  out[4f+3] = <phi_f^2>;
    then out[4nf+0..2] = <V_mass>, <V_quartic>, <V_int>.
@@ -164,7 +164,7 @@ void orc_scalar_sums(const orc_scalar* m, const double* phi, const double* pi, d
   free(part);
 }
 
-/* Energies in program units (Sec. 4.3, E_K = sum <pi^2>/(2a^6),
+/* Energies in program units (Sec. 4.4.1, E_K = sum <pi^2>/(2a^6),
    E_G = sum <(grad phi)^2>/(2a^2), E_V = <V>).
    e[0]=E_K, e[1]=E_G, e[2]=E_V, e[3..5]=V terms, then per field f:
    e[6+4f]=E_K^f, e[7+4f]=E_G^f, e[8+4f]=<phi_f>, e[9+4f]=<phi_f^2>. */
@@ -188,14 +188,14 @@ void orc_scalar_energies(const orc_scalar* m, double a, const double* sums, doub
   e[2] = e[3] + e[4] + e[5];
 }
 
-/* Scale-factor kernel (Sec. 4.3): b' = K_a = (1/3)(f_star/m_p)^2 a^{1+2alpha}
+/* Scale-factor kernel (Sec. 4.3.2): b' = K_a = (1/3)(f_star/m_p)^2 a^{1+2alpha}
    [ (alpha-2) E_K + alpha E_G + (alpha+1) E_V ]. */
 double orc_Ka(const orc_scalar* m, double a, double EK, double EG, double EV) {
   const double al = m->alpha;
   return m->fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) * ((al - 2.0) * EK + al * EG + (al + 1.0) * EV);
 }
 
-/* Hubble constraint right-hand side (Sec. 4.3):
+/* Hubble constraint right-hand side (Sec. 4.3.2):
    (1/3)(f_star/m_p)^2 a^{2(alpha+1)} (E_K + E_G + E_V). */
 double orc_hc_rhs(const orc_scalar* m, double a, double rho) {
   return m->fmp2 / 3.0 * pow(a, 2.0 * (m->alpha + 1.0)) * rho;
@@ -207,7 +207,7 @@ static void energies_of(const orc_scalar* m, double a, const double* phi, const 
   orc_scalar_energies(m, a, s, e);
 }
 
-/* One velocity-Verlet sub-step of weight w (Sec. 4.4, VVn with expansion),
+/* One velocity-Verlet sub-step of weight w (Sec. 4.3.2, VVn with expansion),
    in the paper's order:
      b_{1/2}  = b + (w h/2) K_a[a, E(phi, pi)]
      pi_{1/2} = pi + (w h/2) K[a, phi]
@@ -356,9 +356,9 @@ void orc_lf_observe(const orc_scalar* m, const double* phi, const double* pi, do
   free(K);
 }
 
-/* Observables of a synchronised state (Sec. 4.5), output as
+/* Observables of a synchronised state (Sec. 4.4), output as
    orc_scalar_energies followed by the Hubble-constraint residual
-   |b^2 - rhs| / b^2 (Sec. 4.4, HC of the VVn scheme). */
+   |b^2 - rhs| / b^2 (Sec. 4.3.2, HC of the VVn scheme). */
 void orc_sync_observe(const orc_scalar* m, const double* phi, const double* pi, double a, double b,
                       double* e) {
   energies_of(m, a, phi, pi, e);

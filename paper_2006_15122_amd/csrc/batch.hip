@@ -3,7 +3,7 @@
 // Every pass of every run goes through one batched kernel whose blocks are
 // the tiles of all runs (tile table built on the host), followed by one
 // finish block per run that reduces that run's FP64 partials in a fixed order
-// and advances its a, b (Sec. 4.3).  Kernel boundaries make each pass's
+// and advances its a, b (Sec. 4.3.2).  Kernel boundaries make each pass's
 // results visible across XCDs with one L2 write-back per XCD, so no block
 // ever waits on another.  A whole lattice_batch_step call is captured into a
 // HIP graph and launched once; the graph is cached per (nsteps, buffer

@@ -35,7 +35,7 @@ struct DevState {
   int nonfinite;          // set when a volume average is NaN/Inf
 };
 
-// Parameters of one fused pass (Sec. 3.4/4.4 velocity Verlet with merged
+// Parameters of one fused pass (Sec. 3.3.2/4.3.2 velocity Verlet with merged
 // kicks; Sec. 4.2.1 staggered leapfrog):
 //   a'   = a + wd h b
 //   phi  = phi + wd h pi a_mid^{-(3-alpha)},       a_mid = (a + a')/2

@@ -392,13 +392,19 @@ int init_state(lattice* h) {
 
 using namespace cl;
 
-extern "C" int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* k, double* delta, double* sum_sq,
-                                int64_t* counts, int* nbins) {
-  if (!h || !k || !delta || !sum_sq || !counts || !nbins) { set_error("NULL argument"); return LAT_EINVAL; }
+namespace {
+
+// FFT of one component and its shell histogram, left on the device:
+// S (sum |f|^2), K (mean k), D (delta with 4 pi b^2), C (counts), nb shells.
+struct Bins {
+  double *S, *K, *D;
+  unsigned long long* C;
+  int nb;
+};
+
+int spectrum_bins(lattice_t* h, int which, Bins* out) {
   const int N = h->p.N;
   const int nb = (int)std::floor(std::sqrt(3.0) * N / 2.0) + 1;
-  *nbins = nb;
-  if (nbins_cap < nb) { set_error("nbins_cap too small: need " + std::to_string(nb)); return LAT_ENOMEM; }
   int comp = -1;
   if (h->p.model == LAT_MODEL_SCALAR) {
     if (which >= 0 && which < h->p.nf) comp = which;
@@ -438,12 +444,73 @@ extern "C" int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* 
   hipLaunchKernelGGL(bin_sum_kernel, dim3((nb + 127) / 128), dim3(128), 0, h->stream, pS, pK, pC, nblk, nb,
                      h->p.kIR, norm, S, K, D, C);
   CL_HIP(hipGetLastError());
+  *out = Bins{S, K, D, C, nb};
+  return LAT_OK;
+}
+
+// log10 of the mode-averaged spectrum kbar^3 norm S_b / C_b at nk log-spaced
+// k from kIR to kIR (nb - 1), linear in log k between the centres of shells
+// b >= 1 with modes and positive power, constant beyond the end shells.
+// One thread per output wavenumber; the shells are scanned in order.
+__global__ void logk_kernel(const double* S, const double* K, const unsigned long long* C, int nb, double norm,
+                            double kIR, int nk, float* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nk) return;
+  const double kmax = kIR * (double)(nb - 1);
+  const double x = log10(kIR) + (log10(kmax) - log10(kIR)) * (double)j / (double)(nk - 1);
+  double x0 = 0.0, y0 = 0.0, last = 0.0;
+  bool have = false, done = false;
+  double res = 0.0;
+  for (int b = 1; b < nb && !done; ++b) {
+    if (C[b] == 0ull || !(S[b] > 0.0)) continue;
+    const double kb = K[b];
+    const double xb = log10(kb);
+    const double yb = log10(kb * kb * kb * norm * S[b] / (double)C[b]);
+    if (!have) {
+      if (x <= xb) { res = yb; done = true; }
+    } else if (x <= xb) {
+      res = y0 + (x - x0) / (xb - x0) * (yb - y0);
+      done = true;
+    }
+    have = true;
+    x0 = xb;
+    y0 = yb;
+    last = yb;
+  }
+  if (!done) res = have ? last : -INFINITY;
+  out[j] = (float)res;
+}
+
+}  // namespace
+
+extern "C" int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* k, double* delta, double* sum_sq,
+                                int64_t* counts, int* nbins) {
+  if (!h || !k || !delta || !sum_sq || !counts || !nbins) { set_error("NULL argument"); return LAT_EINVAL; }
+  const int nb = (int)std::floor(std::sqrt(3.0) * h->p.N / 2.0) + 1;
+  *nbins = nb;
+  if (nbins_cap < nb) { set_error("nbins_cap too small: need " + std::to_string(nb)); return LAT_ENOMEM; }
+  Bins B;
+  int rc = spectrum_bins(h, which, &B);
+  if (rc) return rc;
   std::vector<unsigned long long> hC(nb);
-  CL_HIP(hipMemcpyAsync(sum_sq, S, nb * 8, hipMemcpyDeviceToHost, h->stream));
-  CL_HIP(hipMemcpyAsync(k, K, nb * 8, hipMemcpyDeviceToHost, h->stream));
-  CL_HIP(hipMemcpyAsync(delta, D, nb * 8, hipMemcpyDeviceToHost, h->stream));
-  CL_HIP(hipMemcpyAsync(hC.data(), C, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipMemcpyAsync(sum_sq, B.S, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipMemcpyAsync(k, B.K, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipMemcpyAsync(delta, B.D, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipMemcpyAsync(hC.data(), B.C, nb * 8, hipMemcpyDeviceToHost, h->stream));
   CL_HIP(hipStreamSynchronize(h->stream));
   for (int b = 0; b < nb; ++b) counts[b] = (int64_t)hC[b];
+  return LAT_OK;
+}
+
+extern "C" int lattice_spectrum_logk(lattice_t* h, int which, int nk, float* dev_out) {
+  if (!h || !dev_out) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (nk < 2 || nk > 4096) { set_error("nk must be in [2, 4096]"); return LAT_EINVAL; }
+  Bins B;
+  int rc = spectrum_bins(h, which, &B);
+  if (rc) return rc;
+  const double norm = std::pow(h->dx / h->p.N, 3.0) / (2.0 * M_PI * M_PI);
+  hipLaunchKernelGGL(logk_kernel, dim3((nk + 63) / 64), dim3(64), 0, h->stream, B.S, B.K, B.C, B.nb, norm,
+                     h->p.kIR, nk, dev_out);
+  CL_HIP(hipGetLastError());
   return LAT_OK;
 }

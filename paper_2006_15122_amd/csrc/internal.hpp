@@ -37,6 +37,8 @@ struct lattice {
   int staggered;
   int64_t step;
   cl::Tiling tile;
+  std::vector<hipEvent_t> timer;  // start/stop pairs of timed pass launches
+  size_t timer_used = 0;          // pairs recorded since the last read
 };
 
 namespace cl {
@@ -67,6 +69,7 @@ int num_shapes(int fp32, int nf);
 void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,
                               int ry, int xc, int swizzle, const double* phys, int expand, const PassDesc& pd,
-                              double* partials, DevState* st, hipStream_t s, int* nblocks_out, int full);
+                              double* partials, DevState* st, hipStream_t s, int* nblocks_out, int full,
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace cl

@@ -19,7 +19,7 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Yoshida weights of VVn (Sec. 3.5.1, appendix table).  VV4 is the symmetric
+// Yoshida weights of VVn (Sec. 3.4.1, appendix table).  VV4 is the symmetric
 // triple jump w1 = w3 = 1/(2 - 2^{1/3}), w2 = -2^{1/3}/(2 - 2^{1/3}), which
 // sums to one.
 std::vector<double> vv_weights(int integrator) {
@@ -149,10 +149,52 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   return LAT_OK;
 }
 
+static void drop_timer(lattice_t* h) {
+  for (hipEvent_t e : h->timer) hipEventDestroy(e);
+  h->timer.clear();
+  h->timer_used = 0;
+}
+
 int lattice_destroy(lattice_t* h) {
   if (!h) return LAT_OK;
   hipStreamSynchronize(h->stream);
+  drop_timer(h);
   delete h;
+  return LAT_OK;
+}
+
+int lattice_pass_timer(lattice_t* h, int32_t max_launches) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  if (max_launches < 0 || max_launches > (1 << 20)) { set_error("max_launches must be in [0, 2^20]"); return LAT_EINVAL; }
+  if (h->p.model != LAT_MODEL_SCALAR) { set_error("pass timing covers the scalar models"); return LAT_EINVAL; }
+  CL_HIP(hipStreamSynchronize(h->stream));
+  drop_timer(h);
+  h->timer.reserve(2 * (size_t)max_launches);
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      drop_timer(h);
+      set_error(std::string("hipEventCreate: ") + hipGetErrorString(r));
+      return LAT_EHIP;
+    }
+    h->timer.push_back(e);
+  }
+  return LAT_OK;
+}
+
+int lattice_pass_timer_read(lattice_t* h, double* total_ms, int64_t* launches) {
+  if (!h || !total_ms || !launches) { set_error("NULL argument"); return LAT_EINVAL; }
+  CL_HIP(hipStreamSynchronize(h->stream));
+  double t = 0.0;
+  for (size_t i = 0; i < h->timer_used; ++i) {
+    float ms = 0.0f;
+    CL_HIP(hipEventElapsedTime(&ms, h->timer[2 * i], h->timer[2 * i + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)h->timer_used;
+  h->timer_used = 0;
   return LAT_OK;
 }
 
@@ -368,9 +410,15 @@ int scalar_pass(lattice* h, const PassDesc& pd, bool full) {
     dst[2 + f] = h->buf[1 - h->cur][nf + f];
   }
   int nb = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (!full && 2 * h->timer_used + 1 < h->timer.size()) {
+    ev0 = h->timer[2 * h->timer_used];
+    ev1 = h->timer[2 * h->timer_used + 1];
+    ++h->timer_used;
+  }
   hipError_t e = launch_scalar_pass(h->p.precision == LAT_FP32, nf, src, dst, h->p.N, h->tile.tz, h->tile.by,
                                     h->tile.ry, h->tile.xc, 1, phys, h->p.expansion, pd, h->partials, h->st,
-                                    h->stream, &nb, full ? 1 : 0);
+                                    h->stream, &nb, full ? 1 : 0, ev0, ev1);
   if (e != hipSuccess) {
     set_error(std::string("scalar pass launch: ") + hipGetErrorString(e));
     return LAT_EHIP;
@@ -390,7 +438,7 @@ PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update
   return p;
 }
 
-// Passes of one lattice_step(n) call (Sec. 3.4/4.4 with merged kicks; Sec.
+// Passes of one lattice_step(n) call (Sec. 3.3.2/4.3.2 with merged kicks; Sec.
 // 4.2.1).  staggered is updated for leapfrog.
 std::vector<PassDesc> pass_schedule(int integrator, const std::vector<double>& w, int* staggered, int64_t n) {
   std::vector<PassDesc> out;

@@ -1,0 +1,842 @@
+// Spectrum surrogate: 2 -> 256 -> 256 -> 256 -> 64 perceptron with GELU,
+// trained and evaluated on the matrix cores.
+//
+// Every product is C[M][N] = A[M][K] Bt[N][K]^T with BF16 operands stored
+// K-contiguous and FP32 accumulation (v_mfma_f32_16x16x32_bf16).  The
+// training step keeps row-major and transposed BF16 copies of activations,
+// gradients and weights so that all products have this one form:
+//   forward          a_l   = h_{l-1} W_l^T            (A = h_{l-1},  Bt = W_l)
+//   weight gradient  gW_l  = da_l^T h_{l-1}           (A = da_l^T,   Bt = h_{l-1}^T)
+//   input gradient   dh    = da_l W_l                 (A = da_l,     Bt = W_l^T)
+// Weight-gradient products are split over the batch (KSPLIT rows per split)
+// and all cross-block sums (splits, bias columns, loss) are reduced in a
+// fixed order by the finishing kernel, so a training step is deterministic.
+//
+// Operand layout of one 16x16x32 product on a 64-lane wave (verified on the
+// device): lane l holds A[l%16][8(l/16) .. 8(l/16)+7] and
+// Bt[l%16][8(l/16) .. 8(l/16)+7] (8 BF16 each) and receives
+// C[4(l/16) + e][l%16], e = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "../../include/surrogate.h"
+
+using namespace cl;
+
+struct surrogate_t;
+
+namespace {
+
+constexpr int NIN = SURR_N_IN, WID = SURR_WIDTH, NOUT = SURR_N_OUT, NPAR = SURR_NPARAMS;
+// offsets of the tensors in the flat parameter vector
+constexpr int OW1 = 0, OB1 = OW1 + WID * NIN, OW2 = OB1 + WID, OB2 = OW2 + WID * WID, OW3 = OB2 + WID,
+              OB3 = OW3 + WID * WID, OW4 = OB3 + WID, OB4 = OW4 + NOUT * WID;
+static_assert(OB4 + NOUT == NPAR, "parameter count");
+
+constexpr int KSPLIT = 256;      // batch rows per split of a weight-gradient product
+constexpr int MAX_BATCH = 16384;
+constexpr int MAX_STEPS = 65536;
+constexpr int LDH = WID + 8;     // LDS row pitch of the fused forward (BF16), 16 B skew per row
+
+typedef uint16_t bf16_t;
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+// FP32 -> BF16, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ bf16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float a) {
+  return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * expf(-0.5f * a * a);
+}
+
+__device__ __forceinline__ bf16x8 load8(const bf16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ f4 mma(bf16x8 a, bf16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// normalisation constants on the device
+struct Norm {
+  float in_shift[NIN], in_scale[NIN], out_shift[NOUT], out_scale[NOUT];
+};
+
+// ---------------------------------------------------------------------------
+// layer 1 (K = 2, plain FMA): one block per 64 batch rows, one thread per unit
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void l1_forward(const float* __restrict__ X, const int32_t* __restrict__ rows,
+                                                  int n, const Norm* __restrict__ nm, const bf16_t* __restrict__ W1b,
+                                                  const float* __restrict__ b1, float* __restrict__ xn,
+                                                  float* __restrict__ A1, bf16_t* __restrict__ H1,
+                                                  bf16_t* __restrict__ H1t, int ldt) {
+  __shared__ float xs[64][2];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * 64;
+  if (t < 64) {
+    const int i = r0 + t;
+    float x0 = 0.0f, x1 = 0.0f;
+    if (i < n) {
+      const int64_t src = rows ? (int64_t)rows[i] : (int64_t)i;
+      x0 = (X[2 * src] - nm->in_shift[0]) * nm->in_scale[0];
+      x1 = (X[2 * src + 1] - nm->in_shift[1]) * nm->in_scale[1];
+    }
+    xs[t][0] = x0;
+    xs[t][1] = x1;
+    xn[2 * i] = x0;
+    xn[2 * i + 1] = x1;
+  }
+  __syncthreads();
+  const int j = t;
+  const float w0 = from_bf16(W1b[2 * j]), w1 = from_bf16(W1b[2 * j + 1]), bj = b1[j];
+  bf16_t col[64];
+  for (int r = 0; r < 64; ++r) {
+    const float a = xs[r][0] * w0 + xs[r][1] * w1 + bj;
+    const bf16_t h = to_bf16(gelu(a));
+    A1[(size_t)(r0 + r) * WID + j] = a;
+    H1[(size_t)(r0 + r) * WID + j] = h;
+    col[r] = h;
+  }
+  uint4* dst = reinterpret_cast<uint4*>(H1t + (size_t)j * ldt + r0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint4 v;
+    v.x = col[8 * q] | ((uint32_t)col[8 * q + 1] << 16);
+    v.y = col[8 * q + 2] | ((uint32_t)col[8 * q + 3] << 16);
+    v.z = col[8 * q + 4] | ((uint32_t)col[8 * q + 5] << 16);
+    v.w = col[8 * q + 6] | ((uint32_t)col[8 * q + 7] << 16);
+    dst[q] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C = A Bt^T on a 64x64 block tile, 4 waves of 32x32, with a fused epilogue
+// ---------------------------------------------------------------------------
+enum Epi { EPI_FWD_HID = 0, EPI_FWD_LOSS = 1, EPI_WGRAD = 2, EPI_BWD_HID = 3, EPI_BWD_FIRST = 4 };
+
+struct GemmArgs {
+  const bf16_t* A;
+  const bf16_t* Bt;
+  int lda, ldb;
+  int M, N, K, ksplit;
+  const float* bias;     // forward: bias of the layer
+  float* outA;           // EPI_FWD_HID: pre-activations [M][N]
+  bf16_t* outH;          // BF16 result [M][N]
+  bf16_t* outHt;         // and its transpose [N][ldt]
+  int ldt;
+  const float* prevA;    // backward: pre-activations of the layer below [M][N]
+  float* bpart;          // column sums of the FP32 result per 64-row block [M/64][N]
+  float* wpart;          // EPI_WGRAD: [split][M][N]
+  const float* xn;       // EPI_BWD_FIRST: normalised inputs [M][2]
+  float* w1part;         // EPI_BWD_FIRST: [M/64][N][2]
+  const float* T;        // EPI_FWD_LOSS: raw targets, rows selected by `rows`
+  const int32_t* rows;
+  const Norm* nm;
+  double* lpart;         // EPI_FWD_LOSS: sum of squared residuals per 64-row block
+  int nvalid;            // rows >= nvalid are padding (zero gradient)
+  float dscale;          // 2 / (nvalid * 64)
+};
+
+// sum over the 64 rows of the block tile of one value per (lane, ct);
+// the two row-waves meet in LDS; result for local column c in red[c]
+__device__ __forceinline__ void column_sums(float (&cs)[2], float* red, int lane, int wr, int wc) {
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    cs[ct] += __shfl_xor(cs[ct], 16);
+    cs[ct] += __shfl_xor(cs[ct], 32);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) red[wr * 64 + wc * 32 + ct * 16 + lane] = cs[ct];
+  }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt(GemmArgs g) {
+  __shared__ float red[3][2 * 64];
+  __shared__ double lred[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const int row0 = blockIdx.y * 64 + wr * 32, col0 = blockIdx.x * 64 + wc * 32;
+  const int kb = blockIdx.z * g.ksplit;
+  const int ke = min(g.K, kb + g.ksplit);
+  f4 acc[2][2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bf16_t* pa0 = g.A + (size_t)(row0 + r16) * g.lda + kq;
+  const bf16_t* pa1 = pa0 + (size_t)16 * g.lda;
+  const bf16_t* pb0 = g.Bt + (size_t)(col0 + r16) * g.ldb + kq;
+  const bf16_t* pb1 = pb0 + (size_t)16 * g.ldb;
+  // the k range of a block is a multiple of 64: two 32-deep products per trip
+  const int nk = (ke - kb) >> 6;
+  for (int s = 0; s < nk; ++s) {
+    const int k = kb + 64 * s;
+    const bf16x8 a0 = load8(pa0 + k), a1 = load8(pa1 + k);
+    const bf16x8 b0 = load8(pb0 + k), b1 = load8(pb1 + k);
+    const bf16x8 c0 = load8(pa0 + k + 32), c1 = load8(pa1 + k + 32);
+    const bf16x8 d0 = load8(pb0 + k + 32), d1 = load8(pb1 + k + 32);
+    acc[0][0] = mma(a0, b0, acc[0][0]);
+    acc[0][1] = mma(a0, b1, acc[0][1]);
+    acc[1][0] = mma(a1, b0, acc[1][0]);
+    acc[1][1] = mma(a1, b1, acc[1][1]);
+    acc[0][0] = mma(c0, d0, acc[0][0]);
+    acc[0][1] = mma(c0, d1, acc[0][1]);
+    acc[1][0] = mma(c1, d0, acc[1][0]);
+    acc[1][1] = mma(c1, d1, acc[1][1]);
+  }
+
+  const int N = g.N;
+  if constexpr (EPI == EPI_WGRAD) {
+    float* out = g.wpart + (size_t)blockIdx.z * g.M * N;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + rt * 16 + (lane >> 4) * 4 + e, j = col0 + ct * 16 + r16;
+          out[(size_t)i * N + j] = acc[rt][ct][e];
+        }
+    return;
+  } else {
+    float cs[3][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+    double lsum = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const int j = col0 + ct * 16 + r16;
+        const int i0 = row0 + rt * 16 + (lane >> 4) * 4;
+        bf16_t hb[4];
+        float bj = 0.0f, sh = 0.0f, sc = 0.0f;
+        if constexpr (EPI == EPI_FWD_HID || EPI == EPI_FWD_LOSS) bj = g.bias[j];
+        if constexpr (EPI == EPI_FWD_LOSS) {
+          sh = g.nm->out_shift[j];
+          sc = g.nm->out_scale[j];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = i0 + e;
+          const size_t ij = (size_t)i * N + j;
+          if constexpr (EPI == EPI_FWD_HID) {
+            const float a = acc[rt][ct][e] + bj;
+            g.outA[ij] = a;
+            hb[e] = to_bf16(gelu(a));
+            g.outH[ij] = hb[e];
+          } else if constexpr (EPI == EPI_FWD_LOSS) {
+            const float y = acc[rt][ct][e] + bj;
+            float dy = 0.0f;
+            if (i < g.nvalid) {
+              const int64_t src = g.rows ? (int64_t)g.rows[i] : (int64_t)i;
+              const float tn = (g.T[src * NOUT + j] - sh) * sc;
+              const float r = y - tn;
+              lsum += (double)r * (double)r;
+              dy = r * g.dscale;
+            }
+            hb[e] = to_bf16(dy);
+            g.outH[ij] = hb[e];
+            cs[0][ct] += dy;
+          } else {  // backward through GELU of the layer below
+            const float da = acc[rt][ct][e] * gelu_grad(g.prevA[ij]);
+            cs[0][ct] += da;
+            if constexpr (EPI == EPI_BWD_HID) {
+              hb[e] = to_bf16(da);
+              g.outH[ij] = hb[e];
+            } else {
+              cs[1][ct] += da * g.xn[2 * i];
+              cs[2][ct] += da * g.xn[2 * i + 1];
+            }
+          }
+        }
+        if constexpr (EPI != EPI_BWD_FIRST) {
+          uint2 v;
+          v.x = hb[0] | ((uint32_t)hb[1] << 16);
+          v.y = hb[2] | ((uint32_t)hb[3] << 16);
+          *reinterpret_cast<uint2*>(g.outHt + (size_t)j * g.ldt + i0) = v;
+        }
+      }
+    }
+    if constexpr (EPI == EPI_FWD_HID) return;
+    constexpr int NS = (EPI == EPI_BWD_FIRST) ? 3 : 1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) column_sums(cs[s], red[s], lane, wr, wc);
+    if constexpr (EPI == EPI_FWD_LOSS) {
+      for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o);
+      if (lane == 0) lred[w] = lsum;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < 64) {
+      const int j = blockIdx.x * 64 + t;
+      const size_t rb = blockIdx.y;
+      g.bpart[rb * N + j] = red[0][t] + red[0][64 + t];
+      if constexpr (EPI == EPI_BWD_FIRST) {
+        g.w1part[(rb * N + j) * 2] = red[1][t] + red[1][64 + t];
+        g.w1part[(rb * N + j) * 2 + 1] = red[2][t] + red[2][64 + t];
+      }
+    }
+    if constexpr (EPI == EPI_FWD_LOSS) {
+      if (t == 0) g.lpart[blockIdx.y] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradient assembly (fixed-order sums of the partials) and Adam
+// ---------------------------------------------------------------------------
+struct WCopies {
+  bf16_t *W1b, *W2b, *W2t, *W3b, *W3t, *W4b, *W4t;
+};
+
+__device__ __forceinline__ void store_copies(int p, float v, const WCopies& c) {
+  const bf16_t b = to_bf16(v);
+  if (p < OB1) {
+    c.W1b[p] = b;
+  } else if (p >= OW2 && p < OB2) {
+    const int e = p - OW2, o = e / WID, i = e % WID;
+    c.W2b[e] = b;
+    c.W2t[i * WID + o] = b;
+  } else if (p >= OW3 && p < OB3) {
+    const int e = p - OW3, o = e / WID, i = e % WID;
+    c.W3b[e] = b;
+    c.W3t[i * WID + o] = b;
+  } else if (p >= OW4 && p < OB4) {
+    const int e = p - OW4, o = e / WID, i = e % WID;
+    c.W4b[e] = b;
+    c.W4t[i * NOUT + o] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void copies_kernel(const float* __restrict__ P, WCopies c) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < NPAR) store_copies(p, P[p], c);
+}
+
+struct FinishArgs {
+  const float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
+  const double* lpart;
+  int S, R;            // splits of the weight products, 64-row blocks
+  double inv_count;    // 1 / (nvalid * 64)
+  double* loss;        // one FP64
+  float* G;            // gradient out [NPAR]
+  // Adam
+  float *P, *Mo, *Ve;
+  float lr, beta1, beta2, eps, bc1, bc2;
+  WCopies c;
+};
+
+template <bool UPDATE>
+__global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p == 0) {
+    double s = 0.0;
+    for (int r = 0; r < f.R; ++r) s += f.lpart[r];
+    f.loss[0] = s * f.inv_count;
+  }
+  if (p >= NPAR) return;
+  float g = 0.0f;
+  if (p < OB1) {
+    const int j = p >> 1, c = p & 1;
+    for (int r = 0; r < f.R; ++r) g += f.w1p[((size_t)r * WID + j) * 2 + c];
+  } else if (p < OW2) {
+    for (int r = 0; r < f.R; ++r) g += f.bp1[(size_t)r * WID + (p - OB1)];
+  } else if (p < OB2) {
+    for (int s = 0; s < f.S; ++s) g += f.part2[(size_t)s * WID * WID + (p - OW2)];
+  } else if (p < OW3) {
+    for (int r = 0; r < f.R; ++r) g += f.bp2[(size_t)r * WID + (p - OB2)];
+  } else if (p < OB3) {
+    for (int s = 0; s < f.S; ++s) g += f.part3[(size_t)s * WID * WID + (p - OW3)];
+  } else if (p < OW4) {
+    for (int r = 0; r < f.R; ++r) g += f.bp3[(size_t)r * WID + (p - OB3)];
+  } else if (p < OB4) {
+    for (int s = 0; s < f.S; ++s) g += f.part4[(size_t)s * NOUT * WID + (p - OW4)];
+  } else {
+    for (int r = 0; r < f.R; ++r) g += f.bp4[(size_t)r * NOUT + (p - OB4)];
+  }
+  f.G[p] = g;
+  if constexpr (UPDATE) {
+    const float m = f.beta1 * f.Mo[p] + (1.0f - f.beta1) * g;
+    const float v = f.beta2 * f.Ve[p] + (1.0f - f.beta2) * g * g;
+    f.Mo[p] = m;
+    f.Ve[p] = v;
+    const float w = f.P[p] - f.lr * (m / f.bc1) / (sqrtf(v / f.bc2) + f.eps);
+    f.P[p] = w;
+    store_copies(p, w, f.c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused inference: 64 query rows per block, activations stay in LDS
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ X, int64_t n,
+                                                      const Norm* __restrict__ nm, const bf16_t* __restrict__ W1b,
+                                                      const float* __restrict__ b1, const bf16_t* __restrict__ W2b,
+                                                      const float* __restrict__ b2, const bf16_t* __restrict__ W3b,
+                                                      const float* __restrict__ b3, const bf16_t* __restrict__ W4b,
+                                                      const float* __restrict__ b4, float* __restrict__ Y) {
+  __shared__ __align__(16) bf16_t H[64 * LDH];
+  __shared__ float xs[64][2];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  if (t < 64) {
+    const int64_t i = r0 + t;
+    float x0 = 0.0f, x1 = 0.0f;
+    if (i < n) {
+      x0 = (X[2 * i] - nm->in_shift[0]) * nm->in_scale[0];
+      x1 = (X[2 * i + 1] - nm->in_shift[1]) * nm->in_scale[1];
+    }
+    xs[t][0] = x0;
+    xs[t][1] = x1;
+  }
+  __syncthreads();
+  {
+    const int j = t;
+    const float w0 = from_bf16(W1b[2 * j]), w1 = from_bf16(W1b[2 * j + 1]), bj = b1[j];
+    for (int r = 0; r < 64; ++r) H[r * LDH + j] = to_bf16(gelu(xs[r][0] * w0 + xs[r][1] * w1 + bj));
+  }
+  __syncthreads();
+  // hidden layers 2 and 3: wave w owns columns 64w .. 64w+63 of all 64 rows
+  for (int layer = 0; layer < 2; ++layer) {
+    const bf16_t* W = layer ? W3b : W2b;
+    const float* bias = layer ? b3 : b2;
+    f4 acc[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16_t* wb = W + (size_t)(64 * w + r16) * WID + kq;
+#pragma unroll 2
+    for (int kk = 0; kk < WID; kk += 32) {
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) b[ct] = load8(wb + (size_t)ct * 16 * WID + kk);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) a[rt] = load8(&H[(rt * 16 + r16) * LDH + kk + kq]);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = mma(a[rt], b[ct], acc[rt][ct]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int j = 64 * w + ct * 16 + r16;
+      const float bj = bias[j];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          H[(rt * 16 + (lane >> 4) * 4 + e) * LDH + j] = to_bf16(gelu(acc[rt][ct][e] + bj));
+    }
+    __syncthreads();
+  }
+  // output layer: wave w owns columns 16w .. 16w+15
+  f4 acc[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) acc[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bf16_t* wb = W4b + (size_t)(16 * w + r16) * WID + kq;
+#pragma unroll 2
+  for (int kk = 0; kk < WID; kk += 32) {
+    const bf16x8 b = load8(wb + kk);
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = mma(load8(&H[(rt * 16 + r16) * LDH + kk + kq]), b, acc[rt]);
+  }
+  const int j = 16 * w + r16;
+  const float bj = b4[j], sh = nm->out_shift[j], sc = nm->out_scale[j];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = r0 + rt * 16 + (lane >> 4) * 4 + e;
+      if (i < n) Y[i * NOUT + j] = (acc[rt][e] + bj) / sc + sh;
+    }
+}
+
+}  // namespace
+
+// per-column mean and 1/std of the targets (one block per column, FP64,
+// fixed-order tree reduction)
+__global__ __launch_bounds__(256) void column_stats(const float* __restrict__ T, int64_t n, Norm* nm,
+                                                    double* out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = t; i < n; i += 256) s += (double)T[i * NOUT + c];
+  red[t] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  __syncthreads();
+  double q = 0.0;
+  for (int64_t i = t; i < n; i += 256) {
+    const double d = (double)T[i * NOUT + c] - mean;
+    q += d * d;
+  }
+  red[t] = q;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double sd = fmax(sqrt(red[0] / (double)n), 1e-6);
+    out[c] = mean;
+    out[NOUT + c] = 1.0 / sd;
+    nm->out_shift[c] = (float)mean;
+    nm->out_scale[c] = (float)(1.0 / sd);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct surrogate_t {
+  surrogate_params p;
+  hipStream_t stream;
+  int B;  // max_batch
+  float *P, *Mo, *Ve, *G, *xn, *A1, *A2, *A3;
+  Norm* nm;
+  WCopies wc;
+  bf16_t *H1, *H2, *H3, *H1t, *H2t, *H3t, *DYb, *DYt, *D3b, *D3t, *D2b, *D2t;
+  float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
+  double *lpart, *losses, *stats;
+  int64_t t;   // Adam steps taken
+  bool loaded;
+};
+
+namespace {
+
+// carve the workspace (base == nullptr: only measure)
+size_t carve(int B, char* base, surrogate_t* s) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~(size_t)255;
+    char* q = base ? base + off : nullptr;
+    off += bytes;
+    return q;
+  };
+  const int S = (B + KSPLIT - 1) / KSPLIT, R = B / 64;
+  surrogate_t d{};
+  surrogate_t& h = s ? *s : d;
+  h.P = (float*)take(4ull * NPAR);
+  h.Mo = (float*)take(4ull * NPAR);
+  h.Ve = (float*)take(4ull * NPAR);
+  h.G = (float*)take(4ull * NPAR);
+  h.nm = (Norm*)take(sizeof(Norm));
+  h.wc.W1b = (bf16_t*)take(2ull * WID * NIN);
+  h.wc.W2b = (bf16_t*)take(2ull * WID * WID);
+  h.wc.W2t = (bf16_t*)take(2ull * WID * WID);
+  h.wc.W3b = (bf16_t*)take(2ull * WID * WID);
+  h.wc.W3t = (bf16_t*)take(2ull * WID * WID);
+  h.wc.W4b = (bf16_t*)take(2ull * NOUT * WID);
+  h.wc.W4t = (bf16_t*)take(2ull * NOUT * WID);
+  h.xn = (float*)take(4ull * B * NIN);
+  h.A1 = (float*)take(4ull * B * WID);
+  h.A2 = (float*)take(4ull * B * WID);
+  h.A3 = (float*)take(4ull * B * WID);
+  bf16_t** act[] = {&h.H1, &h.H2, &h.H3, &h.H1t, &h.H2t, &h.H3t, &h.D3b, &h.D3t, &h.D2b, &h.D2t};
+  for (bf16_t** a : act) *a = (bf16_t*)take(2ull * B * WID);
+  h.DYb = (bf16_t*)take(2ull * B * NOUT);
+  h.DYt = (bf16_t*)take(2ull * B * NOUT);
+  h.part2 = (float*)take(4ull * S * WID * WID);
+  h.part3 = (float*)take(4ull * S * WID * WID);
+  h.part4 = (float*)take(4ull * S * NOUT * WID);
+  h.bp1 = (float*)take(4ull * R * WID);
+  h.bp2 = (float*)take(4ull * R * WID);
+  h.bp3 = (float*)take(4ull * R * WID);
+  h.bp4 = (float*)take(4ull * R * NOUT);
+  h.w1p = (float*)take(4ull * R * WID * 2);
+  h.lpart = (double*)take(8ull * R);
+  h.losses = (double*)take(8ull * MAX_STEPS);
+  h.stats = (double*)take(8ull * 2 * NOUT);
+  return off + 256;
+}
+
+int validate(const surrogate_params* p) {
+  if (!p) { set_error("NULL params"); return LAT_EINVAL; }
+  if (p->max_batch < 64 || p->max_batch > MAX_BATCH || p->max_batch % 64) {
+    set_error("max_batch must be a multiple of 64 in [64, 16384]");
+    return LAT_EINVAL;
+  }
+  if (!(p->beta1 >= 0.0 && p->beta1 < 1.0 && p->beta2 >= 0.0 && p->beta2 < 1.0 && p->eps > 0.0)) {
+    set_error("Adam parameters: need 0 <= beta < 1 and eps > 0");
+    return LAT_EINVAL;
+  }
+  for (int c = 0; c < NIN; ++c)
+    if (!std::isfinite(p->in_shift[c]) || !std::isfinite(p->in_scale[c]) || p->in_scale[c] == 0.0f) {
+      set_error("input normalisation must be finite with nonzero scale");
+      return LAT_EINVAL;
+    }
+  for (int c = 0; c < NOUT; ++c)
+    if (!std::isfinite(p->out_shift[c]) || !std::isfinite(p->out_scale[c]) || p->out_scale[c] == 0.0f) {
+      set_error("output normalisation must be finite with nonzero scale");
+      return LAT_EINVAL;
+    }
+  return LAT_OK;
+}
+
+template <int EPI>
+int launch_gemm(const GemmArgs& g, hipStream_t st) {
+  if (g.M % 64 || g.N % 64 || g.K % 64 || g.ksplit % 64 || g.K <= 0 || g.ksplit <= 0) {
+    set_error("internal: product shape not tileable");
+    return LAT_EINVAL;
+  }
+  const int splits = (g.K + g.ksplit - 1) / g.ksplit;
+  hipLaunchKernelGGL(gemm_nt<EPI>, dim3(g.N / 64, g.M / 64, splits), dim3(256), 0, st, g);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+// forward + backward of n rows (rows[] may be NULL) into G, loss into *loss_dev;
+// with update, one Adam step on the master weights and their BF16 copies
+int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* rows, int n, float* G,
+               double* loss_dev, bool update, double lr) {
+  hipStream_t st = h->stream;
+  const int Bp = (n + 63) / 64 * 64, R = Bp / 64, S = (Bp + KSPLIT - 1) / KSPLIT, ldt = h->B;
+  const WCopies& c = h->wc;
+  hipLaunchKernelGGL(l1_forward, dim3(R), dim3(256), 0, st, X, rows, n, h->nm, c.W1b, h->P + OB1, h->xn, h->A1,
+                     h->H1, h->H1t, ldt);
+  CL_HIP(hipGetLastError());
+  int rc;
+  GemmArgs g{};
+  g.ldt = ldt;
+  g.nvalid = n;
+  g.nm = h->nm;
+  // forward, hidden layers 2 and 3
+  const bf16_t* hin[2] = {h->H1, h->H2};
+  const bf16_t* wf[2] = {c.W2b, c.W3b};
+  const float* bias[2] = {h->P + OB2, h->P + OB3};
+  float* aout[2] = {h->A2, h->A3};
+  bf16_t* hout[2] = {h->H2, h->H3};
+  bf16_t* htout[2] = {h->H2t, h->H3t};
+  for (int l = 0; l < 2; ++l) {
+    GemmArgs f = g;
+    f.A = hin[l]; f.lda = WID; f.Bt = wf[l]; f.ldb = WID;
+    f.M = Bp; f.N = WID; f.K = WID; f.ksplit = WID;
+    f.bias = bias[l]; f.outA = aout[l]; f.outH = hout[l]; f.outHt = htout[l];
+    if ((rc = launch_gemm<EPI_FWD_HID>(f, st))) return rc;
+  }
+  {  // output layer and loss
+    GemmArgs f = g;
+    f.A = h->H3; f.lda = WID; f.Bt = c.W4b; f.ldb = WID;
+    f.M = Bp; f.N = NOUT; f.K = WID; f.ksplit = WID;
+    f.bias = h->P + OB4; f.outH = h->DYb; f.outHt = h->DYt;
+    f.T = T; f.rows = rows; f.bpart = h->bp4; f.lpart = h->lpart;
+    f.dscale = (float)(2.0 / ((double)n * NOUT));
+    if ((rc = launch_gemm<EPI_FWD_LOSS>(f, st))) return rc;
+  }
+  // backward: layer 4 -> 3 -> 2 -> 1
+  struct Lay {
+    const bf16_t* dAt; int nout;        // gradient of the layer's pre-activation, transposed [nout][ldt]
+    const bf16_t* dA;                   // row-major [Bp][nout]
+    const bf16_t* Hint;                 // transposed input activations [WID][ldt]
+    const bf16_t* Wt;                   // W^T [WID][nout]
+    float* wpart;
+    const float* prevA;                 // pre-activation of the layer below
+    bf16_t *outb, *outt;                // gradient of the layer below
+    float* bpart;
+  };
+  const Lay lays[3] = {
+      {h->DYt, NOUT, h->DYb, h->H3t, c.W4t, h->part4, h->A3, h->D3b, h->D3t, h->bp3},
+      {h->D3t, WID, h->D3b, h->H2t, c.W3t, h->part3, h->A2, h->D2b, h->D2t, h->bp2},
+      {h->D2t, WID, h->D2b, h->H1t, c.W2t, h->part2, h->A1, nullptr, nullptr, h->bp1},
+  };
+  for (int l = 0; l < 3; ++l) {
+    const Lay& L = lays[l];
+    GemmArgs wg = g;
+    wg.A = L.dAt; wg.lda = ldt; wg.Bt = L.Hint; wg.ldb = ldt;
+    wg.M = L.nout; wg.N = WID; wg.K = Bp; wg.ksplit = KSPLIT; wg.wpart = L.wpart;
+    if ((rc = launch_gemm<EPI_WGRAD>(wg, st))) return rc;
+    GemmArgs bg = g;
+    bg.A = L.dA; bg.lda = L.nout; bg.Bt = L.Wt; bg.ldb = L.nout;
+    bg.M = Bp; bg.N = WID; bg.K = L.nout; bg.ksplit = L.nout;
+    bg.prevA = L.prevA; bg.outH = L.outb; bg.outHt = L.outt; bg.bpart = L.bpart;
+    if (l < 2) {
+      if ((rc = launch_gemm<EPI_BWD_HID>(bg, st))) return rc;
+    } else {
+      bg.xn = h->xn; bg.w1part = h->w1p;
+      if ((rc = launch_gemm<EPI_BWD_FIRST>(bg, st))) return rc;
+    }
+  }
+  FinishArgs f{};
+  f.part2 = h->part2; f.part3 = h->part3; f.part4 = h->part4;
+  f.bp1 = h->bp1; f.bp2 = h->bp2; f.bp3 = h->bp3; f.bp4 = h->bp4; f.w1p = h->w1p;
+  f.lpart = h->lpart; f.S = S; f.R = R;
+  f.inv_count = 1.0 / ((double)n * NOUT);
+  f.loss = loss_dev;
+  f.G = G;
+  f.P = h->P; f.Mo = h->Mo; f.Ve = h->Ve;
+  f.c = c;
+  const int fb = (NPAR + 255) / 256;
+  if (update) {
+    h->t += 1;
+    f.lr = (float)lr;
+    f.beta1 = (float)h->p.beta1;
+    f.beta2 = (float)h->p.beta2;
+    f.eps = (float)h->p.eps;
+    f.bc1 = (float)(1.0 - std::pow(h->p.beta1, (double)h->t));
+    f.bc2 = (float)(1.0 - std::pow(h->p.beta2, (double)h->t));
+    hipLaunchKernelGGL(finish_kernel<true>, dim3(fb), dim3(256), 0, st, f);
+  } else {
+    hipLaunchKernelGGL(finish_kernel<false>, dim3(fb), dim3(256), 0, st, f);
+  }
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+}  // namespace
+
+extern "C" int surrogate_workspace_size(const surrogate_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) { set_error("NULL argument"); return LAT_EINVAL; }
+  *bytes = carve(p->max_batch, nullptr, nullptr);
+  return LAT_OK;
+}
+
+extern "C" int surrogate_init(const surrogate_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                              surrogate_t** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!dev_ws || !out) { set_error("NULL argument"); return LAT_EINVAL; }
+  const size_t need = carve(p->max_batch, nullptr, nullptr);
+  if (ws_bytes < need) { set_error("workspace too small: need " + std::to_string(need)); return LAT_ENOMEM; }
+  surrogate_t* h = new (std::nothrow) surrogate_t{};
+  if (!h) { set_error("out of host memory"); return LAT_ENOMEM; }
+  h->p = *p;
+  h->stream = (hipStream_t)hip_stream;
+  h->B = p->max_batch;
+  char* base = (char*)(((uintptr_t)dev_ws + 255) & ~(uintptr_t)255);
+  carve(h->B, base, h);
+  Norm nm;
+  std::memcpy(nm.in_shift, p->in_shift, sizeof nm.in_shift);
+  std::memcpy(nm.in_scale, p->in_scale, sizeof nm.in_scale);
+  std::memcpy(nm.out_shift, p->out_shift, sizeof nm.out_shift);
+  std::memcpy(nm.out_scale, p->out_scale, sizeof nm.out_scale);
+  hipError_t e = hipMemcpyAsync(h->nm, &nm, sizeof(Norm), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    set_error(std::string("surrogate_init: ") + hipGetErrorString(e));
+    delete h;
+    return LAT_EHIP;
+  }
+  *out = h;
+  return LAT_OK;
+}
+
+extern "C" int surrogate_set_weights(surrogate_t* h, const float* host_w) {
+  if (!h || !host_w) { set_error("NULL argument"); return LAT_EINVAL; }
+  for (int i = 0; i < NPAR; ++i)
+    if (!std::isfinite(host_w[i])) { set_error("non-finite weight"); return LAT_EINVAL; }
+  CL_HIP(hipMemcpyAsync(h->P, host_w, 4ull * NPAR, hipMemcpyHostToDevice, h->stream));
+  CL_HIP(hipMemsetAsync(h->Mo, 0, 4ull * NPAR, h->stream));
+  CL_HIP(hipMemsetAsync(h->Ve, 0, 4ull * NPAR, h->stream));
+  hipLaunchKernelGGL(copies_kernel, dim3((NPAR + 255) / 256), dim3(256), 0, h->stream, h->P, h->wc);
+  CL_HIP(hipGetLastError());
+  CL_HIP(hipStreamSynchronize(h->stream));
+  h->t = 0;
+  h->loaded = true;
+  return LAT_OK;
+}
+
+extern "C" int surrogate_get_weights(surrogate_t* h, float* host_w) {
+  if (!h || !host_w) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (!h->loaded) { set_error("weights not set"); return LAT_ESTATE; }
+  CL_HIP(hipMemcpyAsync(host_w, h->P, 4ull * NPAR, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  return LAT_OK;
+}
+
+extern "C" int surrogate_fit_output_scale(surrogate_t* h, const float* dev_t, int64_t n, double* host_shift,
+                                          double* host_scale) {
+  if (!h || !dev_t) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (n < 2) { set_error("need at least 2 target rows"); return LAT_EINVAL; }
+  hipLaunchKernelGGL(column_stats, dim3(NOUT), dim3(256), 0, h->stream, dev_t, n, h->nm, h->stats);
+  CL_HIP(hipGetLastError());
+  double st[2 * NOUT];
+  CL_HIP(hipMemcpyAsync(st, h->stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  for (int c = 0; c < 2 * NOUT; ++c)
+    if (!std::isfinite(st[c])) { set_error("non-finite target statistics"); return LAT_ENONFINITE; }
+  for (int c = 0; c < NOUT; ++c) {
+    h->p.out_shift[c] = (float)st[c];
+    h->p.out_scale[c] = (float)st[NOUT + c];
+    if (host_shift) host_shift[c] = st[c];
+    if (host_scale) host_scale[c] = st[NOUT + c];
+  }
+  return LAT_OK;
+}
+
+extern "C" int surrogate_loss_grad(surrogate_t* h, const float* dev_x, const float* dev_t, const int32_t* rows,
+                                   int32_t n, float* dev_grad, double* loss) {
+  if (!h || !dev_x || !dev_t || !dev_grad || !loss) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (!h->loaded) { set_error("weights not set"); return LAT_ESTATE; }
+  if (n < 1 || n > h->B) { set_error("n must be in [1, max_batch]"); return LAT_EINVAL; }
+  int rc = train_step(h, dev_x, dev_t, rows, n, dev_grad, h->losses, false, 0.0);
+  if (rc) return rc;
+  CL_HIP(hipMemcpyAsync(loss, h->losses, 8, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  if (!std::isfinite(*loss)) { set_error("non-finite loss"); return LAT_ENONFINITE; }
+  return LAT_OK;
+}
+
+extern "C" int surrogate_train_epoch(surrogate_t* h, const float* dev_x, const float* dev_t,
+                                     const int32_t* dev_perm, int64_t n, double lr, double* mean_loss) {
+  if (!h || !dev_x || !dev_t || !dev_perm || !mean_loss) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (!h->loaded) { set_error("weights not set"); return LAT_ESTATE; }
+  if (n < 1) { set_error("n must be positive"); return LAT_EINVAL; }
+  if (!(lr > 0.0) || !std::isfinite(lr)) { set_error("lr must be positive"); return LAT_EINVAL; }
+  const int64_t steps = (n + h->B - 1) / h->B;
+  if (steps > MAX_STEPS) { set_error("too many steps in one epoch (max 65536)"); return LAT_EINVAL; }
+  for (int64_t s = 0; s < steps; ++s) {
+    const int ns = (int)std::min<int64_t>(h->B, n - s * h->B);
+    int rc = train_step(h, dev_x, dev_t, dev_perm + s * h->B, ns, h->G, h->losses + s, true, lr);
+    if (rc) return rc;
+  }
+  std::vector<double> l((size_t)steps);
+  CL_HIP(hipMemcpyAsync(l.data(), h->losses, 8 * steps, hipMemcpyDeviceToHost, h->stream));
+  CL_HIP(hipStreamSynchronize(h->stream));
+  double m = 0.0;
+  for (double v : l) m += v;
+  *mean_loss = m / (double)steps;
+  if (!std::isfinite(*mean_loss)) { set_error("non-finite loss"); return LAT_ENONFINITE; }
+  return LAT_OK;
+}
+
+extern "C" int surrogate_predict(surrogate_t* h, const float* dev_x, int64_t n, float* dev_y) {
+  if (!h || !dev_x || !dev_y) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (!h->loaded) { set_error("weights not set"); return LAT_ESTATE; }
+  if (n < 0 || n > ((int64_t)1 << 36)) { set_error("n out of range"); return LAT_EINVAL; }
+  if (n == 0) return LAT_OK;
+  const WCopies& c = h->wc;
+  hipLaunchKernelGGL(predict_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->stream, dev_x, n, h->nm,
+                     c.W1b, h->P + OB1, c.W2b, h->P + OB2, c.W3b, h->P + OB3, c.W4b, h->P + OB4, dev_y);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+extern "C" int surrogate_destroy(surrogate_t* h) {
+  if (!h) return LAT_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  delete h;
+  if (e != hipSuccess) { set_error(std::string("surrogate_destroy: ") + hipGetErrorString(e)); return LAT_EHIP; }
+  return LAT_OK;
+}

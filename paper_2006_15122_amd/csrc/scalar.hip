@@ -1,12 +1,12 @@
 // Fused scalar-field pass for gfx950: drift, 7-point stencil kick, FP64
 // volume averages and the scale-factor update, in one sweep over the lattice.
 //
-// Method (arXiv:2006.15122): Hamiltonian form of the scalar EOM (Sec. 4.3)
+// Method (arXiv:2006.15122): Hamiltonian form of the scalar EOM (Sec. 4.2.3)
 //   phi' = a^{-(3-alpha)} pi,  pi' = a^{1+alpha} lap phi - a^{3+alpha} V_{,phi},
 //   b'   = (1/3)(f*/m_p)^2 a^{1+2 alpha}[(alpha-2) E_K + alpha E_G + (alpha+1) E_V],
-// integrated by velocity Verlet / Yoshida (Sec. 4.4) or staggered leapfrog
+// integrated by velocity Verlet / Yoshida (Sec. 4.2.3, 4.3.2) or staggered leapfrog
 // scheme III (Sec. 4.2.1).  Consecutive kicks of the Verlet chain are merged
-// (Sec. 3.4: velocity Verlet is leapfrog plus a synchronising half kick), so
+// (Sec. 3.3.2: velocity Verlet is leapfrog plus a synchronising half kick), so
 // one pass = drift of sub-step p followed by the kick that closes p and opens
 // p+1.  The drift needs the global energies of the previous pass: a one-block
 // finish kernel reduces the per-tile FP64 partials in a fixed order and
@@ -17,6 +17,7 @@
 // rows.  The drifted plane x (with a one-site y/z halo) sits in LDS; the x-1,
 // x+1 neighbours stay in registers.  Halo sites are drifted redundantly by the
 // neighbouring tiles, which removes a separate drift pass over HBM.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,9 +35,15 @@ struct Shape {
   int tz, by, ry;
 };
 
+// With ev0/ev1 the dispatch itself carries the device's start and stop
+// timestamps of the pass kernel (hipExtLaunchKernel), nothing else changes.
 template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
-hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
+hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, ev0,
+                          ev1, 0, A);
+  else
+    hipLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(1024), 0, s, A, nblocks);
@@ -67,10 +74,11 @@ static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
 static const int kObsTz = 32, kObsBy = 8, kObsRy = 2, kObsXc = 8;
 
 template <typename T, int NF>
-hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s, bool full) {
-  if (full) return launch_shape<T, NF, true, 32, 8, 2>(A, nblocks, s);
+hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s, bool full,
+                                hipEvent_t ev0, hipEvent_t ev1) {
+  if (full) return launch_shape<T, NF, true, 32, 8, 2>(A, nblocks, s, ev0, ev1);
 #define X(TT, NFF, a, b, c) \
-  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s);
+  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s, ev0, ev1);
   if constexpr (std::is_same<T, float>::value && NF == 2) {
     CL_SHAPES_MAIN(X, T, NF)
   } else {
@@ -95,7 +103,7 @@ void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry) {
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz,
                               int by, int ry, int xc, int swizzle, const double* phys, int expand,
                               const PassDesc& pd, double* partials, DevState* st, hipStream_t s,
-                              int* nblocks_out, int full) {
+                              int* nblocks_out, int full, hipEvent_t ev0, hipEvent_t ev1) {
   if (full) {
     tz = kObsTz;
     by = kObsBy;
@@ -132,11 +140,13 @@ hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* co
   if (fp32) {
     ScalarArgs<float> A;
     fill(A, (float*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s, full) : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s, full);
+    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s, full, ev0, ev1)
+                   : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s, full, ev0, ev1);
   } else {
     ScalarArgs<double> A;
     fill(A, (double*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s, full) : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s, full);
+    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s, full, ev0, ev1)
+                   : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s, full, ev0, ev1);
   }
 }
 

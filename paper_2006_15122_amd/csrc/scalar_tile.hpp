@@ -78,7 +78,7 @@ __device__ void block_partials(const ScalarArgs<T>& A, double (&acc)[Acc<NF, FUL
 
 // One block: combine the partials of all nblocks blocks in block order
 // (thread t takes blocks t, t+256, ...; then shuffles and waves in order),
-// form the volume averages (Sec. 4.3/4.5) and advance b in FP64,
+// form the volume averages (Sec. 4.3.2/4.4) and advance b in FP64,
 //   b_out = b_in + (wk1 + wk2) h K_a(a', E),
 //   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].
 // Sum NB consecutive partial records (starting at `first`) in a fixed order
@@ -110,7 +110,7 @@ __device__ bool reduce_partials(const double* partials, int first, int nb, doubl
   return true;
 }
 
-// From the lattice sums S of one pass: the volume averages (Sec. 4.3/4.5) and
+// From the lattice sums S of one pass: the volume averages (Sec. 4.3.2/4.4) and
 // the FP64 advance of b,
 //   b_out = b_in + (wk1 + wk2) h K_a(a', E),
 //   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].

@@ -23,9 +23,9 @@ ICS = {"vacuum": 0, "homogeneous": 1}
 ERRORS = {-1: "LAT_EINVAL", -2: "LAT_ENOMEM", -3: "LAT_EHIP", -4: "LAT_ENONFINITE", -5: "LAT_ESTATE"}
 
 EXPORTS = ["lattice_workspace_size", "lattice_init", "lattice_set_state", "lattice_get_state",
-           "lattice_step", "lattice_energies", "lattice_spectrum", "lattice_destroy",
+           "lattice_step", "lattice_energies", "lattice_spectrum", "lattice_spectrum_logk", "lattice_destroy",
            "lattice_last_error", "lattice_get_tiling", "lattice_set_tiling",
-           "lattice_field_device_ptr", "lattice_batch_workspace_size", "lattice_batch_init",
+           "lattice_field_device_ptr", "lattice_pass_timer", "lattice_pass_timer_read", "lattice_batch_workspace_size", "lattice_batch_init",
            "lattice_batch_step", "lattice_batch_energies", "lattice_batch_run",
            "lattice_batch_get_tiling", "lattice_batch_set_tiling", "lattice_batch_use_graph",
            "lattice_batch_destroy"]
@@ -213,6 +213,26 @@ class Lattice:
                                       c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(nb)))
         n = nb.value
         return {"k": k[:n], "delta": d[:n], "S": s[:n], "count": c[:n]}
+
+    def spectrum_logk(self, out, which: int = 1, nk: int = 64):
+        """log10 mode-averaged spectrum at nk log-spaced k, written on the device
+        into `out` (a float32 CUDA tensor of nk elements, e.g. a row of a
+        training set).  Asynchronous on the lattice's stream."""
+        import torch
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() < nk or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of at least nk elements")
+        _check(lib().lattice_spectrum_logk(self.h, ctypes.c_int(which), ctypes.c_int(nk),
+                                           ctypes.c_void_p(out.data_ptr())))
+
+    def pass_timer(self, max_launches: int):
+        """Time the next max_launches fused-pass kernels on the device."""
+        _check(lib().lattice_pass_timer(self.h, ctypes.c_int32(int(max_launches))))
+
+    def pass_timer_read(self):
+        """(summed kernel milliseconds, number of timed launches)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lattice_pass_timer_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def tiling(self):
         v = [ctypes.c_int32() for _ in range(4)]

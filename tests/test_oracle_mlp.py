@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from oracle import mlp
+from paper_2006_15122_amd import synth
 
 
 def test_bf16_round_matches_torch_and_ties_to_even():
@@ -36,7 +37,7 @@ def _batch(seed, B=16):
 
 
 def test_gradients_against_central_differences():
-    p = mlp.init_params(1)
+    p = synth.mlp_init(1)
     for k in p:
         p[k] = p[k] + 0.05 * np.random.default_rng(2).standard_normal(p[k].shape)
     x, t = _batch(3)
@@ -56,7 +57,7 @@ def test_gradients_against_central_differences():
 
 
 def test_gradients_against_torch_autograd_fp64():
-    p = mlp.init_params(5)
+    p = synth.mlp_init(5)
     for k in p:
         p[k] = p[k] + 0.05 * np.random.default_rng(6).standard_normal(p[k].shape)
     x, t = _batch(7, B=32)
@@ -74,7 +75,7 @@ def test_gradients_against_torch_autograd_fp64():
 
 
 def test_bf16_emulation_changes_little():
-    p = mlp.init_params(8)
+    p = synth.mlp_init(8)
     x, t = _batch(9, B=64)
     L0, g0 = mlp.loss_and_grads(p, x, t, bf16=False)
     L1, g1 = mlp.loss_and_grads(p, x, t, bf16=True)
@@ -84,7 +85,7 @@ def test_bf16_emulation_changes_little():
 
 
 def test_adam_against_torch_optim():
-    p = mlp.init_params(10)
+    p = synth.mlp_init(10)
     tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
     opt = torch.optim.Adam(list(tp.values()), lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
     state = {}

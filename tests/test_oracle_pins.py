@@ -161,7 +161,7 @@ def test_vv_phase_converges_to_continuum_at_second_order():
 
 
 # --------------------------------------------------------------------------
-# Time reversibility (Sec. 3.6): flip momenta and b, evolve, flip back
+# Time reversibility (Sec. 3.5): flip momenta and b, evolve, flip back
 # --------------------------------------------------------------------------
 def _interacting_cfg(N=6, expansion=True, alpha=1.0):
     return dict(model="scalar", nf=2, N=N, kIR=0.9, alpha=alpha, fstar_over_mp=2.0,
@@ -215,7 +215,7 @@ def test_reversibility_leapfrog_expanding():
 
 
 # --------------------------------------------------------------------------
-# Convergence order (Sec. 3.6): error ratio 4 for LF2 / VV2, 16 for VV4
+# Convergence order (Sec. 3.5): error ratio 4 for LF2 / VV2, 16 for VV4
 # --------------------------------------------------------------------------
 def _run_to(cfg, integ, h, T, seed=21):
     m = oracle.scalar_model(cfg)
@@ -439,3 +439,42 @@ def test_vacuum_ic_variance_matches_continuum_sum():
         vals.append((sum(sp["delta"][b] / b for b in range(1, nb)), np.var(f)))
     for a, b in vals:
         assert abs(a - b) < 1e-10 * b
+
+
+def test_log_interp_matches_numpy_interp_and_hits_shell_centres():
+    rng = np.random.default_rng(3)
+    kbar = np.concatenate([[0.0], np.sort(rng.uniform(0.5, 30.0, 40))])
+    val = 10.0 ** rng.uniform(-8, 2, 41)
+    valid = np.ones(41, bool)
+    valid[0] = False
+    valid[7] = False
+    kq = np.exp(np.linspace(np.log(0.3), np.log(40.0), 200))
+    got = oracle.log_interp(kbar, val, valid, kq)
+    ref = np.interp(np.log10(kq), np.log10(kbar[valid]), np.log10(val[valid]))
+    assert np.max(np.abs(got - ref)) < 1e-12
+    at = oracle.log_interp(kbar, val, valid, kbar[valid])
+    assert np.max(np.abs(at - np.log10(val[valid]))) < 1e-12
+
+
+def test_logk_grid_spans_the_shells():
+    g = oracle.logk_grid(64, 0.6, 64)
+    assert len(g) == 64 and abs(g[0] - 0.6) < 1e-15 and abs(g[-1] - 0.6 * 55) < 1e-12
+    assert np.allclose(np.diff(np.log(g)), np.log(55.0) / 63)
+
+
+def test_spectrum_logk_of_flat_mode_power():
+    # unit power on every mode with b >= 1: the mode average is known in closed
+    # form and the target is the log-log line through it
+    N, kIR = 16, 0.6
+    n1, n2, n3, nabs = oracle.reciprocal(N)
+    b = np.floor(np.sqrt(n1 * n1 + n2 * n2 + n3 * n3)).astype(int)
+    F = np.where((b >= 1), 1.0 + 0j, 0j)
+    f = oracle.paper_idft(F).real
+    s = oracle.spectrum(f, kIR)
+    t = oracle.spectrum_logk(f, kIR, 16)
+    kq = oracle.logk_grid(N, kIR, 16)
+    dx = oracle.lattice_dx(N, kIR)
+    # |F|^2 = 1 on every mode with b >= 1: delta_avg = kbar^3 (dx/N)^3 / (2 pi^2)
+    assert np.allclose(s["delta_avg"][1:], s["k"][1:] ** 3 * (dx / N) ** 3 / (2 * math.pi ** 2), rtol=1e-12)
+    lk, lv = np.log10(s["k"][1:]), np.log10(s["delta_avg"][1:])
+    assert np.max(np.abs(t - np.interp(np.log10(kq), lk, lv))) < 1e-12
