@@ -87,30 +87,33 @@ __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
   return C2<T>{re[i], im[i]};
 }
 
-// one thread per site; neighbours come through the cache hierarchy
+// one thread per site; neighbours come through the cache hierarchy.  Site
+// indices fit in 32 bits (N^3 <= 2^30); the periodic neighbour offsets of each
+// axis are formed once, and n + i - j is the sum of two of them.
 template <typename T>
 __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
   const int N = A.N;
-  const size_t NN = (size_t)N * N;
-  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int x = (int)(s / NN), y = (int)((s / N) % N), z = (int)(s % N);
-  auto at = [&](int dx_, int dy_, int dz_) -> size_t {
-    const int xx = (x + dx_ + N) % N, yy = (y + dy_ + N) % N, zz = (z + dz_ + N) % N;
-    return (size_t)xx * NN + (size_t)yy * N + zz;
+  const int NN = N * N;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  const int x = s / NN, y = (s / N) % N, z = s % N;
+  const int up[3] = {x == N - 1 ? -(N - 1) * NN : NN, y == N - 1 ? -(N - 1) * N : N, z == N - 1 ? -(N - 1) : 1};
+  const int dn[3] = {x == 0 ? (N - 1) * NN : -NN, y == 0 ? (N - 1) * N : -N, z == 0 ? (N - 1) : -1};
+  // site n + step*e_dir + step2*e_dir2 (step, step2 in {-1, 0, 1}, dir != dir2 when both nonzero)
+  auto off = [&](int dir, int step, int dir2, int step2) -> int {
+    int o = s;
+    if (step > 0) o += up[dir];
+    if (step < 0) o += dn[dir];
+    if (step2 > 0) o += up[dir2];
+    if (step2 < 0) o += dn[dir2];
+    return o;
   };
-  auto off = [&](int dir, int step, int dir2, int step2) -> size_t {
-    int d[3] = {0, 0, 0};
-    d[dir] += step;
-    d[dir2] += step2;
-    return at(d[0], d[1], d[2]);
-  };
-  auto theta = [&](int i, size_t site) -> T { return A.c[4 + i][site]; };
-  auto link = [&](int i, size_t site) -> C2<T> {
+  auto theta = [&](int i, int site) -> T { return A.c[4 + i][site]; };
+  auto link = [&](int i, int site) -> C2<T> {
     T sn, cs;
     sincos_t(theta(i, site), &sn, &cs);
     return C2<T>{cs, sn};
   };
-  auto phi = [&](size_t site) -> C2<T> { return ld(A.c[0], A.c[1], site); };
+  auto phi = [&](int site) -> C2<T> { return ld(A.c[0], A.c[1], (size_t)site); };
 
   const double a_in = A.st->a;
   const T cl = (T)(pow(a_in, 1.0 + A.alpha) / (A.dx * A.dx));
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
     th[i] = theta(i, s);
     T sn, cs;
     sincos_t(th[i], &sn, &cs);
-    const size_t sp = off(i, 1, i, 0), sm = off(i, -1, i, 0);
+    const int sp = off(i, 1, i, 0), sm = off(i, -1, i, 0);
     const C2<T> f = cm(C2<T>{cs, sn}, phi(sp));
     const C2<T> b = cm(cc(link(i, sm)), phi(sm));
     lap.x += f.x + b.x;
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
     for (int j = 0; j < 3; ++j) {
       if (j == i) continue;
       const T ph0 = (th[i] + theta(j, off(i, 1, j, 0))) - (theta(i, off(j, 1, i, 0)) + th[j]);
-      const size_t smj = off(j, -1, j, 0);
+      const int smj = off(j, -1, j, 0);
       // Phi_ij(n-j) = th_i(n-j) + th_j(n-j+i) - th_i(n) - th_j(n-j)
       const T ph1 = (theta(i, smj) + theta(j, off(j, -1, i, 1))) - (th[i] + theta(j, smj));
       curl += sin_t(ph0) - sin_t(ph1);

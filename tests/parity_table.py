@@ -1,0 +1,126 @@
+"""Per-observable error table of the GPU path against the FP64 oracle.
+
+Not collected by pytest (a report, not a gate; the gates are the test_gpu_*
+files).  Runs the workloads from the same FP64 initial state on both sides and
+prints, per observable, the largest relative error over the checkpoints as a
+markdown table.  <phi_f> is taken relative to sqrt(<phi_f^2>).
+
+    python tests/parity_table.py [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2006_15122_amd import synth  # noqa: E402
+
+SCALAR_KEYS = ("a", "b", "EK", "EG", "EV", "EV_quartic", "EV_int")
+U1_KEYS = ("a", "b", "EK", "EG", "EV", "EK_A", "EG_A")
+
+
+def _err(g, o, k, scale=None):
+    s = abs(o[k]) if scale is None else scale
+    return abs(g[k] - o[k]) / s if s else abs(g[k])
+
+
+def scalar_case(cfg, nsteps, every):
+    from paper_2006_15122_amd.lattice import Lattice
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    lat = Lattice(cfg, device="cuda:0")
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+    phi, pi, a, b, h = st["phi"].copy(), st["pi"].copy(), st["a"], st["b"], cfg["dt"]
+    nf = cfg["nf"]
+    lf = cfg["integrator"] == "lf2"
+    if lf:
+        a, b = oracle.lf_startup(m, phi, pi, a, b, h)
+    worst = {}
+    for k in range(nsteps // every):
+        lat.step(every)
+        if lf:
+            a, b = oracle.lf_steps(m, phi, pi, a, b, h, every, omp=True)
+            o = oracle.lf_observe(m, phi, pi, a, b, h)
+        else:
+            a, b = oracle.vv_steps(m, phi, pi, a, b, h, cfg["integrator"], every, omp=True)
+            o = oracle.sync_observe(m, phi, pi, a, b)
+        g = lat.energies()
+        row = {kk: _err(g, o, kk) for kk in SCALAR_KEYS if not (kk == "EV_int" and nf < 2)}
+        for f in range(nf):
+            row[f"EK{f}"] = _err(g, o, f"EK{f}")
+            row[f"EG{f}"] = _err(g, o, f"EG{f}")
+            row[f"meansq{f}"] = _err(g, o, f"meansq{f}")
+            row[f"mean{f}"] = _err(g, o, f"mean{f}", math.sqrt(o[f"meansq{f}"]))
+        row["hc (abs)"] = abs(g["hc"] - o["hc"])
+        for kk, v in row.items():
+            worst[kk] = max(worst.get(kk, 0.0), v)
+    lat.close()
+    return worst
+
+
+def u1_case(cfg, nsteps, every):
+    from paper_2006_15122_amd.lattice import Lattice
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = Lattice(cfg, device="cuda:0")
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    h = cfg["dt"]
+    oracle.u1_lf_startup(m, st, h)
+    worst = {}
+    for k in range(nsteps // every):
+        lat.step(every)
+        oracle.u1_lf_steps(m, st, h, every, omp=True)
+        o = oracle.u1_lf_observe(m, st, h)
+        g = lat.energies()
+        row = {kk: _err(g, o, kk) for kk in U1_KEYS}
+        row["EV_quartic"] = _err(g, o, "EV_quartic")
+        sc = math.sqrt(o["meansq"])
+        row["mean0"] = abs(g["mean0"] - o["mean0"]) / sc
+        row["mean1"] = abs(g["mean1"] - o["mean1"]) / sc
+        row["meansq"] = abs(g["meansq0"] - o["meansq"]) / o["meansq"]
+        row["gauss (GPU, abs)"] = g["gauss"]
+        for kk, v in row.items():
+            worst[kk] = max(worst.get(kk, 0.0), v)
+    lat.close()
+    return worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    cases = [
+        ("config 1: one field, 32^3, FP64, LF2, 1000 steps", lambda: scalar_case(synth.config1(), 1000, 100)),
+        ("two fields q=100, 64^3, FP32, VV2, 4000 steps (eta = 20)",
+         lambda: scalar_case(synth.small(synth.config2(q=100.0), 64), 4000, 500)),
+        ("two fields q=1000, 64^3, FP32, VV4, 1000 steps",
+         lambda: scalar_case(synth.small(synth.config2(q=1000.0, integrator="vv4"), 64), 1000, 250)),
+        ("compact U(1), 64^3, FP64, LF2, 400 steps",
+         lambda: u1_case(dict(synth.config3(N=64), precision="fp64"), 400, 100)),
+        ("compact U(1), 64^3, FP32, LF2, 400 steps", lambda: u1_case(synth.config3(N=64), 400, 100)),
+    ]
+    lines = []
+    for name, fn in cases:
+        t0 = time.time()
+        print(f"case: {name}", flush=True)
+        w = fn()
+        lines.append(f"\n**{name}** ({time.time() - t0:.0f} s)\n")
+        lines.append("| observable | max rel. error |")
+        lines.append("|---|---|")
+        for k, v in w.items():
+            lines.append(f"| {k} | {v:.2e} |")
+        print("\n".join(lines[-len(w) - 3:]), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -176,3 +176,29 @@ def test_device_spectrum_targets_match_oracle():
         ref = oracle.spectrum_logk(arr, cfg["kIR"], 64)
         d = np.max(np.abs(got[64 * half:64 * half + 64] - ref) / np.maximum(1.0, np.abs(ref)))
         assert d < 4e-7, (half, d)
+
+
+def test_emulator_routes_outside_domain_to_the_lattice():
+    torch = _torch()
+    from paper_2006_15122_amd import emulator
+    from paper_2006_15122_amd.lattice import Batch
+    m = _model(256, None, None)
+    m.set_weights(_weights(21))
+    em = emulator.SpectrumEmulator(m, N=32)
+    q = np.array([5.0, 100.0, 3e4, 300.0])
+    eta = np.array([1.0, 2.0, 1.0, 40.0])
+    vals, src = em.query(q, eta)
+    assert src.tolist() == [0, 1, 0, 0]
+    # the network answers inside the trained domain
+    x = torch.tensor([[2.0, 2.0]], dtype=torch.float32, device="cuda:0")
+    assert np.array_equal(vals[1], m.predict(x).cpu().numpy()[0])
+    # outside it the answer is a plain lattice run to the requested time
+    for i in (0, 2, 3):
+        c = synth.config2(q=float(q[i]), integrator="vv2", N=32, seed=em.fallback_seed + i)
+        B = Batch([c])
+        B.step(int(round(eta[i] / c["dt"])))
+        out = torch.empty(64, dtype=torch.float32, device="cuda:0")
+        B.runs[0].spectrum_logk(out, which=1, nk=64)
+        B.synchronize()
+        assert np.array_equal(vals[i], out.cpu().numpy()), i
+        B.close()
