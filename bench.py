@@ -32,19 +32,20 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(per_launch_sites: int):
+def _traffic(per_launch_sites: int, tile):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counts, if they were taken on the current kernel source; else None."""
+    counts, if they were taken on the current kernel source and tile; else None."""
     p = os.path.join(ROOT, "profiles", "scalar_pass_256_vv2_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_hash") != _kernel_hash() or d.get("sites") != per_launch_sites:
+    if (d.get("kernel_hash") != _kernel_hash() or d.get("sites") != per_launch_sites
+            or list(d.get("tile", [])) != list(tile)):
         return None
     return d.get("bytes_per_launch")
 
 
-def time_lattice(cfg: dict, steps: int, warmup: int, passes: int = 0):
+def time_lattice(cfg: dict, steps: int, warmup: int, passes: int = 0, tile=None):
     """Time `steps` steps on the lattice's stream (HIP events).  With passes > 0
     the first `passes` fused-pass kernels of the timed region also carry
     their own device start/stop timestamps; returns their mean duration."""
@@ -53,6 +54,8 @@ def time_lattice(cfg: dict, steps: int, warmup: int, passes: int = 0):
     from paper_2006_15122_amd.lattice import Lattice
 
     lat = Lattice(cfg, device="cuda:0")
+    if tile:
+        lat.set_tiling(*tile)
     stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -147,6 +150,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--tile", default=None,
+                    help="tz,by,ry,xc of the main run instead of the autotuner's choice (for counter runs, "
+                         "where profiling overhead can change the tuner's pick)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy, the reference for HBM counter scaling")
     args = ap.parse_args()
@@ -172,7 +178,8 @@ def main():
     N = cfg["N"]
     # one call of lattice_step(K) issues K fused passes plus one opening half-kick pass
     passes = args.steps + 1
-    ms, wall, obs, tile, kernel_ms = time_lattice(cfg, args.steps, args.warmup, passes)
+    forced = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    ms, wall, obs, tile, kernel_ms = time_lattice(cfg, args.steps, args.warmup, passes, forced)
     sites = N ** 3
     ms_per_pass = ms / passes
     value = sites * args.steps / (ms / 1e3)
@@ -195,7 +202,7 @@ def main():
                    "N": N, "integrator": "vv2", "nfields": 2, "storage": "fp32", "sums": "fp64",
                    "tile": {"tz": tile[0], "by": tile[1], "ry": tile[2], "xc": tile[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(sites),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(sites, tile),
                      "kernel": "scalar_pass_kernel<float, 2, false, %d, %d, %d>" % tile[:3],
                      "ms_per_launch": kernel_ms, "launches": passes, "step_ms_per_pass": ms_per_pass,
                      "bytes_per_launch": sites * BYTES_PER_SITE_VV2_NF2_FP32},

@@ -93,6 +93,15 @@ int surrogate_loss_grad(surrogate_t* h, const float* dev_x, const float* dev_t, 
 int surrogate_train_epoch(surrogate_t* h, const float* dev_x, const float* dev_t, const int32_t* dev_perm,
                           int64_t n, double lr, double* mean_loss);
 
+/* Replay whole training epochs from a HIP graph (default on when the
+ * handle's stream is a created stream, off on the null stream).  An epoch is
+ * captured on the first call and replayed while dev_x, dev_t, dev_perm and n
+ * are the same; refill the same perm buffer to reshuffle.  The learning rate
+ * and the Adam step count live on the device, so a replay continues the run
+ * exactly as eager launches would.  on = 0 launches every kernel directly.
+ * Synchronises.  Errors: LAT_EINVAL (on with the null stream), LAT_EHIP. */
+int surrogate_use_graph(surrogate_t* h, int on);
+
 /* Forward pass for n query rows dev_x (FP32 [n][2]) into dev_y (FP32
  * [n][64], denormalised log10 spectra), all layers fused in one kernel.
  * Asynchronous on the stream.  Errors: LAT_EINVAL, LAT_EHIP. */

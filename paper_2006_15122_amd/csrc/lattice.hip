@@ -61,10 +61,13 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, 
   const size_t elem = p->precision == LAT_FP32 ? 4 : 8;
   const int nc = ncomponents(p);
   const int64_t mb = (N / 32) * (N / 8) * (N / 4);
-  const int nacc = 32;
+  // per-block FP64 partials: scalar passes write at most 32 per tile of at
+  // least 32 x 8 x 4 sites; the U(1) site kernels write up to 16 per block of
+  // 256 sites
+  const size_t part_doubles = std::max((size_t)mb * 32, (size_t)(V / 256) * 16);
   size_t o = align_up(sizeof(DevState), 256);
   *off_part = o;
-  o = align_up(o + (size_t)mb * nacc * sizeof(double), 256);
+  o = align_up(o + part_doubles * sizeof(double), 256);
   *off_spec = o;
   o = align_up(o + (size_t)(kSpecBlocks + 2) * spec_bins((int)N) * 24, 256);
   *off_buf0 = o;
@@ -139,12 +142,15 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   L->staggered = 0;
   L->step = 0;
   default_tiling(L);
-  rc = init_state(L);
-  if (rc) { delete L; return rc; }
+  // Tune first, on zeroed buffers, so that the timed passes can ping-pong
+  // between the two state copies exactly as lattice_step does; the initial
+  // state is built afterwards.
   if (p->model == LAT_MODEL_SCALAR && p->N >= 128) {
     rc = autotune(L);
     if (rc) { delete L; return rc; }
   }
+  rc = init_state(L);
+  if (rc) { delete L; return rc; }
   *out = L;
   return LAT_OK;
 }
@@ -514,42 +520,50 @@ void default_tiling(lattice* h) {
 // fastest.  The state itself is not modified (the written buffer is the
 // ping-pong scratch).
 int autotune(lattice* h) {
+  // zero state (finite arithmetic), a = 1, b = 0; the caller builds the real
+  // state after tuning
+  for (int c = 0; c < h->ncomp; ++c) {
+    CL_HIP(hipMemsetAsync(h->buf[0][c], 0, h->comp_bytes, h->stream));
+    CL_HIP(hipMemsetAsync(h->buf[1][c], 0, h->comp_bytes, h->stream));
+  }
+  int rc = upload_scalars(h, 1.0, 0.0, 0.0);
+  if (rc) return rc;
   hipEvent_t e0, e1;
   CL_HIP(hipEventCreate(&e0));
   CL_HIP(hipEventCreate(&e1));
   const int xcs[] = {8, 16, 32, 64};
   float best = 1e30f;
   Tiling bt = h->tile;
-  const int saved_cur = h->cur;
   const int fp32 = h->p.precision == LAT_FP32;
-  for (int i = 0; i < num_shapes(fp32, h->p.nf); ++i) {
+  const PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
+  for (int i = 0; i < num_shapes(fp32, h->p.nf) && !rc; ++i) {
     int tz, by, ry;
     get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
     for (int xc : xcs) {
       Tiling t{tz, by, ry, xc};
       if (!tiling_ok(h, t)) continue;
       h->tile = t;
-      PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
-      int rc = scalar_pass(h, pd);  // warm-up
-      h->cur = saved_cur;
-      if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
-      CL_HIP(hipEventRecord(e0, h->stream));
-      for (int k = 0; k < 3; ++k) {
-        rc = scalar_pass(h, pd);
-        h->cur = saved_cur;
-        if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
-      }
-      CL_HIP(hipEventRecord(e1, h->stream));
-      CL_HIP(hipEventSynchronize(e1));
+      for (int k = 0; k < 2 && !rc; ++k) rc = scalar_pass(h, pd);  // warm-up, ping-pong
+      if (rc) break;
+      hipError_t e = hipEventRecord(e0, h->stream);
+      for (int k = 0; k < 4 && !rc && e == hipSuccess; ++k) rc = scalar_pass(h, pd);
+      if (!rc && e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
-      CL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error(std::string("autotune timing: ") + hipGetErrorString(e));
+        rc = LAT_EHIP;
+        break;
+      }
       if (ms < best) { best = ms; bt = t; }
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  h->cur = 0;
   h->tile = bt;
-  return LAT_OK;
+  return rc;
 }
 
 }  // namespace cl

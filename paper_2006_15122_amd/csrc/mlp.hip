@@ -326,6 +326,13 @@ __global__ __launch_bounds__(256) void copies_kernel(const float* __restrict__ P
   if (p < NPAR) store_copies(p, P[p], c);
 }
 
+// Training control on the device, so that a captured epoch can be replayed:
+// the learning rate of the epoch and the number of Adam steps taken before it.
+struct TrainCtl {
+  double t0;
+  double lr;
+};
+
 struct FinishArgs {
   const float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
   const double* lpart;
@@ -333,11 +340,21 @@ struct FinishArgs {
   double inv_count;    // 1 / (nvalid * 64)
   double* loss;        // one FP64
   float* G;            // gradient out [NPAR]
-  // Adam
+  // Adam: step t = ctl->t0 + step + 1, bias corrections 1 - beta^t
   float *P, *Mo, *Ve;
-  float lr, beta1, beta2, eps, bc1, bc2;
+  const TrainCtl* ctl;
+  int step;
+  double beta1, beta2;
+  float eps;
   WCopies c;
 };
+
+__global__ void ctl_set_lr(TrainCtl* c, double lr) {
+  if (threadIdx.x == 0) c->lr = lr;
+}
+__global__ void ctl_advance(TrainCtl* c, int nsteps) {
+  if (threadIdx.x == 0) c->t0 += (double)nsteps;
+}
 
 template <bool UPDATE>
 __global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
@@ -369,11 +386,14 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
   }
   f.G[p] = g;
   if constexpr (UPDATE) {
-    const float m = f.beta1 * f.Mo[p] + (1.0f - f.beta1) * g;
-    const float v = f.beta2 * f.Ve[p] + (1.0f - f.beta2) * g * g;
+    const double t = f.ctl->t0 + (double)(f.step + 1);
+    const float bc1 = (float)(1.0 - pow(f.beta1, t)), bc2 = (float)(1.0 - pow(f.beta2, t));
+    const float lr = (float)f.ctl->lr, b1 = (float)f.beta1, b2 = (float)f.beta2;
+    const float m = b1 * f.Mo[p] + (1.0f - b1) * g;
+    const float v = b2 * f.Ve[p] + (1.0f - b2) * g * g;
     f.Mo[p] = m;
     f.Ve[p] = v;
-    const float w = f.P[p] - f.lr * (m / f.bc1) / (sqrtf(v / f.bc2) + f.eps);
+    const float w = f.P[p] - lr * (m / bc1) / (sqrtf(v / bc2) + f.eps);
     f.P[p] = w;
     store_copies(p, w, f.c);
   }
@@ -518,8 +538,14 @@ struct surrogate_t {
   bf16_t *H1, *H2, *H3, *H1t, *H2t, *H3t, *DYb, *DYt, *D3b, *D3t, *D2b, *D2t;
   float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
   double *lpart, *losses, *stats;
+  TrainCtl* ctl;
   int64_t t;   // Adam steps taken
   bool loaded;
+  // captured epoch, replayed while its inputs are the same buffers and sizes
+  bool use_graph;
+  hipGraphExec_t graph;
+  const void* gkey[3];
+  int64_t gn;
 };
 
 namespace {
@@ -567,6 +593,7 @@ size_t carve(int B, char* base, surrogate_t* s) {
   h.lpart = (double*)take(8ull * R);
   h.losses = (double*)take(8ull * MAX_STEPS);
   h.stats = (double*)take(8ull * 2 * NOUT);
+  h.ctl = (TrainCtl*)take(sizeof(TrainCtl));
   return off + 256;
 }
 
@@ -605,10 +632,17 @@ int launch_gemm(const GemmArgs& g, hipStream_t st) {
   return LAT_OK;
 }
 
+void drop_graph(surrogate_t* h) {
+  if (h->graph) hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->gkey[0] = h->gkey[1] = h->gkey[2] = nullptr;
+  h->gn = 0;
+}
+
 // forward + backward of n rows (rows[] may be NULL) into G, loss into *loss_dev;
 // with update, one Adam step on the master weights and their BF16 copies
 int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* rows, int n, float* G,
-               double* loss_dev, bool update, double lr) {
+               double* loss_dev, bool update, int step) {
   hipStream_t st = h->stream;
   const int Bp = (n + 63) / 64 * 64, R = Bp / 64, S = (Bp + KSPLIT - 1) / KSPLIT, ldt = h->B;
   const WCopies& c = h->wc;
@@ -687,13 +721,11 @@ int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* ro
   f.c = c;
   const int fb = (NPAR + 255) / 256;
   if (update) {
-    h->t += 1;
-    f.lr = (float)lr;
-    f.beta1 = (float)h->p.beta1;
-    f.beta2 = (float)h->p.beta2;
+    f.ctl = h->ctl;
+    f.step = step;
+    f.beta1 = h->p.beta1;
+    f.beta2 = h->p.beta2;
     f.eps = (float)h->p.eps;
-    f.bc1 = (float)(1.0 - std::pow(h->p.beta1, (double)h->t));
-    f.bc2 = (float)(1.0 - std::pow(h->p.beta2, (double)h->t));
     hipLaunchKernelGGL(finish_kernel<true>, dim3(fb), dim3(256), 0, st, f);
   } else {
     hipLaunchKernelGGL(finish_kernel<false>, dim3(fb), dim3(256), 0, st, f);
@@ -724,6 +756,7 @@ extern "C" int surrogate_init(const surrogate_params* p, void* dev_ws, size_t ws
   h->p = *p;
   h->stream = (hipStream_t)hip_stream;
   h->B = p->max_batch;
+  h->use_graph = hip_stream != nullptr;
   char* base = (char*)(((uintptr_t)dev_ws + 255) & ~(uintptr_t)255);
   carve(h->B, base, h);
   Norm nm;
@@ -749,6 +782,7 @@ extern "C" int surrogate_set_weights(surrogate_t* h, const float* host_w) {
   CL_HIP(hipMemcpyAsync(h->P, host_w, 4ull * NPAR, hipMemcpyHostToDevice, h->stream));
   CL_HIP(hipMemsetAsync(h->Mo, 0, 4ull * NPAR, h->stream));
   CL_HIP(hipMemsetAsync(h->Ve, 0, 4ull * NPAR, h->stream));
+  CL_HIP(hipMemsetAsync(h->ctl, 0, sizeof(TrainCtl), h->stream));
   hipLaunchKernelGGL(copies_kernel, dim3((NPAR + 255) / 256), dim3(256), 0, h->stream, h->P, h->wc);
   CL_HIP(hipGetLastError());
   CL_HIP(hipStreamSynchronize(h->stream));
@@ -790,7 +824,7 @@ extern "C" int surrogate_loss_grad(surrogate_t* h, const float* dev_x, const flo
   if (!h || !dev_x || !dev_t || !dev_grad || !loss) { set_error("NULL argument"); return LAT_EINVAL; }
   if (!h->loaded) { set_error("weights not set"); return LAT_ESTATE; }
   if (n < 1 || n > h->B) { set_error("n must be in [1, max_batch]"); return LAT_EINVAL; }
-  int rc = train_step(h, dev_x, dev_t, rows, n, dev_grad, h->losses, false, 0.0);
+  int rc = train_step(h, dev_x, dev_t, rows, n, dev_grad, h->losses, false, 0);
   if (rc) return rc;
   CL_HIP(hipMemcpyAsync(loss, h->losses, 8, hipMemcpyDeviceToHost, h->stream));
   CL_HIP(hipStreamSynchronize(h->stream));
@@ -806,11 +840,49 @@ extern "C" int surrogate_train_epoch(surrogate_t* h, const float* dev_x, const f
   if (!(lr > 0.0) || !std::isfinite(lr)) { set_error("lr must be positive"); return LAT_EINVAL; }
   const int64_t steps = (n + h->B - 1) / h->B;
   if (steps > MAX_STEPS) { set_error("too many steps in one epoch (max 65536)"); return LAT_EINVAL; }
-  for (int64_t s = 0; s < steps; ++s) {
-    const int ns = (int)std::min<int64_t>(h->B, n - s * h->B);
-    int rc = train_step(h, dev_x, dev_t, dev_perm + s * h->B, ns, h->G, h->losses + s, true, lr);
+  hipLaunchKernelGGL(ctl_set_lr, dim3(1), dim3(64), 0, h->stream, h->ctl, lr);
+  CL_HIP(hipGetLastError());
+  auto record = [&]() -> int {
+    for (int64_t s = 0; s < steps; ++s) {
+      const int ns = (int)std::min<int64_t>(h->B, n - s * h->B);
+      int rc = train_step(h, dev_x, dev_t, dev_perm + s * h->B, ns, h->G, h->losses + s, true, (int)s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(ctl_advance, dim3(1), dim3(64), 0, h->stream, h->ctl, (int)steps);
+    CL_HIP(hipGetLastError());
+    return LAT_OK;
+  };
+  const bool same = h->graph && h->gkey[0] == dev_x && h->gkey[1] == dev_t && h->gkey[2] == dev_perm && h->gn == n;
+  if (h->use_graph && !same) {
+    drop_graph(h);
+    CL_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = record();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    CL_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      h->graph = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+      return LAT_EHIP;
+    }
+    h->gkey[0] = dev_x;
+    h->gkey[1] = dev_t;
+    h->gkey[2] = dev_perm;
+    h->gn = n;
+  }
+  if (h->use_graph) {
+    CL_HIP(hipGraphLaunch(h->graph, h->stream));
+  } else {
+    const int rc = record();
     if (rc) return rc;
   }
+  h->t += steps;
   std::vector<double> l((size_t)steps);
   CL_HIP(hipMemcpyAsync(l.data(), h->losses, 8 * steps, hipMemcpyDeviceToHost, h->stream));
   CL_HIP(hipStreamSynchronize(h->stream));
@@ -833,9 +905,19 @@ extern "C" int surrogate_predict(surrogate_t* h, const float* dev_x, int64_t n, 
   return LAT_OK;
 }
 
+extern "C" int surrogate_use_graph(surrogate_t* h, int on) {
+  if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  if (on && !h->stream) { set_error("graph capture needs a created (non-default) stream"); return LAT_EINVAL; }
+  CL_HIP(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  h->use_graph = on != 0;
+  return LAT_OK;
+}
+
 extern "C" int surrogate_destroy(surrogate_t* h) {
   if (!h) return LAT_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
+  drop_graph(h);
   delete h;
   if (e != hipSuccess) { set_error(std::string("surrogate_destroy: ") + hipGetErrorString(e)); return LAT_EHIP; }
   return LAT_OK;

@@ -2,7 +2,8 @@
 
 The network's forward, backward, loss, Adam and inference all run in the HIP
 library libcosmolat.so; this module packs weights, allocates the device
-workspace with torch and passes pointers and torch's HIP stream.
+workspace with torch and passes pointers and a HIP stream it creates with
+torch (ordered against torch's current stream on entry and exit).
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ SHAPES = (("W1", (WIDTH, N_IN)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2"
 
 EXPORTS = ["surrogate_workspace_size", "surrogate_init", "surrogate_set_weights", "surrogate_get_weights",
            "surrogate_loss_grad", "surrogate_train_epoch", "surrogate_predict", "surrogate_fit_output_scale",
-           "surrogate_destroy"]
+           "surrogate_use_graph", "surrogate_destroy"]
 
 
 class SurrParams(ctypes.Structure):
@@ -86,12 +87,26 @@ class Surrogate:
         self.device = torch.device(device)
         nbytes = workspace_size(self.p)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a created stream (default priority), so that training epochs can be
+        # captured and replayed as HIP graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         torch.cuda.synchronize(self.device)
         self.h = ctypes.c_void_p()
         _check(lib().surrogate_init(ctypes.byref(self.p), ctypes.c_void_p(self.ws.data_ptr()),
                                     ctypes.c_size_t(nbytes + 256), ctypes.c_void_p(self.stream.cuda_stream),
                                     ctypes.byref(self.h)))
+
+    def _enter(self):
+        """Order the library's stream after work already queued by torch."""
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def use_graph(self, on: bool):
+        _check(lib().surrogate_use_graph(self.h, 1 if on else 0))
 
     @property
     def max_batch(self) -> int:
@@ -115,6 +130,7 @@ class Surrogate:
         _dev(t, torch.float32, "t")
         sh = np.zeros(N_OUT)
         sc = np.zeros(N_OUT)
+        self._enter()
         _check(lib().surrogate_fit_output_scale(self.h, _ptr(t), ctypes.c_int64(t.shape[0]),
                                                 sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                                 sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
@@ -131,6 +147,7 @@ class Surrogate:
             _dev(rows, torch.int32, "rows")
         g = torch.empty(NPARAMS, dtype=torch.float32, device=self.device)
         loss = ctypes.c_double()
+        self._enter()
         _check(lib().surrogate_loss_grad(self.h, _ptr(x), _ptr(t), _ptr(rows), ctypes.c_int32(n), _ptr(g),
                                          ctypes.byref(loss)))
         return loss.value, g
@@ -141,6 +158,7 @@ class Surrogate:
         _dev(t, torch.float32, "t")
         _dev(perm, torch.int32, "perm")
         m = ctypes.c_double()
+        self._enter()
         _check(lib().surrogate_train_epoch(self.h, _ptr(x), _ptr(t), _ptr(perm), ctypes.c_int64(perm.numel()),
                                            ctypes.c_double(lr), ctypes.byref(m)))
         return m.value
@@ -151,7 +169,9 @@ class Surrogate:
         if out is None:
             out = torch.empty((x.shape[0], N_OUT), dtype=torch.float32, device=self.device)
         _dev(out, torch.float32, "out")
+        self._enter()
         _check(lib().surrogate_predict(self.h, _ptr(x), ctypes.c_int64(x.shape[0]), _ptr(out)))
+        self._leave()
         return out
 
     def close(self):

@@ -104,7 +104,7 @@ def test_library_exports_every_surrogate_symbol():
     from paper_2006_15122_amd import surrogate
     L = lattice.lib()
     names = _declared_surrogate()
-    assert len(names) == 9
+    assert len(names) == 10
     for n in names:
         assert hasattr(L, n), n
     assert sorted(surrogate.EXPORTS) == names
@@ -149,3 +149,12 @@ def test_unpack_inverts_pack():
     q = surrogate.unpack(surrogate.pack(p))
     for k in p:
         assert np.array_equal(q[k], p[k].astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("N", [32, 192, 512, 1024])
+def test_u1_workspace_holds_state_fft_and_site_kernel_partials(N):
+    # two copies of 10 FP32 components, complex FP64 FFT scratch, and 11 FP64
+    # partials per 256-site block of the U(1) site kernels
+    c = dict(synth.config3(N=N), dt=0.004)   # within the Courant bound at N = 1024
+    need = 2 * 10 * 4 * N ** 3 + 16 * N ** 3 + (N ** 3 // 256) * 11 * 8
+    assert lattice.workspace_size(c) >= need

@@ -202,3 +202,24 @@ def test_emulator_routes_outside_domain_to_the_lattice():
         B.synchronize()
         assert np.array_equal(vals[i], out.cpu().numpy()), i
         B.close()
+
+
+def test_graph_replayed_epochs_match_eager_epochs():
+    torch = _torch()
+    osh, osc = _out_norm(30)
+    x, t = _inputs(31, 0, nrows=1000)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    perm = torch.empty(1000, dtype=torch.int32, device="cuda:0")
+    graph, eager = _model(256, osh, osc), _model(256, osh, osc)
+    eager.use_graph(False)
+    for m in (graph, eager):
+        m.set_weights(_weights(32))
+    rng = np.random.default_rng(33)
+    for ep in range(4):   # captured on the first epoch, replayed on the next three
+        perm.copy_(torch.from_numpy(rng.permutation(1000).astype(np.int32)))
+        lr = 1e-3 * (ep + 1)
+        lg = graph.train_epoch(xd, td, perm, lr)
+        assert float((xd * 2.0).sum().item()) != 0.0   # unrelated eager work between replays
+        le = eager.train_epoch(xd, td, perm, lr)
+        assert lg == le, ep
+        assert np.array_equal(graph.get_weights(), eager.get_weights()), ep
