@@ -55,6 +55,8 @@ struct U1Args {
 };
 
 constexpr int kU1Acc = 11;
+// the workspace reserves 16 FP64 partials per 256-site block
+static_assert(kU1Acc <= 16, "U(1) partials exceed the reserved region");
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -346,6 +348,281 @@ __global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* par
   st->obs.gauss = den > 0.0 ? sqrt(S[0]) / den : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Fused stepping pass: the drift that closes step n-1 followed by the kick of
+// step n, in one sweep over the lattice (source buffer -> destination buffer).
+//
+// A block owns a TY x TZ tile of the (y, z) plane and marches along x over XC
+// planes.  Each plane enters LDS already drifted (phi and the link phases,
+// with a one-site ring including corners, the ring drifted redundantly); two
+// planes are held, x and x+1.  Per plane the block first computes the
+// plaquette sines S_01, S_02, S_12 of its sites and of the y-1 row and z-1
+// column, shared through LDS, so that every plaquette sine is evaluated once
+// instead of once per use.  Values of plane x-1 that the kick needs (phi,
+// theta_0, S_01, S_02 of the own column) stay in registers.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct U1PassArgs {
+  const T* src[10];
+  T* dst[10];
+  int N, XC, swizzle;
+  double dx, alpha, lam, m2, e, wf2, h;
+  int expand;
+  int drift;  // 0: no pending drift (first pass of a call)
+  double* partials;
+  DevState* st;
+};
+
+template <typename T>
+__device__ __forceinline__ T wrap_phase(T t) {
+  const T twopi = (T)6.283185307179586476925286766559;
+  return t - twopi * rint(t / twopi);
+}
+
+template <typename T, int TZ, int BY, int RY>
+__global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
+  constexpr int TY = BY * RY, NT = TZ * BY, LY = TY + 2, LZ = TZ + 2;
+  constexpr int NH = 2 * LZ + 2 * TY;  // ring of the (TY+2) x (TZ+2) plane tile
+  static_assert(NH <= NT, "ring larger than block");
+  static_assert(TZ + TY <= NT, "low ring larger than block");
+  static_assert(NT == 256, "partials assume four waves");
+  __shared__ T Lp[2][2][LY][LZ];       // drifted phi (Re, Im), planes in flight
+  __shared__ T Lt[2][3][LY][LZ];       // drifted link phases
+  __shared__ T Ls[3][TY + 1][TZ + 1];  // S_01, S_02, S_12; index 0 = row y0-1 / column z0-1
+
+  const int N = A.N;
+  const int NN = N * N;
+  const int tid = threadIdx.x, tz = tid % TZ, ty = tid / TZ;
+  int bid = blockIdx.x;
+  if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const int nzt = N / TZ, nyt = N / TY;
+  const int z0 = (bid % nzt) * TZ;
+  const int y0 = ((bid / nzt) % nyt) * TY;
+  const int x0 = (bid / (nzt * nyt)) * A.XC;
+
+  // homogeneous coefficients (FP64, the same in every block)
+  const double a_in = A.st->a;
+  const double amid = A.expand ? A.st->aux[0] : a_in;
+  const bool dr = A.drift != 0;
+  const T cd = dr ? (T)(A.h * pow(amid, -(3.0 - A.alpha))) : T(0);
+  const T cu = dr ? (T)(A.e * A.h * A.dx / (2.0 * pow(amid, 1.0 - A.alpha))) : T(0);
+  const T cl = (T)(pow(a_in, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cp = (T)pow(a_in, 3.0 + A.alpha);
+  const T cj = (T)(pow(a_in, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+  const T cb = (T)(pow(a_in, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+  const T ck = (T)A.h;
+  const T lam = (T)A.lam, m2 = (T)A.m2;
+
+  // ring site owned by this thread (one at most)
+  const bool has_ring = tid < NH;
+  int rly = 0, rlz = 0;
+  if (tid < LZ) { rly = 0; rlz = tid; }
+  else if (tid < 2 * LZ) { rly = TY + 1; rlz = tid - LZ; }
+  else if (tid < 2 * LZ + TY) { rly = 1 + tid - 2 * LZ; rlz = 0; }
+  else { rly = 1 + tid - 2 * LZ - TY; rlz = TZ + 1; }
+  const int ry_g = (y0 - 1 + rly + N) % N, rz_g = (z0 - 1 + rlz + N) % N;
+  // low-ring site whose plaquette sines this thread computes (row y0-1 or column z0-1)
+  const bool has_low = tid < TZ + TY;
+  const int sly = tid < TZ ? 0 : 1 + tid - TZ;
+  const int slz = tid < TZ ? 1 + tid : 0;
+
+  auto site = [&](int x, int y, int z) -> int { return x * NN + y * N + z; };
+
+  // raw values: own column (RY rows) and the ring site of plane x
+  T raw[10][RY], rraw[10];
+  auto load_plane = [&](int x) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int o = site(x, y0 + r * BY + ty, z0 + tz);
+#pragma unroll
+      for (int c = 0; c < 10; ++c) raw[c][r] = A.src[c][o];
+    }
+    if (has_ring) {
+      const int o = site(x, ry_g, rz_g);
+#pragma unroll
+      for (int c = 0; c < 10; ++c) rraw[c] = A.src[c][o];
+    }
+  };
+  // drift the raw values into LDS buffer b
+  auto drift_into = [&](int b) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 1 + r * BY + ty, lz = 1 + tz;
+      Lp[b][0][ly][lz] = raw[0][r] + cd * raw[2][r];
+      Lp[b][1][ly][lz] = raw[1][r] + cd * raw[3][r];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        Lt[b][i][ly][lz] = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+    }
+    if (has_ring) {
+      Lp[b][0][rly][rlz] = rraw[0] + cd * rraw[2];
+      Lp[b][1][rly][rlz] = rraw[1] + cd * rraw[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        Lt[b][i][rly][rlz] = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+    }
+  };
+  // plaquette phases of site (ly, lz) of plane buffer c, plane x+1 in buffer n:
+  //   Phi_ij(m) = th_i(m) + th_j(m+i) - th_i(m+j) - th_j(m)
+  auto plaq = [&](int c, int n, int ly, int lz, T (&ph)[3]) {
+    const T t0 = Lt[c][0][ly][lz], t1 = Lt[c][1][ly][lz], t2 = Lt[c][2][ly][lz];
+    ph[0] = (t0 + Lt[n][1][ly][lz]) - (Lt[c][0][ly + 1][lz] + t1);
+    ph[1] = (t0 + Lt[n][2][ly][lz]) - (Lt[c][0][ly][lz + 1] + t2);
+    ph[2] = (t1 + Lt[c][2][ly + 1][lz]) - (Lt[c][1][ly][lz + 1] + t2);
+  };
+
+  double acc[kU1Acc];
+#pragma unroll
+  for (int k = 0; k < kU1Acc; ++k) acc[k] = 0.0;
+
+  // registers: plane x-1 (own column) and raw momenta of planes x, x+1
+  T pm[2][RY], tm[RY], s01m[RY], s02m[RY];
+  T qc[5][RY], qn[5][RY];
+
+  // prologue: plane x0-1 -> buffer 1, plane x0 -> buffer 0; S_01, S_02 of
+  // plane x0-1; then plane x0+1 -> buffer 1
+  load_plane((x0 - 1 + N) % N);
+  drift_into(1);
+  load_plane(x0);
+  drift_into(0);
+#pragma unroll
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qc[c][r] = raw[c < 2 ? 2 + c : 5 + c][r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int ly = 1 + r * BY + ty, lz = 1 + tz;
+    T ph[3];
+    plaq(1, 0, ly, lz, ph);
+    T sn, cs;
+    sincos_t(T(0.5) * ph[0], &sn, &cs);
+    s01m[r] = T(2) * sn * cs;
+    sincos_t(T(0.5) * ph[1], &sn, &cs);
+    s02m[r] = T(2) * sn * cs;
+    pm[0][r] = Lp[1][0][ly][lz];
+    pm[1][r] = Lp[1][1][ly][lz];
+    tm[r] = Lt[1][0][ly][lz];
+  }
+  __syncthreads();
+  load_plane((x0 + 1) % N);
+  drift_into(1);
+#pragma unroll
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qn[c][r] = raw[c < 2 ? 2 + c : 5 + c][r];
+
+  for (int i = 0; i < A.XC; ++i) {
+    const int x = x0 + i;
+    const int cb_ = i & 1, nb_ = cb_ ^ 1;
+    if (i + 1 < A.XC) load_plane((x + 2) % N);  // in flight during the compute below
+    __syncthreads();
+    // plaquette sines of the own sites and the low ring of plane x
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 1 + r * BY + ty, lz = 1 + tz;
+      T ph[3];
+      plaq(cb_, nb_, ly, lz, ph);
+      double mg = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T sn, cs;
+        sincos_t(T(0.5) * ph[k], &sn, &cs);
+        Ls[k][ly][lz] = T(2) * sn * cs;
+        mg += (double)(T(2) * sn * sn);
+      }
+      acc[7] += mg;
+    }
+    if (has_low) {
+      T ph[3];
+      plaq(cb_, nb_, sly, slz, ph);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T sn, cs;
+        sincos_t(T(0.5) * ph[k], &sn, &cs);
+        Ls[k][sly][slz] = T(2) * sn * cs;
+      }
+    }
+    __syncthreads();
+    // kick of the own sites of plane x
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 1 + r * BY + ty, lz = 1 + tz;
+      const int o = site(x, y0 + r * BY + ty, z0 + tz);
+      const C2<T> p{Lp[cb_][0][ly][lz], Lp[cb_][1][ly][lz]};
+      const C2<T> fw[3] = {C2<T>{Lp[nb_][0][ly][lz], Lp[nb_][1][ly][lz]},
+                           C2<T>{Lp[cb_][0][ly + 1][lz], Lp[cb_][1][ly + 1][lz]},
+                           C2<T>{Lp[cb_][0][ly][lz + 1], Lp[cb_][1][ly][lz + 1]}};
+      const C2<T> bw[3] = {C2<T>{pm[0][r], pm[1][r]}, C2<T>{Lp[cb_][0][ly - 1][lz], Lp[cb_][1][ly - 1][lz]},
+                           C2<T>{Lp[cb_][0][ly][lz - 1], Lp[cb_][1][ly][lz - 1]}};
+      const T th[3] = {Lt[cb_][0][ly][lz], Lt[cb_][1][ly][lz], Lt[cb_][2][ly][lz]};
+      const T thb[3] = {tm[r], Lt[cb_][1][ly - 1][lz], Lt[cb_][2][ly][lz - 1]};
+      C2<T> lap{T(-6) * p.x, T(-6) * p.y};
+      double grad = 0.0;
+      T Kcur[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T sn, cs, snb, csb;
+        sincos_t(th[k], &sn, &cs);
+        sincos_t(thb[k], &snb, &csb);
+        const C2<T> f = cm(C2<T>{cs, sn}, fw[k]);
+        const C2<T> b = cm(cc(C2<T>{csb, snb}), bw[k]);
+        lap.x += f.x + b.x;
+        lap.y += f.y + b.y;
+        const T gx = f.x - p.x, gy = f.y - p.y;
+        grad += (double)(gx * gx + gy * gy);
+        Kcur[k] = cj * (p.x * f.y - p.y * f.x);
+      }
+      const T r2 = p.x * p.x + p.y * p.y;
+      const T dv = T(2) * lam * r2 + m2;
+      const C2<T> Kp{cl * lap.x - cp * dv * p.x, cl * lap.y - cp * dv * p.y};
+      const T S01 = Ls[0][ly][lz], S02 = Ls[1][ly][lz], S12 = Ls[2][ly][lz];
+      const T curl[3] = {(S01 - Ls[0][ly - 1][lz]) + (S02 - Ls[1][ly][lz - 1]),
+                         (-S01 + s01m[r]) + (S12 - Ls[2][ly][lz - 1]),
+                         (-S02 + s02m[r]) + (-S12 + Ls[2][ly - 1][lz])};
+      const C2<T> pin{qc[0][r], qc[1][r]};
+      const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
+      acc[0] += (double)(pin.x * pin.x + pin.y * pin.y);
+      acc[1] += (double)(pout.x * pout.x + pout.y * pout.y);
+      acc[2] += grad;
+      acc[3] += (double)(lam * r2 * r2);
+      acc[4] += (double)(m2 * r2);
+      acc[8] += (double)p.x;
+      acc[9] += (double)p.y;
+      acc[10] += (double)r2;
+      __builtin_nontemporal_store(p.x, &A.dst[0][o]);
+      __builtin_nontemporal_store(p.y, &A.dst[1][o]);
+      __builtin_nontemporal_store(pout.x, &A.dst[2][o]);
+      __builtin_nontemporal_store(pout.y, &A.dst[3][o]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T ain = qc[2 + k][r];
+        const T aout = ain + ck * (Kcur[k] + cb * curl[k]);
+        acc[5] += (double)(ain * ain);
+        acc[6] += (double)(aout * aout);
+        __builtin_nontemporal_store(th[k], &A.dst[4 + k][o]);
+        __builtin_nontemporal_store(aout, &A.dst[7 + k][o]);
+      }
+      // plane x becomes plane x-1 of the next step
+      pm[0][r] = p.x;
+      pm[1][r] = p.y;
+      tm[r] = th[0];
+      s01m[r] = S01;
+      s02m[r] = S02;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        qc[c][r] = qn[c][r];
+        qn[c][r] = raw[c < 2 ? 2 + c : 5 + c][r];
+      }
+    __syncthreads();
+    if (i + 1 < A.XC) drift_into(cb_);  // plane x+2 replaces plane x
+  }
+  u1_block_partials<kU1Acc>(acc, A.partials);
+}
+
 template <typename T>
 static void fill_args(lattice* h, U1Args<T>& A) {
   for (int c = 0; c < 10; ++c) A.c[c] = static_cast<T*>(h->buf[h->cur][c]);
@@ -403,6 +680,60 @@ static int u1_gauss_t(lattice* h) {
   return LAT_OK;
 }
 
+// One fused pass (pending drift, then the kick of the next step) from the
+// current buffer into the other one, followed by the FP64 finish that
+// advances a and b.
+template <typename T, int TZ, int BY, int RY>
+static int u1_pass_t(lattice* h) {
+  U1PassArgs<T> A;
+  for (int c = 0; c < 10; ++c) {
+    A.src[c] = static_cast<const T*>(h->buf[h->cur][c]);
+    A.dst[c] = static_cast<T*>(h->buf[1 - h->cur][c]);
+  }
+  const int N = h->p.N;
+  constexpr int TY = BY * RY;
+  const int tiles = (N / TZ) * (N / TY);
+  int xc = 4;
+  for (int c : {16, 8}) {
+    if (N % c == 0 && (int64_t)tiles * (N / c) >= 1024) { xc = c; break; }
+  }
+  A.N = N;
+  A.XC = xc;
+  const int nb = tiles * (N / xc);
+  A.swizzle = (nb % 8 == 0) ? 1 : 0;
+  A.dx = h->dx;
+  A.alpha = h->p.alpha;
+  A.lam = h->p.lambda;
+  A.m2 = h->p.m2[0];
+  A.e = h->p.e;
+  A.wf2 = h->p.omega_over_f * h->p.omega_over_f;
+  A.h = h->p.dt;
+  A.expand = h->p.expansion;
+  A.drift = 1;
+  A.partials = h->partials;
+  A.st = h->st;
+  hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
+  CL_HIP(hipGetLastError());
+  h->cur ^= 1;
+  U1Args<T> F;
+  fill_args(h, F);
+  F.ck = 1.0;
+  F.mode = MODE_LF;
+  F.write = 1;
+  F.advance = 1;
+  hipLaunchKernelGGL(u1_finish_kernel<T>, dim3(1), dim3(1024), 0, h->stream, F, nb);
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+static int u1_pass(lattice* h) {
+  if (h->p.precision == LAT_FP32) {
+    if (h->p.N % 64 == 0) return u1_pass_t<float, 64, 4, 2>(h);
+    return u1_pass_t<float, 32, 8, 1>(h);
+  }
+  return u1_pass_t<double, 32, 8, 1>(h);
+}
+
 static int u1_kick(lattice* h, double ck, int mode, int write, int advance) {
   return h->p.precision == LAT_FP32 ? u1_kick_t<float>(h, ck, mode, write, advance)
                                     : u1_kick_t<double>(h, ck, mode, write, advance);
@@ -420,12 +751,17 @@ int u1_step(lattice* h, int64_t n) {
     if (rc) return rc;
     h->staggered = 1;
   }
-  for (int64_t j = 0; j < n; ++j) {
-    rc = u1_kick(h, 1.0, MODE_LF, 1, 1);
-    if (rc) return rc;
-    rc = u1_drift(h);
+  if (n == 0) return LAT_OK;
+  // kick of the first step in place, then one fused pass per further step
+  // (drift of step j-1 and kick of step j), then the closing drift in place
+  rc = u1_kick(h, 1.0, MODE_LF, 1, 1);
+  if (rc) return rc;
+  for (int64_t j = 1; j < n; ++j) {
+    rc = u1_pass(h);
     if (rc) return rc;
   }
+  rc = u1_drift(h);
+  if (rc) return rc;
   h->step += n;
   return LAT_OK;
 }

@@ -151,3 +151,30 @@ def test_u1_spectrum_matches_oracle():
         o = oracle.spectrum(arr, cfg["kIR"])
         assert np.array_equal(g["count"], o["count"])
         assert np.max(np.abs(g["S"] - o["S"])) < 1e-10 * np.max(o["S"])
+
+
+@pytest.mark.parametrize("N,precision,tol", [(32, "fp64", 1e-12), (64, "fp32", 1e-5), (96, "fp32", 1e-5)])
+def test_u1_fused_passes_match_single_steps(N, precision, tol):
+    # lattice_step(n) runs one fused drift+kick pass per step after the first;
+    # lattice_step(1) runs the separate kick and drift kernels.  In FP64 the two
+    # agree to round-off (the arithmetic is the same up to evaluating a
+    # plaquette sine as 2 sin(x/2) cos(x/2)); in FP32 two rounding paths drift
+    # apart by a few 1e-6 over 30 steps (measured 2.1e-6 at 96^3), inside the
+    # 1e-5 that bounds either FP32 path against the FP64 oracle.
+    cfg = _cfg(N, precision)
+    a, b = _lattice(cfg), _lattice(cfg)
+    a.step(30)
+    for _ in range(30):
+        b.step(1)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa["step"] == sb["step"] == 30
+    for key in ("phi", "pi", "piA"):
+        d = np.max(np.abs(sa[key] - sb[key])) / np.max(np.abs(sb[key]))
+        assert d < tol, (key, d)
+    ta = np.arctan2(sa["links"][:, 1], sa["links"][:, 0])
+    tb = np.arctan2(sb["links"][:, 1], sb["links"][:, 0])
+    dl = np.max(np.abs(np.angle(np.exp(1j * (ta - tb)))))
+    assert dl < tol * 10, dl
+    ea, eb = a.energies(), b.energies()
+    for k in ("a", "b", "EK", "EG", "EK_A", "EG_A"):
+        assert abs(ea[k] - eb[k]) <= 10 * tol * abs(eb[k]) + 1e-300, k
