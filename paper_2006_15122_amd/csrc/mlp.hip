@@ -75,17 +75,22 @@ struct Norm {
 };
 
 // ---------------------------------------------------------------------------
-// layer 1 (K = 2, plain FMA): one block per 64 batch rows, one thread per unit
+// layer 1 (K = 2, plain FMA): a block covers 32 batch rows x 64 units, each
+// thread one unit over 8 rows (one 16-byte store of the transposed copy)
 // ---------------------------------------------------------------------------
+constexpr int L1_ROWS = 32;
+
 __global__ __launch_bounds__(256) void l1_forward(const float* __restrict__ X, const int32_t* __restrict__ rows,
                                                   int n, const Norm* __restrict__ nm, const bf16_t* __restrict__ W1b,
                                                   const float* __restrict__ b1, float* __restrict__ xn,
                                                   float* __restrict__ A1, bf16_t* __restrict__ H1,
                                                   bf16_t* __restrict__ H1t, int ldt) {
-  __shared__ float xs[64][2];
+  __shared__ float xs[L1_ROWS][2];
   const int t = threadIdx.x;
-  const int r0 = blockIdx.x * 64;
-  if (t < 64) {
+  const int r0 = blockIdx.x * L1_ROWS;
+  const int j = blockIdx.y * 64 + (t & 63);
+  const int g = t >> 6;  // rows r0 + 8g .. r0 + 8g + 7
+  if (t < L1_ROWS) {
     const int i = r0 + t;
     float x0 = 0.0f, x1 = 0.0f;
     if (i < n) {
@@ -95,30 +100,30 @@ __global__ __launch_bounds__(256) void l1_forward(const float* __restrict__ X, c
     }
     xs[t][0] = x0;
     xs[t][1] = x1;
-    xn[2 * i] = x0;
-    xn[2 * i + 1] = x1;
+    if (blockIdx.y == 0) {
+      xn[2 * i] = x0;
+      xn[2 * i + 1] = x1;
+    }
   }
   __syncthreads();
-  const int j = t;
   const float w0 = from_bf16(W1b[2 * j]), w1 = from_bf16(W1b[2 * j + 1]), bj = b1[j];
-  bf16_t col[64];
-  for (int r = 0; r < 64; ++r) {
-    const float a = xs[r][0] * w0 + xs[r][1] * w1 + bj;
-    const bf16_t h = to_bf16(gelu(a));
-    A1[(size_t)(r0 + r) * WID + j] = a;
-    H1[(size_t)(r0 + r) * WID + j] = h;
-    col[r] = h;
-  }
-  uint4* dst = reinterpret_cast<uint4*>(H1t + (size_t)j * ldt + r0);
+  uint32_t packed[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    uint4 v;
-    v.x = col[8 * q] | ((uint32_t)col[8 * q + 1] << 16);
-    v.y = col[8 * q + 2] | ((uint32_t)col[8 * q + 3] << 16);
-    v.z = col[8 * q + 4] | ((uint32_t)col[8 * q + 5] << 16);
-    v.w = col[8 * q + 6] | ((uint32_t)col[8 * q + 7] << 16);
-    dst[q] = v;
+  for (int r = 0; r < 8; ++r) {
+    const int lr = 8 * g + r;
+    const float a = xs[lr][0] * w0 + xs[lr][1] * w1 + bj;
+    const bf16_t h = to_bf16(gelu(a));
+    A1[(size_t)(r0 + lr) * WID + j] = a;
+    H1[(size_t)(r0 + lr) * WID + j] = h;
+    if (r & 1) packed[r >> 1] |= (uint32_t)h << 16;
+    else packed[r >> 1] = h;
   }
+  uint4 v;
+  v.x = packed[0];
+  v.y = packed[1];
+  v.z = packed[2];
+  v.w = packed[3];
+  *reinterpret_cast<uint4*>(H1t + (size_t)j * ldt + r0 + 8 * g) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -181,22 +186,29 @@ __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g) {
   const bf16_t* pa1 = pa0 + (size_t)16 * g.lda;
   const bf16_t* pb0 = g.Bt + (size_t)(col0 + r16) * g.ldb + kq;
   const bf16_t* pb1 = pb0 + (size_t)16 * g.ldb;
-  // the k range of a block is a multiple of 64: two 32-deep products per trip
-  const int nk = (ke - kb) >> 6;
-  for (int s = 0; s < nk; ++s) {
-    const int k = kb + 64 * s;
-    const bf16x8 a0 = load8(pa0 + k), a1 = load8(pa1 + k);
-    const bf16x8 b0 = load8(pb0 + k), b1 = load8(pb1 + k);
-    const bf16x8 c0 = load8(pa0 + k + 32), c1 = load8(pa1 + k + 32);
-    const bf16x8 d0 = load8(pb0 + k + 32), d1 = load8(pb1 + k + 32);
-    acc[0][0] = mma(a0, b0, acc[0][0]);
-    acc[0][1] = mma(a0, b1, acc[0][1]);
-    acc[1][0] = mma(a1, b0, acc[1][0]);
-    acc[1][1] = mma(a1, b1, acc[1][1]);
-    acc[0][0] = mma(c0, d0, acc[0][0]);
-    acc[0][1] = mma(c0, d1, acc[0][1]);
-    acc[1][0] = mma(c1, d0, acc[1][0]);
-    acc[1][1] = mma(c1, d1, acc[1][1]);
+  // The k range of a block is a multiple of 64 and at most 256 (one split):
+  // all of its operand fragments are loaded first, so the block waits for
+  // memory once, then runs its products back to back.
+  const int nk = (ke - kb) >> 5;  // 32-deep products: 2, 4, 6 or 8
+  bf16x8 fa[8][2], fb[8][2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    if (s < nk) {
+      const int k = kb + 32 * s;
+      fa[s][0] = load8(pa0 + k);
+      fa[s][1] = load8(pa1 + k);
+      fb[s][0] = load8(pb0 + k);
+      fb[s][1] = load8(pb1 + k);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    if (s < nk) {
+      acc[0][0] = mma(fa[s][0], fb[s][0], acc[0][0]);
+      acc[0][1] = mma(fa[s][0], fb[s][1], acc[0][1]);
+      acc[1][0] = mma(fa[s][1], fb[s][0], acc[1][0]);
+      acc[1][1] = mma(fa[s][1], fb[s][1], acc[1][1]);
+    }
   }
 
   const int N = g.N;
@@ -622,7 +634,7 @@ int validate(const surrogate_params* p) {
 
 template <int EPI>
 int launch_gemm(const GemmArgs& g, hipStream_t st) {
-  if (g.M % 64 || g.N % 64 || g.K % 64 || g.ksplit % 64 || g.K <= 0 || g.ksplit <= 0) {
+  if (g.M % 64 || g.N % 64 || g.K % 64 || g.ksplit % 64 || g.K <= 0 || g.ksplit <= 0 || g.ksplit > 256) {
     set_error("internal: product shape not tileable");
     return LAT_EINVAL;
   }
@@ -646,8 +658,8 @@ int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* ro
   hipStream_t st = h->stream;
   const int Bp = (n + 63) / 64 * 64, R = Bp / 64, S = (Bp + KSPLIT - 1) / KSPLIT, ldt = h->B;
   const WCopies& c = h->wc;
-  hipLaunchKernelGGL(l1_forward, dim3(R), dim3(256), 0, st, X, rows, n, h->nm, c.W1b, h->P + OB1, h->xn, h->A1,
-                     h->H1, h->H1t, ldt);
+  hipLaunchKernelGGL(l1_forward, dim3(Bp / L1_ROWS, WID / 64), dim3(256), 0, st, X, rows, n, h->nm, c.W1b,
+                     h->P + OB1, h->xn, h->A1, h->H1, h->H1t, ldt);
   CL_HIP(hipGetLastError());
   int rc;
   GemmArgs g{};
