@@ -22,6 +22,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+# (tz, by, ry) shapes the library's autotuner times for FP32 two-field lattices
+TUNER_SHAPES = ((64, 4, 4), (64, 4, 2), (64, 8, 2), (64, 4, 8), (32, 8, 2), (32, 4, 4), (32, 8, 4))
 BYTES_PER_SITE_VV2_NF2_FP32 = 32  # read phi, chi, pi_phi, pi_chi; write the same (FP32)
 
 
@@ -34,15 +36,15 @@ def _kernel_hash() -> str:
 
 def _traffic(per_launch_sites: int, tile):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counts, if they were taken on the current kernel source and tile; else None."""
+    counts, if they were taken on the current kernel source for this tile;
+    else None."""
     p = os.path.join(ROOT, "profiles", "scalar_pass_256_vv2_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if (d.get("kernel_hash") != _kernel_hash() or d.get("sites") != per_launch_sites
-            or list(d.get("tile", [])) != list(tile)):
+    if d.get("kernel_hash") != _kernel_hash() or d.get("sites") != per_launch_sites:
         return None
-    return d.get("bytes_per_launch")
+    return d.get("bytes_per_launch", {}).get(",".join(str(v) for v in tile))
 
 
 def time_lattice(cfg: dict, steps: int, warmup: int, passes: int = 0, tile=None):
@@ -126,6 +128,41 @@ def time_batch(steps: int) -> dict:
             "steps_batched": steps, "steps_sequential": seq_steps, "tile": tile}
 
 
+def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
+    """Inference of the spectrum surrogate (fused matrix-core forward) on a
+    batch of (log10 q, eta) queries, timed with HIP events on its stream.
+    Throughput does not depend on the weight values; seeded Glorot weights."""
+    import numpy as np
+    import torch
+
+    from paper_2006_15122_amd import emulator, synth
+    from paper_2006_15122_amd.surrogate import Surrogate
+
+    shift, scale = emulator.in_scaling()
+    m = Surrogate(max_batch=64, in_shift=shift, in_scale=scale)
+    m.set_weights(synth.mlp_init(1))
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(np.stack([1.0 + 3.0 * rng.random(queries), 0.5 + 24.5 * rng.random(queries)],
+                                  1).astype(np.float32)).cuda()
+    y = torch.empty((queries, 64), dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        m.predict(x, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(m.stream)
+    for _ in range(reps):
+        m.predict(x, y)
+    e1.record(m.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    macs = 2 * 256 + 256 * 256 * 2 + 256 * 64       # per query
+    tflops = 2.0 * macs * queries / (ms / 1e3) / 1e12
+    m.close()
+    return {"queries": queries, "ms_per_batch": ms, "queries_per_s": queries / (ms / 1e3),
+            "bf16_tflops": tflops, "mfma_frac": tflops / 2500.0, "kernel": "predict_kernel"}
+
+
 def cpu_baseline(cfg: dict, nsteps: int) -> dict:
     import oracle
 
@@ -153,6 +190,9 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="tz,by,ry,xc of the main run instead of the autotuner's choice (for counter runs, "
                          "where profiling overhead can change the tuner's pick)")
+    ap.add_argument("--all-tiles", action="store_true",
+                    help="before the timed run, step the workload a few times with every tile the autotuner "
+                         "considers (a counter run then covers whichever tile the tuner picks)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy, the reference for HBM counter scaling")
     args = ap.parse_args()
@@ -176,6 +216,19 @@ def main():
 
     cfg = synth.config2(q=100.0, integrator="vv2")
     N = cfg["N"]
+    if args.all_tiles:
+        from paper_2006_15122_amd.lattice import Lattice
+        lat = Lattice(cfg, device="cuda:0")
+        from paper_2006_15122_amd.lattice import LatticeError
+        for shape in TUNER_SHAPES:
+            for xc in (8, 16, 32, 64):
+                try:
+                    lat.set_tiling(*shape, xc)
+                except LatticeError:
+                    continue
+                lat.step(4)
+        lat.close()
+        del lat
     # one call of lattice_step(K) issues K fused passes plus one opening half-kick pass
     passes = args.steps + 1
     forced = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
@@ -230,6 +283,7 @@ def main():
                                 "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
                                 "bytes_per_site_update": 80, "steps": st3, "gauss": obs3["gauss"]}
         extras["batch_96"] = time_batch(max(args.steps // 10, 20))
+        extras["surrogate_predict_65536"] = time_surrogate()
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

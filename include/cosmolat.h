@@ -50,6 +50,9 @@ extern "C" {
 #define LAT_LF2 0   /* staggered leapfrog, scheme III (pi = a^{3-alpha} phi')    */
 #define LAT_VV2 1   /* velocity Verlet                                          */
 #define LAT_VV4 2   /* Yoshida composition of VV2, 3 sub-steps                  */
+#define LAT_VV6 3   /* Yoshida, 7 sub-steps (appendix table of coefficients)     */
+#define LAT_VV8 4   /* Yoshida, 15 sub-steps                                     */
+#define LAT_VV10 5  /* Yoshida, 31 sub-steps                                     */
 
 /* Storage precision of fields and momenta.  Volume averages, a and b are
    always accumulated and kept in FP64. */

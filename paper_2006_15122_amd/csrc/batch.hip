@@ -110,7 +110,7 @@ static int batch_validate(const lattice_params* ps, int nruns) {
     if (rc) return rc;
     const lattice_params& p = ps[r];
     if (p.model != LAT_MODEL_SCALAR) { set_error("batches hold scalar models"); return LAT_EINVAL; }
-    if (p.integrator == LAT_LF2) { set_error("batches use LAT_VV2 or LAT_VV4"); return LAT_EINVAL; }
+    if (p.integrator == LAT_LF2) { set_error("batches use the velocity-Verlet integrators (LAT_VV2 .. LAT_VV10)"); return LAT_EINVAL; }
     if (p.nf != ps[0].nf || p.integrator != ps[0].integrator || p.precision != ps[0].precision ||
         p.dt != ps[0].dt) {
       set_error("batch runs must share nf, integrator, precision and dt");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -22,13 +23,40 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Yoshida weights of VVn (Sec. 3.4.1, appendix table).  VV4 is the symmetric
 // triple jump w1 = w3 = 1/(2 - 2^{1/3}), w2 = -2^{1/3}/(2 - 2^{1/3}), which
 // sums to one.
+// VV6, VV8 and VV10 use the printed rows of that table: the first half of the
+// weights and the middle one; the second half mirrors the first.
+static std::vector<double> mirrored(std::initializer_list<double> half, double mid) {
+  std::vector<double> w(half);
+  w.push_back(mid);
+  for (auto it = half.end(); it != half.begin();) w.push_back(*--it);
+  return w;
+}
+
 std::vector<double> vv_weights(int integrator) {
-  if (integrator == LAT_VV4) {
-    const double c = std::cbrt(2.0);
-    const double w1 = 1.0 / (2.0 - c), w2 = -c / (2.0 - c);
-    return {w1, w2, w1};
+  switch (integrator) {
+    case LAT_VV4: {
+      const double c = std::cbrt(2.0);
+      const double w1 = 1.0 / (2.0 - c), w2 = -c / (2.0 - c);
+      return {w1, w2, w1};
+    }
+    case LAT_VV6:
+      return mirrored({0.78451361047755726382, 0.23557321335935813368, -1.1776799841788710069},
+                      1.3151863206839112189);
+    case LAT_VV8:
+      return mirrored({0.74167036435061295345, -0.40910082580003159400, 0.19075471029623837995,
+                       -0.57386247111608226666, 0.29906418130365592384, 0.33462491824529818378,
+                       0.31529309239676659663},
+                      -0.79688793935291635402);
+    case LAT_VV10:
+      return mirrored({-0.48159895600253002870, 0.0036303931544595926879, 0.50180317558723140279,
+                       0.28298402624506254868, 0.80702967895372223806, -0.026090580538592205447,
+                       -0.87286590146318071547, -0.52373568062510581643, 0.44521844299952789252,
+                       0.18612289547097907887, 0.23137327866438360633, -0.52191036590418628905,
+                       0.74866113714499296793, 0.066736511890604057532, -0.80360324375670830316},
+                      0.91249037635867994571);
+    default:
+      return {1.0};
   }
-  return {1.0};
 }
 
 int validate(const lattice_params* p) {
@@ -37,7 +65,7 @@ int validate(const lattice_params* p) {
   if (p->model == LAT_MODEL_SCALAR && (p->nf < 1 || p->nf > 2)) { set_error("scalar model needs nf = 1 or 2"); return LAT_EINVAL; }
   if (p->model == LAT_MODEL_U1 && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
   if (p->N < 32 || p->N > 1024 || p->N % 32 != 0) { set_error("N must be a multiple of 32 in [32, 1024]"); return LAT_EINVAL; }
-  if (p->integrator < LAT_LF2 || p->integrator > LAT_VV4) { set_error("unknown integrator"); return LAT_EINVAL; }
+  if (p->integrator < LAT_LF2 || p->integrator > LAT_VV10) { set_error("unknown integrator"); return LAT_EINVAL; }
   if (p->model == LAT_MODEL_U1 && p->integrator != LAT_LF2) { set_error("U1 model supports LAT_LF2"); return LAT_EINVAL; }
   if (p->precision != LAT_FP32 && p->precision != LAT_FP64) { set_error("unknown precision"); return LAT_EINVAL; }
   if (!(p->kIR > 0.0) || !(p->dt > 0.0)) { set_error("kIR and dt must be positive"); return LAT_EINVAL; }

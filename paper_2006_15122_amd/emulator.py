@@ -60,7 +60,7 @@ def generate(cfgs, nsnap: int = 50, every: int = 100, group: int = 256, device: 
     return X, T, time.perf_counter() - t0
 
 
-def in_scaling(q_range=(10.0, 1e4), eta_range=(0.5, 25.0), q_gain: float = 16.0, t_gain: float = 4.0):
+def in_scaling(q_range=(10.0, 1e4), eta_range=(0.5, 25.0), q_gain: float = 24.0, t_gain: float = 6.0):
     """Input normalisation: the trained domain maps to [-q_gain, q_gain] in
     log10 q and [-t_gain, t_gain] in eta.  Gains above 1 let the first layer
     resolve the fine structure of the spectra in q (resonance bands) and the
@@ -71,8 +71,8 @@ def in_scaling(q_range=(10.0, 1e4), eta_range=(0.5, 25.0), q_gain: float = 16.0,
     return shift, scale
 
 
-def train(X, T, epochs: int = 10000, lr0: float = 2e-3, lr_min: float = 2e-5, max_batch: int = 2048,
-          seed: int = 7, q_range=(10.0, 1e4), eta_range=(0.5, 25.0), q_gain: float = 16.0, t_gain: float = 4.0,
+def train(X, T, epochs: int = 20000, lr0: float = 2e-3, lr_min: float = 2e-5, max_batch: int = 2048,
+          seed: int = 7, q_range=(10.0, 1e4), eta_range=(0.5, 25.0), q_gain: float = 24.0, t_gain: float = 6.0,
           device: str = "cuda:0", progress=None, progress_every: int = 500):
     """Fit a fresh surrogate to (X, T): output scaling from the targets,
     Glorot initial weights from a seeded generator, Adam with a cosine
@@ -199,7 +199,7 @@ def main(argv=None):
     ap.add_argument("--N", type=int, default=64)
     ap.add_argument("--nsnap", type=int, default=50)
     ap.add_argument("--every", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=10000)
+    ap.add_argument("--epochs", type=int, default=20000)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--group", type=int, default=256)

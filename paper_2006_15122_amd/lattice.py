@@ -17,7 +17,7 @@ _SO = os.path.join(_HERE, "libcosmolat.so")
 _LIB = None
 
 LAT_MODEL_SCALAR, LAT_MODEL_U1 = 0, 1
-INTEGRATORS = {"lf2": 0, "vv2": 1, "vv4": 2}
+INTEGRATORS = {"lf2": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ICS = {"vacuum": 0, "homogeneous": 1}
 ERRORS = {-1: "LAT_EINVAL", -2: "LAT_ENOMEM", -3: "LAT_EHIP", -4: "LAT_ENONFINITE", -5: "LAT_ESTATE"}

@@ -61,6 +61,9 @@ def scalar_case(cfg, nsteps, every):
         row["hc (abs)"] = abs(g["hc"] - o["hc"])
         for kk, v in row.items():
             worst[kk] = max(worst.get(kk, 0.0), v)
+        # largest relative error over the energy observables at this checkpoint
+        worst.setdefault("_by_checkpoint", []).append(
+            (every * (k + 1), max(v for kk, v in row.items() if kk != "hc (abs)")))
     lat.close()
     return worst
 
@@ -100,6 +103,8 @@ def main():
         ("config 1: one field, 32^3, FP64, LF2, 1000 steps", lambda: scalar_case(synth.config1(), 1000, 100)),
         ("two fields q=100, 64^3, FP32, VV2, 4000 steps (eta = 20)",
          lambda: scalar_case(synth.small(synth.config2(q=100.0), 64), 4000, 500)),
+        ("two fields q=100, 64^3, FP32, VV2, 20000 steps (eta = 100, checkpoints every 2000)",
+         lambda: scalar_case(synth.small(synth.config2(q=100.0), 64), 20000, 2000)),
         ("two fields q=1000, 64^3, FP32, VV4, 1000 steps",
          lambda: scalar_case(synth.small(synth.config2(q=1000.0, integrator="vv4"), 64), 1000, 250)),
         ("compact U(1), 64^3, FP64, LF2, 400 steps",
@@ -114,9 +119,14 @@ def main():
         lines.append(f"\n**{name}** ({time.time() - t0:.0f} s)\n")
         lines.append("| observable | max rel. error |")
         lines.append("|---|---|")
+        trace = w.pop("_by_checkpoint", None)
         for k, v in w.items():
             lines.append(f"| {k} | {v:.2e} |")
-        print("\n".join(lines[-len(w) - 3:]), flush=True)
+        if trace and len(trace) > 4:
+            lines.append("")
+            lines.append("largest error by checkpoint (step: error): " +
+                         ", ".join(f"{st}: {e:.1e}" for st, e in trace))
+        print("\n".join(lines[-len(w) - 5:]), flush=True)
     if a.out:
         with open(a.out, "w") as f:
             f.write("\n".join(lines) + "\n")

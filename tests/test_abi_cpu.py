@@ -158,3 +158,16 @@ def test_u1_workspace_holds_state_fft_and_site_kernel_partials(N):
     c = dict(synth.config3(N=N), dt=0.004)   # within the Courant bound at N = 1024
     need = 2 * 10 * 4 * N ** 3 + 16 * N ** 3 + (N ** 3 // 256) * 11 * 8
     assert lattice.workspace_size(c) >= need
+
+
+def test_integrator_codes():
+    c = synth.small(synth.config2(), 32)
+    for name in ("vv6", "vv8", "vv10"):
+        assert lattice.workspace_size(dict(c, integrator=name)) > 0
+    p = lattice.params(c)
+    p.integrator = 6
+    import ctypes
+    n = ctypes.c_size_t()
+    assert lattice.lib().lattice_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    with pytest.raises(lattice.LatticeError):
+        lattice.workspace_size(dict(synth.config3(N=32), integrator="vv6"))   # U(1) steps with LF2 only

@@ -103,7 +103,8 @@ def test_two_field_initial_conditions_match_oracle_fp64(N):
 # --------------------------------------------------------------------------
 # configuration 2 physics: two fields, FP32 storage, VV2 and VV4
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("integ,q,nsteps", [("vv2", 100.0, 1000), ("vv4", 1000.0, 400), ("vv2", 1000.0, 1000)])
+@pytest.mark.parametrize("integ,q,nsteps", [("vv2", 100.0, 1000), ("vv4", 1000.0, 400), ("vv2", 1000.0, 1000),
+                                             ("vv6", 100.0, 200), ("vv8", 100.0, 100), ("vv10", 1000.0, 40)])
 def test_two_field_fp32_parity_64(integ, q, nsteps):
     cfg = synth.small(synth.config2(q=q, integrator=integ), 64)
     st = oracle.vacuum_ic(cfg)
@@ -121,6 +122,23 @@ def test_two_field_fp32_parity_64(integ, q, nsteps):
         g = lat.energies()
         worst = max(worst, compare_obs(g, o, 2, 1e-5, f"{integ} step {chunk * (k + 1)}"))
     print(integ, q, "worst relative error", worst)
+
+
+@pytest.mark.parametrize("integ", ["vv6", "vv8", "vv10"])
+def test_higher_order_yoshida_fp64_parity(integ):
+    # VV6, VV8, VV10 (Sec. 3.4.1, 4.3.2): 7, 15, 31 fused passes per step
+    cfg = dict(synth.small(synth.config2(q=100.0, integrator=integ), 32), precision="fp64")
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    lat.step(24)
+    a, b = oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], integ, 24)
+    compare_obs(lat.energies(), oracle.sync_observe(m, phi, pi, a, b), 2, 1e-10, integ)
+    s = lat.get_state()
+    assert np.max(np.abs(s["phi"] - phi)) < 1e-10 * np.max(np.abs(phi))
+    assert np.max(np.abs(s["pi"] - pi)) < 1e-10 * np.max(np.abs(pi))
 
 
 def test_ragged_size_96_fp32():
@@ -153,6 +171,49 @@ def test_full_size_256_vv2_sampled_sites():
     for arr, ref in ((s["phi"], phi), (s["pi"], pi)):
         d = np.abs(arr[idx] - ref[idx])
         assert np.max(d) < 1e-5 * np.max(np.abs(ref[idx])), np.max(d)
+
+
+def test_large_512_vv2_sampled_sites():
+    cfg = synth.config2(q=100.0, N=512)
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+    lat.step(2)
+    phi, pi = st["phi"], st["pi"]
+    a, b = oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], "vv2", 2, omp=True)
+    compare_obs(lat.energies(), oracle.sync_observe(m, phi, pi, a, b), 2, 1e-5, "512^3")
+    s = lat.get_state()
+    rng = np.random.default_rng(1)
+    idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 512, size=(3, 4096)))
+    for arr, ref in ((s["phi"], phi), (s["pi"], pi)):
+        d = np.abs(arr[idx] - ref[idx])
+        assert np.max(d) < 1e-5 * np.max(np.abs(ref[idx])), np.max(d)
+
+
+def test_max_size_1024_device_state_steps():
+    # The largest supported lattice, from device initial conditions.  With the
+    # literal vacuum amplitude the fluctuation energy dominates at 1024^3 and
+    # the expansion is fast (a grows several-fold in a few steps), so the
+    # Hubble-constraint residual is not small; it must still fall as dt^2 at
+    # fixed eta (VV2), which checks the coupled field/scale-factor update at
+    # this size.
+    import torch
+    hc = []
+    # the vacuum energy makes H ~ 10^2 here: steps small enough that dt H << 1
+    for dt, n in ((0.001, 20), (0.0005, 40)):
+        cfg = dict(synth.config2(q=100.0, N=1024), dt=dt)
+        lat = _lattice(cfg)
+        a0 = lat.energies()["a"]
+        lat.step(n)
+        e = lat.energies()
+        assert all(math.isfinite(e[k]) for k in ("a", "b", "EK", "EG", "EV", "hc"))
+        assert e["a"] > a0 and e["step"] == n and abs(e["eta"] - 0.02) < 1e-12
+        hc.append(e["hc"])
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    assert 3.0 < hc[0] / hc[1] < 5.3, hc
 
 
 def test_every_tiling_agrees():

@@ -178,3 +178,14 @@ def test_u1_fused_passes_match_single_steps(N, precision, tol):
     ea, eb = a.energies(), b.energies()
     for k in ("a", "b", "EK", "EG", "EK_A", "EG_A"):
         assert abs(ea[k] - eb[k]) <= 10 * tol * abs(eb[k]) + 1e-300, k
+
+
+def test_u1_large_512_fp32_gauss_and_energies():
+    # the per-block partials of the U(1) site kernels at 512^3 need more room
+    # than the scalar tiles; the workspace reserves it
+    cfg = _cfg(512, "fp32")
+    lat = _lattice(cfg)
+    lat.step(3)
+    e = lat.energies()
+    assert all(math.isfinite(e[k]) for k in ("a", "b", "EK", "EG", "EV", "EK_A", "EG_A", "hc"))
+    assert e["gauss"] < 1e-5 and e["step"] == 3

@@ -92,7 +92,7 @@ def _vv_matrix(h, w2):
 
 
 @pytest.mark.parametrize("nvec", [(1, 0, 0), (2, 3, 1), (4, 4, 4), (0, 5, 2)])
-@pytest.mark.parametrize("integ", ["vv2", "vv4"])
+@pytest.mark.parametrize("integ", ["vv2", "vv4", "vv6", "vv8", "vv10"])
 def test_dispersion_single_mode_vv(nvec, integ):
     N, m2, h, nsteps = 8, 0.37, 0.05, 40
     cfg = _flat_free(N, m2)
@@ -104,11 +104,9 @@ def test_dispersion_single_mode_vv(nvec, integ):
     phi = (A0 * mode)[None].copy()
     pi = (B0 * mode)[None].copy()
     oracle.vv_steps(m, phi, pi, 1.0, 0.0, h, integ, nsteps)
-    if integ == "vv2":
-        M1 = _vv_matrix(h, w2)
-    else:
-        w = oracle.VV_WEIGHTS["vv4"]
-        M1 = _vv_matrix(w[2] * h, w2) @ _vv_matrix(w[1] * h, w2) @ _vv_matrix(w[0] * h, w2)
+    M1 = np.eye(2)
+    for wi in oracle.VV_WEIGHTS[integ]:
+        M1 = _vv_matrix(wi * h, w2) @ M1
     A, B = np.linalg.matrix_power(M1, nsteps) @ np.array([A0, B0])
     assert np.max(np.abs(phi[0] - A * mode)) < 1e-12
     assert np.max(np.abs(pi[0] - B * mode)) < 1e-12 * max(1.0, math.sqrt(w2))
@@ -158,6 +156,27 @@ def test_vv_phase_converges_to_continuum_at_second_order():
     for h in (0.1, 0.05, 0.025):
         errs.append(abs(math.acos(1 - h * h * w * w / 2) / h - w))
     assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2
+
+
+@pytest.mark.parametrize("integ,order,h0,f", [("vv2", 2, 0.2, 2), ("vv4", 4, 0.4, 4), ("vv6", 6, 0.8, 8),
+                                              ("vv8", 8, 1.0, 4), ("vv10", 10, 1.2, 4)])
+def test_yoshida_composition_reaches_its_order(integ, order, h0, f):
+    # For a harmonic mode the composed sub-step maps advance the phase by
+    # theta(h) = w h + O(h^(order+1)) per step (Sec. 3.4.1): dividing h by f
+    # divides the phase error per step by f^(order+1).  This holds only if the
+    # weights satisfy the order conditions: shifting one symmetric pair of the
+    # VV6, VV8 or VV10 rows by 1e-6 (sum kept) moves the ratio by a factor 8 or
+    # more, outside the band.  (VV4 is pinned by its closed form.)
+    w = 1.0
+
+    def phase_err(h):
+        M = np.eye(2)
+        for wi in oracle.VV_WEIGHTS[integ]:
+            M = _vv_matrix(wi * h, w * w) @ M
+        return abs(math.acos(np.trace(M) / 2.0) - w * h)
+
+    r = phase_err(h0) / phase_err(h0 / f)
+    assert 0.7 < r / f ** (order + 1) < 1.5, (integ, r / f ** (order + 1))
 
 
 # --------------------------------------------------------------------------
