@@ -472,6 +472,17 @@ def u1_lf_steps(m: U1, st: dict, h: float, nsteps: int, omp: bool = False):
     st["a"], st["b"] = ca.value, cb.value
 
 
+def u1_vv_steps(m: U1, st: dict, h: float, integrator: str = "vv2", nsteps: int = 1, omp: bool = False):
+    """nsteps compact velocity-Verlet steps (Sec. 5.3.2; Yoshida VVn, Sec. 5.3.3)
+    of a synchronised state, in place on st."""
+    w = np.ascontiguousarray(VV_WEIGHTS[integrator], dtype=np.float64)
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib(omp).orc_u1_vv_steps(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["piA"]),
+                             ctypes.byref(ca), ctypes.byref(cb), ctypes.c_double(h), _p(w), ctypes.c_int(len(w)),
+                             ctypes.c_int64(nsteps))
+    st["a"], st["b"] = ca.value, cb.value
+
+
 def _u1_obs(e, a):
     d = {"a": a, "EK": e[0], "EG": e[1], "EV": e[2], "EK_A": e[3], "EG_A": e[4], "EV_quartic": e[5],
          "EV_mass": e[6], "b": e[7], "hc": e[8], "gauss": e[9], "mean0": e[10], "mean1": e[11],

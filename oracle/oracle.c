@@ -607,6 +607,55 @@ void orc_u1_lf_steps(const orc_u1* m, double* phi, double* pi, double* L, double
   free(KA);
 }
 
+/* Compact velocity Verlet (Sec. 5.3.2) and its Yoshida compositions
+   (Sec. 5.3.3): for each sub-step weight w, with hw = w h,
+     b   += (hw/2) K_a[a, E(phi, pi, V, piA)]
+     pi  += (hw/2) K_phi[a, phi, V],   piA += (hw/2) K_A[a, phi, V]
+     a'   = a + hw b,  a_mid = (a + a')/2
+     phi += hw pi / a_mid^{3-alpha},   V = Cayley(hw, piA, a_mid) V,   a = a'
+     pi  += (hw/2) K_phi[a, phi, V],   piA += (hw/2) K_A[a, phi, V]
+     b   += (hw/2) K_a[a, E(phi, pi, V, piA)]
+   (the same order as the scalar scheme, orc_vv_substep). */
+void orc_u1_vv_steps(const orc_u1* m, double* phi, double* pi, double* L, double* piA, double* a, double* b,
+                     double h, const double* w, int nw, int64_t nsteps) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 2 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double s[9], e[7];
+  for (int64_t it = 0; it < nsteps; ++it) {
+    for (int p = 0; p < nw; ++p) {
+      const double hw = w[p] * h;
+      if (m->expand) {
+        orc_u1_sums(m, phi, pi, L, piA, s);
+        u1_energies(m, *a, s, -1.0, -1.0, e);
+        *b += 0.5 * hw * orc_u1_Ka(m, *a, e);
+      }
+      orc_u1_kernels(m, *a, phi, L, Kp, KA);
+      for (int64_t i = 0; i < 2 * V; ++i) pi[i] += 0.5 * hw * Kp[i];
+      for (int64_t i = 0; i < 3 * V; ++i) piA[i] += 0.5 * hw * KA[i];
+      double anew = *a, amid = *a;
+      if (m->expand) {
+        anew = *a + hw * (*b);
+        amid = 0.5 * (*a + anew);
+      }
+      const double cd = hw * pow(amid, -(3.0 - m->alpha));
+      for (int64_t i = 0; i < 2 * V; ++i) phi[i] += cd * pi[i];
+      u1_link_drift(m, L, piA, hw, amid);
+      *a = anew;
+      orc_u1_kernels(m, *a, phi, L, Kp, KA);
+      for (int64_t i = 0; i < 2 * V; ++i) pi[i] += 0.5 * hw * Kp[i];
+      for (int64_t i = 0; i < 3 * V; ++i) piA[i] += 0.5 * hw * KA[i];
+      if (m->expand) {
+        orc_u1_sums(m, phi, pi, L, piA, s);
+        u1_energies(m, *a, s, -1.0, -1.0, e);
+        *b += 0.5 * hw * orc_u1_Ka(m, *a, e);
+      }
+    }
+  }
+  free(Kp);
+  free(KA);
+}
+
 /* Gauss-law residual (Sec. 5.2 discrete Gauss law, sign fixed by the kick):
    G(n) = sum_i (piA_i(n) - piA_i(n-i))/dx - 2 e (f_star/w_star)^2 Im[conj phi(n) pi(n)];
    out[0] = sum G^2, out[1] = sum (div piA)^2, out[2] = sum rho^2, out[3] = sum rho. */

@@ -189,3 +189,68 @@ def test_u1_hubble_constraint_with_gauge_energy(alpha):
         oracle.u1_lf_steps(m, st, h, int(round(0.6 / h)))
         hcs.append(oracle.u1_lf_observe(m, st, h)["hc"])
     assert hcs[0] < 2e-3 and 2.5 < hcs[0] / hcs[1] < 6.0, hcs
+
+
+# --------------------------------------------------------------------------
+# Compact velocity Verlet and its Yoshida compositions (Sec. 5.3.2, 5.3.3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("integ", ["vv2", "vv4"])
+def test_u1_vv_conserves_gauss_and_reverses(integ):
+    cfg = _cfg(N=8)
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    h = 0.02
+    st0 = _copy(st)
+    oracle.u1_vv_steps(m, st, h, integ, 30)
+    o = oracle.u1_sync_observe(m, st)
+    assert o["gauss"] < 1e-12, o["gauss"]
+    assert st["a"] > st0["a"] * 1.005
+    # time reversal: flip the momenta and b, evolve, flip back
+    for k in ("pi", "piA"):
+        st[k] = -st[k]
+    st["b"] = -st["b"]
+    oracle.u1_vv_steps(m, st, h, integ, 30)
+    for k in ("pi", "piA"):
+        st[k] = -st[k]
+    st["b"] = -st["b"]
+    for k in ("phi", "pi", "links", "piA"):
+        assert np.max(np.abs(st[k] - st0[k])) < 1e-11 * max(1.0, np.max(np.abs(st0[k]))), k
+    assert abs(st["a"] - st0["a"]) < 1e-12 and abs(st["b"] - st0["b"]) < 1e-11
+
+
+@pytest.mark.parametrize("integ,ratio", [("vv2", 4.0), ("vv4", 16.0)])
+def test_u1_vv_convergence_order(integ, ratio):
+    cfg = _cfg(N=6, omega_over_f=1.0)
+    st0 = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    T = 0.4
+    res = []
+    for h in (0.04, 0.02, 0.01):
+        st = _copy(st0)
+        oracle.u1_vv_steps(m, st, h, integ, int(round(T / h)))
+        res.append(st)
+    for key in ("phi", "piA"):
+        e1 = np.max(np.abs(res[0][key] - res[1][key]))
+        e2 = np.max(np.abs(res[1][key] - res[2][key]))
+        assert 0.8 * ratio < e1 / e2 < 1.25 * ratio, (integ, key, e1 / e2)
+    ea1, ea2 = abs(res[0]["a"] - res[1]["a"]), abs(res[1]["a"] - res[2]["a"])
+    assert 0.8 * ratio < ea1 / ea2 < 1.25 * ratio
+
+
+def test_u1_vv_and_leapfrog_agree_to_second_order():
+    # two different second-order schemes for the same equations: their
+    # difference at fixed time shrinks as h^2
+    cfg = _cfg(N=6, omega_over_f=1.0)
+    st0 = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    T = 0.4
+    diffs = []
+    for h in (0.02, 0.01):
+        n = int(round(T / h))
+        v = _copy(st0)
+        oracle.u1_vv_steps(m, v, h, "vv2", n)
+        lf = _copy(st0)
+        oracle.u1_lf_startup(m, lf, h)
+        oracle.u1_lf_steps(m, lf, h, n)
+        diffs.append(np.max(np.abs(v["phi"] - lf["phi"])))
+    assert 3.2 < diffs[0] / diffs[1] < 5.0, diffs
