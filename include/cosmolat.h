@@ -199,13 +199,13 @@ int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int3
    the shape is not compiled or does not divide N. */
 int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t xc);
 
-/* Kernel timing of the fused scalar pass.  After lattice_pass_timer(h, n),
+/* Kernel timing of the fused pass (scalar or U(1)).  After lattice_pass_timer(h, n),
    the next n stepping-pass launches of lattice_step carry the device's own
    start and stop timestamps of their dispatch (the launch is otherwise the
    same; no work is added or skipped).  lattice_pass_timer_read synchronises
    the stream and returns the summed kernel time of the recorded launches
    and their number, then starts a new count with the same events.
-   n = 0 releases the events.  Scalar models only.
+   n = 0 releases the events.
    Errors: LAT_EINVAL, LAT_EHIP. */
 int lattice_pass_timer(lattice_t* h, int32_t max_launches);
 int lattice_pass_timer_read(lattice_t* h, double* total_ms, int64_t* launches);

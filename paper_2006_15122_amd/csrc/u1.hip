@@ -1,7 +1,8 @@
-// Complex scalar with compact U(1) links on gfx950 (Sec. 5.3, compact
-// staggered leapfrog).  One step = kick (in place) -> FP64 finish -> drift
-// (in place).  The kick of pi at n reads only phi and links, and the drift of
-// phi and V at n reads only pi and piA at n, so no state buffer is doubled.
+// Complex scalar with compact U(1) links on gfx950 (Sec. 5.3: staggered
+// leapfrog, velocity Verlet and its Yoshida compositions).  Every pass is the
+// drift of one (sub-)step followed by the merged kicks that close it and open
+// the next, read from one state buffer and written to the other, then an
+// FP64 finish that advances a and b; the pass sequence is the scalar path's.
 //
 // Components (storage precision, N^3 each): 0,1 = Re, Im phi; 2,3 = Re, Im
 // pi; 4 + i = phase th_i of the link V_i = exp(i th_i); 7 + i = piA_i.
@@ -16,6 +17,7 @@
 //   K_{A,i} = a^{1+alpha}(2 e/dx)(f/w)^2 Im[conj phi V_i phi_{+i}]
 //             + a^{alpha-1}/(e dx^3) sum_{j!=i} (Im V_ij(n) - Im V_ij(n-j)),
 //   V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,18 +40,13 @@ __device__ __forceinline__ C2<T> cc(C2<T> a) {
   return C2<T>{a.x, -a.y};
 }
 
+// arguments of the Gauss-law residual kernel
 template <typename T>
 struct U1Args {
   T* c[10];
   int N;
   double dx, alpha, fmp2, lam, m2, e, wf2, h;
   int expand;
-  // kick: pi += ck h K (ck = 1 LF step, -1/2 start-up, 0 observation);
-  // mode LF: E_K from the mean of <pi_in^2> and <pi_out^2>, VV: from pi_in
-  double ck;
-  int mode;
-  int write;
-  int advance;  // finish: after the kick, a' = a + h b_out and a_mid for the drift
   double* partials;
   DevState* st;
 };
@@ -87,227 +84,6 @@ __device__ __forceinline__ double atan_t(double x) { return atan(x); }
 template <typename T>
 __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
   return C2<T>{re[i], im[i]};
-}
-
-// one thread per site; neighbours come through the cache hierarchy.  Site
-// indices fit in 32 bits (N^3 <= 2^30); the periodic neighbour offsets of each
-// axis are formed once, and n + i - j is the sum of two of them.
-template <typename T>
-__global__ __launch_bounds__(256) void u1_kick_kernel(U1Args<T> A) {
-  const int N = A.N;
-  const int NN = N * N;
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  const int x = s / NN, y = (s / N) % N, z = s % N;
-  const int up[3] = {x == N - 1 ? -(N - 1) * NN : NN, y == N - 1 ? -(N - 1) * N : N, z == N - 1 ? -(N - 1) : 1};
-  const int dn[3] = {x == 0 ? (N - 1) * NN : -NN, y == 0 ? (N - 1) * N : -N, z == 0 ? (N - 1) : -1};
-  // site n + step*e_dir + step2*e_dir2 (step, step2 in {-1, 0, 1}, dir != dir2 when both nonzero)
-  auto off = [&](int dir, int step, int dir2, int step2) -> int {
-    int o = s;
-    if (step > 0) o += up[dir];
-    if (step < 0) o += dn[dir];
-    if (step2 > 0) o += up[dir2];
-    if (step2 < 0) o += dn[dir2];
-    return o;
-  };
-  auto theta = [&](int i, int site) -> T { return A.c[4 + i][site]; };
-  auto link = [&](int i, int site) -> C2<T> {
-    T sn, cs;
-    sincos_t(theta(i, site), &sn, &cs);
-    return C2<T>{cs, sn};
-  };
-  auto phi = [&](int site) -> C2<T> { return ld(A.c[0], A.c[1], (size_t)site); };
-
-  const double a_in = A.st->a;
-  const T cl = (T)(pow(a_in, 1.0 + A.alpha) / (A.dx * A.dx));
-  const T cp = (T)pow(a_in, 3.0 + A.alpha);
-  const T cj = (T)(pow(a_in, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-  const T cb = (T)(pow(a_in, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
-  const T ck = (T)(A.ck * A.h);
-  const T lam = (T)A.lam, m2 = (T)A.m2;
-
-  const C2<T> p = phi(s);
-  C2<T> lap{T(-6) * p.x, T(-6) * p.y};
-  double grad = 0.0;
-  T th[3];
-  T Kcur[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    th[i] = theta(i, s);
-    T sn, cs;
-    sincos_t(th[i], &sn, &cs);
-    const int sp = off(i, 1, i, 0), sm = off(i, -1, i, 0);
-    const C2<T> f = cm(C2<T>{cs, sn}, phi(sp));
-    const C2<T> b = cm(cc(link(i, sm)), phi(sm));
-    lap.x += f.x + b.x;
-    lap.y += f.y + b.y;
-    const T gx = f.x - p.x, gy = f.y - p.y;
-    grad += (double)(gx * gx + gy * gy);
-    Kcur[i] = cj * (p.x * f.y - p.y * f.x);  // Im(conj p * f)
-  }
-  const T r2 = p.x * p.x + p.y * p.y;
-  const T dv = T(2) * lam * r2 + m2;
-  const C2<T> Kp{cl * lap.x - cp * dv * p.x, cl * lap.y - cp * dv * p.y};
-
-  // plaquette phases: Phi_ij(n) = th_i(n) + th_j(n+i) - th_i(n+j) - th_j(n)
-  double mag = 0.0;
-  T KA[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    T curl = T(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      if (j == i) continue;
-      const T ph0 = (th[i] + theta(j, off(i, 1, j, 0))) - (theta(i, off(j, 1, i, 0)) + th[j]);
-      const int smj = off(j, -1, j, 0);
-      // Phi_ij(n-j) = th_i(n-j) + th_j(n-j+i) - th_i(n) - th_j(n-j)
-      const T ph1 = (theta(i, smj) + theta(j, off(j, -1, i, 1))) - (th[i] + theta(j, smj));
-      curl += sin_t(ph0) - sin_t(ph1);
-      if (j > i) {
-        const T sh = sin_t(T(0.5) * ph0);
-        mag += (double)(T(2) * sh * sh);
-      }
-    }
-    KA[i] = Kcur[i] + cb * curl;
-  }
-
-  const C2<T> pin = ld(A.c[2], A.c[3], s);
-  const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
-  const bool lf = A.mode == MODE_LF;
-  double acc[kU1Acc];
-  acc[0] = (double)(pin.x * pin.x + pin.y * pin.y);
-  acc[1] = lf ? (double)(pout.x * pout.x + pout.y * pout.y) : acc[0];
-  acc[2] = grad;
-  acc[3] = (double)(lam * r2 * r2);
-  acc[4] = (double)(m2 * r2);
-  double ka0 = 0.0, ka1 = 0.0;
-  T aout[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T ain = A.c[7 + i][s];
-    aout[i] = ain + ck * KA[i];
-    ka0 += (double)(ain * ain);
-    ka1 += (double)(aout[i] * aout[i]);
-  }
-  acc[5] = ka0;
-  acc[6] = lf ? ka1 : ka0;
-  acc[7] = mag;
-  acc[8] = (double)p.x;
-  acc[9] = (double)p.y;
-  acc[10] = (double)r2;
-  if (A.write) {
-    A.c[2][s] = pout.x;
-    A.c[3][s] = pout.y;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) A.c[7 + i][s] = aout[i];
-  }
-  u1_block_partials<kU1Acc>(acc, A.partials);
-}
-
-// Combine the partials in block order; energies of Sec. 5.4.1 and the scale-
-// factor kernel with the gauge term (Sec. 5.1):
-//   K_a = (1/3)(f/m_p)^2 a^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V
-//                                       + (alpha-1)(E_K^A + E_G^A)].
-template <typename T>
-__global__ __launch_bounds__(1024) void u1_finish_kernel(U1Args<T> A, int nblocks) {
-  constexpr int NACC = kU1Acc, NW = 16;
-  __shared__ double red[NW][NACC];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double tot[NACC];
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
-  for (int b = tid; b < nblocks; b += 1024) {
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) tot[k] += A.partials[(size_t)b * NACC + k];
-  }
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const double s = wsum(tot[k]);
-    if (lane == 0) red[wv][k] = s;
-  }
-  __syncthreads();
-  if (tid != 0) return;
-  double S[NACC];
-  for (int k = 0; k < NACC; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += red[w][k];
-    S[k] = s;
-  }
-  const double V = (double)A.N * A.N * A.N;
-  const double a = A.st->a, b_in = A.st->b, al = A.alpha;
-  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = A.dx * A.dx;
-  lattice_obs o;
-  o.EK = 0.5 * (S[0] + S[1]) / V / a6;
-  o.EG = S[2] / V / (a2 * dx2);
-  o.EV_term[0] = S[4] / V;
-  o.EV_term[1] = S[3] / V;
-  o.EV_term[2] = 0.0;
-  o.EV = o.EV_term[0] + o.EV_term[1];
-  o.EK_A = A.wf2 * 0.5 * (S[5] + S[6]) / V / (2.0 * a4);
-  o.EG_A = A.wf2 * S[7] / V / (a4 * dx2 * dx2 * A.e * A.e);
-  o.EK_f[0] = o.EK;
-  o.EK_f[1] = 0.0;
-  o.EG_f[0] = o.EG;
-  o.EG_f[1] = 0.0;
-  o.mean_f[0] = S[8] / V;
-  o.mean_f[1] = S[9] / V;
-  o.meansq_f[0] = S[10] / V;
-  o.meansq_f[1] = 0.0;
-  bool bad = false;
-  for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
-  const double rho = o.EK + o.EG + o.EV + o.EK_A + o.EG_A;
-  double b_out = b_in, b_sync = b_in, hc = 0.0, anext = a;
-  if (A.expand) {
-    const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
-                      ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * (o.EK_A + o.EG_A));
-    b_out = b_in + A.ck * A.h * Ka;
-    b_sync = (A.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in;
-    const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
-    hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
-    if (A.advance) anext = a + A.h * b_out;
-  }
-  o.eta = A.st->eta;
-  o.a = a;
-  o.b = b_sync;
-  o.H = b_sync / a;
-  o.rho = rho;
-  o.p = o.EK - o.EG / 3.0 - o.EV + (o.EK_A + o.EG_A) / 3.0;
-  o.w = rho != 0.0 ? o.p / rho : 0.0;
-  o.hc = hc;
-  o.gauss = A.st->obs.gauss;
-  o.step = 0;
-  o.staggered = (A.mode == MODE_LF) ? 1 : 0;
-  o.reserved = 0;
-  A.st->obs = o;
-  if (bad) A.st->nonfinite = 1;
-  if (A.write) {
-    A.st->b = b_out;
-    if (A.advance) {
-      A.st->aux[0] = 0.5 * (a + anext);  // a_{n+1/2} for the drift
-      A.st->a = anext;
-      A.st->eta = A.st->eta + A.h;
-    }
-  }
-}
-
-// phi <- phi + h pi / a_mid^{3-alpha};  V_i <- (1 - i u)/(1 + i u) V_i,
-// u = e h dx piA_i / (2 a_mid^{1-alpha})  (Sec. 5.3, drift from momenta).
-// (1 - i u)/(1 + i u) = exp(-2 i atan u), so th_i <- th_i - 2 atan u, kept in (-pi, pi].
-template <typename T>
-__global__ __launch_bounds__(256) void u1_drift_kernel(U1Args<T> A) {
-  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const double amid = A.expand ? A.st->aux[0] : A.st->a;
-  const T cd = (T)(A.h * pow(amid, -(3.0 - A.alpha)));
-  const T cu = (T)(A.e * A.h * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
-  A.c[0][s] = A.c[0][s] + cd * A.c[2][s];
-  A.c[1][s] = A.c[1][s] + cd * A.c[3][s];
-  const T twopi = (T)6.283185307179586476925286766559;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T u = cu * A.c[7 + i][s];
-    T t = A.c[4 + i][s] - T(2) * atan_t(u);
-    t -= twopi * rint(t / twopi);
-    A.c[4 + i][s] = t;
-  }
 }
 
 // Gauss residual G(n) = sum_i (piA_i(n) - piA_i(n-i))/dx - 2e (f/w)^2 Im[conj phi pi]
@@ -349,10 +125,7 @@ __global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* par
 }
 
 // ---------------------------------------------------------------------------
-// Fused stepping pass: the drift that closes step n-1 followed by the kick of
-// step n, in one sweep over the lattice (source buffer -> destination buffer).
-//
-// A block owns a TY x TZ tile of the (y, z) plane and marches along x over XC
+// The pass kernel.  A block owns a TY x TZ tile of the (y, z) plane and marches along x over XC
 // planes.  Each plane enters LDS already drifted (phi and the link phases,
 // with a one-site ring including corners, the ring drifted redundantly); two
 // planes are held, x and x+1.  Per plane the block first computes the
@@ -361,14 +134,20 @@ __global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* par
 // instead of once per use.  Values of plane x-1 that the kick needs (phi,
 // theta_0, S_01, S_02 of the own column) stay in registers.
 // ---------------------------------------------------------------------------
+// One pass (as PassDesc of the scalar path, Sec. 3.3.2 merged kicks):
+//   a'  = a + wd h b,  a_mid = (a + a')/2
+//   phi = phi + wd h pi / a_mid^{3-alpha},  V = Cayley(wd h, piA, a_mid) V
+//   pi  = pi + (wk1 + wk2) h K_phi(a'),     piA = piA + (wk1 + wk2) h K_A(a')
+// E_K from pi_in and pi + wk1 h K (VV) or from the mean of <pi_in^2> and
+// <pi_out^2> (LF), likewise for piA.
 template <typename T>
 struct U1PassArgs {
   const T* src[10];
   T* dst[10];
   int N, XC, swizzle;
-  double dx, alpha, lam, m2, e, wf2, h;
+  double dx, alpha, fmp2, lam, m2, e, wf2, h;
   int expand;
-  int drift;  // 0: no pending drift (first pass of a call)
+  PassDesc pd;
   double* partials;
   DevState* st;
 };
@@ -401,16 +180,20 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const int x0 = (bid / (nzt * nyt)) * A.XC;
 
   // homogeneous coefficients (FP64, the same in every block)
-  const double a_in = A.st->a;
-  const double amid = A.expand ? A.st->aux[0] : a_in;
-  const bool dr = A.drift != 0;
-  const T cd = dr ? (T)(A.h * pow(amid, -(3.0 - A.alpha))) : T(0);
-  const T cu = dr ? (T)(A.e * A.h * A.dx / (2.0 * pow(amid, 1.0 - A.alpha))) : T(0);
-  const T cl = (T)(pow(a_in, 1.0 + A.alpha) / (A.dx * A.dx));
-  const T cp = (T)pow(a_in, 3.0 + A.alpha);
-  const T cj = (T)(pow(a_in, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-  const T cb = (T)(pow(a_in, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
-  const T ck = (T)A.h;
+  const double a_in = A.st->a, b_in = A.st->b;
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double amid = 0.5 * (a_in + anew);
+  const bool dr = A.pd.wd != 0.0;
+  const double hw = A.pd.wd * A.h;
+  const T cd = dr ? (T)(hw * pow(amid, -(3.0 - A.alpha))) : T(0);
+  const T cu = dr ? (T)(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha))) : T(0);
+  const T cl = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cp = (T)pow(anew, 3.0 + A.alpha);
+  const T cj = (T)(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+  const T cb = (T)(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+  const T ck = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
+  const T cE = (T)((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
+  const bool wr = A.pd.write != 0;
   const T lam = (T)A.lam, m2 = (T)A.m2;
 
   // ring site owned by this thread (one at most)
@@ -582,26 +365,32 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
                          (-S02 + s02m[r]) + (-S12 + Ls[2][ly - 1][lz])};
       const C2<T> pin{qc[0][r], qc[1][r]};
       const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
+      const C2<T> pe{pin.x + cE * Kp.x, pin.y + cE * Kp.y};
       acc[0] += (double)(pin.x * pin.x + pin.y * pin.y);
-      acc[1] += (double)(pout.x * pout.x + pout.y * pout.y);
+      acc[1] += (double)(pe.x * pe.x + pe.y * pe.y);
       acc[2] += grad;
       acc[3] += (double)(lam * r2 * r2);
       acc[4] += (double)(m2 * r2);
       acc[8] += (double)p.x;
       acc[9] += (double)p.y;
       acc[10] += (double)r2;
-      __builtin_nontemporal_store(p.x, &A.dst[0][o]);
-      __builtin_nontemporal_store(p.y, &A.dst[1][o]);
-      __builtin_nontemporal_store(pout.x, &A.dst[2][o]);
-      __builtin_nontemporal_store(pout.y, &A.dst[3][o]);
+      if (wr) {
+        __builtin_nontemporal_store(p.x, &A.dst[0][o]);
+        __builtin_nontemporal_store(p.y, &A.dst[1][o]);
+        __builtin_nontemporal_store(pout.x, &A.dst[2][o]);
+        __builtin_nontemporal_store(pout.y, &A.dst[3][o]);
+      }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const T ain = qc[2 + k][r];
-        const T aout = ain + ck * (Kcur[k] + cb * curl[k]);
+        const T KA = Kcur[k] + cb * curl[k];
+        const T aout = ain + ck * KA, ae = ain + cE * KA;
         acc[5] += (double)(ain * ain);
-        acc[6] += (double)(aout * aout);
-        __builtin_nontemporal_store(th[k], &A.dst[4 + k][o]);
-        __builtin_nontemporal_store(aout, &A.dst[7 + k][o]);
+        acc[6] += (double)(ae * ae);
+        if (wr) {
+          __builtin_nontemporal_store(th[k], &A.dst[4 + k][o]);
+          __builtin_nontemporal_store(aout, &A.dst[7 + k][o]);
+        }
       }
       // plane x becomes plane x-1 of the next step
       pm[0][r] = p.x;
@@ -623,6 +412,92 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   u1_block_partials<kU1Acc>(acc, A.partials);
 }
 
+// Combine the partials in block order; energies of Sec. 5.4.1 at a' and the
+// scale-factor kernel with the gauge term (Sec. 5.1),
+//   K_a = (1/3)(f/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V
+//                                        + (alpha-1)(E_K^A + E_G^A)],
+//   b_out = b + (wk1 + wk2) h K_a;  a, b, eta advanced when the pass updates.
+template <typename T>
+__global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblocks) {
+  constexpr int NACC = kU1Acc, NW = 16;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double tot[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
+  for (int b = tid; b < nblocks; b += 1024) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) tot[k] += A.partials[(size_t)b * NACC + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wsum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double S[NACC];
+  for (int k = 0; k < NACC; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][k];
+    S[k] = s;
+  }
+  const double V = (double)A.N * A.N * A.N;
+  const double a_in = A.st->a, b_in = A.st->b, al = A.alpha;
+  const double a = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const bool lf = A.pd.mode == MODE_LF;
+  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = A.dx * A.dx;
+  lattice_obs o;
+  o.EK = (lf ? 0.5 * (S[0] + S[1]) : S[1]) / V / a6;
+  o.EG = S[2] / V / (a2 * dx2);
+  o.EV_term[0] = S[4] / V;
+  o.EV_term[1] = S[3] / V;
+  o.EV_term[2] = 0.0;
+  o.EV = o.EV_term[0] + o.EV_term[1];
+  o.EK_A = A.wf2 * (lf ? 0.5 * (S[5] + S[6]) : S[6]) / V / (2.0 * a4);
+  o.EG_A = A.wf2 * S[7] / V / (a4 * dx2 * dx2 * A.e * A.e);
+  o.EK_f[0] = o.EK;
+  o.EK_f[1] = 0.0;
+  o.EG_f[0] = o.EG;
+  o.EG_f[1] = 0.0;
+  o.mean_f[0] = S[8] / V;
+  o.mean_f[1] = S[9] / V;
+  o.meansq_f[0] = S[10] / V;
+  o.meansq_f[1] = 0.0;
+  bool bad = false;
+  for (int k = 0; k < NACC; ++k) bad = bad || !isfinite(S[k]);
+  const double rho = o.EK + o.EG + o.EV + o.EK_A + o.EG_A;
+  double b_out = b_in, b_sync = b_in, hc = 0.0;
+  if (A.expand) {
+    const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+                      ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * (o.EK_A + o.EG_A));
+    b_out = b_in + (A.pd.wk1 + A.pd.wk2) * A.h * Ka;
+    b_sync = lf ? 0.5 * (b_in + b_out) : b_in + A.pd.wk1 * A.h * Ka;
+    const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
+    hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
+  }
+  const double eta_new = A.st->eta + A.pd.wd * A.h;
+  o.eta = eta_new;
+  o.a = a;
+  o.b = b_sync;
+  o.H = b_sync / a;
+  o.rho = rho;
+  o.p = o.EK - o.EG / 3.0 - o.EV + (o.EK_A + o.EG_A) / 3.0;
+  o.w = rho != 0.0 ? o.p / rho : 0.0;
+  o.hc = hc;
+  o.gauss = A.st->obs.gauss;
+  o.step = 0;
+  o.staggered = lf ? 1 : 0;
+  o.reserved = 0;
+  A.st->obs = o;
+  if (bad) A.st->nonfinite = 1;
+  if (A.pd.update) {
+    A.st->a = a;
+    A.st->b = b_out;
+    A.st->eta = eta_new;
+  }
+}
+
 template <typename T>
 static void fill_args(lattice* h, U1Args<T>& A) {
   for (int c = 0; c < 10; ++c) A.c[c] = static_cast<T*>(h->buf[h->cur][c]);
@@ -641,33 +516,6 @@ static void fill_args(lattice* h, U1Args<T>& A) {
 }
 
 template <typename T>
-static int u1_kick_t(lattice* h, double ck, int mode, int write, int advance) {
-  U1Args<T> A;
-  fill_args(h, A);
-  A.ck = ck;
-  A.mode = mode;
-  A.write = write;
-  A.advance = advance;
-  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
-  const int nb = (int)(V / 256);
-  hipLaunchKernelGGL(u1_kick_kernel<T>, dim3(nb), dim3(256), 0, h->stream, A);
-  CL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(u1_finish_kernel<T>, dim3(1), dim3(1024), 0, h->stream, A, nb);
-  CL_HIP(hipGetLastError());
-  return LAT_OK;
-}
-
-template <typename T>
-static int u1_drift_t(lattice* h) {
-  U1Args<T> A;
-  fill_args(h, A);
-  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
-  hipLaunchKernelGGL(u1_drift_kernel<T>, dim3((int)(V / 256)), dim3(256), 0, h->stream, A);
-  CL_HIP(hipGetLastError());
-  return LAT_OK;
-}
-
-template <typename T>
 static int u1_gauss_t(lattice* h) {
   U1Args<T> A;
   fill_args(h, A);
@@ -680,11 +528,10 @@ static int u1_gauss_t(lattice* h) {
   return LAT_OK;
 }
 
-// One fused pass (pending drift, then the kick of the next step) from the
-// current buffer into the other one, followed by the FP64 finish that
-// advances a and b.
+// One pass from the current buffer into the other (or no stores for an
+// observation), then the FP64 finish.
 template <typename T, int TZ, int BY, int RY>
-static int u1_pass_t(lattice* h) {
+static int u1_pass_t(lattice* h, const PassDesc& pd) {
   U1PassArgs<T> A;
   for (int c = 0; c < 10; ++c) {
     A.src[c] = static_cast<const T*>(h->buf[h->cur][c]);
@@ -703,65 +550,51 @@ static int u1_pass_t(lattice* h) {
   A.swizzle = (nb % 8 == 0) ? 1 : 0;
   A.dx = h->dx;
   A.alpha = h->p.alpha;
+  A.fmp2 = h->p.fstar_over_mp * h->p.fstar_over_mp;
   A.lam = h->p.lambda;
   A.m2 = h->p.m2[0];
   A.e = h->p.e;
   A.wf2 = h->p.omega_over_f * h->p.omega_over_f;
   A.h = h->p.dt;
   A.expand = h->p.expansion;
-  A.drift = 1;
+  A.pd = pd;
   A.partials = h->partials;
   A.st = h->st;
-  hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (pd.write && 2 * h->timer_used + 1 < h->timer.size()) {
+    ev0 = h->timer[2 * h->timer_used];
+    ev1 = h->timer[2 * h->timer_used + 1];
+    ++h->timer_used;
+  }
+  if (ev0)
+    hipExtLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, ev0, ev1, 0, A);
+  else
+    hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
   CL_HIP(hipGetLastError());
-  h->cur ^= 1;
-  U1Args<T> F;
-  fill_args(h, F);
-  F.ck = 1.0;
-  F.mode = MODE_LF;
-  F.write = 1;
-  F.advance = 1;
-  hipLaunchKernelGGL(u1_finish_kernel<T>, dim3(1), dim3(1024), 0, h->stream, F, nb);
+  hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, nb);
   CL_HIP(hipGetLastError());
+  if (pd.write) h->cur ^= 1;
   return LAT_OK;
 }
 
-static int u1_pass(lattice* h) {
+static int u1_pass(lattice* h, const PassDesc& pd) {
   if (h->p.precision == LAT_FP32) {
-    if (h->p.N % 64 == 0) return u1_pass_t<float, 64, 4, 2>(h);
-    return u1_pass_t<float, 32, 8, 1>(h);
+    if (h->p.N % 64 == 0) return u1_pass_t<float, 64, 4, 2>(h, pd);
+    return u1_pass_t<float, 32, 8, 1>(h, pd);
   }
-  return u1_pass_t<double, 32, 8, 1>(h);
+  return u1_pass_t<double, 32, 8, 1>(h, pd);
 }
 
-static int u1_kick(lattice* h, double ck, int mode, int write, int advance) {
-  return h->p.precision == LAT_FP32 ? u1_kick_t<float>(h, ck, mode, write, advance)
-                                    : u1_kick_t<double>(h, ck, mode, write, advance);
-}
-static int u1_drift(lattice* h) {
-  return h->p.precision == LAT_FP32 ? u1_drift_t<float>(h) : u1_drift_t<double>(h);
-}
 int u1_gauss(lattice* h) { return h->p.precision == LAT_FP32 ? u1_gauss_t<float>(h) : u1_gauss_t<double>(h); }
 
+// The pass sequence of the scalar path (merged kicks; leapfrog start-up,
+// drift+kick passes and closing drift), run with the U(1) pass.
 int u1_step(lattice* h, int64_t n) {
-  int rc;
-  if (!h->staggered) {
-    // pi_{-1/2} = pi_0 - (h/2) K, piA likewise, b_{-1/2} = b_0 - (h/2) K_a(synchronised E)
-    rc = u1_kick(h, -0.5, MODE_VV, 1, 0);
-    if (rc) return rc;
-    h->staggered = 1;
-  }
-  if (n == 0) return LAT_OK;
-  // kick of the first step in place, then one fused pass per further step
-  // (drift of step j-1 and kick of step j), then the closing drift in place
-  rc = u1_kick(h, 1.0, MODE_LF, 1, 1);
-  if (rc) return rc;
-  for (int64_t j = 1; j < n; ++j) {
-    rc = u1_pass(h);
+  const std::vector<PassDesc> sched = pass_schedule(h->p.integrator, h->weights, &h->staggered, n);
+  for (const PassDesc& pd : sched) {
+    const int rc = u1_pass(h, pd);
     if (rc) return rc;
   }
-  rc = u1_drift(h);
-  if (rc) return rc;
   h->step += n;
   return LAT_OK;
 }
@@ -971,8 +804,8 @@ int u1_init_state(lattice* h) {
 int u1_energies(lattice* h) {
   int rc = u1_gauss(h);
   if (rc) return rc;
-  if (h->staggered) return u1_kick(h, 1.0, MODE_LF, 0, 0);
-  return u1_kick(h, 0.0, MODE_VV, 0, 0);
+  if (h->staggered) return u1_pass(h, pass(0.0, 0.0, 1.0, MODE_LF, 0, 0));
+  return u1_pass(h, pass(0.0, 0.0, 0.0, MODE_VV, 0, 0));
 }
 
 }  // namespace cl

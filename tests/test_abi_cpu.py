@@ -169,5 +169,6 @@ def test_integrator_codes():
     import ctypes
     n = ctypes.c_size_t()
     assert lattice.lib().lattice_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
-    with pytest.raises(lattice.LatticeError):
-        lattice.workspace_size(dict(synth.config3(N=32), integrator="vv6"))   # U(1) steps with LF2 only
+    # the compact U(1) model steps with the leapfrog and every velocity-Verlet order
+    for name in ("lf2", "vv2", "vv4", "vv10"):
+        assert lattice.workspace_size(dict(synth.config3(N=32), integrator=name)) > 0

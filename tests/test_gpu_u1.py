@@ -189,3 +189,28 @@ def test_u1_large_512_fp32_gauss_and_energies():
     e = lat.energies()
     assert all(math.isfinite(e[k]) for k in ("a", "b", "EK", "EG", "EV", "EK_A", "EG_A", "hc"))
     assert e["gauss"] < 1e-5 and e["step"] == 3
+
+
+@pytest.mark.parametrize("integ,N,precision,tol,nsteps", [("vv2", 32, "fp64", 1e-10, 60), ("vv4", 32, "fp64", 1e-10, 20),
+                                                          ("vv2", 64, "fp32", 1e-5, 200)])
+def test_u1_velocity_verlet_parity(integ, N, precision, tol, nsteps):
+    # compact velocity Verlet and Yoshida (Sec. 5.3.2, 5.3.3) through the same
+    # fused pass as the leapfrog, against the oracle's VV stepper
+    cfg = _cfg(N, precision, integrator=integ)
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    h = cfg["dt"]
+    for k in range(2):
+        lat.step(nsteps // 2)
+        oracle.u1_vv_steps(m, st, h, integ, nsteps // 2, omp=True)
+        o = oracle.u1_sync_observe(m, st)
+        g = lat.energies()
+        compare(g, o, tol, f"{integ} {precision} step {nsteps // 2 * (k + 1)}")
+        assert g["gauss"] < (1e-12 if precision == "fp64" else 1e-5)
+    s = lat.get_state()
+    assert not s["staggered"] and s["step"] == nsteps
+    if precision == "fp64":
+        for key in ("phi", "pi", "links", "piA"):
+            assert np.max(np.abs(s[key] - st[key])) < tol * np.max(np.abs(st[key])), key
