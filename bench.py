@@ -163,6 +163,39 @@ def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
             "bf16_tflops": tflops, "mfma_frac": tflops / 2500.0, "kernel": "predict_kernel"}
 
 
+def time_spectrum(N: int = 256, reps: int = 10) -> dict:
+    """One power spectrum of a 256^3 FP32 field (Sec. 3.1): complex FP64 3D FFT,
+    shell binning and the log-k interpolation, all queued on the lattice's
+    stream and timed there with HIP events."""
+    import torch
+
+    from paper_2006_15122_amd import synth
+    from paper_2006_15122_amd.lattice import Lattice
+
+    lat = Lattice(dict(synth.config2(q=100.0), N=N), device="cuda:0")
+    out = torch.empty(64, dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        lat.spectrum_logk(out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    for _ in range(reps):
+        lat.spectrum_logk(out)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    # algorithmic HBM bytes per spectrum: FP32 field read (4) and complex FP64
+    # written (16); three line passes of the FFT, each reading and writing the
+    # complex volume (3 x 32); the shell binning reads it once more (16)
+    per_site = 4 + 16 + 96 + 16
+    return {"N": N, "ms_per_spectrum": ms, "spectra_per_s": 1e3 / ms, "bytes_per_site": per_site,
+            "hbm_frac": N ** 3 * per_site / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def cpu_baseline(cfg: dict, nsteps: int) -> dict:
     import oracle
 
@@ -277,13 +310,15 @@ def main():
         # pi (2), link phases (3), link momenta (3) = 10 FP32, read and written once per step
         c3 = synth.config3()
         st3 = max(args.steps // 10, 10)
-        ms3, _, obs3, _, _ = time_lattice(c3, st3, 5)
+        ms3, _, obs3, _, k3 = time_lattice(c3, st3, 5, st3)
         n3 = c3["N"] ** 3
         extras["u1_192_lf2"] = {"site_updates_per_s": n3 * st3 / (ms3 / 1e3),
-                                "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                "bytes_per_site_update": 80, "steps": st3, "gauss": obs3["gauss"]}
+                                "hbm_frac": n3 * 80 / (k3 / 1e3) / 1e9 / HBM_PEAK_GBS, "kernel_ms": k3,
+                                "step_ms": ms3 / st3, "bytes_per_site_update": 80, "steps": st3,
+                                "gauss": obs3["gauss"]}
         extras["batch_96"] = time_batch(max(args.steps // 10, 20))
         extras["surrogate_predict_65536"] = time_surrogate()
+        extras["spectrum_256"] = time_spectrum()
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

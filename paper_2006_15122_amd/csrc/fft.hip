@@ -46,11 +46,113 @@ __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
   return Cx<R>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
+// Table of the N-th roots of unity W[m] = e^{+2 pi i m/N} (FP64), built once per
+// lattice; the inverse transform uses their conjugates.
+__global__ void twiddle_kernel(Cx<double>* W, int N) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < N) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)N, &sv, &cv);
+    W[m] = Cx<double>{cv, sv};
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> twiddle(const Cx<double>* __restrict__ W, int q, double sg) {
+  const Cx<double> w = W[q];
+  return Cx<R>{(R)w.x, (R)(sg * w.y)};
+}
+
+// Length-RAD DFT o[m] = sum_r v[r] e^{sgn 2 pi i r m / RAD}; radices 2 and 4
+// in closed form, others with roots from the table (index r m N/RAD mod N).
+template <typename R, int RAD>
+__device__ __forceinline__ void small_dft(const Cx<R>* v, Cx<R>* o, const Cx<double>* __restrict__ W, int N,
+                                          double sg) {
+  if constexpr (RAD == 2) {
+    o[0] = Cx<R>{v[0].x + v[1].x, v[0].y + v[1].y};
+    o[1] = Cx<R>{v[0].x - v[1].x, v[0].y - v[1].y};
+  } else if constexpr (RAD == 4) {
+    // e^{sgn 2 pi i m r/4}: multiplication by sgn*i for m r = 1 (mod 4)
+    const R s = (R)sg;
+    const Cx<R> a0{v[0].x + v[2].x, v[0].y + v[2].y}, a1{v[0].x - v[2].x, v[0].y - v[2].y};
+    const Cx<R> b0{v[1].x + v[3].x, v[1].y + v[3].y}, b1{v[1].x - v[3].x, v[1].y - v[3].y};
+    o[0] = Cx<R>{a0.x + b0.x, a0.y + b0.y};
+    o[2] = Cx<R>{a0.x - b0.x, a0.y - b0.y};
+    o[1] = Cx<R>{a1.x - s * b1.y, a1.y + s * b1.x};
+    o[3] = Cx<R>{a1.x + s * b1.y, a1.y - s * b1.x};
+  } else {
+#pragma unroll
+    for (int m = 0; m < RAD; ++m) {
+      double sx = (double)v[0].x, sy = (double)v[0].y;
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        const Cx<R> w = twiddle<R>(W, ((r * m) % RAD) * (N / RAD), sg);
+        sx += (double)v[r].x * (double)w.x - (double)v[r].y * (double)w.y;
+        sy += (double)v[r].x * (double)w.y + (double)v[r].y * (double)w.x;
+      }
+      o[m] = Cx<R>{(R)sx, (R)sy};
+    }
+  }
+}
+
+// One Stockham stage of radix RAD over B lines of length N held in LDS
+// (in -> out); Ns is the length of the sub-transforms already done.
+template <typename R, int RAD>
+__device__ __forceinline__ void fft_stage(const Cx<R>* in, Cx<R>* out, const Cx<double>* __restrict__ W, int N,
+                                          int B, int Ns, double sg) {
+  const int M = N / RAD;
+  const int stride = N / (Ns * RAD);  // k r stride < N for k < Ns, r < RAD
+  for (int t = threadIdx.x; t < B * M; t += blockDim.x) {
+    const int b = t / M, j = t - b * M, k = j % Ns;
+    Cx<R> v[RAD], o[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      Cx<R> x = in[b * N + j + r * M];
+      if (r > 0 && k > 0) x = cmul(x, twiddle<R>(W, k * r * stride, sg));
+      v[r] = x;
+    }
+    small_dft<R, RAD>(v, o, W, N, sg);
+    const int idxD = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) out[b * N + idxD + r * Ns] = o[r];
+  }
+}
+
+// Stage of any radix up to kMaxRadix (sizes with prime factors above 5; its
+// runtime-indexed arrays live in scratch, so only that kernel variant has it).
+template <typename R>
+__device__ void fft_stage_any(const Cx<R>* in, Cx<R>* out, const Cx<double>* __restrict__ W, int N, int B, int Ns,
+                              int Rr, double sg) {
+  const int M = N / Rr;
+  const int stride = N / (Ns * Rr);
+  for (int t = threadIdx.x; t < B * M; t += blockDim.x) {
+    const int b = t / M, j = t - b * M, k = j % Ns;
+    Cx<R> v[kMaxRadix];
+    for (int r = 0; r < Rr; ++r) {
+      Cx<R> x = in[b * N + j + r * M];
+      if (r > 0 && k > 0) x = cmul(x, twiddle<R>(W, k * r * stride, sg));
+      v[r] = x;
+    }
+    const int idxD = (j / Ns) * Ns * Rr + k;
+    for (int m = 0; m < Rr; ++m) {
+      double sx = 0.0, sy = 0.0;
+      for (int r = 0; r < Rr; ++r) {
+        const Cx<R> w = twiddle<R>(W, ((r * m) % Rr) * (N / Rr), sg);
+        sx += (double)v[r].x * (double)w.x - (double)v[r].y * (double)w.y;
+        sy += (double)v[r].x * (double)w.y + (double)v[r].y * (double)w.x;
+      }
+      out[b * N + idxD + m * Ns] = Cx<R>{(R)sx, (R)sy};
+    }
+  }
+}
+
 // One batch of B lines along `axis`, transformed with exponent sign `sgn`
 // (+1: forward of Sec. 3.1, -1: inverse without the 1/N^3), then scaled.
-template <typename R>
-__global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, FFTPlan P, int axis, int B, double sgn,
-                                                         double scale) {
+// Lines along z are contiguous; along y and x a batch is B neighbouring z
+// columns, so every row of the gather is B contiguous elements.
+template <typename R, bool ANY>
+__global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, const Cx<double>* __restrict__ W, FFTPlan P,
+                                                         int axis, int B, double sgn, double scale) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* bufA = reinterpret_cast<Cx<R>*>(smem_raw);
   Cx<R>* bufB = bufA + (size_t)B * P.N;
@@ -74,51 +176,17 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, FFTPlan P, 
   Cx<R>* in = bufA;
   Cx<R>* out = bufB;
   int Ns = 1;
-  const double twopi = 6.283185307179586476925286766559;
+  const double sg = sgn < 0.0 ? -1.0 : 1.0;
   for (int f = 0; f < P.nfac; ++f) {
     const int Rr = P.fac[f];
-    const int M = N / Rr;
-    for (int t = tid; t < B * M; t += NT) {
-      const int b = t / M, j = t % M, k = j % Ns;
-      Cx<R> v[kMaxRadix];
-      const double ang = sgn * twopi * (double)k / (double)(Ns * Rr);
-      for (int r = 0; r < Rr; ++r) {
-        Cx<R> x = in[b * N + j + r * M];
-        if (r > 0 && k > 0) {
-          double sv, cv;
-          sincos(ang * r, &sv, &cv);
-          x = cmul(x, Cx<R>{(R)cv, (R)sv});
-        }
-        v[r] = x;
-      }
-      Cx<R> o[kMaxRadix];
-      if (Rr == 2) {
-        o[0] = Cx<R>{v[0].x + v[1].x, v[0].y + v[1].y};
-        o[1] = Cx<R>{v[0].x - v[1].x, v[0].y - v[1].y};
-      } else if (Rr == 4) {
-        // e^{sgn 2 pi i m r/4}: multiplication by sgn*i for m r = 1 (mod 4)
-        const R s = (R)sgn;
-        const Cx<R> a0{v[0].x + v[2].x, v[0].y + v[2].y}, a1{v[0].x - v[2].x, v[0].y - v[2].y};
-        const Cx<R> b0{v[1].x + v[3].x, v[1].y + v[3].y}, b1{v[1].x - v[3].x, v[1].y - v[3].y};
-        // i*s*b1 = (-s b1.y, s b1.x)
-        o[0] = Cx<R>{a0.x + b0.x, a0.y + b0.y};
-        o[2] = Cx<R>{a0.x - b0.x, a0.y - b0.y};
-        o[1] = Cx<R>{a1.x - s * b1.y, a1.y + s * b1.x};
-        o[3] = Cx<R>{a1.x + s * b1.y, a1.y - s * b1.x};
-      } else {
-        for (int m = 0; m < Rr; ++m) {
-          double sx = 0.0, sy = 0.0;
-          for (int r = 0; r < Rr; ++r) {
-            double sv, cv;
-            sincos(sgn * twopi * (double)((r * m) % Rr) / (double)Rr, &sv, &cv);
-            sx += (double)v[r].x * cv - (double)v[r].y * sv;
-            sy += (double)v[r].x * sv + (double)v[r].y * cv;
-          }
-          o[m] = Cx<R>{(R)sx, (R)sy};
-        }
-      }
-      const int idxD = (j / Ns) * Ns * Rr + k;
-      for (int r = 0; r < Rr; ++r) out[b * N + idxD + r * Ns] = o[r];
+    switch (Rr) {
+      case 2: fft_stage<R, 2>(in, out, W, N, B, Ns, sg); break;
+      case 3: fft_stage<R, 3>(in, out, W, N, B, Ns, sg); break;
+      case 4: fft_stage<R, 4>(in, out, W, N, B, Ns, sg); break;
+      case 5: fft_stage<R, 5>(in, out, W, N, B, Ns, sg); break;
+      default:
+        if constexpr (ANY) fft_stage_any<R>(in, out, W, N, B, Ns, Rr, sg);
+        break;
     }
     __syncthreads();
     Cx<R>* tmp = in;
@@ -136,18 +204,32 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, FFTPlan P, 
   }
 }
 
+// Three line passes (z, y, x).  Lines per block: as many as 64 KiB of LDS
+// (two buffers) allows, fewer where that leaves under 2048 blocks, but at
+// least 8 on the strided axes so that each gathered row is 128 bytes.
 template <typename R>
-static int fft3d(Cx<R>* data, int N, double sgn, double scale, hipStream_t s) {
+static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double scale, hipStream_t s) {
   const FFTPlan P = make_plan(N);
-  for (int f = 0; f < P.nfac; ++f)
+  bool any = false;
+  for (int f = 0; f < P.nfac; ++f) {
     if (P.fac[f] > kMaxRadix) { set_error("FFT radix above 32"); return LAT_EINVAL; }
-  int B = 32;
-  while (B > 1 && (size_t)2 * B * N * sizeof(Cx<R>) > 65536) B >>= 1;
-  const size_t shm = (size_t)2 * B * N * sizeof(Cx<R>);
-  const int nblk = (int)((size_t)N * N / B);
+    any = any || P.fac[f] > 5;
+  }
+  int Bmax = 32;
+  while (Bmax > 1 && (size_t)2 * Bmax * N * sizeof(Cx<R>) > 65536) Bmax >>= 1;
+  while (Bmax > 1 && N % Bmax) Bmax >>= 1;
   for (int axis = 2; axis >= 0; --axis) {
+    const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
+    int B = Bmax;
+    while (B > minB && (size_t)N * N / B < 2048 && N % (B / 2) == 0) B >>= 1;
+    const size_t shm = (size_t)2 * B * N * sizeof(Cx<R>);
+    const int nblk = (int)((size_t)N * N / B);
+    const int nt = std::min(256, std::max(64, (B * N / 4 + 63) / 64 * 64));
     const double sc = axis == 0 ? scale : 1.0;
-    hipLaunchKernelGGL(fft_lines_kernel<R>, dim3(nblk), dim3(256), shm, s, data, P, axis, B, sgn, sc);
+    if (any)
+      hipLaunchKernelGGL((fft_lines_kernel<R, true>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B, sgn, sc);
+    else
+      hipLaunchKernelGGL((fft_lines_kernel<R, false>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B, sgn, sc);
     CL_HIP(hipGetLastError());
   }
   return LAT_OK;
@@ -164,15 +246,19 @@ __global__ void real_to_complex_kernel(const T* f, Cx<R>* c, int64_t V) {
 
 __device__ __forceinline__ int wrapk(int i, int N) { return i <= N / 2 ? i : i - N; }
 
-// Per-block shell histograms of |f(n~)|^2, sum of |n~| and mode counts.
-template <typename R>
+// Per-block shell histograms of |f(n~)|^2 and, with GEOM, of the shell
+// geometry (sum of |n~| and mode counts), which does not depend on the field.
+template <typename R, bool GEOM>
 __global__ __launch_bounds__(256) void bin_kernel(const Cx<R>* F, int N, int nbins, int64_t per_block,
                                                   double* pS, double* pK, unsigned long long* pC) {
   extern __shared__ unsigned char smem_raw[];
   double* hS = reinterpret_cast<double*>(smem_raw);
   double* hK = hS + nbins;
   unsigned long long* hC = reinterpret_cast<unsigned long long*>(hK + nbins);
-  for (int b = threadIdx.x; b < nbins; b += blockDim.x) { hS[b] = 0.0; hK[b] = 0.0; hC[b] = 0ull; }
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    hS[b] = 0.0;
+    if (GEOM) { hK[b] = 0.0; hC[b] = 0ull; }
+  }
   __syncthreads();
   const int64_t V = (int64_t)N * N * N;
   const int64_t i0 = (int64_t)blockIdx.x * per_block;
@@ -187,38 +273,68 @@ __global__ __launch_bounds__(256) void bin_kernel(const Cx<R>* F, int N, int nbi
     const Cx<R> v = F[i];
     const double p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     atomicAdd(&hS[b], p);
-    atomicAdd(&hK[b], sqrt((double)n2s));
-    atomicAdd(&hC[b], 1ull);
+    if (GEOM) {
+      atomicAdd(&hK[b], sqrt((double)n2s));
+      atomicAdd(&hC[b], 1ull);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
     pS[(size_t)blockIdx.x * nbins + b] = hS[b];
-    pK[(size_t)blockIdx.x * nbins + b] = hK[b];
-    pC[(size_t)blockIdx.x * nbins + b] = hC[b];
+    if (GEOM) {
+      pK[(size_t)blockIdx.x * nbins + b] = hK[b];
+      pC[(size_t)blockIdx.x * nbins + b] = hC[b];
+    }
   }
 }
 
 // Sum the per-block histograms in block order and normalise (Sec. 3.1):
 //   k[b] = k_IR <|n~|>_shell,
 //   delta[b] = (k_IR b)^3/(2 pi^2) (dx/N)^3 S_b / (4 pi b^2)   (b >= 1).
-__global__ void bin_sum_kernel(const double* pS, const double* pK, const unsigned long long* pC, int nblk,
-                               int nbins, double kIR, double norm, double* S, double* K, double* D,
-                               unsigned long long* C) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
+// One block per shell; each thread sums a strided subset of the per-block
+// histograms in block order, then a fixed-shape tree in LDS (deterministic).
+// Without GEOM, K and C keep the values of the first (GEOM) call.
+template <bool GEOM>
+__global__ __launch_bounds__(256) void bin_sum_kernel(const double* pS, const double* pK,
+                                                      const unsigned long long* pC, int nblk, int nbins, double kIR,
+                                                      double norm, double* S, double* K, double* D,
+                                                      unsigned long long* C) {
+  __shared__ double rs[256], rk[256];
+  __shared__ unsigned long long rc[256];
+  const int b = blockIdx.x, t = threadIdx.x;
   double s = 0.0, k = 0.0;
   unsigned long long c = 0;
-  for (int j = 0; j < nblk; ++j) {
+  for (int j = t; j < nblk; j += 256) {
     s += pS[(size_t)j * nbins + b];
-    k += pK[(size_t)j * nbins + b];
-    c += pC[(size_t)j * nbins + b];
+    if (GEOM) {
+      k += pK[(size_t)j * nbins + b];
+      c += pC[(size_t)j * nbins + b];
+    }
   }
-  const double pi = 3.14159265358979323846264338327950288;
-  S[b] = s;
-  K[b] = c ? kIR * k / (double)c : 0.0;
-  const double kb = kIR * (double)b;
-  D[b] = b > 0 ? kb * kb * kb * norm * s / (4.0 * pi * (double)b * (double)b) : 0.0;
-  C[b] = c;
+  rs[t] = s;
+  rk[t] = k;
+  rc[t] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      rs[t] += rs[t + w];
+      rk[t] += rk[t + w];
+      rc[t] += rc[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double pi = 3.14159265358979323846264338327950288;
+    s = rs[0];
+    S[b] = s;
+    const double kb = kIR * (double)b;
+    D[b] = b > 0 ? kb * kb * kb * norm * s / (4.0 * pi * (double)b * (double)b) : 0.0;
+    if (GEOM) {
+      c = rc[0];
+      K[b] = c ? kIR * rk[0] / (double)c : 0.0;
+      C[b] = c;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -316,7 +432,13 @@ static double curvature_host(const lattice_params& p, int f) {
 }
 
 int run_fft3d(lattice* h, int sign, double scale) {
-  return fft3d(reinterpret_cast<Cx<double>*>(h->fft), h->p.N, (double)sign, scale, h->stream);
+  Cx<double>* W = reinterpret_cast<Cx<double>*>(h->twiddle);
+  if (!h->twiddle_ready) {
+    hipLaunchKernelGGL(twiddle_kernel, dim3((h->p.N + 255) / 256), dim3(256), 0, h->stream, W, h->p.N);
+    CL_HIP(hipGetLastError());
+    h->twiddle_ready = true;
+  }
+  return fft3d(reinterpret_cast<Cx<double>*>(h->fft), W, h->p.N, (double)sign, scale, h->stream);
 }
 
 // Homogeneous values plus (optionally) vacuum fluctuations for the scalar
@@ -438,12 +560,24 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
   double* D = K + nb;
   unsigned long long* C = (unsigned long long*)(D + nb);
   const size_t shm = (size_t)nb * 24;
-  hipLaunchKernelGGL(bin_kernel<double>, dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK, pC);
-  CL_HIP(hipGetLastError());
   const double norm = std::pow(h->dx / N, 3.0) / (2.0 * M_PI * M_PI);
-  hipLaunchKernelGGL(bin_sum_kernel, dim3((nb + 127) / 128), dim3(128), 0, h->stream, pS, pK, pC, nblk, nb,
-                     h->p.kIR, norm, S, K, D, C);
-  CL_HIP(hipGetLastError());
+  // the shell geometry (K, C) is binned on the first spectrum only; later
+  // calls find it in place (nothing else writes this region)
+  if (!h->spec_geom_ready) {
+    hipLaunchKernelGGL((bin_kernel<double, true>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK, pC);
+    CL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bin_sum_kernel<true>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, nblk, nb, h->p.kIR,
+                       norm, S, K, D, C);
+    CL_HIP(hipGetLastError());
+    h->spec_geom_ready = true;
+  } else {
+    hipLaunchKernelGGL((bin_kernel<double, false>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK,
+                       pC);
+    CL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bin_sum_kernel<false>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, nblk, nb, h->p.kIR,
+                       norm, S, K, D, C);
+    CL_HIP(hipGetLastError());
+  }
   *out = Bins{S, K, D, C, nb};
   return LAT_OK;
 }
@@ -451,34 +585,48 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
 // log10 of the mode-averaged spectrum kbar^3 norm S_b / C_b at nk log-spaced
 // k from kIR to kIR (nb - 1), linear in log k between the centres of shells
 // b >= 1 with modes and positive power, constant beyond the end shells.
-// One thread per output wavenumber; the shells are scanned in order.
-__global__ void logk_kernel(const double* S, const double* K, const unsigned long long* C, int nb, double norm,
-                            double kIR, int nk, float* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nk) return;
-  const double kmax = kIR * (double)(nb - 1);
-  const double x = log10(kIR) + (log10(kmax) - log10(kIR)) * (double)j / (double)(nk - 1);
-  double x0 = 0.0, y0 = 0.0, last = 0.0;
-  bool have = false, done = false;
-  double res = 0.0;
-  for (int b = 1; b < nb && !done; ++b) {
-    if (C[b] == 0ull || !(S[b] > 0.0)) continue;
-    const double kb = K[b];
-    const double xb = log10(kb);
-    const double yb = log10(kb * kb * kb * norm * S[b] / (double)C[b]);
-    if (!have) {
-      if (x <= xb) { res = yb; done = true; }
-    } else if (x <= xb) {
-      res = y0 + (x - x0) / (xb - x0) * (yb - y0);
-      done = true;
-    }
-    have = true;
-    x0 = xb;
-    y0 = yb;
-    last = yb;
+// One block: the usable shells are compacted in order into LDS (their
+// centres increase with b), then each output finds its bracket by bisection.
+constexpr int kLogkMaxBins = 1024;
+__global__ __launch_bounds__(1024) void logk_kernel(const double* S, const double* K, const unsigned long long* C,
+                                                    int nb, double norm, double kIR, int nk, float* out) {
+  __shared__ double xs[kLogkMaxBins], ys[kLogkMaxBins];
+  __shared__ int pos[kLogkMaxBins];
+  const int t = threadIdx.x;
+  const bool ok = t >= 1 && t < nb && C[t] != 0ull && S[t] > 0.0;
+  pos[t] = ok ? 1 : 0;
+  __syncthreads();
+  for (int w = 1; w < kLogkMaxBins; w <<= 1) {  // inclusive prefix sum of the flags
+    const int v = t >= w ? pos[t - w] : 0;
+    __syncthreads();
+    pos[t] += v;
+    __syncthreads();
   }
-  if (!done) res = have ? last : -INFINITY;
-  out[j] = (float)res;
+  const int nv = pos[kLogkMaxBins - 1];
+  if (ok) {
+    const double kb = K[t];
+    xs[pos[t] - 1] = log10(kb);
+    ys[pos[t] - 1] = log10(kb * kb * kb * norm * S[t] / (double)C[t]);
+  }
+  __syncthreads();
+  const double lo = log10(kIR), hi = log10(kIR * (double)(nb - 1));
+  for (int j = t; j < nk; j += blockDim.x) {
+    const double x = lo + (hi - lo) * (double)j / (double)(nk - 1);
+    double res;
+    if (nv == 0) {
+      res = -INFINITY;
+    } else {
+      int a = 0, e = nv;  // first i with x <= xs[i]
+      while (a < e) {
+        const int m = (a + e) >> 1;
+        if (x <= xs[m]) e = m; else a = m + 1;
+      }
+      if (a == 0) res = ys[0];
+      else if (a == nv) res = ys[nv - 1];
+      else res = ys[a - 1] + (x - xs[a - 1]) / (xs[a] - xs[a - 1]) * (ys[a] - ys[a - 1]);
+    }
+    out[j] = (float)res;
+  }
 }
 
 }  // namespace
@@ -509,7 +657,8 @@ extern "C" int lattice_spectrum_logk(lattice_t* h, int which, int nk, float* dev
   int rc = spectrum_bins(h, which, &B);
   if (rc) return rc;
   const double norm = std::pow(h->dx / h->p.N, 3.0) / (2.0 * M_PI * M_PI);
-  hipLaunchKernelGGL(logk_kernel, dim3((nk + 63) / 64), dim3(64), 0, h->stream, B.S, B.K, B.C, B.nb, norm,
+  if (B.nb > kLogkMaxBins) { set_error("spectrum_logk: too many shells"); return LAT_EINVAL; }
+  hipLaunchKernelGGL(logk_kernel, dim3(1), dim3(kLogkMaxBins), 0, h->stream, B.S, B.K, B.C, B.nb, norm,
                      h->p.kIR, nk, dev_out);
   CL_HIP(hipGetLastError());
   return LAT_OK;

@@ -31,6 +31,9 @@ struct lattice {
   size_t comp_bytes;
   void* buf[2][16];     // ping-pong state buffers, per component
   void* fft;            // complex FP64 scratch of N^3 entries
+  void* twiddle;        // N complex FP64 roots of unity for the FFT
+  bool twiddle_ready = false;
+  bool spec_geom_ready = false;  // shell centres and mode counts binned
   int cur;
   double dx;
   std::vector<double> weights;

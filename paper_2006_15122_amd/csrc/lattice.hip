@@ -66,7 +66,6 @@ int validate(const lattice_params* p) {
   if (p->model == LAT_MODEL_U1 && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
   if (p->N < 32 || p->N > 1024 || p->N % 32 != 0) { set_error("N must be a multiple of 32 in [32, 1024]"); return LAT_EINVAL; }
   if (p->integrator < LAT_LF2 || p->integrator > LAT_VV10) { set_error("unknown integrator"); return LAT_EINVAL; }
-  if (p->model == LAT_MODEL_U1 && p->integrator != LAT_LF2) { set_error("U1 model supports LAT_LF2"); return LAT_EINVAL; }
   if (p->precision != LAT_FP32 && p->precision != LAT_FP64) { set_error("unknown precision"); return LAT_EINVAL; }
   if (!(p->kIR > 0.0) || !(p->dt > 0.0)) { set_error("kIR and dt must be positive"); return LAT_EINVAL; }
   const double dx = 2.0 * M_PI / (p->kIR * p->N);
@@ -105,6 +104,7 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, 
   o += (size_t)nc * (*comp_bytes);
   *off_fft = o;
   o = align_up(o + (size_t)V * 16, 256);
+  o = align_up(o + (size_t)N * 16, 256);  // FFT twiddle table, right after the scratch
   *total = o;
   *ncomp = nc;
   *max_blocks = mb;
@@ -164,6 +164,7 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
     L->buf[1][c] = ws + off_b1 + (size_t)c * cb;
   }
   L->fft = ws + off_fft;
+  L->twiddle = ws + off_fft + align_up((size_t)p->N * p->N * p->N * 16, 256);
   L->cur = 0;
   L->dx = 2.0 * M_PI / (p->kIR * p->N);
   L->weights = vv_weights(p->integrator);
@@ -200,7 +201,6 @@ int lattice_destroy(lattice_t* h) {
 int lattice_pass_timer(lattice_t* h, int32_t max_launches) {
   if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
   if (max_launches < 0 || max_launches > (1 << 20)) { set_error("max_launches must be in [0, 2^20]"); return LAT_EINVAL; }
-  if (h->p.model != LAT_MODEL_SCALAR) { set_error("pass timing covers the scalar models"); return LAT_EINVAL; }
   CL_HIP(hipStreamSynchronize(h->stream));
   drop_timer(h);
   h->timer.reserve(2 * (size_t)max_launches);
