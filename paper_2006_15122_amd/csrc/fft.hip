@@ -146,6 +146,103 @@ __device__ void fft_stage_any(const Cx<R>* in, Cx<R>* out, const Cx<double>* __r
   }
 }
 
+// In-place variant of a stage for the single-buffer kernel: every thread
+// takes up to PMAX butterflies' inputs (twiddled) into registers, the block
+// synchronises, then the outputs overwrite the same LDS lines.  The launch
+// guarantees B N / RAD <= PMAX blockDim.x.
+template <typename R, int RAD, int PMAX>
+__device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* Wl, int N, int B, int Ns,
+                                                  double sg) {
+  const int M = N / RAD;
+  const int stride = N / (Ns * RAD);
+  const int nbf = B * M;
+  Cx<R> v[PMAX][RAD];
+#pragma unroll
+  for (int p = 0; p < PMAX; ++p) {
+    const int t = threadIdx.x + p * blockDim.x;
+    if (t < nbf) {
+      const int b = t / M, j = t - b * M, k = j % Ns;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        Cx<R> x = buf[b * N + j + r * M];
+        if (r > 0 && k > 0) x = cmul(x, twiddle<R>(Wl, k * r * stride, sg));
+        v[p][r] = x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PMAX; ++p) {
+    const int t = threadIdx.x + p * blockDim.x;
+    if (t < nbf) {
+      const int b = t / M, j = t - b * M, k = j % Ns;
+      Cx<R> o[RAD];
+      small_dft<R, RAD>(v[p], o, Wl, N, sg);
+      const int idxD = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[b * N + idxD + r * Ns] = o[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Butterflies per thread the in-place stages hold in registers, by radix.
+__host__ __device__ constexpr int inplace_pmax(int rad) { return rad == 2 ? 4 : rad == 3 ? 3 : 2; }
+
+// Sizes whose factors are all 2, 3, 4 or 5: one LDS buffer of B lines plus
+// the N roots of unity, so that more blocks fit on a compute unit.
+template <typename R, bool POW2>
+__global__ __launch_bounds__(256) void fft_lines_inplace_kernel(Cx<R>* data, const Cx<double>* __restrict__ W,
+                                                                 FFTPlan P, int axis, int B, double sgn,
+                                                                 double scale) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = P.N;
+  Cx<double>* Wl = reinterpret_cast<Cx<double>*>(smem_raw);
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(Wl + N);
+  const size_t NN = (size_t)N * N;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int lb = blockIdx.x;
+  const int nzb = N / B;
+  auto addr = [&](int b, int i) -> size_t {
+    if (axis == 2) return ((size_t)lb * B + b) * N + i;
+    const int o = lb / nzb, z0 = (lb % nzb) * B;
+    if (axis == 1) return (size_t)o * NN + (size_t)i * N + z0 + b;
+    return (size_t)i * NN + (size_t)o * N + z0 + b;
+  };
+  for (int m = tid; m < N; m += NT) Wl[m] = W[m];
+  for (int e = tid; e < B * N; e += NT) {
+    int b, i;
+    if (axis == 2) { b = e / N; i = e % N; } else { i = e / B; b = e % B; }
+    buf[b * N + i] = data[addr(b, i)];
+  }
+  __syncthreads();
+  int Ns = 1;
+  const double sg = sgn < 0.0 ? -1.0 : 1.0;
+  for (int f = 0; f < P.nfac; ++f) {
+    const int Rr = P.fac[f];
+    if constexpr (POW2) {  // power-of-two sizes: only radices 4 and 2 (fewer registers)
+      if (Rr == 4) fft_stage_inplace<R, 4, inplace_pmax(4)>(buf, Wl, N, B, Ns, sg);
+      else fft_stage_inplace<R, 2, inplace_pmax(2)>(buf, Wl, N, B, Ns, sg);
+    } else {
+      switch (Rr) {
+        case 2: fft_stage_inplace<R, 2, inplace_pmax(2)>(buf, Wl, N, B, Ns, sg); break;
+        case 3: fft_stage_inplace<R, 3, inplace_pmax(3)>(buf, Wl, N, B, Ns, sg); break;
+        case 4: fft_stage_inplace<R, 4, inplace_pmax(4)>(buf, Wl, N, B, Ns, sg); break;
+        default: fft_stage_inplace<R, 5, inplace_pmax(5)>(buf, Wl, N, B, Ns, sg); break;
+      }
+    }
+    Ns *= Rr;
+  }
+  for (int e = tid; e < B * N; e += NT) {
+    int b, i;
+    if (axis == 2) { b = e / N; i = e % N; } else { i = e / B; b = e % B; }
+    Cx<R> v = buf[b * N + i];
+    v.x = (R)(v.x * scale);
+    v.y = (R)(v.y * scale);
+    data[addr(b, i)] = v;
+  }
+}
+
 // One batch of B lines along `axis`, transformed with exponent sign `sgn`
 // (+1: forward of Sec. 3.1, -1: inverse without the 1/N^3), then scaled.
 // Lines along z are contiguous; along y and x a batch is B neighbouring z
@@ -204,9 +301,11 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, const Cx<do
   }
 }
 
-// Three line passes (z, y, x).  Lines per block: as many as 64 KiB of LDS
-// (two buffers) allows, fewer where that leaves under 2048 blocks, but at
-// least 8 on the strided axes so that each gathered row is 128 bytes.
+// Three line passes (z, y, x).  Lines per block B: the most that fit (one
+// buffer of at most 2048 elements plus the roots for the in-place kernel,
+// two buffers within 64 KiB for the generic one), fewer where that leaves
+// under 2048 blocks, but at least 8 on the strided axes so that each
+// gathered row is 128 bytes.
 template <typename R>
 static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double scale, hipStream_t s) {
   const FFTPlan P = make_plan(N);
@@ -216,20 +315,35 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
     any = any || P.fac[f] > 5;
   }
   int Bmax = 32;
-  while (Bmax > 1 && (size_t)2 * Bmax * N * sizeof(Cx<R>) > 65536) Bmax >>= 1;
+  if (any)
+    while (Bmax > 1 && (size_t)2 * Bmax * N * sizeof(Cx<R>) > 65536) Bmax >>= 1;
+  else
+    while (Bmax > 1 && Bmax * N > 2048) Bmax >>= 1;
   while (Bmax > 1 && N % Bmax) Bmax >>= 1;
   for (int axis = 2; axis >= 0; --axis) {
     const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
     int B = Bmax;
-    while (B > minB && (size_t)N * N / B < 2048 && N % (B / 2) == 0) B >>= 1;
-    const size_t shm = (size_t)2 * B * N * sizeof(Cx<R>);
+    while (B > minB && (size_t)N * N / B < 2048) B >>= 1;
     const int nblk = (int)((size_t)N * N / B);
     const int nt = std::min(256, std::max(64, (B * N / 4 + 63) / 64 * 64));
     const double sc = axis == 0 ? scale : 1.0;
-    if (any)
+    if (any) {
+      const size_t shm = (size_t)2 * B * N * sizeof(Cx<R>);
       hipLaunchKernelGGL((fft_lines_kernel<R, true>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B, sgn, sc);
-    else
-      hipLaunchKernelGGL((fft_lines_kernel<R, false>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B, sgn, sc);
+    } else {
+      for (int f = 0; f < P.nfac; ++f)
+        if ((B * N / P.fac[f] + nt - 1) / nt > inplace_pmax(P.fac[f])) {
+          set_error("FFT: in-place stage does not cover the batch");
+          return LAT_EINVAL;
+        }
+      const size_t shm = (size_t)N * sizeof(Cx<double>) + (size_t)B * N * sizeof(Cx<R>);
+      if ((N & (N - 1)) == 0)
+        hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
+                           sgn, sc);
+      else
+        hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
+                           sgn, sc);
+    }
     CL_HIP(hipGetLastError());
   }
   return LAT_OK;
