@@ -53,6 +53,17 @@ struct PassDesc {
   int update;   // store a, b, eta into DevState
 };
 
+// The finish of the previous pass, carried by the next pass of a chain: every
+// block reduces that pass's partial records itself (same fixed order, so the
+// same a and b in every block) and block 0 stores the resulting state in
+// `out`.  partials == nullptr: nothing pending, a and b come from st.
+struct PrevPass {
+  const double* partials;
+  int nblocks;
+  PassDesc pd;
+  DevState* out;
+};
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), device and host.
 struct Philox4 {
   uint32_t v[4];

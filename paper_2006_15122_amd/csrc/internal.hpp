@@ -23,8 +23,10 @@ struct lattice {
   lattice_params p;
   hipStream_t stream;
   char* ws;
-  cl::DevState* st;
+  cl::DevState* st;     // state of the lattice between calls
+  cl::DevState* st2;    // second state slot of a chain of passes
   double* partials;
+  double* partials2;    // partial records of every other pass in a chain
   char* spec;           // spectrum partial histograms
   int64_t max_blocks;
   int ncomp;
@@ -56,7 +58,8 @@ int upload_components(lattice* h, const double* const* comps, int n);
 int download_components(lattice* h, double* const* comps, int n);
 int upload_scalars(lattice* h, double a, double b, double eta);
 int init_state(lattice* h);
-int scalar_pass(lattice* h, const PassDesc& pd, bool full = false);
+struct PassChain;
+int scalar_pass(lattice* h, const PassDesc& pd, bool full = false, PassChain* chain = nullptr);
 int scalar_step(lattice* h, int64_t n);
 int scalar_energies(lattice* h);
 int u1_step(lattice* h, int64_t n);
@@ -73,6 +76,8 @@ void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,
                               int ry, int xc, int swizzle, const double* phys, int expand, const PassDesc& pd,
                               double* partials, DevState* st, hipStream_t s, int* nblocks_out, int full,
-                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                              hipEvent_t ev0, hipEvent_t ev1, const PrevPass& prev, DevState* fin);
+hipError_t launch_scalar_finish(int fp32, int nf, int N, const double* phys, int expand, const PassDesc& pd,
+                                double* partials, int nblocks, DevState* in, DevState* out, hipStream_t s);
 
 }  // namespace cl

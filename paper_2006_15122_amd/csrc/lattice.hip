@@ -77,10 +77,11 @@ int validate(const lattice_params* p) {
 }
 
 // Workspace layout (each region 256-byte aligned):
-//   DevState | pass partials | spectrum partials | state buffer 0 | state buffer 1 | FFT scratch
+//   2 DevState | pass partials | chain partials | spectrum partials | state buffer 0 | state buffer 1 |
+//   FFT scratch | FFT roots
 static int spec_bins(int N) { return (int)std::floor(std::sqrt(3.0) * N / 2.0) + 1; }
 
-static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, size_t* off_buf0,
+static void layout(const lattice_params* p, size_t* off_part, size_t* off_part2, size_t* off_spec, size_t* off_buf0,
                    size_t* off_buf1, size_t* off_fft, size_t* total, size_t* comp_bytes, int* ncomp,
                    int64_t* max_blocks) {
   const int64_t N = p->N;
@@ -92,9 +93,12 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_spec, 
   // least 32 x 8 x 4 sites; the U(1) site kernels write up to 16 per block of
   // 256 sites
   const size_t part_doubles = std::max((size_t)mb * 32, (size_t)(V / 256) * 16);
-  size_t o = align_up(sizeof(DevState), 256);
+  size_t o = align_up(2 * sizeof(DevState), 256);
   *off_part = o;
   o = align_up(o + part_doubles * sizeof(double), 256);
+  // every other pass of a chain writes its 4 stepping sums per block here
+  *off_part2 = o;
+  o = align_up(o + (size_t)mb * 4 * sizeof(double), 256);
   *off_spec = o;
   o = align_up(o + (size_t)(kSpecBlocks + 2) * spec_bins((int)N) * 24, 256);
   *off_buf0 = o;
@@ -127,10 +131,10 @@ int lattice_workspace_size(const lattice_params* p, size_t* bytes) {
   const int rc = cl::validate(p);
   if (rc) return rc;
   if (!bytes) { set_error("bytes is NULL"); return LAT_EINVAL; }
-  size_t a, b, c, d, e, t, cb;
+  size_t a, a2, b, c, d, e, t, cb;
   int nc;
   int64_t mb;
-  layout(p, &a, &e, &b, &c, &d, &t, &cb, &nc, &mb);
+  layout(p, &a, &a2, &e, &b, &c, &d, &t, &cb, &nc, &mb);
   *bytes = t;
   return LAT_OK;
 }
@@ -139,10 +143,10 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   int rc = validate(p);
   if (rc) return rc;
   if (!out || !dev_ws) { set_error("out or dev_ws is NULL"); return LAT_EINVAL; }
-  size_t off_part, off_spec, off_b0, off_b1, off_fft, total, cb;
+  size_t off_part, off_part2, off_spec, off_b0, off_b1, off_fft, total, cb;
   int nc;
   int64_t mb;
-  layout(p, &off_part, &off_spec, &off_b0, &off_b1, &off_fft, &total, &cb, &nc, &mb);
+  layout(p, &off_part, &off_part2, &off_spec, &off_b0, &off_b1, &off_fft, &total, &cb, &nc, &mb);
   if (ws_bytes < total) {
     set_error("workspace too small: need " + std::to_string(total) + " bytes");
     return LAT_ENOMEM;
@@ -154,7 +158,9 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   char* ws = (char*)dev_ws;
   L->ws = ws;
   L->st = (DevState*)ws;
+  L->st2 = L->st + 1;
   L->partials = (double*)(ws + off_part);
+  L->partials2 = (double*)(ws + off_part2);
   L->spec = ws + off_spec;
   L->max_blocks = mb;
   L->ncomp = nc;
@@ -429,7 +435,17 @@ void phys_of(const lattice* h, double* phys) {
   phys[7] = h->p.dt;
 }
 
-int scalar_pass(lattice* h, const PassDesc& pd, bool full) {
+// A chain of stepping passes whose finishes are deferred: pass k reduces the
+// partial records of pass k-1 at its start (PrevPass), the records alternate
+// between two regions and the state between two slots, and one finish kernel
+// closes the chain after its last pass.
+struct PassChain {
+  int k = 0;       // passes launched
+  int rd = 0;      // state slot the next pass starts from (0: h->st, 1: h->st2)
+  PrevPass prev{};  // finish still to be applied
+};
+
+int scalar_pass(lattice* h, const PassDesc& pd, bool full, PassChain* chain) {
   double phys[8];
   phys_of(h, phys);
   const int nf = h->p.nf;
@@ -450,14 +466,32 @@ int scalar_pass(lattice* h, const PassDesc& pd, bool full) {
     ev1 = h->timer[2 * h->timer_used + 1];
     ++h->timer_used;
   }
+  DevState* slot[2] = {h->st, h->st2};
+  DevState* st = h->st;
+  DevState* fin = h->st;
+  double* part = h->partials;
+  PrevPass prev{};
+  if (chain) {
+    if (full) { set_error("observation passes do not chain"); return LAT_EINVAL; }
+    st = slot[chain->rd];
+    part = (chain->k & 1) ? h->partials2 : h->partials;
+    prev = chain->prev;
+    if (prev.partials) prev.out = slot[1 - chain->rd];
+    fin = nullptr;
+  }
   hipError_t e = launch_scalar_pass(h->p.precision == LAT_FP32, nf, src, dst, h->p.N, h->tile.tz, h->tile.by,
-                                    h->tile.ry, h->tile.xc, 1, phys, h->p.expansion, pd, h->partials, h->st,
-                                    h->stream, &nb, full ? 1 : 0, ev0, ev1);
+                                    h->tile.ry, h->tile.xc, 1, phys, h->p.expansion, pd, part, st, h->stream, &nb,
+                                    full ? 1 : 0, ev0, ev1, prev, fin);
   if (e != hipSuccess) {
     set_error(std::string("scalar pass launch: ") + hipGetErrorString(e));
     return LAT_EHIP;
   }
   if (pd.write) h->cur ^= 1;
+  if (chain) {
+    if (prev.partials) chain->rd ^= 1;
+    chain->prev = PrevPass{part, nb, pd, nullptr};
+    ++chain->k;
+  }
   return LAT_OK;
 }
 
@@ -502,9 +536,23 @@ std::vector<PassDesc> pass_schedule(int integrator, const std::vector<double>& w
 
 int scalar_step(lattice* h, int64_t n) {
   const std::vector<PassDesc> sched = pass_schedule(h->p.integrator, h->weights, &h->staggered, n);
+  PassChain chain;
   for (const PassDesc& pd : sched) {
-    const int rc = scalar_pass(h, pd);
+    const int rc = scalar_pass(h, pd, false, &chain);
     if (rc) return rc;
+  }
+  if (chain.k > 0) {
+    // the last pass's finish, from the slot it started from into h->st
+    double phys[8];
+    phys_of(h, phys);
+    DevState* slot[2] = {h->st, h->st2};
+    const hipError_t e = launch_scalar_finish(h->p.precision == LAT_FP32, h->p.nf, h->p.N, phys, h->p.expansion,
+                                              chain.prev.pd, const_cast<double*>(chain.prev.partials),
+                                              chain.prev.nblocks, slot[chain.rd], h->st, h->stream);
+    if (e != hipSuccess) {
+      set_error(std::string("finish launch: ") + hipGetErrorString(e));
+      return LAT_EHIP;
+    }
   }
   h->step += n;
   return LAT_OK;

@@ -37,16 +37,19 @@ struct Shape {
 
 // With ev0/ev1 the dispatch itself carries the device's start and stop
 // timestamps of the pass kernel (hipExtLaunchKernel), nothing else changes.
+// fin: where the finish kernel after the pass stores the state (nullptr: no
+// finish kernel; the next pass of the chain carries it).
 template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
-hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                        DevState* fin) {
   if (ev0)
     hipExtLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, ev0,
                           ev1, 0, A);
   else
     hipLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(1024), 0, s, A, nblocks);
+  if (e != hipSuccess || !fin) return e;
+  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
   return hipGetLastError();
 }
 
@@ -75,10 +78,11 @@ static const int kObsTz = 32, kObsBy = 8, kObsRy = 2, kObsXc = 8;
 
 template <typename T, int NF>
 hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s, bool full,
-                                hipEvent_t ev0, hipEvent_t ev1) {
-  if (full) return launch_shape<T, NF, true, 32, 8, 2>(A, nblocks, s, ev0, ev1);
+                                hipEvent_t ev0, hipEvent_t ev1, DevState* fin) {
+  if (full) return launch_shape<T, NF, true, 32, 8, 2>(A, nblocks, s, ev0, ev1, fin);
 #define X(TT, NFF, a, b, c) \
-  if (sh.tz == a && sh.by == b && sh.ry == c) return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s, ev0, ev1);
+  if (sh.tz == a && sh.by == b && sh.ry == c)  \
+    return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s, ev0, ev1, fin);
   if constexpr (std::is_same<T, float>::value && NF == 2) {
     CL_SHAPES_MAIN(X, T, NF)
   } else {
@@ -103,7 +107,9 @@ void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry) {
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz,
                               int by, int ry, int xc, int swizzle, const double* phys, int expand,
                               const PassDesc& pd, double* partials, DevState* st, hipStream_t s,
-                              int* nblocks_out, int full, hipEvent_t ev0, hipEvent_t ev1) {
+                              int* nblocks_out, int full, hipEvent_t ev0, hipEvent_t ev1, const PrevPass& prev,
+                              DevState* fin) {
+  if (full && (prev.partials || !fin)) return hipErrorInvalidValue;  // observation passes finish themselves
   if (full) {
     tz = kObsTz;
     by = kObsBy;
@@ -136,18 +142,49 @@ hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* co
     A.pd = pd;
     A.partials = partials;
     A.st = st;
+    A.prev = prev;
   };
   if (fp32) {
     ScalarArgs<float> A;
     fill(A, (float*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s, full, ev0, ev1)
-                   : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s, full, ev0, ev1);
+    return nf == 1 ? launch_scalar_pass_t<float, 1>(A, sh, nblocks, s, full, ev0, ev1, fin)
+                   : launch_scalar_pass_t<float, 2>(A, sh, nblocks, s, full, ev0, ev1, fin);
   } else {
     ScalarArgs<double> A;
     fill(A, (double*)nullptr);
-    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s, full, ev0, ev1)
-                   : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s, full, ev0, ev1);
+    return nf == 1 ? launch_scalar_pass_t<double, 1>(A, sh, nblocks, s, full, ev0, ev1, fin)
+                   : launch_scalar_pass_t<double, 2>(A, sh, nblocks, s, full, ev0, ev1, fin);
   }
+}
+
+// Finish kernel alone: the pass `pd` that wrote `nblocks` partial records
+// started from state `in`; the result goes to `out` (the trailing finish of a
+// chain of passes).
+hipError_t launch_scalar_finish(int fp32, int nf, int N, const double* phys, int expand, const PassDesc& pd,
+                                double* partials, int nblocks, DevState* in, DevState* out, hipStream_t s) {
+  auto go = [&](auto* tag) -> hipError_t {
+    using TT = std::remove_pointer_t<decltype(tag)>;
+    ScalarArgs<TT> A = {};
+    A.N = N;
+    A.dx = phys[0];
+    A.alpha = phys[1];
+    A.fmp2 = phys[2];
+    A.m2_0 = phys[3];
+    A.m2_1 = phys[4];
+    A.lam = phys[5];
+    A.q = phys[6];
+    A.h = phys[7];
+    A.expand = expand;
+    A.pd = pd;
+    A.partials = partials;
+    A.st = in;
+    if (nf == 1)
+      hipLaunchKernelGGL((scalar_finish_kernel<TT, 1, false>), dim3(1), dim3(1024), 0, s, A, nblocks, out);
+    else
+      hipLaunchKernelGGL((scalar_finish_kernel<TT, 2, false>), dim3(1), dim3(1024), 0, s, A, nblocks, out);
+    return hipGetLastError();
+  };
+  return fp32 ? go((float*)nullptr) : go((double*)nullptr);
 }
 
 }  // namespace cl

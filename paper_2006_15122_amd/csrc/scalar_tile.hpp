@@ -11,7 +11,6 @@
 
 namespace cl {
 
-
 template <typename T>
 struct ScalarArgs {
   const T* src[4];   // phi_0, phi_1, pi_0, pi_1 (nf = 1 uses entries 0 and 2)
@@ -24,6 +23,7 @@ struct ScalarArgs {
   PassDesc pd;
   double* partials;  // [gridDim.x][NACC]
   DevState* st;
+  PrevPass prev;     // single-lattice passes only; batched launches leave it empty
 };
 
 // Accumulators of one pass.  FULL (observation passes): per field
@@ -110,15 +110,19 @@ __device__ bool reduce_partials(const double* partials, int first, int nb, doubl
   return true;
 }
 
-// From the lattice sums S of one pass: the volume averages (Sec. 4.3.2/4.4) and
-// the FP64 advance of b,
+// From the lattice sums S of pass `pd`, which started from state `in`: the
+// volume averages (Sec. 4.3.2/4.4) and the FP64 advance of b,
 //   b_out = b_in + (wk1 + wk2) h K_a(a', E),
 //   K_a = (1/3)(f*/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V].
+// The resulting state goes to `out` (may be `in`; nullptr: not stored); a and b
+// after the pass are returned in a_next, b_next.
 template <typename T, int NF, bool FULL>
-__device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<NF, FULL>::N]) {
+__device__ void finish_state(const ScalarArgs<T>& A, const PassDesc& pd, const DevState* in,
+                             const double (&S)[Acc<NF, FULL>::N], DevState* out, double& a_next,
+                             double& b_next) {
   constexpr int NACC = Acc<NF, FULL>::N;
-  const double a_in = A.st->a, b_in = A.st->b;
-  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double a_in = in->a, b_in = in->b, eta_in = in->eta;
+  const double anew = A.expand ? a_in + pd.wd * A.h * b_in : a_in;
   const double V = (double)A.N * (double)A.N * (double)A.N;
   const double al = A.alpha;
   const double a6 = pow(anew, 6.0), a2 = anew * anew, dx2 = A.dx * A.dx;
@@ -130,7 +134,7 @@ __device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<N
   if constexpr (FULL) {
     for (int f = 0; f < NF; ++f) {
       const double k1 = S[5 * f + 0] / V, k2 = S[5 * f + 1] / V;
-      const double ek = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+      const double ek = (pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
       const double eg = S[5 * f + 2] / V / (2.0 * a2 * dx2);
       o.EK_f[f] = ek;
       o.EG_f[f] = eg;
@@ -145,7 +149,7 @@ __device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<N
     o.EV = o.EV_term[0] + o.EV_term[1] + o.EV_term[2];
   } else {
     const double k1 = S[0] / V, k2 = S[1] / V;
-    o.EK = (A.pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
+    o.EK = (pd.mode == MODE_LF) ? (k1 + k2) / (4.0 * a6) : k2 / (2.0 * a6);
     o.EG = S[2] / V / (2.0 * a2 * dx2);
     o.EV = S[3] / V;
     o.EV_term[0] = o.EV_term[1] = o.EV_term[2] = NAN;
@@ -157,12 +161,12 @@ __device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<N
   if (A.expand) {
     const double Ka = A.fmp2 / 3.0 * pow(anew, 1.0 + 2.0 * al) *
                       ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV);
-    b_out = b_in + (A.pd.wk1 + A.pd.wk2) * A.h * Ka;
-    b_sync = (A.pd.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in + A.pd.wk1 * A.h * Ka;
+    b_out = b_in + (pd.wk1 + pd.wk2) * A.h * Ka;
+    b_sync = (pd.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in + pd.wk1 * A.h * Ka;
     const double rhs = A.fmp2 / 3.0 * pow(anew, 2.0 * (al + 1.0)) * rho;
     hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
   }
-  const double eta_new = A.st->eta + A.pd.wd * A.h;
+  const double eta_new = eta_in + pd.wd * A.h;
   o.eta = eta_new;
   o.a = anew;
   o.b = b_sync;
@@ -174,30 +178,42 @@ __device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<N
   o.hc = hc;
   o.gauss = NAN;
   o.step = 0;
-  o.staggered = (A.pd.mode == MODE_LF) ? 1 : 0;
+  o.staggered = (pd.mode == MODE_LF) ? 1 : 0;
   o.reserved = 0;
-  A.st->obs = o;
-  if (bad) A.st->nonfinite = 1;
-  if (A.pd.update) {
-    A.st->a = anew;
-    A.st->b = b_out;
-    A.st->eta = eta_new;
+  a_next = pd.update ? anew : a_in;
+  b_next = pd.update ? b_out : b_in;
+  if (!out) return;
+  if (out != in) *out = *in;
+  out->obs = o;
+  if (bad) out->nonfinite = 1;
+  if (pd.update) {
+    out->a = anew;
+    out->b = b_out;
+    out->eta = eta_new;
   }
+}
+
+// In-place finish of the pass described by A (the batched path).
+template <typename T, int NF, bool FULL>
+__device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<NF, FULL>::N]) {
+  double an, bn;
+  finish_state<T, NF, FULL>(A, A.pd, A.st, S, A.st, an, bn);
 }
 
 // One block: combine the partials of all nblocks tiles in block order and
 // update the homogeneous state.
 template <typename T, int NF, bool FULL>
-__global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks) {
+__global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks, DevState* out) {
   double S[Acc<NF, FULL>::N];
   if (!reduce_partials<Acc<NF, FULL>::N, 1024>(A.partials, 0, nblocks, S)) return;
-  finish_from_sums<T, NF, FULL>(A, S);
+  double an, bn;
+  finish_state<T, NF, FULL>(A, A.pd, A.st, S, out, an, bn);
 }
 
 // One tile (index `tile` in the order z-tile fastest, then y-tile, then
 // x-chunk) of one lattice; its sums go to partial record `pidx`.
 template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
-__device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, int pidx) {
+__device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, int pidx, double a_in, double b_in) {
   constexpr int TY = BY * RY;
   constexpr int NT = TZ * BY;
   constexpr int LZ = TZ + 2;
@@ -217,7 +233,6 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   const size_t NN = (size_t)N * N;
 
   // homogeneous coefficients (FP64, identical in every block)
-  const double a_in = A.st->a, b_in = A.st->b;
   const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
   const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
@@ -395,7 +410,26 @@ template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
 __global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
   int bid = blockIdx.x;
   if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
-  scalar_tile<T, NF, FULL, TZ, BY, RY>(A, bid, blockIdx.x);
+  double a_in, b_in;
+  if (A.prev.partials) {
+    // finish of the previous pass (stepping passes only, Acc<NF, false>)
+    constexpr int NP = Acc<NF, false>::N;
+    __shared__ double ab[2];
+    double S[NP];
+    if (reduce_partials<NP, TZ * BY>(A.prev.partials, 0, A.prev.nblocks, S)) {
+      double an, bn;
+      finish_state<T, NF, false>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
+      ab[0] = an;
+      ab[1] = bn;
+    }
+    __syncthreads();
+    a_in = ab[0];
+    b_in = ab[1];
+  } else {
+    a_in = A.st->a;
+    b_in = A.st->b;
+  }
+  scalar_tile<T, NF, FULL, TZ, BY, RY>(A, bid, blockIdx.x, a_in, b_in);
 }
 
 
