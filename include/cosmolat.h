@@ -190,9 +190,12 @@ int lattice_destroy(lattice_t* h);
 /* Text of the calling thread's last error ("" if none). */
 const char* lattice_last_error(void);
 
-/* Tile shape of the fused scalar pass: threads along z (32 or 64), rows of
-   threads along y, rows per thread, x-planes per block.  lattice_init picks
-   one with the built-in autotuner; this call reports it.  */
+/* Tile shape of the fused pass: threads along z (32 or 64), rows of threads
+   along y, rows per thread, x-planes per block.  Scalar lattices compile
+   (64,4,4) (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) for FP32 two
+   fields and (64,4,2) (32,8,2) (32,4,4) otherwise; U(1) lattices (64,4,2) and
+   (32,8,1) in FP32, (32,8,1) in FP64.  lattice_init picks one (the built-in
+   autotuner times them for N >= 128); this call reports it.  */
 int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc);
 
 /* Force a tile shape (for the autotuner and tests).  Errors: LAT_EINVAL if

@@ -71,6 +71,9 @@ bool tiling_ok(const lattice* h, const Tiling& t);
 void default_tiling(lattice* h);
 int autotune(lattice* h);
 
+int u1_num_shapes(int fp32);
+void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry);
+int u1_pass(lattice* h, const PassDesc& pd);
 int num_shapes(int fp32, int nf);
 void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,

@@ -180,7 +180,7 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   // Tune first, on zeroed buffers, so that the timed passes can ping-pong
   // between the two state copies exactly as lattice_step does; the initial
   // state is built afterwards.
-  if (p->model == LAT_MODEL_SCALAR && p->N >= 128) {
+  if (p->N >= 128) {
     rc = autotune(L);
     if (rc) { delete L; return rc; }
   }
@@ -569,9 +569,12 @@ int scalar_energies(lattice* h) {
 bool tiling_ok(const lattice* h, const Tiling& t) {
   bool compiled = false;
   const int fp32 = h->p.precision == LAT_FP32;
-  for (int i = 0; i < num_shapes(fp32, h->p.nf); ++i) {
+  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const int ns = u1 ? u1_num_shapes(fp32) : num_shapes(fp32, h->p.nf);
+  for (int i = 0; i < ns; ++i) {
     int tz, by, ry;
-    get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
+    if (u1) u1_get_shape(fp32, i, &tz, &by, &ry);
+    else get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
     if (tz == t.tz && by == t.by && ry == t.ry) compiled = true;
   }
   if (!compiled) return false;
@@ -584,11 +587,21 @@ bool tiling_ok(const lattice* h, const Tiling& t) {
 
 void default_tiling(lattice* h) {
   const int N = h->p.N;
+  if (h->p.model == LAT_MODEL_U1) {
+    // the 64-wide tile where it divides N; the largest x-chunk that still
+    // gives 1024 blocks
+    const bool wide = h->p.precision == LAT_FP32 && N % 64 == 0;
+    Tiling t = wide ? Tiling{64, 4, 2, 4} : Tiling{32, 8, 1, 4};
+    const int64_t tiles = (int64_t)(N / t.tz) * (N / (t.by * t.ry));
+    for (int c : {16, 8})
+      if (N % c == 0 && tiles * (N / c) >= 1024) { t.xc = c; break; }
+    h->tile = t;
+    return;
+  }
   Tiling cands[] = {{64, 4, 4, 16}, {64, 4, 2, 16}, {32, 8, 2, 8}, {32, 4, 4, 4}};
   for (const Tiling& t : cands)
     if (tiling_ok(h, t)) { h->tile = t; return; }
   h->tile = Tiling{32, 4, 4, 4};
-  (void)N;
 }
 
 // Time every compiled tile shape and x-chunk on the real state with a full
@@ -607,22 +620,26 @@ int autotune(lattice* h) {
   hipEvent_t e0, e1;
   CL_HIP(hipEventCreate(&e0));
   CL_HIP(hipEventCreate(&e1));
-  const int xcs[] = {8, 16, 32, 64};
+  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const std::vector<int> xcs = u1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
   float best = 1e30f;
   Tiling bt = h->tile;
   const int fp32 = h->p.precision == LAT_FP32;
   const PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
-  for (int i = 0; i < num_shapes(fp32, h->p.nf) && !rc; ++i) {
+  auto one = [&]() { return u1 ? u1_pass(h, pd) : scalar_pass(h, pd); };
+  const int ns = u1 ? u1_num_shapes(fp32) : num_shapes(fp32, h->p.nf);
+  for (int i = 0; i < ns && !rc; ++i) {
     int tz, by, ry;
-    get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
+    if (u1) u1_get_shape(fp32, i, &tz, &by, &ry);
+    else get_shape(fp32, h->p.nf, i, &tz, &by, &ry);
     for (int xc : xcs) {
       Tiling t{tz, by, ry, xc};
       if (!tiling_ok(h, t)) continue;
       h->tile = t;
-      for (int k = 0; k < 2 && !rc; ++k) rc = scalar_pass(h, pd);  // warm-up, ping-pong
+      for (int k = 0; k < 2 && !rc; ++k) rc = one();  // warm-up, ping-pong
       if (rc) break;
       hipError_t e = hipEventRecord(e0, h->stream);
-      for (int k = 0; k < 4 && !rc && e == hipSuccess; ++k) rc = scalar_pass(h, pd);
+      for (int k = 0; k < 4 && !rc && e == hipSuccess; ++k) rc = one();
       if (!rc && e == hipSuccess) e = hipEventRecord(e1, h->stream);
       if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

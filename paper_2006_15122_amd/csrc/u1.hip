@@ -28,7 +28,7 @@
 namespace cl {
 
 template <typename T>
-struct C2 {
+struct alignas(2 * sizeof(T)) C2 {
   T x, y;
 };
 template <typename T>
@@ -166,7 +166,8 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   static_assert(TZ + TY <= NT, "low ring larger than block");
   static_assert(NT == 256, "partials assume four waves");
   __shared__ T Lp[2][2][LY][LZ];       // drifted phi (Re, Im), planes in flight
-  __shared__ T Lt[2][3][LY][LZ];       // drifted link phases
+  __shared__ T Lt[2][3][LY][LZ];       // drifted link phases (own sites are stored)
+  __shared__ C2<T> Lu[2][3][LY][LZ];   // drifted links U_i = e^{i theta_i} (cos, sin)
   __shared__ T Ls[3][TY + 1][TZ + 1];  // S_01, S_02, S_12; index 0 = row y0-1 / column z0-1
 
   const int N = A.N;
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
     }
   };
   // drift the raw values into LDS buffer b
+  // (the only transcendentals of the pass: one arctangent and one sincos per link)
   auto drift_into = [&](int b) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -234,24 +236,41 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       Lp[b][0][ly][lz] = raw[0][r] + cd * raw[2][r];
       Lp[b][1][ly][lz] = raw[1][r] + cd * raw[3][r];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        Lt[b][i][ly][lz] = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+      for (int i = 0; i < 3; ++i) {
+        const T th = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+        Lt[b][i][ly][lz] = th;
+        T sn, cs;
+        sincos_t(th, &sn, &cs);
+        Lu[b][i][ly][lz] = C2<T>{cs, sn};
+      }
     }
     if (has_ring) {
       Lp[b][0][rly][rlz] = rraw[0] + cd * rraw[2];
       Lp[b][1][rly][rlz] = rraw[1] + cd * rraw[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        Lt[b][i][rly][rlz] = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+      for (int i = 0; i < 3; ++i) {
+        const T th = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+        T sn, cs;
+        sincos_t(th, &sn, &cs);
+        Lu[b][i][rly][rlz] = C2<T>{cs, sn};
+      }
     }
   };
-  // plaquette phases of site (ly, lz) of plane buffer c, plane x+1 in buffer n:
-  //   Phi_ij(m) = th_i(m) + th_j(m+i) - th_i(m+j) - th_j(m)
-  auto plaq = [&](int c, int n, int ly, int lz, T (&ph)[3]) {
-    const T t0 = Lt[c][0][ly][lz], t1 = Lt[c][1][ly][lz], t2 = Lt[c][2][ly][lz];
-    ph[0] = (t0 + Lt[n][1][ly][lz]) - (Lt[c][0][ly + 1][lz] + t1);
-    ph[1] = (t0 + Lt[n][2][ly][lz]) - (Lt[c][0][ly][lz + 1] + t2);
-    ph[2] = (t1 + Lt[c][2][ly + 1][lz]) - (Lt[c][1][ly][lz + 1] + t2);
+  // plaquettes of site (ly, lz) of plane buffer c (plane x+1 in buffer n) as
+  // products of links, P_ij(m) = U_i(m) U_j(m+i) U_i(m+j)^* U_j(m)^* = e^{i Phi_ij}:
+  // sin Phi_ij = Im P and 1 - cos Phi_ij = (Im P)^2 / (1 + Re P) (no cancellation
+  // for small Phi; 1 - Re P where Re P < 0).
+  auto plaq = [&](int c, int n, int ly, int lz, T (&sn)[3], T (&om)[3]) {
+    const C2<T> u0 = Lu[c][0][ly][lz], u1 = Lu[c][1][ly][lz], u2 = Lu[c][2][ly][lz];
+    C2<T> P[3];
+    P[0] = cm(cm(u0, Lu[n][1][ly][lz]), cc(cm(Lu[c][0][ly + 1][lz], u1)));
+    P[1] = cm(cm(u0, Lu[n][2][ly][lz]), cc(cm(Lu[c][0][ly][lz + 1], u2)));
+    P[2] = cm(cm(u1, Lu[c][2][ly + 1][lz]), cc(cm(Lu[c][1][ly][lz + 1], u2)));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sn[k] = P[k].y;
+      om[k] = P[k].x >= T(0) ? P[k].y * P[k].y / (T(1) + P[k].x) : T(1) - P[k].x;
+    }
   };
 
   double acc[kU1Acc];
@@ -259,7 +278,8 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   for (int k = 0; k < kU1Acc; ++k) acc[k] = 0.0;
 
   // registers: plane x-1 (own column) and raw momenta of planes x, x+1
-  T pm[2][RY], tm[RY], s01m[RY], s02m[RY];
+  T pm[2][RY], s01m[RY], s02m[RY];
+  C2<T> um[RY];  // U_0 of the own column at plane x-1
   T qc[5][RY], qn[5][RY];
 
   // prologue: plane x0-1 -> buffer 1, plane x0 -> buffer 0; S_01, S_02 of
@@ -276,16 +296,13 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int ly = 1 + r * BY + ty, lz = 1 + tz;
-    T ph[3];
-    plaq(1, 0, ly, lz, ph);
-    T sn, cs;
-    sincos_t(T(0.5) * ph[0], &sn, &cs);
-    s01m[r] = T(2) * sn * cs;
-    sincos_t(T(0.5) * ph[1], &sn, &cs);
-    s02m[r] = T(2) * sn * cs;
+    T sn[3], om[3];
+    plaq(1, 0, ly, lz, sn, om);
+    s01m[r] = sn[0];
+    s02m[r] = sn[1];
     pm[0][r] = Lp[1][0][ly][lz];
     pm[1][r] = Lp[1][1][ly][lz];
-    tm[r] = Lt[1][0][ly][lz];
+    um[r] = Lu[1][0][ly][lz];
   }
   __syncthreads();
   load_plane((x0 + 1) % N);
@@ -304,27 +321,21 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int ly = 1 + r * BY + ty, lz = 1 + tz;
-      T ph[3];
-      plaq(cb_, nb_, ly, lz, ph);
+      T sn[3], om[3];
+      plaq(cb_, nb_, ly, lz, sn, om);
       double mg = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        T sn, cs;
-        sincos_t(T(0.5) * ph[k], &sn, &cs);
-        Ls[k][ly][lz] = T(2) * sn * cs;
-        mg += (double)(T(2) * sn * sn);
+        Ls[k][ly][lz] = sn[k];
+        mg += (double)om[k];
       }
       acc[7] += mg;
     }
     if (has_low) {
-      T ph[3];
-      plaq(cb_, nb_, sly, slz, ph);
+      T sn[3], om[3];
+      plaq(cb_, nb_, sly, slz, sn, om);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        T sn, cs;
-        sincos_t(T(0.5) * ph[k], &sn, &cs);
-        Ls[k][sly][slz] = T(2) * sn * cs;
-      }
+      for (int k = 0; k < 3; ++k) Ls[k][sly][slz] = sn[k];
     }
     __syncthreads();
     // kick of the own sites of plane x
@@ -339,17 +350,15 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       const C2<T> bw[3] = {C2<T>{pm[0][r], pm[1][r]}, C2<T>{Lp[cb_][0][ly - 1][lz], Lp[cb_][1][ly - 1][lz]},
                            C2<T>{Lp[cb_][0][ly][lz - 1], Lp[cb_][1][ly][lz - 1]}};
       const T th[3] = {Lt[cb_][0][ly][lz], Lt[cb_][1][ly][lz], Lt[cb_][2][ly][lz]};
-      const T thb[3] = {tm[r], Lt[cb_][1][ly - 1][lz], Lt[cb_][2][ly][lz - 1]};
+      const C2<T> uf[3] = {Lu[cb_][0][ly][lz], Lu[cb_][1][ly][lz], Lu[cb_][2][ly][lz]};
+      const C2<T> ub[3] = {um[r], Lu[cb_][1][ly - 1][lz], Lu[cb_][2][ly][lz - 1]};
       C2<T> lap{T(-6) * p.x, T(-6) * p.y};
       double grad = 0.0;
       T Kcur[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        T sn, cs, snb, csb;
-        sincos_t(th[k], &sn, &cs);
-        sincos_t(thb[k], &snb, &csb);
-        const C2<T> f = cm(C2<T>{cs, sn}, fw[k]);
-        const C2<T> b = cm(cc(C2<T>{csb, snb}), bw[k]);
+        const C2<T> f = cm(uf[k], fw[k]);
+        const C2<T> b = cm(cc(ub[k]), bw[k]);
         lap.x += f.x + b.x;
         lap.y += f.y + b.y;
         const T gx = f.x - p.x, gy = f.y - p.y;
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       // plane x becomes plane x-1 of the next step
       pm[0][r] = p.x;
       pm[1][r] = p.y;
-      tm[r] = th[0];
+      um[r] = uf[0];
       s01m[r] = S01;
       s02m[r] = S02;
     }
@@ -540,10 +549,7 @@ static int u1_pass_t(lattice* h, const PassDesc& pd) {
   const int N = h->p.N;
   constexpr int TY = BY * RY;
   const int tiles = (N / TZ) * (N / TY);
-  int xc = 4;
-  for (int c : {16, 8}) {
-    if (N % c == 0 && (int64_t)tiles * (N / c) >= 1024) { xc = c; break; }
-  }
+  const int xc = h->tile.xc;
   A.N = N;
   A.XC = xc;
   const int nb = tiles * (N / xc);
@@ -577,12 +583,29 @@ static int u1_pass_t(lattice* h, const PassDesc& pd) {
   return LAT_OK;
 }
 
-static int u1_pass(lattice* h, const PassDesc& pd) {
+// Compiled tile shapes of the U(1) pass (256 threads each): TZ x (BY RY).
+static const int kU1Shapes32[][3] = {{64, 4, 2}, {32, 8, 1}};
+static const int kU1Shapes64[][3] = {{32, 8, 1}};
+
+int u1_num_shapes(int fp32) { return fp32 ? 2 : 1; }
+void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry) {
+  const int* s = fp32 ? kU1Shapes32[i] : kU1Shapes64[i];
+  *tz = s[0];
+  *by = s[1];
+  *ry = s[2];
+}
+
+// Shape and x-chunk from h->tile (checked by tiling_ok).
+int u1_pass(lattice* h, const PassDesc& pd) {
+  const Tiling& t = h->tile;
   if (h->p.precision == LAT_FP32) {
-    if (h->p.N % 64 == 0) return u1_pass_t<float, 64, 4, 2>(h, pd);
-    return u1_pass_t<float, 32, 8, 1>(h, pd);
+    if (t.tz == 64 && t.by == 4 && t.ry == 2) return u1_pass_t<float, 64, 4, 2>(h, pd);
+    if (t.tz == 32 && t.by == 8 && t.ry == 1) return u1_pass_t<float, 32, 8, 1>(h, pd);
+  } else if (t.tz == 32 && t.by == 8 && t.ry == 1) {
+    return u1_pass_t<double, 32, 8, 1>(h, pd);
   }
-  return u1_pass_t<double, 32, 8, 1>(h, pd);
+  set_error("U(1) pass: tile shape not compiled");
+  return LAT_EINVAL;
 }
 
 int u1_gauss(lattice* h) { return h->p.precision == LAT_FP32 ? u1_gauss_t<float>(h) : u1_gauss_t<double>(h); }

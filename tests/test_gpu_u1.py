@@ -109,6 +109,30 @@ def test_u1_fp32_parity_64_400_steps():
         assert g["gauss"] < 1e-5, g["gauss"]
 
 
+def test_u1_every_tiling_agrees():
+    """Each compiled U(1) tile shape and x-chunk gives the oracle's observables."""
+    cfg = _cfg(64, "fp32")
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    st0 = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in st.items()}
+    h = cfg["dt"]
+    oracle.u1_lf_startup(m, st, h)
+    oracle.u1_lf_steps(m, st, h, 100, omp=True)
+    o = oracle.u1_lf_observe(m, st, h)
+    lat = _lattice(cfg)
+    n = 0
+    for (tz, by, ry) in ((64, 4, 2), (32, 8, 1)):
+        for xc in (4, 8, 16, 32):
+            lat.set_tiling(tz, by, ry, xc)
+            lat.set_state(st0["phi"], st0["pi"], st0["a"], st0["b"], links=st0["links"], piA=st0["piA"])
+            lat.step(100)
+            g = lat.energies()
+            compare(g, o, 1e-5, f"tile {tz},{by},{ry},{xc}")
+            assert g["gauss"] < 1e-5, (tz, by, ry, xc, g["gauss"])
+            n += 1
+    assert n == 8
+
+
 def test_u1_full_size_192_sampled_sites():
     cfg = _cfg(192, "fp32")
     st = oracle.u1_vacuum_ic(cfg)
