@@ -58,7 +58,15 @@ int upload_components(lattice* h, const double* const* comps, int n);
 int download_components(lattice* h, double* const* comps, int n);
 int upload_scalars(lattice* h, double a, double b, double eta);
 int init_state(lattice* h);
-struct PassChain;
+// A chain of stepping passes whose finishes are deferred: pass k reduces the
+// partial records of pass k-1 at its start (PrevPass), the records alternate
+// between two regions and the state between two slots, and one finish kernel
+// closes the chain after its last pass.
+struct PassChain {
+  int k = 0;        // passes launched
+  int rd = 0;       // state slot the next pass starts from (0: h->st, 1: h->st2)
+  PrevPass prev{};  // finish still to be applied
+};
 int scalar_pass(lattice* h, const PassDesc& pd, bool full = false, PassChain* chain = nullptr);
 int scalar_step(lattice* h, int64_t n);
 int scalar_energies(lattice* h);
@@ -73,7 +81,9 @@ int autotune(lattice* h);
 
 int u1_num_shapes(int fp32);
 void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry);
-int u1_pass(lattice* h, const PassDesc& pd);
+int u1_pass(lattice* h, const PassDesc& pd, PassChain* chain = nullptr);
+int u1_chain_end(lattice* h, const PassChain& chain);
+int scalar_chain_end(lattice* h, const PassChain& chain);
 int num_shapes(int fp32, int nf);
 void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,

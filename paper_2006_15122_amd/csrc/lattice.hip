@@ -96,9 +96,10 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_part2,
   size_t o = align_up(2 * sizeof(DevState), 256);
   *off_part = o;
   o = align_up(o + part_doubles * sizeof(double), 256);
-  // every other pass of a chain writes its 4 stepping sums per block here
+  // every other pass of a chain writes its records here: at most mb blocks
+  // (tiles of at least 1024 sites) of 4 scalar or 11 U(1) sums
   *off_part2 = o;
-  o = align_up(o + (size_t)mb * 4 * sizeof(double), 256);
+  o = align_up(o + (size_t)mb * 16 * sizeof(double), 256);
   *off_spec = o;
   o = align_up(o + (size_t)(kSpecBlocks + 2) * spec_bins((int)N) * 24, 256);
   *off_buf0 = o;
@@ -435,16 +436,6 @@ void phys_of(const lattice* h, double* phys) {
   phys[7] = h->p.dt;
 }
 
-// A chain of stepping passes whose finishes are deferred: pass k reduces the
-// partial records of pass k-1 at its start (PrevPass), the records alternate
-// between two regions and the state between two slots, and one finish kernel
-// closes the chain after its last pass.
-struct PassChain {
-  int k = 0;       // passes launched
-  int rd = 0;      // state slot the next pass starts from (0: h->st, 1: h->st2)
-  PrevPass prev{};  // finish still to be applied
-};
-
 int scalar_pass(lattice* h, const PassDesc& pd, bool full, PassChain* chain) {
   double phys[8];
   phys_of(h, phys);
@@ -541,20 +532,25 @@ int scalar_step(lattice* h, int64_t n) {
     const int rc = scalar_pass(h, pd, false, &chain);
     if (rc) return rc;
   }
-  if (chain.k > 0) {
-    // the last pass's finish, from the slot it started from into h->st
-    double phys[8];
-    phys_of(h, phys);
-    DevState* slot[2] = {h->st, h->st2};
-    const hipError_t e = launch_scalar_finish(h->p.precision == LAT_FP32, h->p.nf, h->p.N, phys, h->p.expansion,
-                                              chain.prev.pd, const_cast<double*>(chain.prev.partials),
-                                              chain.prev.nblocks, slot[chain.rd], h->st, h->stream);
-    if (e != hipSuccess) {
-      set_error(std::string("finish launch: ") + hipGetErrorString(e));
-      return LAT_EHIP;
-    }
-  }
+  const int rc = scalar_chain_end(h, chain);
+  if (rc) return rc;
   h->step += n;
+  return LAT_OK;
+}
+
+// The last pass's finish, from the slot it started from into h->st.
+int scalar_chain_end(lattice* h, const PassChain& chain) {
+  if (chain.k == 0) return LAT_OK;
+  double phys[8];
+  phys_of(h, phys);
+  DevState* slot[2] = {h->st, h->st2};
+  const hipError_t e = launch_scalar_finish(h->p.precision == LAT_FP32, h->p.nf, h->p.N, phys, h->p.expansion,
+                                            chain.prev.pd, const_cast<double*>(chain.prev.partials),
+                                            chain.prev.nblocks, slot[chain.rd], h->st, h->stream);
+  if (e != hipSuccess) {
+    set_error(std::string("finish launch: ") + hipGetErrorString(e));
+    return LAT_EHIP;
+  }
   return LAT_OK;
 }
 
@@ -604,10 +600,10 @@ void default_tiling(lattice* h) {
   h->tile = Tiling{32, 4, 4, 4};
 }
 
-// Time every compiled tile shape and x-chunk on the real state with a full
-// pass that writes the scratch buffer and leaves a, b untouched; keep the
-// fastest.  The state itself is not modified (the written buffer is the
-// ping-pong scratch).
+// Time every compiled tile shape and x-chunk on zeroed state buffers with
+// chains of full passes (a, b left untouched) that ping-pong between the two
+// buffers as lattice_step does; keep the fastest.  The caller builds the
+// initial state afterwards.
 int autotune(lattice* h) {
   // zero state (finite arithmetic), a = 1, b = 0; the caller builds the real
   // state after tuning
@@ -626,7 +622,14 @@ int autotune(lattice* h) {
   Tiling bt = h->tile;
   const int fp32 = h->p.precision == LAT_FP32;
   const PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
-  auto one = [&]() { return u1 ? u1_pass(h, pd) : scalar_pass(h, pd); };
+  // k passes chained as lattice_step chains them, and the closing finish
+  auto run = [&](int k) {
+    PassChain c;
+    int r = LAT_OK;
+    for (int j = 0; j < k && !r; ++j) r = u1 ? u1_pass(h, pd, &c) : scalar_pass(h, pd, false, &c);
+    if (!r) r = u1 ? u1_chain_end(h, c) : scalar_chain_end(h, c);
+    return r;
+  };
   const int ns = u1 ? u1_num_shapes(fp32) : num_shapes(fp32, h->p.nf);
   for (int i = 0; i < ns && !rc; ++i) {
     int tz, by, ry;
@@ -636,10 +639,10 @@ int autotune(lattice* h) {
       Tiling t{tz, by, ry, xc};
       if (!tiling_ok(h, t)) continue;
       h->tile = t;
-      for (int k = 0; k < 2 && !rc; ++k) rc = one();  // warm-up, ping-pong
+      rc = run(2);  // warm-up, ping-pong
       if (rc) break;
       hipError_t e = hipEventRecord(e0, h->stream);
-      for (int k = 0; k < 4 && !rc && e == hipSuccess; ++k) rc = one();
+      if (e == hipSuccess) rc = run(6);
       if (!rc && e == hipSuccess) e = hipEventRecord(e1, h->stream);
       if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

@@ -150,7 +150,14 @@ struct U1PassArgs {
   PassDesc pd;
   double* partials;
   DevState* st;
+  PrevPass prev;  // finish of the previous pass of a chain (partials == nullptr: none)
 };
+
+template <typename T>
+__device__ void u1_finish_state(const U1PassArgs<T>& A, const PassDesc& pd, const DevState* in,
+                                const double (&S)[kU1Acc], DevState* out, double& a_next, double& b_next);
+template <int NT>
+__device__ bool u1_reduce_partials(const double* partials, int nb, double (&S)[kU1Acc]);
 
 template <typename T>
 __device__ __forceinline__ T wrap_phase(T t) {
@@ -180,8 +187,25 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const int y0 = ((bid / nzt) % nyt) * TY;
   const int x0 = (bid / (nzt * nyt)) * A.XC;
 
-  // homogeneous coefficients (FP64, the same in every block)
-  const double a_in = A.st->a, b_in = A.st->b;
+  // homogeneous coefficients (FP64, the same in every block); a chained pass
+  // first applies the previous pass's finish (every block, same order)
+  double a_in, b_in;
+  if (A.prev.partials) {
+    __shared__ double ab[2];
+    double S[kU1Acc];
+    if (u1_reduce_partials<NT>(A.prev.partials, A.prev.nblocks, S)) {
+      double an, bn;
+      u1_finish_state<T>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
+      ab[0] = an;
+      ab[1] = bn;
+    }
+    __syncthreads();
+    a_in = ab[0];
+    b_in = ab[1];
+  } else {
+    a_in = A.st->a;
+    b_in = A.st->b;
+  }
   const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
   const bool dr = A.pd.wd != 0.0;
@@ -421,40 +445,22 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   u1_block_partials<kU1Acc>(acc, A.partials);
 }
 
-// Combine the partials in block order; energies of Sec. 5.4.1 at a' and the
-// scale-factor kernel with the gauge term (Sec. 5.1),
+// Energies of Sec. 5.4.1 at a' from the lattice sums S of pass `pd`, which
+// started from state `in`, and the scale-factor kernel with the gauge term
+// (Sec. 5.1),
 //   K_a = (1/3)(f/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G + (alpha+1)E_V
 //                                        + (alpha-1)(E_K^A + E_G^A)],
 //   b_out = b + (wk1 + wk2) h K_a;  a, b, eta advanced when the pass updates.
+// The state goes to `out` (may be `in`; nullptr: not stored); a and b after
+// the pass are returned in a_next, b_next.
 template <typename T>
-__global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblocks) {
-  constexpr int NACC = kU1Acc, NW = 16;
-  __shared__ double red[NW][NACC];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double tot[NACC];
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
-  for (int b = tid; b < nblocks; b += 1024) {
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) tot[k] += A.partials[(size_t)b * NACC + k];
-  }
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const double s = wsum(tot[k]);
-    if (lane == 0) red[wv][k] = s;
-  }
-  __syncthreads();
-  if (tid != 0) return;
-  double S[NACC];
-  for (int k = 0; k < NACC; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += red[w][k];
-    S[k] = s;
-  }
+__device__ void u1_finish_state(const U1PassArgs<T>& A, const PassDesc& pd, const DevState* in,
+                                const double (&S)[kU1Acc], DevState* out, double& a_next, double& b_next) {
+  constexpr int NACC = kU1Acc;
   const double V = (double)A.N * A.N * A.N;
-  const double a_in = A.st->a, b_in = A.st->b, al = A.alpha;
-  const double a = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
-  const bool lf = A.pd.mode == MODE_LF;
+  const double a_in = in->a, b_in = in->b, al = A.alpha;
+  const double a = A.expand ? a_in + pd.wd * A.h * b_in : a_in;
+  const bool lf = pd.mode == MODE_LF;
   const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = A.dx * A.dx;
   lattice_obs o;
   o.EK = (lf ? 0.5 * (S[0] + S[1]) : S[1]) / V / a6;
@@ -480,12 +486,12 @@ __global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblo
   if (A.expand) {
     const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
                       ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * (o.EK_A + o.EG_A));
-    b_out = b_in + (A.pd.wk1 + A.pd.wk2) * A.h * Ka;
-    b_sync = lf ? 0.5 * (b_in + b_out) : b_in + A.pd.wk1 * A.h * Ka;
+    b_out = b_in + (pd.wk1 + pd.wk2) * A.h * Ka;
+    b_sync = lf ? 0.5 * (b_in + b_out) : b_in + pd.wk1 * A.h * Ka;
     const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
     hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
   }
-  const double eta_new = A.st->eta + A.pd.wd * A.h;
+  const double eta_new = in->eta + pd.wd * A.h;
   o.eta = eta_new;
   o.a = a;
   o.b = b_sync;
@@ -494,17 +500,60 @@ __global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblo
   o.p = o.EK - o.EG / 3.0 - o.EV + (o.EK_A + o.EG_A) / 3.0;
   o.w = rho != 0.0 ? o.p / rho : 0.0;
   o.hc = hc;
-  o.gauss = A.st->obs.gauss;
+  o.gauss = in->obs.gauss;
   o.step = 0;
   o.staggered = lf ? 1 : 0;
   o.reserved = 0;
-  A.st->obs = o;
-  if (bad) A.st->nonfinite = 1;
-  if (A.pd.update) {
-    A.st->a = a;
-    A.st->b = b_out;
-    A.st->eta = eta_new;
+  a_next = pd.update ? a : a_in;
+  b_next = pd.update ? b_out : b_in;
+  if (!out) return;
+  if (out != in) *out = *in;
+  out->obs = o;
+  if (bad) out->nonfinite = 1;
+  if (pd.update) {
+    out->a = a;
+    out->b = b_out;
+    out->eta = eta_new;
   }
+}
+
+
+// Sums of NB partial records in block order by one block of NT threads
+// (strided per thread, then waves in order); thread 0 returns them in S.
+template <int NT>
+__device__ bool u1_reduce_partials(const double* partials, int nb, double (&S)[kU1Acc]) {
+  constexpr int NACC = kU1Acc, NW = NT / 64;
+  __shared__ double red[NW][NACC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double tot[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
+  for (int b = tid; b < nb; b += NT) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) tot[k] += partials[(size_t)b * NACC + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double s = wsum(tot[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return false;
+  for (int k = 0; k < NACC; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][k];
+    S[k] = s;
+  }
+  return true;
+}
+
+// The finish of the pass described by A, into `out`.
+template <typename T>
+__global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblocks, DevState* out) {
+  double S[kU1Acc];
+  if (!u1_reduce_partials<1024>(A.partials, nblocks, S)) return;
+  double an, bn;
+  u1_finish_state<T>(A, A.pd, A.st, S, out, an, bn);
 }
 
 template <typename T>
@@ -540,7 +589,7 @@ static int u1_gauss_t(lattice* h) {
 // One pass from the current buffer into the other (or no stores for an
 // observation), then the FP64 finish.
 template <typename T, int TZ, int BY, int RY>
-static int u1_pass_t(lattice* h, const PassDesc& pd) {
+static int u1_pass_t(lattice* h, const PassDesc& pd, PassChain* chain) {
   U1PassArgs<T> A;
   for (int c = 0; c < 10; ++c) {
     A.src[c] = static_cast<const T*>(h->buf[h->cur][c]);
@@ -566,6 +615,14 @@ static int u1_pass_t(lattice* h, const PassDesc& pd) {
   A.pd = pd;
   A.partials = h->partials;
   A.st = h->st;
+  A.prev = PrevPass{};
+  DevState* slot[2] = {h->st, h->st2};
+  if (chain) {
+    A.st = slot[chain->rd];
+    A.partials = (chain->k & 1) ? h->partials2 : h->partials;
+    A.prev = chain->prev;
+    if (A.prev.partials) A.prev.out = slot[1 - chain->rd];
+  }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (pd.write && 2 * h->timer_used + 1 < h->timer.size()) {
     ev0 = h->timer[2 * h->timer_used];
@@ -577,9 +634,38 @@ static int u1_pass_t(lattice* h, const PassDesc& pd) {
   else
     hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
   CL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, nb);
-  CL_HIP(hipGetLastError());
+  if (chain) {
+    if (A.prev.partials) chain->rd ^= 1;
+    chain->prev = PrevPass{A.partials, nb, pd, nullptr};
+    ++chain->k;
+  } else {
+    hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, nb, h->st);
+    CL_HIP(hipGetLastError());
+  }
   if (pd.write) h->cur ^= 1;
+  return LAT_OK;
+}
+
+// Trailing finish of a chain: the last pass's records, from the slot that
+// pass started from, into h->st.
+template <typename T>
+static int u1_chain_finish(lattice* h, const PassChain& c) {
+  U1PassArgs<T> A = {};
+  A.N = h->p.N;
+  A.dx = h->dx;
+  A.alpha = h->p.alpha;
+  A.fmp2 = h->p.fstar_over_mp * h->p.fstar_over_mp;
+  A.lam = h->p.lambda;
+  A.m2 = h->p.m2[0];
+  A.e = h->p.e;
+  A.wf2 = h->p.omega_over_f * h->p.omega_over_f;
+  A.h = h->p.dt;
+  A.expand = h->p.expansion;
+  A.pd = c.prev.pd;
+  A.partials = const_cast<double*>(c.prev.partials);
+  A.st = c.rd ? h->st2 : h->st;
+  hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, c.prev.nblocks, h->st);
+  CL_HIP(hipGetLastError());
   return LAT_OK;
 }
 
@@ -596,13 +682,13 @@ void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry) {
 }
 
 // Shape and x-chunk from h->tile (checked by tiling_ok).
-int u1_pass(lattice* h, const PassDesc& pd) {
+int u1_pass(lattice* h, const PassDesc& pd, PassChain* chain) {
   const Tiling& t = h->tile;
   if (h->p.precision == LAT_FP32) {
-    if (t.tz == 64 && t.by == 4 && t.ry == 2) return u1_pass_t<float, 64, 4, 2>(h, pd);
-    if (t.tz == 32 && t.by == 8 && t.ry == 1) return u1_pass_t<float, 32, 8, 1>(h, pd);
+    if (t.tz == 64 && t.by == 4 && t.ry == 2) return u1_pass_t<float, 64, 4, 2>(h, pd, chain);
+    if (t.tz == 32 && t.by == 8 && t.ry == 1) return u1_pass_t<float, 32, 8, 1>(h, pd, chain);
   } else if (t.tz == 32 && t.by == 8 && t.ry == 1) {
-    return u1_pass_t<double, 32, 8, 1>(h, pd);
+    return u1_pass_t<double, 32, 8, 1>(h, pd, chain);
   }
   set_error("U(1) pass: tile shape not compiled");
   return LAT_EINVAL;
@@ -612,12 +698,20 @@ int u1_gauss(lattice* h) { return h->p.precision == LAT_FP32 ? u1_gauss_t<float>
 
 // The pass sequence of the scalar path (merged kicks; leapfrog start-up,
 // drift+kick passes and closing drift), run with the U(1) pass.
+int u1_chain_end(lattice* h, const PassChain& chain) {
+  if (chain.k == 0) return LAT_OK;
+  return h->p.precision == LAT_FP32 ? u1_chain_finish<float>(h, chain) : u1_chain_finish<double>(h, chain);
+}
+
 int u1_step(lattice* h, int64_t n) {
   const std::vector<PassDesc> sched = pass_schedule(h->p.integrator, h->weights, &h->staggered, n);
+  PassChain chain;
   for (const PassDesc& pd : sched) {
-    const int rc = u1_pass(h, pd);
+    const int rc = u1_pass(h, pd, &chain);
     if (rc) return rc;
   }
+  const int rc = u1_chain_end(h, chain);
+  if (rc) return rc;
   h->step += n;
   return LAT_OK;
 }
