@@ -305,7 +305,7 @@ def main():
                                       "the pass launches in it (gaps and the one closing finish kernel included)",
                      "ms_per_launch_ext_events": kernel_ms,
                      "ext_events_note": "per-launch hipExtLaunchKernel start/stop events on a second region of "
-                                        "the same steps; they bracket the dispatch as well, about 3% longer",
+                                        "the same steps; within a few percent of the region figure",
                      "bytes_per_launch": sites * BYTES_PER_SITE_VV2_NF2_FP32},
         "wall_s": wall,
         "final_obs": {k: obs[k] for k in ("a", "b", "EK", "EG", "EV", "hc")},

@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -68,6 +70,29 @@ def scalar_case(cfg, nsteps, every):
     return worst
 
 
+def chaos_case(cfg, nsteps, every):
+    """Oracle against itself: the same FP64 run from the initial state rounded
+    once to FP32.  Shows how far two correct trajectories drift apart in the
+    nonlinear stage from a single FP32 rounding (no GPU)."""
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    h = cfg["dt"]
+    A = [st["phi"].copy(), st["pi"].copy(), st["a"], st["b"]]
+    B = [st["phi"].astype(np.float32).astype(np.float64), st["pi"].astype(np.float32).astype(np.float64),
+         st["a"], st["b"]]
+    worst = {}
+    for k in range(nsteps // every):
+        for S in (A, B):
+            S[2], S[3] = oracle.vv_steps(m, S[0], S[1], S[2], S[3], h, cfg["integrator"], every, omp=True)
+        oa = oracle.sync_observe(m, A[0], A[1], A[2], A[3])
+        ob = oracle.sync_observe(m, B[0], B[1], B[2], B[3])
+        row = {kk: _err(ob, oa, kk) for kk in ("a", "b", "EK", "EG", "EV")}
+        for kk, v in row.items():
+            worst[kk] = max(worst.get(kk, 0.0), v)
+        worst.setdefault("_by_checkpoint", []).append((every * (k + 1), max(row.values())))
+    return worst
+
+
 def u1_case(cfg, nsteps, every):
     from paper_2006_15122_amd.lattice import Lattice
     st = oracle.u1_vacuum_ic(cfg)
@@ -105,6 +130,9 @@ def main():
          lambda: scalar_case(synth.small(synth.config2(q=100.0), 64), 4000, 500)),
         ("two fields q=100, 64^3, FP32, VV2, 20000 steps (eta = 100, checkpoints every 2000)",
          lambda: scalar_case(synth.small(synth.config2(q=100.0), 64), 20000, 2000)),
+        ("oracle against itself from the initial state rounded once to FP32, two fields q=100, 64^3, VV2, "
+         "20000 steps (no GPU)",
+         lambda: chaos_case(synth.small(synth.config2(q=100.0), 64), 20000, 2000)),
         ("two fields q=1000, 64^3, FP32, VV4, 1000 steps",
          lambda: scalar_case(synth.small(synth.config2(q=1000.0, integrator="vv4"), 64), 1000, 250)),
         ("compact U(1), 64^3, FP64, LF2, 400 steps",
