@@ -429,8 +429,9 @@ def spectrum_logk(f: np.ndarray, kIR: float, nk: int = 64) -> np.ndarray:
 # Complex scalar with compact U(1) links (Sec. 5.1, 5.3, 5.4; ICs Sec. 7.2)
 # ---------------------------------------------------------------------------
 class U1(ctypes.Structure):
-    """Parameters of the compact Abelian-Higgs model."""
-    _fields_ = [("N", ctypes.c_int32), ("expand", ctypes.c_int32), ("pad0", ctypes.c_int32),
+    """Parameters of the Abelian-Higgs model (compact links, or with
+    noncompact = 1 the real gauge field A_i of Sec. 5.2)."""
+    _fields_ = [("N", ctypes.c_int32), ("expand", ctypes.c_int32), ("noncompact", ctypes.c_int32),
                 ("pad1", ctypes.c_int32), ("dx", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("fmp2", ctypes.c_double), ("lam", ctypes.c_double), ("m2", ctypes.c_double),
                 ("e", ctypes.c_double), ("wf2", ctypes.c_double)]
@@ -440,6 +441,7 @@ def u1_model(cfg: dict) -> U1:
     m = U1()
     m.N = int(cfg["N"])
     m.expand = 1 if cfg.get("expansion", True) else 0
+    m.noncompact = 1 if cfg.get("model") == "u1nc" else 0
     m.dx = lattice_dx(m.N, cfg["kIR"])
     m.alpha = float(cfg.get("alpha", 1.0))
     m.fmp2 = float(cfg.get("fstar_over_mp", 1.0)) ** 2
@@ -530,6 +532,8 @@ def u1_vacuum_ic(cfg: dict) -> dict:
     the discrete Gauss law sum_i Delta^-_i piA_i = rho in Fourier space with
     the minimum-norm solution E_i = conj(s_i) rho / sum_j |s_j|^2,
     s_j = (1 - exp(+2 pi i n~_j / N)) / dx; b_0 from the Hubble constraint.
+    For the non-compact model ("model": "u1nc") "links" holds A_i = 0,
+    shape (3, N, N, N); compact links are (Re, Im) pairs, shape (3, 2, N, N, N).
     """
     N = int(cfg["N"])
     kIR = float(cfg["kIR"])
@@ -587,8 +591,11 @@ def u1_vacuum_ic(cfg: dict) -> dict:
     zero = den == 0
     piA = np.stack([a ** (1.0 - alpha) * paper_idft(np.where(zero, 0.0, np.conj(x) * Rh / np.where(zero, 1.0, den))).real
                     for x in sj])
-    links = np.zeros((3, 2, N, N, N))
-    links[:, 0] = 1.0
+    if cfg.get("model") == "u1nc":
+        links = np.zeros((3, N, N, N))
+    else:
+        links = np.zeros((3, 2, N, N, N))
+        links[:, 0] = 1.0
     st = {"phi": phi, "pi": pi, "links": links, "piA": piA, "a": a, "b": 1.0}
     if expand:
         o = u1_sync_observe(u1_model(cfg), st)

@@ -385,9 +385,15 @@ int orc_num_threads(void) {
 /* link V_i(n) = exp(-i e dx A_i) lives on n + i/2, stored (Re, Im);    */
 /* pi_A,i is one real per link.  Plaquette                              */
 /*   V_ij(n) = V_i(n) V_j(n+i) conj V_i(n+j) conj V_j(n).               */
+/* With noncompact = 1 (Sec. 5.2) the link array holds the real gauge  */
+/* field A_i(n) instead (3 N^3), V_i = exp(-i e dx A_i) is formed where  */
+/* the scalar needs it, and the gauge sector is the quadratic one:     */
+/* magnetic kernel sum_j (D-_j D+_j A_i - D-_j D+_i A_j), energy        */
+/* sum_{i<j} F_ij^2 / 2 with F_ij = D+_i A_j - D+_j A_i, drift          */
+/* A += h piA / a_mid^{1-alpha}.                                       */
 /* ------------------------------------------------------------------ */
 typedef struct {
-  int32_t N, expand, pad0, pad1;
+  int32_t N, expand, noncompact, pad1;
   double dx, alpha, fmp2;
   double lambda;   /* V = lambda |phi|^4 + m2 |phi|^2 */
   double m2;
@@ -402,7 +408,7 @@ static inline cpx cconj_(cpx a) { return cmk(a.re, -a.im); }
 
 /* array views: phi[c*V + s] (c = 0 Re, 1 Im); links[(2*i + c)*V + s] */
 static inline cpx phi_at(const double* phi, int64_t V, int64_t s) { return cmk(phi[s], phi[V + s]); }
-static inline cpx link_at(const double* L, int64_t V, int i, int64_t s) { return cmk(L[(2 * i) * V + s], L[(2 * i + 1) * V + s]); }
+static inline cpx link_c(const double* L, int64_t V, int i, int64_t s) { return cmk(L[(2 * i) * V + s], L[(2 * i + 1) * V + s]); }
 
 static int64_t shift(int N, int64_t s, int dir, int step) {
   int x = (int)(s / ((int64_t)N * N)), y = (int)((s / N) % N), z = (int)(s % N);
@@ -410,14 +416,47 @@ static int64_t shift(int N, int64_t s, int dir, int step) {
   return site(N, x, y, z);
 }
 
+/* the link V_i(n) of either formulation */
+static cpx link_at(const orc_u1* m, const double* L, int64_t V, int i, int64_t s) {
+  if (!m->noncompact) return link_c(L, V, i, s);
+  const double t = -m->e * m->dx * L[i * V + s];
+  return cmk(cos(t), sin(t));
+}
+
 static cpx plaquette(const orc_u1* m, const double* L, int i, int j, int64_t s) {
   const int N = m->N;
   const int64_t V = (int64_t)N * N * N;
-  const cpx a = link_at(L, V, i, s);
-  const cpx b = link_at(L, V, j, shift(N, s, i, 1));
-  const cpx c = cconj_(link_at(L, V, i, shift(N, s, j, 1)));
-  const cpx d = cconj_(link_at(L, V, j, s));
+  const cpx a = link_at(m, L, V, i, s);
+  const cpx b = link_at(m, L, V, j, shift(N, s, i, 1));
+  const cpx c = cconj_(link_at(m, L, V, i, shift(N, s, j, 1)));
+  const cpx d = cconj_(link_at(m, L, V, j, s));
   return cmul_(cmul_(a, b), cmul_(c, d));
+}
+
+/* Non-compact field strength F_ij(n) = D+_i A_j(n) - D+_j A_i(n) (Sec. 5.2). */
+static double nc_F(const orc_u1* m, const double* A, int i, int j, int64_t s) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  return ((A[j * V + shift(N, s, i, 1)] - A[j * V + s]) - (A[i * V + shift(N, s, j, 1)] - A[i * V + s])) / m->dx;
+}
+
+/* Non-compact magnetic kernel sum_j (D-_j D+_j A_i - D-_j D+_i A_j)(n) (Sec. 5.2),
+   each term written out from the forward and backward differences. */
+static double nc_magnetic(const orc_u1* m, const double* A, int i, int64_t s) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const double dx2 = m->dx * m->dx;
+  double r = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    const int64_t sjp = shift(N, s, j, 1), sjm = shift(N, s, j, -1);
+    /* D-_j D+_j A_i */
+    const double djj = (A[i * V + sjp] - 2.0 * A[i * V + s] + A[i * V + sjm]) / dx2;
+    /* D-_j D+_i A_j = [D+_i A_j](n) - [D+_i A_j](n - j), over dx */
+    const double dpi_n = A[j * V + shift(N, s, i, 1)] - A[j * V + s];
+    const double dpi_m = A[j * V + shift(N, sjm, i, 1)] - A[j * V + sjm];
+    r += djj - (dpi_n - dpi_m) / dx2;
+  }
+  return r;
 }
 
 /* Kernels of the compact U(1) scheme (Sec. 5.1 kernels, Sec. 5.3 gauge kernel):
@@ -432,6 +471,7 @@ void orc_u1_kernels(const orc_u1* m, double a, const double* phi, const double* 
   const double cp = pow(a, 3.0 + m->alpha);
   const double cj = pow(a, 1.0 + m->alpha) * 2.0 * m->e / m->dx / m->wf2;
   const double cb = pow(a, m->alpha - 1.0) / (m->e * m->dx * m->dx * m->dx);
+  const double cbn = pow(a, m->alpha - 1.0);
 #pragma omp parallel for schedule(static)
   for (int x = 0; x < N; ++x)
     for (int y = 0; y < N; ++y)
@@ -441,8 +481,8 @@ void orc_u1_kernels(const orc_u1* m, double a, const double* phi, const double* 
         cpx lap = cmk(-6.0 * p.re, -6.0 * p.im);
         for (int i = 0; i < 3; ++i) {
           const int64_t sp = shift(N, s, i, 1), sm = shift(N, s, i, -1);
-          const cpx f = cmul_(link_at(L, V, i, s), phi_at(phi, V, sp));
-          const cpx b = cmul_(cconj_(link_at(L, V, i, sm)), phi_at(phi, V, sm));
+          const cpx f = cmul_(link_at(m, L, V, i, s), phi_at(phi, V, sp));
+          const cpx b = cmul_(cconj_(link_at(m, L, V, i, sm)), phi_at(phi, V, sm));
           lap.re += f.re + b.re;
           lap.im += f.im + b.im;
         }
@@ -451,7 +491,11 @@ void orc_u1_kernels(const orc_u1* m, double a, const double* phi, const double* 
         Kphi[s] = cl * lap.re - cp * dv * p.re;
         Kphi[V + s] = cl * lap.im - cp * dv * p.im;
         for (int i = 0; i < 3; ++i) {
-          const cpx cur = cmul_(cconj_(p), cmul_(link_at(L, V, i, s), phi_at(phi, V, shift(N, s, i, 1))));
+          const cpx cur = cmul_(cconj_(p), cmul_(link_at(m, L, V, i, s), phi_at(phi, V, shift(N, s, i, 1))));
+          if (m->noncompact) {
+            KA[i * V + s] = cj * cur.im + cbn * nc_magnetic(m, L, i, s);
+            continue;
+          }
           double mag = 0.0;
           for (int j = 0; j < 3; ++j) {
             if (j == i) continue;
@@ -464,7 +508,8 @@ void orc_u1_kernels(const orc_u1* m, double a, const double* phi, const double* 
 
 /* Raw volume averages (Sec. 5.4): out[0] = <|pi|^2>, out[1] = <sum_i |V_i phi_{+i} - phi|^2>
    (no 1/dx^2), out[2] = <lambda |phi|^4>, out[3] = <m2 |phi|^2>, out[4] = <sum_i piA_i^2>,
-   out[5] = <sum_{i<j} (1 - Re V_ij)>, out[6] = <Re phi>, out[7] = <Im phi>, out[8] = <|phi|^2>. */
+   out[5] = <sum_{i<j} (1 - Re V_ij)> (non-compact: <sum_{i<j} F_ij^2>), out[6] = <Re phi>,
+   out[7] = <Im phi>, out[8] = <|phi|^2>. */
 void orc_u1_sums(const orc_u1* m, const double* phi, const double* pi, const double* L, const double* piA,
                  double* out) {
   const int N = m->N;
@@ -480,7 +525,7 @@ void orc_u1_sums(const orc_u1* m, const double* phi, const double* pi, const dou
         const cpx p = phi_at(phi, V, s);
         if (pi) acc[0] += pi[s] * pi[s] + pi[V + s] * pi[V + s];
         for (int i = 0; i < 3; ++i) {
-          const cpx f = cmul_(link_at(L, V, i, s), phi_at(phi, V, shift(N, s, i, 1)));
+          const cpx f = cmul_(link_at(m, L, V, i, s), phi_at(phi, V, shift(N, s, i, 1)));
           acc[1] += (f.re - p.re) * (f.re - p.re) + (f.im - p.im) * (f.im - p.im);
           if (piA) acc[4] += piA[i * V + s] * piA[i * V + s];
         }
@@ -488,7 +533,14 @@ void orc_u1_sums(const orc_u1* m, const double* phi, const double* pi, const dou
         acc[2] += m->lambda * r2 * r2;
         acc[3] += m->m2 * r2;
         for (int i = 0; i < 3; ++i)
-          for (int j = i + 1; j < 3; ++j) acc[5] += 1.0 - plaquette(m, L, i, j, s).re;
+          for (int j = i + 1; j < 3; ++j) {
+            if (m->noncompact) {
+              const double F = nc_F(m, L, i, j, s);
+              acc[5] += F * F;
+            } else {
+              acc[5] += 1.0 - plaquette(m, L, i, j, s).re;
+            }
+          }
         acc[6] += p.re;
         acc[7] += p.im;
         acc[8] += r2;
@@ -504,7 +556,9 @@ void orc_u1_sums(const orc_u1* m, const double* phi, const double* pi, const dou
 
 /* Energies (Sec. 5.4.1): e[0] = E_K^phi = <|pi|^2>/a^6, e[1] = E_G^phi = <sum|D+phi|^2>/a^2,
    e[2] = E_V, e[3] = E_K^A = (w_star/f_star)^2 sum <piA^2>/(2 a^4),
-   e[4] = E_G^A = (w_star/f_star)^2 /(a^4 dx^4 e^2) sum_{i<j} <1 - Re V_ij>,
+   e[4] = E_G^A = (w_star/f_star)^2 /(a^4 dx^4 e^2) sum_{i<j} <1 - Re V_ij>
+          (non-compact: (w_star/f_star)^2 /(2 a^4) sum_{i<j} <F_ij^2>, Sec. 5.2 read with
+          F_ij = D+_i A_j - D+_j A_i),
    e[5] = <lambda|phi|^4>, e[6] = <m2|phi|^2>.  kin_phi / kin_A override the kinetic
    averages when >= 0 (staggered averages). */
 static void u1_energies(const orc_u1* m, double a, const double* s, double kin_phi, double kin_A, double* e) {
@@ -513,7 +567,7 @@ static void u1_energies(const orc_u1* m, double a, const double* s, double kin_p
   e[1] = s[1] / (a2 * dx2);
   e[2] = s[2] + s[3];
   e[3] = m->wf2 * (kin_A >= 0.0 ? kin_A : s[4]) / (2.0 * a4);
-  e[4] = m->wf2 * s[5] / (a4 * dx2 * dx2 * m->e * m->e);
+  e[4] = m->noncompact ? m->wf2 * s[5] / (2.0 * a4) : m->wf2 * s[5] / (a4 * dx2 * dx2 * m->e * m->e);
   e[5] = s[2];
   e[6] = s[3];
 }
@@ -531,13 +585,19 @@ double orc_u1_Ka(const orc_u1* m, double a, const double* e) {
    V <- (1 - i u)/(1 + i u) V,  u = e h dx piA / (2 a_mid^{1-alpha}). */
 static void u1_link_drift(const orc_u1* m, double* L, const double* piA, double h, double amid) {
   const int64_t V = (int64_t)m->N * m->N * m->N;
+  if (m->noncompact) {
+    /* A_i += h piA_i / a_mid^{1-alpha} (Sec. 5.2) */
+    const double cA = h / pow(amid, 1.0 - m->alpha);
+    for (int64_t k = 0; k < 3 * V; ++k) L[k] += cA * piA[k];
+    return;
+  }
   const double c = m->e * h * m->dx / (2.0 * pow(amid, 1.0 - m->alpha));
   for (int i = 0; i < 3; ++i)
     for (int64_t s = 0; s < V; ++s) {
       const double u = c * piA[i * V + s];
       const double d = 1.0 + u * u;
       const cpx r = cmk((1.0 - u * u) / d, -2.0 * u / d);
-      const cpx v = cmul_(r, link_at(L, V, i, s));
+      const cpx v = cmul_(r, link_c(L, V, i, s));
       L[(2 * i) * V + s] = v.re;
       L[(2 * i + 1) * V + s] = v.im;
     }

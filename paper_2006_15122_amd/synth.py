@@ -53,6 +53,15 @@ def config3(N: int = 192) -> dict:
                 expansion=True, ic="vacuum", seed=5, a0=1.0)
 
 
+def config3_noncompact(N: int = 192) -> dict:
+    """The same Abelian-Higgs physics with the non-compact gauge field of
+    Sec. 5.2 (A_i evolved directly, quadratic magnetic energy)."""
+    c = config3(N)
+    c["model"] = "u1nc"
+    c["name"] = f"u1nc_higgs_{N}_lf2_fp32"
+    return c
+
+
 def config4_runs(nruns: int = 96, sizes=(32, 64, 96), nsteps: int = 5000) -> list:
     """96 independent two-scalar VV2 runs, sizes split evenly among 32^3,
     64^3, 96^3, q = 10^(1+3u) with u uniform from a seeded generator, seeds
