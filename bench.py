@@ -331,6 +331,13 @@ def main():
                                 "hbm_frac": n3 * 80 / (ms3 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
                                 "ms_per_pass": ms3 / st3, "ms_per_pass_ext_events": k3,
                                 "bytes_per_site_update": 80, "steps": st3, "gauss": obs3["gauss"]}
+        # the same physics with the non-compact gauge field (Sec. 5.2), same 80 B/site
+        c3n = synth.config3_noncompact()
+        ms4, _, obs4, _, k4 = time_lattice(c3n, st3, 5, st3)
+        extras["u1nc_192_lf2"] = {"site_updates_per_s": n3 * st3 / (ms4 / 1e3),
+                                  "hbm_frac": n3 * 80 / (ms4 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "ms_per_pass": ms4 / st3, "ms_per_pass_ext_events": k4,
+                                  "bytes_per_site_update": 80, "steps": st3, "gauss": obs4["gauss"]}
         extras["batch_96"] = time_batch(max(args.steps // 10, 20))
         extras["surrogate_predict_65536"] = time_surrogate()
         extras["spectrum_256"] = time_spectrum()

@@ -45,6 +45,10 @@ extern "C" {
                                    + q phi_0^2 phi_1^2/2                      */
 #define LAT_MODEL_U1 1      /* complex scalar with compact U(1) links (Sec. 5.3):
                                V = lambda |phi|^4 + m2[0] |phi|^2            */
+#define LAT_MODEL_U1_NC 2   /* the same with the non-compact gauge field A_i
+                               (Sec. 5.2): A' = a^{-(1-alpha)} pi_A, magnetic
+                               kernel sum_j (D-_j D+_j A_i - D-_j D+_i A_j),
+                               E_G^A from F_ij = D+_i A_j - D+_j A_i         */
 
 /* Integrators (Sec. 3.3-3.4, 4.2-4.3) */
 #define LAT_LF2 0   /* staggered leapfrog, scheme III (pi = a^{3-alpha} phi')    */
@@ -65,7 +69,7 @@ extern "C" {
 
 typedef struct lattice_params {
   int32_t model;       /* LAT_MODEL_*                                      */
-  int32_t nf;          /* LAT_MODEL_SCALAR: 1 or 2; LAT_MODEL_U1: 2        */
+  int32_t nf;          /* LAT_MODEL_SCALAR: 1 or 2; LAT_MODEL_U1(_NC): 2    */
   int32_t N;           /* sites per side: multiple of 32, 32 <= N <= 1024  */
   int32_t integrator;  /* LAT_LF2, LAT_VV2, LAT_VV4                         */
   int32_t precision;   /* LAT_FP64 or LAT_FP32                              */
@@ -81,7 +85,7 @@ typedef struct lattice_params {
   double m2[2];        /* mass terms                                         */
   double lambda;       /* quartic coupling                                   */
   double q;            /* phi^2 chi^2 coupling                               */
-  double e;            /* gauge coupling g_A Q_A (LAT_MODEL_U1)              */
+  double e;            /* gauge coupling g_A Q_A (LAT_MODEL_U1, U1_NC)       */
   double phi0[2];      /* homogeneous field values                           */
   double dphi0[2];     /* homogeneous d phi / d eta                          */
   double a0;           /* initial scale factor (1)                           */
@@ -138,8 +142,10 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
 /* Replace the state by host FP64 arrays (converted to the storage
    precision).  Scalar model: fields and momenta are nf*N^3 values.  U1:
    fields and momenta are 2*N^3 (Re, Im of the complex scalar phi), links
-   3*2*N^3 (direction i, then Re/Im, of V_i), link_momenta 3*N^3 (pi_A,i);
-   links and link_momenta must be NULL for scalar models.
+   3*2*N^3 (direction i, then Re/Im, of V_i), link_momenta 3*N^3 (pi_A,i).
+   U1_NC: as U1 but links holds the gauge field A_i, 3*N^3 values (the
+   link is V_i = exp(-i e dx A_i)).  links and link_momenta must be NULL for
+   scalar models.
    Errors: LAT_EINVAL (NULL arrays), LAT_ENONFINITE, LAT_EHIP. */
 int lattice_set_state(lattice_t* h, const double* fields, const double* momenta,
                       const double* links, const double* link_momenta,

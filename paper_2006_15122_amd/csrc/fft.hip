@@ -524,7 +524,7 @@ __global__ void store_real_kernel(const Cx<double>* F, T* out, int64_t V, double
 
 static double potential_host(const lattice_params& p, const double* phis) {
   const double a = phis[0], c = p.nf > 1 ? phis[1] : 0.0;
-  if (p.model == LAT_MODEL_U1) {
+  if (is_u1(p)) {
     const double r2 = 0.5 * (a * a + c * c);  // |phi|^2 with phi = (phi0 + i phi1)/sqrt 2
     return p.lambda * r2 * r2 + p.m2[0] * r2;
   }
@@ -536,7 +536,7 @@ static double potential_host(const lattice_params& p, const double* phis) {
 // d^2 V / d phi_f^2 at the homogeneous values
 static double curvature_host(const lattice_params& p, int f) {
   const double a = p.phi0[0], c = p.nf > 1 ? p.phi0[1] : 0.0;
-  if (p.model == LAT_MODEL_U1) {
+  if (is_u1(p)) {
     // V = lambda (phi0^2 + phi1^2)^2 / 4 + m2 (phi0^2 + phi1^2) / 2
     const double s = a * a + c * c, x = f == 0 ? a : c;
     return p.lambda * (s + 2.0 * x * x) + p.m2[0];
@@ -559,7 +559,7 @@ int run_fft3d(lattice* h, int sign, double scale) {
 // model, then b from the Hubble constraint with the full-lattice energies.
 int init_state(lattice* h) {
   const lattice_params& p = h->p;
-  if (p.model == LAT_MODEL_U1) return u1_init_state(h);
+  if (is_u1(p)) return u1_init_state(h);
   const int N = p.N;
   const int64_t V = (int64_t)N * N * N;
   const double a = p.a0, al = p.alpha;
@@ -612,7 +612,7 @@ int init_state(lattice* h) {
   h->staggered = 0;
   h->step = 0;
   if (p.expansion) {
-    rc = (p.model == LAT_MODEL_U1) ? u1_energies(h) : scalar_energies(h);
+    rc = (is_u1(p)) ? u1_energies(h) : scalar_energies(h);
     if (rc) return rc;
     DevState d;
     CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));

@@ -48,6 +48,8 @@ struct lattice {
 
 namespace cl {
 
+// compact or non-compact U(1) (10 components, the U(1) pass)
+inline bool is_u1(const lattice_params& p) { return p.model == LAT_MODEL_U1 || p.model == LAT_MODEL_U1_NC; }
 int ncomponents(const lattice_params* p);
 int validate(const lattice_params* p);
 PassDesc pass(double wd, double wk1, double wk2, int mode, int write, int update);

@@ -61,9 +61,9 @@ std::vector<double> vv_weights(int integrator) {
 
 int validate(const lattice_params* p) {
   if (!p) { set_error("params is NULL"); return LAT_EINVAL; }
-  if (p->model != LAT_MODEL_SCALAR && p->model != LAT_MODEL_U1) { set_error("unknown model"); return LAT_EINVAL; }
+  if (p->model != LAT_MODEL_SCALAR && !is_u1(*p)) { set_error("unknown model"); return LAT_EINVAL; }
   if (p->model == LAT_MODEL_SCALAR && (p->nf < 1 || p->nf > 2)) { set_error("scalar model needs nf = 1 or 2"); return LAT_EINVAL; }
-  if (p->model == LAT_MODEL_U1 && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
+  if (is_u1(*p) && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
   if (p->N < 32 || p->N > 1024 || p->N % 32 != 0) { set_error("N must be a multiple of 32 in [32, 1024]"); return LAT_EINVAL; }
   if (p->integrator < LAT_LF2 || p->integrator > LAT_VV10) { set_error("unknown integrator"); return LAT_EINVAL; }
   if (p->precision != LAT_FP32 && p->precision != LAT_FP64) { set_error("unknown precision"); return LAT_EINVAL; }
@@ -116,7 +116,7 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_part2,
 }
 
 int ncomponents(const lattice_params* p) {
-  if (p->model == LAT_MODEL_U1) return 10;  // phi (2), pi (2), link phases (3), piA (3)
+  if (is_u1(*p)) return 10;  // phi (2), pi (2), link phases or A_i (3), piA (3)
   return 2 * p->nf;
 }
 
@@ -267,7 +267,7 @@ int lattice_field_device_ptr(lattice_t* h, int c, void** ptr, int32_t* elem_byte
 int lattice_set_state(lattice_t* h, const double* fields, const double* momenta, const double* links,
                       const double* link_momenta, const lattice_scalars* s) {
   if (!h || !fields || !momenta || !s) { set_error("NULL argument"); return LAT_EINVAL; }
-  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const bool u1 = is_u1(h->p), nc = h->p.model == LAT_MODEL_U1_NC;
   if (u1 && (!links || !link_momenta)) { set_error("U1 state needs links and link momenta"); return LAT_EINVAL; }
   if (!u1 && (links || link_momenta)) { set_error("scalar state takes no links"); return LAT_EINVAL; }
   const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
@@ -276,7 +276,11 @@ int lattice_set_state(lattice_t* h, const double* fields, const double* momenta,
   for (int f = 0; f < nf; ++f) comps.push_back(fields + f * V);
   for (int f = 0; f < nf; ++f) comps.push_back(momenta + f * V);
   std::vector<double> phases;
-  if (u1) {
+  if (nc) {
+    // the gauge field A_i is stored as given
+    for (int i = 0; i < 3; ++i) comps.push_back(links + i * V);
+    for (int c = 0; c < 3; ++c) comps.push_back(link_momenta + c * V);
+  } else if (u1) {
     // a unit link (Re, Im) is stored by its phase
     phases.resize((size_t)3 * V);
     for (int i = 0; i < 3; ++i)
@@ -305,14 +309,17 @@ int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* lin
   if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
   const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
   const int nf = h->p.nf;
-  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const bool u1 = is_u1(h->p), nc = h->p.model == LAT_MODEL_U1_NC;
   std::vector<double*> comps((size_t)h->ncomp, nullptr);
   for (int f = 0; f < nf; ++f) {
     if (fields) comps[f] = fields + f * V;
     if (momenta) comps[nf + f] = momenta + f * V;
   }
   std::vector<double> phases;
-  if (u1) {
+  if (nc) {
+    for (int i = 0; i < 3; ++i) if (links) comps[4 + i] = links + i * V;
+    for (int c = 0; c < 3; ++c) if (link_momenta) comps[7 + c] = link_momenta + c * V;
+  } else if (u1) {
     if (links) {
       phases.resize((size_t)3 * V);
       for (int i = 0; i < 3; ++i) comps[4 + i] = phases.data() + (size_t)i * V;
@@ -321,7 +328,7 @@ int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* lin
   }
   int rc = download_components(h, comps.data(), (int)comps.size());
   if (rc) return rc;
-  if (u1 && links) {
+  if (u1 && !nc && links) {
     for (int i = 0; i < 3; ++i)
       for (int64_t k = 0; k < V; ++k) {
         const double t = phases[(size_t)i * V + k];
@@ -346,13 +353,13 @@ int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* lin
 int lattice_step(lattice_t* h, int64_t nsteps) {
   if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
   if (nsteps < 0) { set_error("nsteps < 0"); return LAT_EINVAL; }
-  if (h->p.model == LAT_MODEL_U1) return u1_step(h, nsteps);
+  if (is_u1(h->p)) return u1_step(h, nsteps);
   return scalar_step(h, nsteps);
 }
 
 int lattice_energies(lattice_t* h, lattice_obs* out) {
   if (!h || !out) { set_error("NULL argument"); return LAT_EINVAL; }
-  int rc = (h->p.model == LAT_MODEL_U1) ? u1_energies(h) : scalar_energies(h);
+  int rc = is_u1(h->p) ? u1_energies(h) : scalar_energies(h);
   if (rc) return rc;
   DevState d;
   CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
@@ -565,7 +572,7 @@ int scalar_energies(lattice* h) {
 bool tiling_ok(const lattice* h, const Tiling& t) {
   bool compiled = false;
   const int fp32 = h->p.precision == LAT_FP32;
-  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const bool u1 = is_u1(h->p);
   const int ns = u1 ? u1_num_shapes(fp32) : num_shapes(fp32, h->p.nf);
   for (int i = 0; i < ns; ++i) {
     int tz, by, ry;
@@ -583,7 +590,7 @@ bool tiling_ok(const lattice* h, const Tiling& t) {
 
 void default_tiling(lattice* h) {
   const int N = h->p.N;
-  if (h->p.model == LAT_MODEL_U1) {
+  if (is_u1(h->p)) {
     // the 64-wide tile where it divides N; the largest x-chunk that still
     // gives 1024 blocks
     const bool wide = h->p.precision == LAT_FP32 && N % 64 == 0;
@@ -616,7 +623,7 @@ int autotune(lattice* h) {
   hipEvent_t e0, e1;
   CL_HIP(hipEventCreate(&e0));
   CL_HIP(hipEventCreate(&e1));
-  const bool u1 = h->p.model == LAT_MODEL_U1;
+  const bool u1 = is_u1(h->p);
   const std::vector<int> xcs = u1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
   float best = 1e30f;
   Tiling bt = h->tile;

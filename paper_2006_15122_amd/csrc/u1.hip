@@ -165,7 +165,12 @@ __device__ __forceinline__ T wrap_phase(T t) {
   return t - twopi * rint(t / twopi);
 }
 
-template <typename T, int TZ, int BY, int RY>
+// NC: non-compact gauge field (Sec. 5.2).  The three link slots then hold A_i;
+// the drift is linear, the link phase is theta_i = -e dx A_i, and the
+// plaquette terms are the angles themselves (Phi = -e dx^2 F_ij; Phi^2/2 for
+// the magnetic energy), which turns the compact kernels into the quadratic
+// ones with the same coefficients.
+template <typename T, int TZ, int BY, int RY, bool NC>
 __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   constexpr int TY = BY * RY, NT = TZ * BY, LY = TY + 2, LZ = TZ + 2;
   constexpr int NH = 2 * LZ + 2 * TY;  // ring of the (TY+2) x (TZ+2) plane tile
@@ -212,6 +217,8 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const double hw = A.pd.wd * A.h;
   const T cd = dr ? (T)(hw * pow(amid, -(3.0 - A.alpha))) : T(0);
   const T cu = dr ? (T)(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha))) : T(0);
+  const T cA = dr ? (T)(hw / pow(amid, 1.0 - A.alpha)) : T(0);  // non-compact A drift
+  const T mth = (T)(-A.e * A.dx);                                // theta = -e dx A
   const T cl = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
   const T cp = (T)pow(anew, 3.0 + A.alpha);
   const T cj = (T)(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
@@ -261,10 +268,15 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       Lp[b][1][ly][lz] = raw[1][r] + cd * raw[3][r];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const T th = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+        T th;
+        if constexpr (NC) {
+          th = raw[4 + i][r] + cA * raw[7 + i][r];  // A_i after the drift
+        } else {
+          th = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+        }
         Lt[b][i][ly][lz] = th;
         T sn, cs;
-        sincos_t(th, &sn, &cs);
+        sincos_t(NC ? mth * th : th, &sn, &cs);
         Lu[b][i][ly][lz] = C2<T>{cs, sn};
       }
     }
@@ -273,9 +285,15 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       Lp[b][1][rly][rlz] = rraw[1] + cd * rraw[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const T th = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+        T th;
+        if constexpr (NC) {
+          th = rraw[4 + i] + cA * rraw[7 + i];
+          Lt[b][i][rly][rlz] = th;  // the plaquette angles need A on the ring
+        } else {
+          th = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+        }
         T sn, cs;
-        sincos_t(th, &sn, &cs);
+        sincos_t(NC ? mth * th : th, &sn, &cs);
         Lu[b][i][rly][rlz] = C2<T>{cs, sn};
       }
     }
@@ -285,6 +303,16 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   // sin Phi_ij = Im P and 1 - cos Phi_ij = (Im P)^2 / (1 + Re P) (no cancellation
   // for small Phi; 1 - Re P where Re P < 0).
   auto plaq = [&](int c, int n, int ly, int lz, T (&sn)[3], T (&om)[3]) {
+    if constexpr (NC) {
+      // Phi_ij = theta_i(m) + theta_j(m+i) - theta_i(m+j) - theta_j(m) with theta = -e dx A
+      const T a0 = Lt[c][0][ly][lz], a1 = Lt[c][1][ly][lz], a2 = Lt[c][2][ly][lz];
+      sn[0] = mth * ((a0 + Lt[n][1][ly][lz]) - (Lt[c][0][ly + 1][lz] + a1));
+      sn[1] = mth * ((a0 + Lt[n][2][ly][lz]) - (Lt[c][0][ly][lz + 1] + a2));
+      sn[2] = mth * ((a1 + Lt[c][2][ly + 1][lz]) - (Lt[c][1][ly][lz + 1] + a2));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) om[k] = T(0.5) * sn[k] * sn[k];
+      return;
+    }
     const C2<T> u0 = Lu[c][0][ly][lz], u1 = Lu[c][1][ly][lz], u2 = Lu[c][2][ly][lz];
     C2<T> P[3];
     P[0] = cm(cm(u0, Lu[n][1][ly][lz]), cc(cm(Lu[c][0][ly + 1][lz], u1)));
@@ -588,7 +616,7 @@ static int u1_gauss_t(lattice* h) {
 
 // One pass from the current buffer into the other (or no stores for an
 // observation), then the FP64 finish.
-template <typename T, int TZ, int BY, int RY>
+template <typename T, int TZ, int BY, int RY, bool NC>
 static int u1_pass_t(lattice* h, const PassDesc& pd, PassChain* chain) {
   U1PassArgs<T> A;
   for (int c = 0; c < 10; ++c) {
@@ -630,9 +658,10 @@ static int u1_pass_t(lattice* h, const PassDesc& pd, PassChain* chain) {
     ++h->timer_used;
   }
   if (ev0)
-    hipExtLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, ev0, ev1, 0, A);
+    hipExtLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY, NC>), dim3(nb), dim3(TZ * BY), 0, h->stream, ev0, ev1, 0,
+                          A);
   else
-    hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
+    hipLaunchKernelGGL((u1_pass_kernel<T, TZ, BY, RY, NC>), dim3(nb), dim3(TZ * BY), 0, h->stream, A);
   CL_HIP(hipGetLastError());
   if (chain) {
     if (A.prev.partials) chain->rd ^= 1;
@@ -682,16 +711,22 @@ void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry) {
 }
 
 // Shape and x-chunk from h->tile (checked by tiling_ok).
-int u1_pass(lattice* h, const PassDesc& pd, PassChain* chain) {
+template <bool NC>
+static int u1_pass_nc(lattice* h, const PassDesc& pd, PassChain* chain) {
   const Tiling& t = h->tile;
   if (h->p.precision == LAT_FP32) {
-    if (t.tz == 64 && t.by == 4 && t.ry == 2) return u1_pass_t<float, 64, 4, 2>(h, pd, chain);
-    if (t.tz == 32 && t.by == 8 && t.ry == 1) return u1_pass_t<float, 32, 8, 1>(h, pd, chain);
+    if (t.tz == 64 && t.by == 4 && t.ry == 2) return u1_pass_t<float, 64, 4, 2, NC>(h, pd, chain);
+    if (t.tz == 32 && t.by == 8 && t.ry == 1) return u1_pass_t<float, 32, 8, 1, NC>(h, pd, chain);
   } else if (t.tz == 32 && t.by == 8 && t.ry == 1) {
-    return u1_pass_t<double, 32, 8, 1>(h, pd, chain);
+    return u1_pass_t<double, 32, 8, 1, NC>(h, pd, chain);
   }
   set_error("U(1) pass: tile shape not compiled");
   return LAT_EINVAL;
+}
+
+int u1_pass(lattice* h, const PassDesc& pd, PassChain* chain) {
+  if (h->p.model == LAT_MODEL_U1_NC) return u1_pass_nc<true>(h, pd, chain);
+  return u1_pass_nc<false>(h, pd, chain);
 }
 
 int u1_gauss(lattice* h) { return h->p.precision == LAT_FP32 ? u1_gauss_t<float>(h) : u1_gauss_t<double>(h); }

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libcosmolat.so")
 _LIB = None
 
-LAT_MODEL_SCALAR, LAT_MODEL_U1 = 0, 1
+LAT_MODEL_SCALAR, LAT_MODEL_U1, LAT_MODEL_U1_NC = 0, 1, 2
+MODELS = {"scalar": LAT_MODEL_SCALAR, "u1": LAT_MODEL_U1, "u1nc": LAT_MODEL_U1_NC}
 INTEGRATORS = {"lf2": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ICS = {"vacuum": 0, "homogeneous": 1}
@@ -88,7 +89,7 @@ def _check(rc):
 
 def params(cfg: dict) -> Params:
     p = Params()
-    p.model = LAT_MODEL_U1 if cfg.get("model", "scalar") == "u1" else LAT_MODEL_SCALAR
+    p.model = MODELS[cfg.get("model", "scalar")]
     p.nf = int(cfg["nf"])
     p.N = int(cfg["N"])
     p.integrator = INTEGRATORS[cfg.get("integrator", "vv2")]
@@ -172,9 +173,16 @@ class Lattice:
         s = Scalars(a=float(a), b=float(b), eta=float(eta), step=int(step),
                     staggered=1 if staggered else 0, reserved=0)
         lk = pa = None
+        V = self.N ** 3
+        if phi.size != self.nf * V or pi.size != self.nf * V:
+            raise ValueError(f"phi and pi must hold {self.nf} x N^3 values")
         if links is not None:
             lk = np.ascontiguousarray(links, dtype=np.float64)
             pa = np.ascontiguousarray(piA, dtype=np.float64)
+            # compact links are (Re, Im) pairs; the non-compact model takes A_i
+            want = 3 * V if self.p.model == LAT_MODEL_U1_NC else 6 * V
+            if lk.size != want or pa.size != 3 * V:
+                raise ValueError(f"links must hold {want} values and piA {3 * V}")
         _check(lib().lattice_set_state(self.h, _dp(phi), _dp(pi), _dp(lk) if lk is not None else None,
                                        _dp(pa) if pa is not None else None, ctypes.byref(s)))
 
@@ -186,6 +194,9 @@ class Lattice:
         links = piA = None
         if self.p.model == LAT_MODEL_U1:
             links = np.empty((3, 2, N, N, N))
+            piA = np.empty((3, N, N, N))
+        elif self.p.model == LAT_MODEL_U1_NC:
+            links = np.empty((3, N, N, N))
             piA = np.empty((3, N, N, N))
         _check(lib().lattice_get_state(self.h, _dp(phi), _dp(pi), _dp(links) if links is not None else None,
                                        _dp(piA) if piA is not None else None, ctypes.byref(s)))

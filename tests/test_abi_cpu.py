@@ -172,3 +172,19 @@ def test_integrator_codes():
     # the compact U(1) model steps with the leapfrog and every velocity-Verlet order
     for name in ("lf2", "vv2", "vv4", "vv10"):
         assert lattice.workspace_size(dict(synth.config3(N=32), integrator=name)) > 0
+
+
+def test_model_codes_and_noncompact_layout():
+    import ctypes
+    # the non-compact U(1) model has the compact model's component layout
+    for N in (32, 192):
+        assert lattice.workspace_size(synth.config3_noncompact(N=N)) == lattice.workspace_size(synth.config3(N=N))
+    for name in ("lf2", "vv2", "vv10"):
+        assert lattice.workspace_size(dict(synth.config3_noncompact(N=32), integrator=name)) > 0
+    p = lattice.params(synth.config3_noncompact(N=32))
+    assert p.model == lattice.LAT_MODEL_U1_NC == 2
+    n = ctypes.c_size_t()
+    p.model = 3
+    assert lattice.lib().lattice_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p.model, p.nf = lattice.LAT_MODEL_U1_NC, 1
+    assert lattice.lib().lattice_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
