@@ -120,10 +120,35 @@ def test_u1nc_strong_gauge_field_parity_fp64():
         assert np.max(np.abs(s[key] - st[key])) < 1e-10 * np.max(np.abs(st[key])), key
 
 
+def test_u1nc_full_size_192_sampled_sites():
+    """The benchmark configuration (192^3 FP32, autotuned tile, chained
+    passes): observables against the oracle and 4096 sampled sites of every
+    component after 3 leapfrog steps."""
+    cfg = _cfg(192, "fp32")
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    _set(lat, st)
+    h = cfg["dt"]
+    lat.step(3)
+    oracle.u1_lf_startup(m, st, h)
+    oracle.u1_lf_steps(m, st, h, 3, omp=True)
+    o = oracle.u1_lf_observe(m, st, h)
+    g = lat.energies()
+    compare(g, o, 1e-5, "192^3")
+    assert g["gauss"] < 3e-5
+    s = lat.get_state()
+    rng = np.random.default_rng(1)
+    for key, nc in (("phi", 2), ("pi", 2), ("links", 3), ("piA", 3)):
+        idx = (rng.integers(0, nc, 4096),) + tuple(rng.integers(0, 192, (3, 4096)))
+        d = np.abs(s[key][idx] - st[key][idx])
+        assert np.max(d) < 2e-5 * np.max(np.abs(st[key][idx])), key
+
+
 def test_u1nc_every_tiling_and_192_run():
     """Each compiled tile of the non-compact pass at 64^3 FP32 against the
-    oracle; then a device-initialised 192^3 run (the benchmark size, autotuned
-    tile) keeps the Gauss law and a finite, growing scale factor."""
+    oracle; then a device-initialised 192^3 run of 200 steps keeps the Gauss
+    law and a finite, growing scale factor."""
     cfg = _cfg(64, "fp32")
     st = oracle.u1_vacuum_ic(cfg)
     m = oracle.u1_model(cfg)
