@@ -2,15 +2,17 @@
 // trained and evaluated on the matrix cores.
 //
 // Every product is C[M][N] = A[M][K] Bt[N][K]^T with BF16 operands stored
-// K-contiguous and FP32 accumulation (v_mfma_f32_16x16x32_bf16).  The
-// training step keeps row-major and transposed BF16 copies of activations,
-// gradients and weights so that all products have this one form:
+// K-contiguous and FP32 accumulation (v_mfma_f32_16x16x32_bf16):
 //   forward          a_l   = h_{l-1} W_l^T            (A = h_{l-1},  Bt = W_l)
-//   weight gradient  gW_l  = da_l^T h_{l-1}           (A = da_l^T,   Bt = h_{l-1}^T)
 //   input gradient   dh    = da_l W_l                 (A = da_l,     Bt = W_l^T)
-// Weight-gradient products are split over the batch (KSPLIT rows per split)
-// and all cross-block sums (splits, bias columns, loss) are reduced in a
-// fixed order by the finishing kernel, so a training step is deterministic.
+//   weight gradient  gW_l  = da_l^T h_{l-1}           (A = da_l^T,   Bt = h_{l-1}^T)
+// A training step is three kernels.  The first takes 16 batch rows per block
+// through the forward pass, the loss and the input-gradient chain with the
+// activations in LDS (all of that is local to a row), and writes BF16
+// transposed copies of h_l and da_l.  The second computes the three weight
+// gradients in one launch, split over the batch (KSPLIT rows per split).  The
+// third sums every partial (splits, bias columns, loss) in a fixed order and
+// applies Adam, so a training step is deterministic.
 //
 // Operand layout of one 16x16x32 product on a 64-lane wave (verified on the
 // device): lane l holds A[l%16][8(l/16) .. 8(l/16)+7] and
@@ -75,121 +77,285 @@ struct Norm {
 };
 
 // ---------------------------------------------------------------------------
-// layer 1 (K = 2, plain FMA): a block covers 32 batch rows x 64 units, each
-// thread one unit over 8 rows (one 16-byte store of the transposed copy)
+// training step, part 1: everything that is local to a batch row.  One block
+// takes RB = 16 rows through the forward pass, the loss and the backward pass
+// down to the input layer; the 16 x 256 activations and gradients stay in
+// LDS between layers.  Wave w owns hidden units 64w .. 64w+63 (output units
+// 16w .. 16w+15), so the thread that writes a pre-activation a_l[i][j] is the
+// one that reads it back for GELU'(a_l) on the way down.  It writes what the
+// weight-gradient products need (h_l^T, da_l^T, BF16) and per-block partial
+// sums of the bias gradients, of the first layer's weight gradient and of the
+// loss.
 // ---------------------------------------------------------------------------
-constexpr int L1_ROWS = 32;
+constexpr int RB = 16;          // batch rows per block of the fused step kernel
+constexpr int LDY = NOUT + 8;   // LDS pitch of dL/dy (BF16)
 
-__global__ __launch_bounds__(256) void l1_forward(const float* __restrict__ X, const int32_t* __restrict__ rows,
-                                                  int n, const Norm* __restrict__ nm, const bf16_t* __restrict__ W1b,
-                                                  const float* __restrict__ b1, float* __restrict__ xn,
-                                                  float* __restrict__ A1, bf16_t* __restrict__ H1,
-                                                  bf16_t* __restrict__ H1t, int ldt) {
-  __shared__ float xs[L1_ROWS][2];
-  const int t = threadIdx.x;
-  const int r0 = blockIdx.x * L1_ROWS;
-  const int j = blockIdx.y * 64 + (t & 63);
-  const int g = t >> 6;  // rows r0 + 8g .. r0 + 8g + 7
-  if (t < L1_ROWS) {
+struct RowArgs {
+  const float* X;        // raw inputs [*][2], rows selected by `rows` (or the first n)
+  const float* T;        // raw targets [*][NOUT]
+  const int32_t* rows;
+  int nvalid;            // rows >= nvalid are padding (zero gradient)
+  float dscale;          // 2 / (nvalid * NOUT)
+  const Norm* nm;
+  const bf16_t *W1b, *W2b, *W3b, *W4b, *W2t, *W3t, *W4t;
+  const float *b1, *b2, *b3, *b4;
+  float *A1, *A2, *A3;              // FP32 pre-activations [Bp][WID]
+  bf16_t *H1t, *H2t, *H3t;          // BF16 h_l^T [WID][ldt]
+  bf16_t *DYt, *D3t, *D2t;          // BF16 dL/dy^T [NOUT][ldt], dL/da_l^T [WID][ldt]
+  int ldt;
+  float *bp1, *bp2, *bp3, *bp4;     // per-block bias-gradient columns [R][width]
+  float* w1p;                       // per-block first-layer weight gradient [R][WID][2]
+  double* lpart;                    // per-block sum of squared residuals [R]
+};
+
+// sum over the block's 16 rows of per-lane column values (lanes l, l^16, l^32,
+// l^48 share a column); lanes 0..15 return the column sums
+__device__ __forceinline__ float col_sum16(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// one 16 x 64 slab of C = A Bt^T: A is the block's 16 rows in LDS (pitch lda),
+// Bt rows col0 .. col0+63 in global memory (pitch ldb), K = 32 * NK.  All
+// weight fragments are requested before the first product, so the wave waits
+// for memory once per layer instead of once per 32-deep step.
+template <int NK>
+__device__ __forceinline__ void slab16x64(const bf16_t* As, int lda, const bf16_t* __restrict__ Bt, int ldb,
+                                          int col0, int lane, f4 (&acc)[4]) {
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bf16_t* pb = Bt + (size_t)(col0 + r16) * ldb + kq;
+  bf16x8 b[NK][4];
+#pragma unroll
+  for (int s = 0; s < NK; ++s)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) b[s][ct] = load8(pb + (size_t)ct * 16 * ldb + 32 * s);
+  bf16x8 a[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) a[s] = load8(As + r16 * lda + 32 * s + kq);
+  // keep the scheduler from sinking the loads back between the products
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = 0; s < NK; ++s)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = mma(a[s], b[s][ct], acc[ct]);
+}
+
+__device__ __forceinline__ void store_t4(bf16_t* Ht, int j, int ldt, int i0, const bf16_t (&hb)[4]) {
+  uint2 v;
+  v.x = hb[0] | ((uint32_t)hb[1] << 16);
+  v.y = hb[2] | ((uint32_t)hb[3] << 16);
+  *reinterpret_cast<uint2*>(Ht + (size_t)j * ldt + i0) = v;
+}
+
+__global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
+  __shared__ __align__(16) bf16_t HA[RB * LDH];
+  __shared__ __align__(16) bf16_t HB[RB * LDH];
+  __shared__ __align__(16) bf16_t DY[RB * LDY];
+  __shared__ float xs[RB][2];
+  __shared__ double lred[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rq = (lane >> 4) * 4;  // first of this lane's 4 rows in a 16-row tile
+  const int rb = blockIdx.x, r0 = rb * RB;
+  const int ldt = g.ldt;
+
+  // layer 1 (K = 2, plain FMA): thread t is unit t for the 16 rows
+  if (t < RB) {
     const int i = r0 + t;
     float x0 = 0.0f, x1 = 0.0f;
-    if (i < n) {
-      const int64_t src = rows ? (int64_t)rows[i] : (int64_t)i;
-      x0 = (X[2 * src] - nm->in_shift[0]) * nm->in_scale[0];
-      x1 = (X[2 * src + 1] - nm->in_shift[1]) * nm->in_scale[1];
+    if (i < g.nvalid) {
+      const int64_t src = g.rows ? (int64_t)g.rows[i] : (int64_t)i;
+      x0 = (g.X[2 * src] - g.nm->in_shift[0]) * g.nm->in_scale[0];
+      x1 = (g.X[2 * src + 1] - g.nm->in_shift[1]) * g.nm->in_scale[1];
     }
     xs[t][0] = x0;
     xs[t][1] = x1;
-    if (blockIdx.y == 0) {
-      xn[2 * i] = x0;
-      xn[2 * i + 1] = x1;
-    }
   }
   __syncthreads();
-  const float w0 = from_bf16(W1b[2 * j]), w1 = from_bf16(W1b[2 * j + 1]), bj = b1[j];
-  uint32_t packed[4];
+  {
+    const int j = t;
+    const float w0 = from_bf16(g.W1b[2 * j]), w1 = from_bf16(g.W1b[2 * j + 1]), bj = g.b1[j];
+    uint32_t packed[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int lr = 8 * g + r;
-    const float a = xs[lr][0] * w0 + xs[lr][1] * w1 + bj;
-    const bf16_t h = to_bf16(gelu(a));
-    A1[(size_t)(r0 + lr) * WID + j] = a;
-    H1[(size_t)(r0 + lr) * WID + j] = h;
-    if (r & 1) packed[r >> 1] |= (uint32_t)h << 16;
-    else packed[r >> 1] = h;
+    for (int r = 0; r < RB; ++r) {
+      const float a = xs[r][0] * w0 + xs[r][1] * w1 + bj;
+      const bf16_t hv = to_bf16(gelu(a));
+      g.A1[(size_t)(r0 + r) * WID + j] = a;
+      HA[r * LDH + j] = hv;
+      if (r & 1) packed[r >> 1] |= (uint32_t)hv << 16;
+      else packed[r >> 1] = hv;
+    }
+    uint4* dst = reinterpret_cast<uint4*>(g.H1t + (size_t)j * ldt + r0);
+    dst[0] = uint4{packed[0], packed[1], packed[2], packed[3]};
+    dst[1] = uint4{packed[4], packed[5], packed[6], packed[7]};
   }
-  uint4 v;
-  v.x = packed[0];
-  v.y = packed[1];
-  v.z = packed[2];
-  v.w = packed[3];
-  *reinterpret_cast<uint4*>(H1t + (size_t)j * ldt + r0 + 8 * g) = v;
+  __syncthreads();
+
+  // hidden layers 2 and 3: a = h W^T + b, h' = BF16(GELU(a))
+  {
+    const bf16_t* Wl[2] = {g.W2b, g.W3b};
+    const float* bl[2] = {g.b2, g.b3};
+    float* Al[2] = {g.A2, g.A3};
+    bf16_t* Htl[2] = {g.H2t, g.H3t};
+    bf16_t* src[2] = {HA, HB};
+    bf16_t* dstb[2] = {HB, HA};
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      f4 acc[4];
+      slab16x64<WID / 32>(src[l], LDH, Wl[l], WID, 64 * w, lane, acc);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int j = 64 * w + 16 * ct + (lane & 15);
+        const float bj = bl[l][j];
+        bf16_t hb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = rq + e;
+          const float a = acc[ct][e] + bj;
+          Al[l][(size_t)(r0 + r) * WID + j] = a;
+          hb[e] = to_bf16(gelu(a));
+          dstb[l][r * LDH + j] = hb[e];
+        }
+        store_t4(Htl[l], j, ldt, r0 + rq, hb);
+      }
+      __syncthreads();
+    }
+  }
+
+  // output layer, loss and dL/dy = 2 (y - t) / (n NOUT) in normalised units;
+  // wave w owns outputs 16w .. 16w+15
+  {
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16_t* pb = g.W4b + (size_t)(16 * w + r16) * WID + kq;
+#pragma unroll
+    for (int s = 0; s < WID / 32; ++s) acc = mma(load8(HA + r16 * LDH + 32 * s + kq), load8(pb + 32 * s), acc);
+    // (8 independent 16-byte loads: the compiler issues them together)
+    const int j = 16 * w + r16;
+    const float bj = g.b4[j], sh = g.nm->out_shift[j], sc = g.nm->out_scale[j];
+    double lsum = 0.0;
+    float cs = 0.0f;
+    bf16_t hb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rq + e, i = r0 + r;
+      const float y = acc[e] + bj;
+      float dy = 0.0f;
+      if (i < g.nvalid) {
+        const int64_t src = g.rows ? (int64_t)g.rows[i] : (int64_t)i;
+        const float tn = (g.T[src * NOUT + j] - sh) * sc;
+        const float res = y - tn;
+        lsum += (double)res * (double)res;
+        dy = res * g.dscale;
+      }
+      hb[e] = to_bf16(dy);
+      DY[r * LDY + j] = hb[e];
+      cs += dy;
+    }
+    store_t4(g.DYt, j, ldt, r0 + rq, hb);
+    cs = col_sum16(cs);
+    if (lane < 16) g.bp4[(size_t)rb * NOUT + j] = cs;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o);
+    if (lane == 0) lred[w] = lsum;
+  }
+  __syncthreads();
+  if (t == 0) g.lpart[rb] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+
+  // backward through layers 4 -> 3 -> 2 (da_l = (da_{l+1} W_{l+1}) GELU'(a_l)) and 2 -> 1
+  {
+    const bf16_t* Wt[3] = {g.W4t, g.W3t, g.W2t};
+    const float* Al[3] = {g.A3, g.A2, g.A1};
+    bf16_t* Dt[2] = {g.D3t, g.D2t};
+    float* bp[3] = {g.bp3, g.bp2, g.bp1};
+    const bf16_t* src[3] = {DY, HB, HA};
+    const int lds[3] = {LDY, LDH, LDH};
+    bf16_t* dstb[2] = {HB, HA};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      f4 acc[4];
+      if (l == 0) slab16x64<NOUT / 32>(src[l], lds[l], Wt[l], NOUT, 64 * w, lane, acc);
+      else slab16x64<WID / 32>(src[l], lds[l], Wt[l], WID, 64 * w, lane, acc);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int j = 64 * w + 16 * ct + (lane & 15);
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        bf16_t hb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = rq + e;
+          const float da = acc[ct][e] * gelu_grad(Al[l][(size_t)(r0 + r) * WID + j]);
+          c0 += da;
+          if (l < 2) {
+            hb[e] = to_bf16(da);
+            dstb[l][r * LDH + j] = hb[e];
+          } else {
+            c1 += da * xs[r][0];
+            c2 += da * xs[r][1];
+          }
+        }
+        if (l < 2) store_t4(Dt[l], j, ldt, r0 + rq, hb);
+        c0 = col_sum16(c0);
+        if (l == 2) {
+          c1 = col_sum16(c1);
+          c2 = col_sum16(c2);
+        }
+        if (lane < 16) {
+          bp[l][(size_t)rb * WID + j] = c0;
+          if (l == 2) {
+            g.w1p[((size_t)rb * WID + j) * 2] = c1;
+            g.w1p[((size_t)rb * WID + j) * 2 + 1] = c2;
+          }
+        }
+      }
+      if (l < 2) __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// C = A Bt^T on a 64x64 block tile, 4 waves of 32x32, with a fused epilogue
+// training step, part 2: the three weight-gradient products
+//   gW_l[M][N] = sum over batch rows of da_l^T h_{l-1}  (A = da_l^T, Bt = h_{l-1}^T)
+// in one launch, each split over KSPLIT batch rows into its own partial slab
+// (summed in split order by the finishing kernel).  64 x 64 block tiles, four
+// waves of 32 x 32; all operand fragments of a block are loaded first.
 // ---------------------------------------------------------------------------
-enum Epi { EPI_FWD_HID = 0, EPI_FWD_LOSS = 1, EPI_WGRAD = 2, EPI_BWD_HID = 3, EPI_BWD_FIRST = 4 };
-
-struct GemmArgs {
-  const bf16_t* A;
-  const bf16_t* Bt;
-  int lda, ldb;
-  int M, N, K, ksplit;
-  const float* bias;     // forward: bias of the layer
-  float* outA;           // EPI_FWD_HID: pre-activations [M][N]
-  bf16_t* outH;          // BF16 result [M][N]
-  bf16_t* outHt;         // and its transpose [N][ldt]
-  int ldt;
-  const float* prevA;    // backward: pre-activations of the layer below [M][N]
-  float* bpart;          // column sums of the FP32 result per 64-row block [M/64][N]
-  float* wpart;          // EPI_WGRAD: [split][M][N]
-  const float* xn;       // EPI_BWD_FIRST: normalised inputs [M][2]
-  float* w1part;         // EPI_BWD_FIRST: [M/64][N][2]
-  const float* T;        // EPI_FWD_LOSS: raw targets, rows selected by `rows`
-  const int32_t* rows;
-  const Norm* nm;
-  double* lpart;         // EPI_FWD_LOSS: sum of squared residuals per 64-row block
-  int nvalid;            // rows >= nvalid are padding (zero gradient)
-  float dscale;          // 2 / (nvalid * 64)
+struct WgradProduct {
+  const bf16_t* A;   // [M][K], pitch ld
+  const bf16_t* Bt;  // [N][K], pitch ld
+  float* part;       // [splits][M][N]
+  int M;
 };
 
-// sum over the 64 rows of the block tile of one value per (lane, ct);
-// the two row-waves meet in LDS; result for local column c in red[c]
-__device__ __forceinline__ void column_sums(float (&cs)[2], float* red, int lane, int wr, int wc) {
-#pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    cs[ct] += __shfl_xor(cs[ct], 16);
-    cs[ct] += __shfl_xor(cs[ct], 32);
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) red[wr * 64 + wc * 32 + ct * 16 + lane] = cs[ct];
-  }
-}
+struct WgradArgs {
+  WgradProduct p[3];
+  int ld, K, S;      // pitch (= max batch), batch rows, splits
+  int first[4];      // first block of each product (cumulative)
+};
 
-template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt(GemmArgs g) {
-  __shared__ float red[3][2 * 64];
-  __shared__ double lred[4];
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
+  const int b = blockIdx.x;
+  const int pi = b < g.first[1] ? 0 : (b < g.first[2] ? 1 : 2);
+  const WgradProduct& P = g.p[pi];
+  constexpr int N = WID, TX = WID / 64;
+  const int ty = P.M / 64, loc = b - g.first[pi];
+  const int bx = loc % TX, by = (loc / TX) % ty, bz = loc / (TX * ty);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   const int r16 = lane & 15, kq = (lane >> 4) * 8;
-  const int row0 = blockIdx.y * 64 + wr * 32, col0 = blockIdx.x * 64 + wc * 32;
-  const int kb = blockIdx.z * g.ksplit;
-  const int ke = min(g.K, kb + g.ksplit);
+  const int row0 = by * 64 + wr * 32, col0 = bx * 64 + wc * 32;
+  const int kb = bz * KSPLIT, ke = min(g.K, kb + KSPLIT);
+  const int nk = (ke - kb) >> 5;  // 2, 4, 6 or 8
+  const bf16_t* pa0 = P.A + (size_t)(row0 + r16) * g.ld + kq;
+  const bf16_t* pa1 = pa0 + (size_t)16 * g.ld;
+  const bf16_t* pb0 = P.Bt + (size_t)(col0 + r16) * g.ld + kq;
+  const bf16_t* pb1 = pb0 + (size_t)16 * g.ld;
   f4 acc[2][2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  const bf16_t* pa0 = g.A + (size_t)(row0 + r16) * g.lda + kq;
-  const bf16_t* pa1 = pa0 + (size_t)16 * g.lda;
-  const bf16_t* pb0 = g.Bt + (size_t)(col0 + r16) * g.ldb + kq;
-  const bf16_t* pb1 = pb0 + (size_t)16 * g.ldb;
-  // The k range of a block is a multiple of 64 and at most 256 (one split):
-  // all of its operand fragments are loaded first, so the block waits for
-  // memory once, then runs its products back to back.
-  const int nk = (ke - kb) >> 5;  // 32-deep products: 2, 4, 6 or 8
   bf16x8 fa[8][2], fb[8][2];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
@@ -210,101 +376,16 @@ __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g) {
       acc[1][1] = mma(fa[s][1], fb[s][1], acc[1][1]);
     }
   }
-
-  const int N = g.N;
-  if constexpr (EPI == EPI_WGRAD) {
-    float* out = g.wpart + (size_t)blockIdx.z * g.M * N;
+  float* out = P.part + (size_t)bz * P.M * N;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = row0 + rt * 16 + (lane >> 4) * 4 + e, j = col0 + ct * 16 + r16;
-          out[(size_t)i * N + j] = acc[rt][ct][e];
-        }
-    return;
-  } else {
-    float cs[3][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
-    double lsum = 0.0;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const int j = col0 + ct * 16 + r16;
-        const int i0 = row0 + rt * 16 + (lane >> 4) * 4;
-        bf16_t hb[4];
-        float bj = 0.0f, sh = 0.0f, sc = 0.0f;
-        if constexpr (EPI == EPI_FWD_HID || EPI == EPI_FWD_LOSS) bj = g.bias[j];
-        if constexpr (EPI == EPI_FWD_LOSS) {
-          sh = g.nm->out_shift[j];
-          sc = g.nm->out_scale[j];
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = i0 + e;
-          const size_t ij = (size_t)i * N + j;
-          if constexpr (EPI == EPI_FWD_HID) {
-            const float a = acc[rt][ct][e] + bj;
-            g.outA[ij] = a;
-            hb[e] = to_bf16(gelu(a));
-            g.outH[ij] = hb[e];
-          } else if constexpr (EPI == EPI_FWD_LOSS) {
-            const float y = acc[rt][ct][e] + bj;
-            float dy = 0.0f;
-            if (i < g.nvalid) {
-              const int64_t src = g.rows ? (int64_t)g.rows[i] : (int64_t)i;
-              const float tn = (g.T[src * NOUT + j] - sh) * sc;
-              const float r = y - tn;
-              lsum += (double)r * (double)r;
-              dy = r * g.dscale;
-            }
-            hb[e] = to_bf16(dy);
-            g.outH[ij] = hb[e];
-            cs[0][ct] += dy;
-          } else {  // backward through GELU of the layer below
-            const float da = acc[rt][ct][e] * gelu_grad(g.prevA[ij]);
-            cs[0][ct] += da;
-            if constexpr (EPI == EPI_BWD_HID) {
-              hb[e] = to_bf16(da);
-              g.outH[ij] = hb[e];
-            } else {
-              cs[1][ct] += da * g.xn[2 * i];
-              cs[2][ct] += da * g.xn[2 * i + 1];
-            }
-          }
-        }
-        if constexpr (EPI != EPI_BWD_FIRST) {
-          uint2 v;
-          v.x = hb[0] | ((uint32_t)hb[1] << 16);
-          v.y = hb[2] | ((uint32_t)hb[3] << 16);
-          *reinterpret_cast<uint2*>(g.outHt + (size_t)j * g.ldt + i0) = v;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int i = row0 + rt * 16 + (lane >> 4) * 4 + e, j = col0 + ct * 16 + r16;
+        out[(size_t)i * N + j] = acc[rt][ct][e];
       }
-    }
-    if constexpr (EPI == EPI_FWD_HID) return;
-    constexpr int NS = (EPI == EPI_BWD_FIRST) ? 3 : 1;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) column_sums(cs[s], red[s], lane, wr, wc);
-    if constexpr (EPI == EPI_FWD_LOSS) {
-      for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o);
-      if (lane == 0) lred[w] = lsum;
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t < 64) {
-      const int j = blockIdx.x * 64 + t;
-      const size_t rb = blockIdx.y;
-      g.bpart[rb * N + j] = red[0][t] + red[0][64 + t];
-      if constexpr (EPI == EPI_BWD_FIRST) {
-        g.w1part[(rb * N + j) * 2] = red[1][t] + red[1][64 + t];
-        g.w1part[(rb * N + j) * 2 + 1] = red[2][t] + red[2][64 + t];
-      }
-    }
-    if constexpr (EPI == EPI_FWD_LOSS) {
-      if (t == 0) g.lpart[blockIdx.y] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -348,7 +429,7 @@ struct TrainCtl {
 struct FinishArgs {
   const float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
   const double* lpart;
-  int S, R;            // splits of the weight products, 64-row blocks
+  int S, R;            // splits of the weight products, RB-row blocks
   double inv_count;    // 1 / (nvalid * 64)
   double* loss;        // one FP64
   float* G;            // gradient out [NPAR]
@@ -368,6 +449,21 @@ __global__ void ctl_advance(TrainCtl* c, int nsteps) {
   if (threadIdx.x == 0) c->t0 += (double)nsteps;
 }
 
+// sum_{r < n} base[r * stride] in order r = 0, 1, ...; the loads are issued
+// 16 at a time so that the chain waits for memory once per 16 terms
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ base, size_t stride, int n) {
+  float g = 0.0f;
+  for (int r0 = 0; r0 < n; r0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = (r0 + k < n) ? base[(size_t)(r0 + k) * stride] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (r0 + k < n) g += v[k];
+  }
+  return g;
+}
+
 template <bool UPDATE>
 __global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -377,24 +473,24 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
     f.loss[0] = s * f.inv_count;
   }
   if (p >= NPAR) return;
-  float g = 0.0f;
+  float g;
   if (p < OB1) {
     const int j = p >> 1, c = p & 1;
-    for (int r = 0; r < f.R; ++r) g += f.w1p[((size_t)r * WID + j) * 2 + c];
+    g = ordered_sum(f.w1p + (size_t)j * 2 + c, (size_t)WID * 2, f.R);
   } else if (p < OW2) {
-    for (int r = 0; r < f.R; ++r) g += f.bp1[(size_t)r * WID + (p - OB1)];
+    g = ordered_sum(f.bp1 + (p - OB1), WID, f.R);
   } else if (p < OB2) {
-    for (int s = 0; s < f.S; ++s) g += f.part2[(size_t)s * WID * WID + (p - OW2)];
+    g = ordered_sum(f.part2 + (p - OW2), (size_t)WID * WID, f.S);
   } else if (p < OW3) {
-    for (int r = 0; r < f.R; ++r) g += f.bp2[(size_t)r * WID + (p - OB2)];
+    g = ordered_sum(f.bp2 + (p - OB2), WID, f.R);
   } else if (p < OB3) {
-    for (int s = 0; s < f.S; ++s) g += f.part3[(size_t)s * WID * WID + (p - OW3)];
+    g = ordered_sum(f.part3 + (p - OW3), (size_t)WID * WID, f.S);
   } else if (p < OW4) {
-    for (int r = 0; r < f.R; ++r) g += f.bp3[(size_t)r * WID + (p - OB3)];
+    g = ordered_sum(f.bp3 + (p - OB3), WID, f.R);
   } else if (p < OB4) {
-    for (int s = 0; s < f.S; ++s) g += f.part4[(size_t)s * NOUT * WID + (p - OW4)];
+    g = ordered_sum(f.part4 + (p - OW4), (size_t)NOUT * WID, f.S);
   } else {
-    for (int r = 0; r < f.R; ++r) g += f.bp4[(size_t)r * NOUT + (p - OB4)];
+    g = ordered_sum(f.bp4 + (p - OB4), NOUT, f.R);
   }
   f.G[p] = g;
   if constexpr (UPDATE) {
@@ -544,10 +640,10 @@ struct surrogate_t {
   surrogate_params p;
   hipStream_t stream;
   int B;  // max_batch
-  float *P, *Mo, *Ve, *G, *xn, *A1, *A2, *A3;
+  float *P, *Mo, *Ve, *G, *A1, *A2, *A3;
   Norm* nm;
   WCopies wc;
-  bf16_t *H1, *H2, *H3, *H1t, *H2t, *H3t, *DYb, *DYt, *D3b, *D3t, *D2b, *D2t;
+  bf16_t *H1t, *H2t, *H3t, *DYt, *D3t, *D2t;
   float *part2, *part3, *part4, *bp1, *bp2, *bp3, *bp4, *w1p;
   double *lpart, *losses, *stats;
   TrainCtl* ctl;
@@ -571,7 +667,7 @@ size_t carve(int B, char* base, surrogate_t* s) {
     off += bytes;
     return q;
   };
-  const int S = (B + KSPLIT - 1) / KSPLIT, R = B / 64;
+  const int S = (B + KSPLIT - 1) / KSPLIT, R = B / RB;
   surrogate_t d{};
   surrogate_t& h = s ? *s : d;
   h.P = (float*)take(4ull * NPAR);
@@ -586,13 +682,11 @@ size_t carve(int B, char* base, surrogate_t* s) {
   h.wc.W3t = (bf16_t*)take(2ull * WID * WID);
   h.wc.W4b = (bf16_t*)take(2ull * NOUT * WID);
   h.wc.W4t = (bf16_t*)take(2ull * NOUT * WID);
-  h.xn = (float*)take(4ull * B * NIN);
   h.A1 = (float*)take(4ull * B * WID);
   h.A2 = (float*)take(4ull * B * WID);
   h.A3 = (float*)take(4ull * B * WID);
-  bf16_t** act[] = {&h.H1, &h.H2, &h.H3, &h.H1t, &h.H2t, &h.H3t, &h.D3b, &h.D3t, &h.D2b, &h.D2t};
+  bf16_t** act[] = {&h.H1t, &h.H2t, &h.H3t, &h.D3t, &h.D2t};
   for (bf16_t** a : act) *a = (bf16_t*)take(2ull * B * WID);
-  h.DYb = (bf16_t*)take(2ull * B * NOUT);
   h.DYt = (bf16_t*)take(2ull * B * NOUT);
   h.part2 = (float*)take(4ull * S * WID * WID);
   h.part3 = (float*)take(4ull * S * WID * WID);
@@ -632,18 +726,6 @@ int validate(const surrogate_params* p) {
   return LAT_OK;
 }
 
-template <int EPI>
-int launch_gemm(const GemmArgs& g, hipStream_t st) {
-  if (g.M % 64 || g.N % 64 || g.K % 64 || g.ksplit % 64 || g.K <= 0 || g.ksplit <= 0 || g.ksplit > 256) {
-    set_error("internal: product shape not tileable");
-    return LAT_EINVAL;
-  }
-  const int splits = (g.K + g.ksplit - 1) / g.ksplit;
-  hipLaunchKernelGGL(gemm_nt<EPI>, dim3(g.N / 64, g.M / 64, splits), dim3(256), 0, st, g);
-  CL_HIP(hipGetLastError());
-  return LAT_OK;
-}
-
 void drop_graph(surrogate_t* h) {
   if (h->graph) hipGraphExecDestroy(h->graph);
   h->graph = nullptr;
@@ -656,72 +738,34 @@ void drop_graph(surrogate_t* h) {
 int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* rows, int n, float* G,
                double* loss_dev, bool update, int step) {
   hipStream_t st = h->stream;
-  const int Bp = (n + 63) / 64 * 64, R = Bp / 64, S = (Bp + KSPLIT - 1) / KSPLIT, ldt = h->B;
+  const int Bp = (n + 63) / 64 * 64, R = Bp / RB, S = (Bp + KSPLIT - 1) / KSPLIT, ldt = h->B;
   const WCopies& c = h->wc;
-  hipLaunchKernelGGL(l1_forward, dim3(Bp / L1_ROWS, WID / 64), dim3(256), 0, st, X, rows, n, h->nm, c.W1b,
-                     h->P + OB1, h->xn, h->A1, h->H1, h->H1t, ldt);
+  // rows: forward, loss, backward to the input layer
+  RowArgs ra{};
+  ra.X = X; ra.T = T; ra.rows = rows; ra.nvalid = n;
+  ra.dscale = (float)(2.0 / ((double)n * NOUT));
+  ra.nm = h->nm;
+  ra.W1b = c.W1b; ra.W2b = c.W2b; ra.W3b = c.W3b; ra.W4b = c.W4b;
+  ra.W2t = c.W2t; ra.W3t = c.W3t; ra.W4t = c.W4t;
+  ra.b1 = h->P + OB1; ra.b2 = h->P + OB2; ra.b3 = h->P + OB3; ra.b4 = h->P + OB4;
+  ra.A1 = h->A1; ra.A2 = h->A2; ra.A3 = h->A3;
+  ra.H1t = h->H1t; ra.H2t = h->H2t; ra.H3t = h->H3t;
+  ra.DYt = h->DYt; ra.D3t = h->D3t; ra.D2t = h->D2t;
+  ra.ldt = ldt;
+  ra.bp1 = h->bp1; ra.bp2 = h->bp2; ra.bp3 = h->bp3; ra.bp4 = h->bp4;
+  ra.w1p = h->w1p; ra.lpart = h->lpart;
+  hipLaunchKernelGGL(step_rows_kernel, dim3(R), dim3(256), 0, st, ra);
   CL_HIP(hipGetLastError());
-  int rc;
-  GemmArgs g{};
-  g.ldt = ldt;
-  g.nvalid = n;
-  g.nm = h->nm;
-  // forward, hidden layers 2 and 3
-  const bf16_t* hin[2] = {h->H1, h->H2};
-  const bf16_t* wf[2] = {c.W2b, c.W3b};
-  const float* bias[2] = {h->P + OB2, h->P + OB3};
-  float* aout[2] = {h->A2, h->A3};
-  bf16_t* hout[2] = {h->H2, h->H3};
-  bf16_t* htout[2] = {h->H2t, h->H3t};
-  for (int l = 0; l < 2; ++l) {
-    GemmArgs f = g;
-    f.A = hin[l]; f.lda = WID; f.Bt = wf[l]; f.ldb = WID;
-    f.M = Bp; f.N = WID; f.K = WID; f.ksplit = WID;
-    f.bias = bias[l]; f.outA = aout[l]; f.outH = hout[l]; f.outHt = htout[l];
-    if ((rc = launch_gemm<EPI_FWD_HID>(f, st))) return rc;
-  }
-  {  // output layer and loss
-    GemmArgs f = g;
-    f.A = h->H3; f.lda = WID; f.Bt = c.W4b; f.ldb = WID;
-    f.M = Bp; f.N = NOUT; f.K = WID; f.ksplit = WID;
-    f.bias = h->P + OB4; f.outH = h->DYb; f.outHt = h->DYt;
-    f.T = T; f.rows = rows; f.bpart = h->bp4; f.lpart = h->lpart;
-    f.dscale = (float)(2.0 / ((double)n * NOUT));
-    if ((rc = launch_gemm<EPI_FWD_LOSS>(f, st))) return rc;
-  }
-  // backward: layer 4 -> 3 -> 2 -> 1
-  struct Lay {
-    const bf16_t* dAt; int nout;        // gradient of the layer's pre-activation, transposed [nout][ldt]
-    const bf16_t* dA;                   // row-major [Bp][nout]
-    const bf16_t* Hint;                 // transposed input activations [WID][ldt]
-    const bf16_t* Wt;                   // W^T [WID][nout]
-    float* wpart;
-    const float* prevA;                 // pre-activation of the layer below
-    bf16_t *outb, *outt;                // gradient of the layer below
-    float* bpart;
-  };
-  const Lay lays[3] = {
-      {h->DYt, NOUT, h->DYb, h->H3t, c.W4t, h->part4, h->A3, h->D3b, h->D3t, h->bp3},
-      {h->D3t, WID, h->D3b, h->H2t, c.W3t, h->part3, h->A2, h->D2b, h->D2t, h->bp2},
-      {h->D2t, WID, h->D2b, h->H1t, c.W2t, h->part2, h->A1, nullptr, nullptr, h->bp1},
-  };
-  for (int l = 0; l < 3; ++l) {
-    const Lay& L = lays[l];
-    GemmArgs wg = g;
-    wg.A = L.dAt; wg.lda = ldt; wg.Bt = L.Hint; wg.ldb = ldt;
-    wg.M = L.nout; wg.N = WID; wg.K = Bp; wg.ksplit = KSPLIT; wg.wpart = L.wpart;
-    if ((rc = launch_gemm<EPI_WGRAD>(wg, st))) return rc;
-    GemmArgs bg = g;
-    bg.A = L.dA; bg.lda = L.nout; bg.Bt = L.Wt; bg.ldb = L.nout;
-    bg.M = Bp; bg.N = WID; bg.K = L.nout; bg.ksplit = L.nout;
-    bg.prevA = L.prevA; bg.outH = L.outb; bg.outHt = L.outt; bg.bpart = L.bpart;
-    if (l < 2) {
-      if ((rc = launch_gemm<EPI_BWD_HID>(bg, st))) return rc;
-    } else {
-      bg.xn = h->xn; bg.w1part = h->w1p;
-      if ((rc = launch_gemm<EPI_BWD_FIRST>(bg, st))) return rc;
-    }
-  }
+  // weight gradients of layers 4, 3, 2
+  WgradArgs wa{};
+  wa.p[0] = WgradProduct{h->DYt, h->H3t, h->part4, NOUT};
+  wa.p[1] = WgradProduct{h->D3t, h->H2t, h->part3, WID};
+  wa.p[2] = WgradProduct{h->D2t, h->H1t, h->part2, WID};
+  wa.ld = ldt; wa.K = Bp; wa.S = S;
+  wa.first[0] = 0;
+  for (int q = 0; q < 3; ++q) wa.first[q + 1] = wa.first[q] + (WID / 64) * (wa.p[q].M / 64) * S;
+  hipLaunchKernelGGL(wgrad_kernel, dim3(wa.first[3]), dim3(256), 0, st, wa);
+  CL_HIP(hipGetLastError());
   FinishArgs f{};
   f.part2 = h->part2; f.part3 = h->part3; f.part4 = h->part4;
   f.bp1 = h->bp1; f.bp2 = h->bp2; f.bp3 = h->bp3; f.bp4 = h->bp4; f.w1p = h->w1p;
