@@ -80,9 +80,10 @@ struct Norm {
 // training step, part 1: everything that is local to a batch row.  One block
 // takes RB = 16 rows through the forward pass, the loss and the backward pass
 // down to the input layer; the 16 x 256 activations and gradients stay in
-// LDS between layers.  Wave w owns hidden units 64w .. 64w+63 (output units
-// 16w .. 16w+15), so the thread that writes a pre-activation a_l[i][j] is the
-// one that reads it back for GELU'(a_l) on the way down.  It writes what the
+// LDS between layers.  Sixteen waves; wave w owns hidden units 16w .. 16w+15
+// (waves 0-3 also output units 16w .. 16w+15), so the thread that writes a
+// pre-activation a_l[i][j] is the one that reads it back for GELU'(a_l) on
+// the way down.  It writes what the
 // weight-gradient products need (h_l^T, da_l^T, BF16) and per-block partial
 // sums of the bias gradients, of the first layer's weight gradient and of the
 // loss.
@@ -116,22 +117,23 @@ __device__ __forceinline__ float col_sum16(float v) {
   return v;
 }
 
-// one 16 x 64 slab of C = A Bt^T: A is the block's 16 rows in LDS (pitch lda),
-// Bt rows col0 .. col0+63 in global memory (pitch ldb), K = 32 * NK.  All
-// weight fragments are requested before the first product, so the wave waits
-// for memory once per layer instead of once per 32-deep step.
+// one 16 x (16 CT) slab of C = A Bt^T: A is the block's 16 rows in LDS (pitch
+// lda), Bt rows col0 .. col0 + 16 CT - 1 in global memory (pitch ldb),
+// K = 32 NK.  All weight fragments are requested before the first product, so
+// the wave waits for memory once per layer instead of once per 32-deep step.
+constexpr int CT = 1;  // 16-column tiles per wave
 template <int NK>
-__device__ __forceinline__ void slab16x64(const bf16_t* As, int lda, const bf16_t* __restrict__ Bt, int ldb,
-                                          int col0, int lane, f4 (&acc)[4]) {
+__device__ __forceinline__ void slab16(const bf16_t* As, int lda, const bf16_t* __restrict__ Bt, int ldb,
+                                       int col0, int lane, f4 (&acc)[CT]) {
   const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   const bf16_t* pb = Bt + (size_t)(col0 + r16) * ldb + kq;
-  bf16x8 b[NK][4];
+  bf16x8 b[NK][CT];
 #pragma unroll
   for (int s = 0; s < NK; ++s)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) b[s][ct] = load8(pb + (size_t)ct * 16 * ldb + 32 * s);
+    for (int ct = 0; ct < CT; ++ct) b[s][ct] = load8(pb + (size_t)ct * 16 * ldb + 32 * s);
   bf16x8 a[NK];
 #pragma unroll
   for (int s = 0; s < NK; ++s) a[s] = load8(As + r16 * lda + 32 * s + kq);
@@ -140,7 +142,7 @@ __device__ __forceinline__ void slab16x64(const bf16_t* As, int lda, const bf16_
 #pragma unroll
   for (int s = 0; s < NK; ++s)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[ct] = mma(a[s], b[s][ct], acc[ct]);
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = mma(a[s], b[s][ct], acc[ct]);
 }
 
 __device__ __forceinline__ void store_t4(bf16_t* Ht, int j, int ldt, int i0, const bf16_t (&hb)[4]) {
@@ -150,7 +152,10 @@ __device__ __forceinline__ void store_t4(bf16_t* Ht, int j, int ldt, int i0, con
   *reinterpret_cast<uint2*>(Ht + (size_t)j * ldt + i0) = v;
 }
 
-__global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
+constexpr int NWAVE = WID / (16 * CT);       // 16
+constexpr int L1R = RB * WID / (64 * NWAVE);  // layer-1 rows per thread (4)
+
+__global__ __launch_bounds__(64 * NWAVE) void step_rows_kernel(RowArgs g) {
   __shared__ __align__(16) bf16_t HA[RB * LDH];
   __shared__ __align__(16) bf16_t HB[RB * LDH];
   __shared__ __align__(16) bf16_t DY[RB * LDY];
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
   const int rb = blockIdx.x, r0 = rb * RB;
   const int ldt = g.ldt;
 
-  // layer 1 (K = 2, plain FMA): thread t is unit t for the 16 rows
+  // layer 1 (K = 2, plain FMA): thread t is unit t % 256 for L1R rows
   if (t < RB) {
     const int i = r0 + t;
     float x0 = 0.0f, x1 = 0.0f;
@@ -175,21 +180,21 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
   }
   __syncthreads();
   {
-    const int j = t;
+    const int j = t & (WID - 1), rh = (t / WID) * L1R;
     const float w0 = from_bf16(g.W1b[2 * j]), w1 = from_bf16(g.W1b[2 * j + 1]), bj = g.b1[j];
-    uint32_t packed[8];
+    uint32_t packed[L1R / 2];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
+    for (int q = 0; q < L1R; ++q) {
+      const int r = rh + q;
       const float a = xs[r][0] * w0 + xs[r][1] * w1 + bj;
       const bf16_t hv = to_bf16(gelu(a));
       g.A1[(size_t)(r0 + r) * WID + j] = a;
       HA[r * LDH + j] = hv;
-      if (r & 1) packed[r >> 1] |= (uint32_t)hv << 16;
-      else packed[r >> 1] = hv;
+      if (q & 1) packed[q >> 1] |= (uint32_t)hv << 16;
+      else packed[q >> 1] = hv;
     }
-    uint4* dst = reinterpret_cast<uint4*>(g.H1t + (size_t)j * ldt + r0);
-    dst[0] = uint4{packed[0], packed[1], packed[2], packed[3]};
-    dst[1] = uint4{packed[4], packed[5], packed[6], packed[7]};
+    static_assert(L1R == 4, "layer-1 rows per thread");
+    *reinterpret_cast<uint2*>(g.H1t + (size_t)j * ldt + r0 + rh) = uint2{packed[0], packed[1]};
   }
   __syncthreads();
 
@@ -203,11 +208,11 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
     bf16_t* dstb[2] = {HB, HA};
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
-      f4 acc[4];
-      slab16x64<WID / 32>(src[l], LDH, Wl[l], WID, 64 * w, lane, acc);
+      f4 acc[CT];
+      slab16<WID / 32>(src[l], LDH, Wl[l], WID, 16 * CT * w, lane, acc);
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int j = 64 * w + 16 * ct + (lane & 15);
+      for (int ct = 0; ct < CT; ++ct) {
+        const int j = 16 * CT * w + 16 * ct + (lane & 15);
         const float bj = bl[l][j];
         bf16_t hb[4];
 #pragma unroll
@@ -225,8 +230,8 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
   }
 
   // output layer, loss and dL/dy = 2 (y - t) / (n NOUT) in normalised units;
-  // wave w owns outputs 16w .. 16w+15
-  {
+  // waves 0-3 own outputs 16w .. 16w+15
+  if (w < NOUT / 16) {
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const bf16_t* pb = g.W4b + (size_t)(16 * w + r16) * WID + kq;
@@ -261,6 +266,7 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
     for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o);
     if (lane == 0) lred[w] = lsum;
   }
+  static_assert(NOUT / 16 == 4, "loss partials of four waves");
   __syncthreads();
   if (t == 0) g.lpart[rb] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
 
@@ -275,12 +281,12 @@ __global__ __launch_bounds__(256) void step_rows_kernel(RowArgs g) {
     bf16_t* dstb[2] = {HB, HA};
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      f4 acc[4];
-      if (l == 0) slab16x64<NOUT / 32>(src[l], lds[l], Wt[l], NOUT, 64 * w, lane, acc);
-      else slab16x64<WID / 32>(src[l], lds[l], Wt[l], WID, 64 * w, lane, acc);
+      f4 acc[CT];
+      if (l == 0) slab16<NOUT / 32>(src[l], lds[l], Wt[l], NOUT, 16 * CT * w, lane, acc);
+      else slab16<WID / 32>(src[l], lds[l], Wt[l], WID, 16 * CT * w, lane, acc);
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int j = 64 * w + 16 * ct + (lane & 15);
+      for (int ct = 0; ct < CT; ++ct) {
+        const int j = 16 * CT * w + 16 * ct + (lane & 15);
         float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
         bf16_t hb[4];
 #pragma unroll
@@ -754,7 +760,7 @@ int train_step(surrogate_t* h, const float* X, const float* T, const int32_t* ro
   ra.ldt = ldt;
   ra.bp1 = h->bp1; ra.bp2 = h->bp2; ra.bp3 = h->bp3; ra.bp4 = h->bp4;
   ra.w1p = h->w1p; ra.lpart = h->lpart;
-  hipLaunchKernelGGL(step_rows_kernel, dim3(R), dim3(256), 0, st, ra);
+  hipLaunchKernelGGL(step_rows_kernel, dim3(R), dim3(64 * NWAVE), 0, st, ra);
   CL_HIP(hipGetLastError());
   // weight gradients of layers 4, 3, 2
   WgradArgs wa{};
