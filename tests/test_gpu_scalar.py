@@ -173,6 +173,31 @@ def test_full_size_256_vv2_sampled_sites():
         assert np.max(d) < 1e-5 * np.max(np.abs(ref[idx])), np.max(d)
 
 
+def test_wide_tiles_256_against_oracle():
+    """The z-wide tile shapes (128 and 256 threads along z, one z-tile per
+    plane at 256^3) over every x-chunk, against the oracle after 5 steps."""
+    cfg = synth.config2(q=100.0)
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    a, b = oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], "vv2", 5, omp=True)
+    o = oracle.sync_observe(m, phi, pi, a, b)
+    lat = _lattice(cfg)
+    rng = np.random.default_rng(2)
+    idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 256, size=(3, 4096)))
+    n = 0
+    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4)):
+        for xc in (8, 16, 32, 64):
+            lat.set_tiling(tz, by, ry, xc)
+            lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+            lat.step(5)
+            compare_obs(lat.energies(), o, 2, 1e-5, f"tile {tz},{by},{ry},{xc}")
+            s = lat.get_state()
+            assert np.max(np.abs(s["phi"][idx] - phi[idx])) < 1e-5 * np.max(np.abs(phi[idx])), (tz, by, ry, xc)
+            n += 1
+    assert n == 12
+
+
 def test_large_512_vv2_sampled_sites():
     cfg = synth.config2(q=100.0, N=512)
     st = oracle.vacuum_ic(cfg)
