@@ -61,9 +61,12 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-template <int NACC>
+// Per-block sums of NT threads' accumulators (waves in order) into the
+// block's record.
+template <int NT, int NACC>
 __device__ void u1_block_partials(double (&acc)[NACC], double* partials) {
-  __shared__ double red[4][NACC];
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW][NACC];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
@@ -71,7 +74,12 @@ __device__ void u1_block_partials(double (&acc)[NACC], double* partials) {
     if (lane == 0) red[wv][k] = s;
   }
   __syncthreads();
-  if (tid < NACC) partials[(size_t)blockIdx.x * NACC + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid < NACC) {
+    double s = red[0][tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += red[w][tid];
+    partials[(size_t)blockIdx.x * NACC + tid] = s;
+  }
 }
 
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -80,6 +88,10 @@ __device__ __forceinline__ float sin_t(float x) { return sinf(x); }
 __device__ __forceinline__ double sin_t(double x) { return sin(x); }
 __device__ __forceinline__ float atan_t(float x) { return atanf(x); }
 __device__ __forceinline__ double atan_t(double x) { return atan(x); }
+// a / b; FP32 through the hardware reciprocal (1 ulp), which is below the
+// rounding already in a and b
+__device__ __forceinline__ float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div_t(double a, double b) { return a / b; }
 
 template <typename T>
 __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
@@ -102,7 +114,7 @@ __global__ __launch_bounds__(256) void u1_gauss_kernel(U1Args<T> A) {
   const double rho = 2.0 * A.e / A.wf2 *
                      ((double)A.c[0][s] * (double)A.c[3][s] - (double)A.c[1][s] * (double)A.c[2][s]);
   double acc[4] = {(div - rho) * (div - rho), div * div, rho * rho, rho};
-  u1_block_partials<4>(acc, A.partials);
+  u1_block_partials<256>(acc, A.partials);
 }
 
 __global__ __launch_bounds__(1024) void u1_gauss_finish_kernel(const double* partials, int nblocks, DevState* st) {
@@ -161,8 +173,10 @@ __device__ bool u1_reduce_partials(const double* partials, int nb, double (&S)[k
 
 template <typename T>
 __device__ __forceinline__ T wrap_phase(T t) {
+  // any integer count of turns gives the same link, so the turn count may
+  // come from a product with 1/(2 pi)
   const T twopi = (T)6.283185307179586476925286766559;
-  return t - twopi * rint(t / twopi);
+  return t - twopi * rint(t * (T)0.15915494309189533576888376337251);
 }
 
 // NC: non-compact gauge field (Sec. 5.2).  The three link slots then hold A_i;
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   constexpr int NH = 2 * LZ + 2 * TY;  // ring of the (TY+2) x (TZ+2) plane tile
   static_assert(NH <= NT, "ring larger than block");
   static_assert(TZ + TY <= NT, "low ring larger than block");
-  static_assert(NT == 256, "partials assume four waves");
+  static_assert(NT == 256, "partials and LDS sized for four waves");
   __shared__ T Lp[2][2][LY][LZ];       // drifted phi (Re, Im), planes in flight
   __shared__ T Lt[2][3][LY][LZ];       // drifted link phases (own sites are stored)
   __shared__ C2<T> Lu[2][3][LY][LZ];   // drifted links U_i = e^{i theta_i} (cos, sin)
@@ -321,7 +335,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       sn[k] = P[k].y;
-      om[k] = P[k].x >= T(0) ? P[k].y * P[k].y / (T(1) + P[k].x) : T(1) - P[k].x;
+      om[k] = P[k].x >= T(0) ? div_t(P[k].y * P[k].y, T(1) + P[k].x) : T(1) - P[k].x;
     }
   };
 
@@ -367,22 +381,27 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   for (int i = 0; i < A.XC; ++i) {
     const int x = x0 + i;
     const int cb_ = i & 1, nb_ = cb_ ^ 1;
-    if (i + 1 < A.XC) load_plane((x + 2) % N);  // in flight during the compute below
+    // plane x+2 is in flight during the compute below; the last iteration
+    // re-reads plane x+1 (unused) so that the loads are unconditional and
+    // the compiler need not wait for them at the first barrier
+    load_plane(i + 1 < A.XC ? (x + 2) % N : (x + 1) % N);
     __syncthreads();
-    // plaquette sines of the own sites and the low ring of plane x
+    // plaquette sines of the own sites and the low ring of plane x; the
+    // handful of terms a thread adds per plane are summed in T, the running
+    // sums over planes are FP64
+    T mg = T(0);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int ly = 1 + r * BY + ty, lz = 1 + tz;
       T sn[3], om[3];
       plaq(cb_, nb_, ly, lz, sn, om);
-      double mg = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         Ls[k][ly][lz] = sn[k];
-        mg += (double)om[k];
+        mg += om[k];
       }
-      acc[7] += mg;
     }
+    acc[7] += (double)mg;
     if (has_low) {
       T sn[3], om[3];
       plaq(cb_, nb_, sly, slz, sn, om);
@@ -391,6 +410,9 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
     }
     __syncthreads();
     // kick of the own sites of plane x
+    T ts[kU1Acc];
+#pragma unroll
+    for (int k = 0; k < kU1Acc; ++k) ts[k] = T(0);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int ly = 1 + r * BY + ty, lz = 1 + tz;
@@ -405,7 +427,6 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       const C2<T> uf[3] = {Lu[cb_][0][ly][lz], Lu[cb_][1][ly][lz], Lu[cb_][2][ly][lz]};
       const C2<T> ub[3] = {um[r], Lu[cb_][1][ly - 1][lz], Lu[cb_][2][ly][lz - 1]};
       C2<T> lap{T(-6) * p.x, T(-6) * p.y};
-      double grad = 0.0;
       T Kcur[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
         lap.x += f.x + b.x;
         lap.y += f.y + b.y;
         const T gx = f.x - p.x, gy = f.y - p.y;
-        grad += (double)(gx * gx + gy * gy);
+        ts[2] += gx * gx + gy * gy;
         Kcur[k] = cj * (p.x * f.y - p.y * f.x);
       }
       const T r2 = p.x * p.x + p.y * p.y;
@@ -427,14 +448,13 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       const C2<T> pin{qc[0][r], qc[1][r]};
       const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
       const C2<T> pe{pin.x + cE * Kp.x, pin.y + cE * Kp.y};
-      acc[0] += (double)(pin.x * pin.x + pin.y * pin.y);
-      acc[1] += (double)(pe.x * pe.x + pe.y * pe.y);
-      acc[2] += grad;
-      acc[3] += (double)(lam * r2 * r2);
-      acc[4] += (double)(m2 * r2);
-      acc[8] += (double)p.x;
-      acc[9] += (double)p.y;
-      acc[10] += (double)r2;
+      ts[0] += pin.x * pin.x + pin.y * pin.y;
+      ts[1] += pe.x * pe.x + pe.y * pe.y;
+      ts[3] += lam * r2 * r2;
+      ts[4] += m2 * r2;
+      ts[8] += p.x;
+      ts[9] += p.y;
+      ts[10] += r2;
       if (wr) {
         __builtin_nontemporal_store(p.x, &A.dst[0][o]);
         __builtin_nontemporal_store(p.y, &A.dst[1][o]);
@@ -446,8 +466,8 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
         const T ain = qc[2 + k][r];
         const T KA = Kcur[k] + cb * curl[k];
         const T aout = ain + ck * KA, ae = ain + cE * KA;
-        acc[5] += (double)(ain * ain);
-        acc[6] += (double)(ae * ae);
+        ts[5] += ain * ain;
+        ts[6] += ae * ae;
         if (wr) {
           __builtin_nontemporal_store(th[k], &A.dst[4 + k][o]);
           __builtin_nontemporal_store(aout, &A.dst[7 + k][o]);
@@ -461,6 +481,9 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       s02m[r] = S02;
     }
 #pragma unroll
+    for (int k = 0; k < kU1Acc; ++k)
+      if (k != 7) acc[k] += (double)ts[k];
+#pragma unroll
     for (int r = 0; r < RY; ++r)
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
@@ -470,7 +493,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
     __syncthreads();
     if (i + 1 < A.XC) drift_into(cb_);  // plane x+2 replaces plane x
   }
-  u1_block_partials<kU1Acc>(acc, A.partials);
+  u1_block_partials<NT, kU1Acc>(acc, A.partials);
 }
 
 // Energies of Sec. 5.4.1 at a' from the lattice sums S of pass `pd`, which
@@ -698,7 +721,7 @@ static int u1_chain_finish(lattice* h, const PassChain& c) {
   return LAT_OK;
 }
 
-// Compiled tile shapes of the U(1) pass (256 threads each): TZ x (BY RY).
+// Compiled tile shapes of the U(1) pass (256 threads each): TZ x (BY RY) sites.
 static const int kU1Shapes32[][3] = {{64, 4, 2}, {32, 8, 1}};
 static const int kU1Shapes64[][3] = {{32, 8, 1}};
 
