@@ -30,7 +30,11 @@ __global__ __launch_bounds__(TZ* BY) void batch_pass_kernel(const ScalarArgs<T>*
   ScalarArgs<T> A = runs[tile_run[b]];
   A.pd = pd;
   A.partials = partials;
-  scalar_tile<T, NF, false, TZ, BY, RY>(A, tile_local[b], b, A.st->a, A.st->b);
+  const DevState* st = A.st;
+  scalar_tile<T, NF, false, TZ, BY, RY>(A, tile_local[b], b, [st](double& a, double& bb) {
+    a = st->a;
+    bb = st->b;
+  });
 }
 
 template <typename T, int NF>

@@ -211,9 +211,12 @@ __global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, in
 }
 
 // One tile (index `tile` in the order z-tile fastest, then y-tile, then
-// x-chunk) of one lattice; its sums go to partial record `pidx`.
-template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
-__device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, int pidx, double a_in, double b_in) {
+// x-chunk) of one lattice; its sums go to partial record `pidx`.  get_ab(a, b)
+// supplies the scale factor and its derivative at the start of the pass; it
+// is called once the first planes' loads are in flight (it may reduce the
+// previous pass's records and synchronise the block).
+template <typename T, int NF, bool FULL, int TZ, int BY, int RY, typename GetAB>
+__device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, int pidx, GetAB get_ab) {
   constexpr int TY = BY * RY;
   constexpr int NT = TZ * BY;
   constexpr int LZ = TZ + 2;
@@ -232,12 +235,6 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   const int z0 = zt * TZ, y0 = yt * TY, x0 = xcI * A.XC;
   const size_t NN = (size_t)N * N;
 
-  // homogeneous coefficients (FP64, identical in every block)
-  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
-  const double amid = 0.5 * (a_in + anew);
-  const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
-  const T clap = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const T cpot = (T)pow(anew, 3.0 + A.alpha);
   const T ckick = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
   const T cE = (T)((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
   const T m2_0 = (T)A.m2_0, m2_1 = (T)A.m2_1, lam = (T)A.lam, q = (T)A.q;
@@ -290,6 +287,24 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       }
     }
   };
+
+  // prologue: planes x0-1 (drifted), x0 (drifted, into LDS), x0+1 (raw, in flight)
+  const int xm = (x0 - 1 + N) % N;
+  load_own(xm, pm, qf);  // qf: momentum of plane x0-1, only needed for its drift
+
+  // homogeneous coefficients (FP64, identical in every block), while the
+  // loads above are in flight
+  double a_in, b_in;
+  get_ab(a_in, b_in);
+  load_own(x0, pc, qc);
+  load_halo(x0, hp1, hq1);
+  load_own((x0 + 1) % N, pn, qn);
+  if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
+  const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
+  const double amid = 0.5 * (a_in + anew);
+  const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
+  const T clap = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const T cpot = (T)pow(anew, 3.0 + A.alpha);
   // drifted plane into LDS: own columns from registers, halo drifted here
   auto store_lds = [&](const T (&p)[NF][RY], const T (&hp)[NF], const T (&hq)[NF]) {
 #pragma unroll
@@ -301,15 +316,7 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       for (int f = 0; f < NF; ++f) lds[f][hly][hlz] = hp[f] + cdrift * hq[f];
     }
   };
-
-  // prologue: planes x0-1 (drifted), x0 (drifted, into LDS), x0+1 (raw, in flight)
   {
-    const int xm = (x0 - 1 + N) % N;
-    load_own(xm, pm, qf);  // qf: momentum of plane x0-1, only needed for its drift
-    load_own(x0, pc, qc);
-    load_halo(x0, hp1, hq1);
-    load_own((x0 + 1) % N, pn, qn);
-    if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -407,29 +414,30 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
 }
 
 template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
-__global__ __launch_bounds__(TZ* BY) void scalar_pass_kernel(ScalarArgs<T> A) {
+__global__ __launch_bounds__(TZ* BY, RY <= 4 ? 4 : 1) void scalar_pass_kernel(ScalarArgs<T> A) {
   int bid = blockIdx.x;
   if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
-  double a_in, b_in;
-  if (A.prev.partials) {
-    // finish of the previous pass (stepping passes only, Acc<NF, false>)
-    constexpr int NP = Acc<NF, false>::N;
-    __shared__ double ab[2];
-    double S[NP];
-    if (reduce_partials<NP, TZ * BY>(A.prev.partials, 0, A.prev.nblocks, S)) {
-      double an, bn;
-      finish_state<T, NF, false>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
-      ab[0] = an;
-      ab[1] = bn;
+  auto get_ab = [&](double& a_in, double& b_in) {
+    if (A.prev.partials) {
+      // finish of the previous pass (stepping passes only, Acc<NF, false>)
+      constexpr int NP = Acc<NF, false>::N;
+      __shared__ double ab[2];
+      double S[NP];
+      if (reduce_partials<NP, TZ * BY>(A.prev.partials, 0, A.prev.nblocks, S)) {
+        double an, bn;
+        finish_state<T, NF, false>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
+        ab[0] = an;
+        ab[1] = bn;
+      }
+      __syncthreads();
+      a_in = ab[0];
+      b_in = ab[1];
+    } else {
+      a_in = A.st->a;
+      b_in = A.st->b;
     }
-    __syncthreads();
-    a_in = ab[0];
-    b_in = ab[1];
-  } else {
-    a_in = A.st->a;
-    b_in = A.st->b;
-  }
-  scalar_tile<T, NF, FULL, TZ, BY, RY>(A, bid, blockIdx.x, a_in, b_in);
+  };
+  scalar_tile<T, NF, FULL, TZ, BY, RY>(A, bid, blockIdx.x, get_ab);
 }
 
 
