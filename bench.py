@@ -196,10 +196,10 @@ def time_spectrum(N: int = 256, reps: int = 10) -> dict:
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    # algorithmic HBM bytes per spectrum: FP32 field read (4) and complex FP64
-    # written (16); three line passes of the FFT, each reading and writing the
-    # complex volume (3 x 32); the shell binning reads it once more (16)
-    per_site = 4 + 16 + 96 + 16
+    # algorithmic HBM bytes per spectrum of the three line passes: the z pass
+    # reads the FP32 field (4) and writes the complex FP64 volume (16), the y
+    # pass reads and writes it (32), the x pass reads it (16) and bins in LDS
+    per_site = 4 + 16 + 32 + 16
     return {"N": N, "ms_per_spectrum": ms, "spectra_per_s": 1e3 / ms, "bytes_per_site": per_site,
             "hbm_frac": N ** 3 * per_site / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 

@@ -16,8 +16,10 @@
 
 namespace cl {
 
+// complex number; 2 sizeof(R) alignment lets one 16-byte access move an FP64
+// value (LDS and HBM)
 template <typename R>
-struct Cx {
+struct alignas(2 * sizeof(R)) Cx {
   R x, y;
 };
 
@@ -57,15 +59,18 @@ __global__ void twiddle_kernel(Cx<double>* W, int N) {
   }
 }
 
-template <typename R>
+// Root W[q] (conjugated for sg < 0).  PAD: the table is the LDS copy, with
+// one entry of padding after every 16 (the lanes of a stage read roots at
+// strides that are multiples of 16 entries).
+template <typename R, bool PAD = false>
 __device__ __forceinline__ Cx<R> twiddle(const Cx<double>* __restrict__ W, int q, double sg) {
-  const Cx<double> w = W[q];
+  const Cx<double> w = W[PAD ? q + (q >> 4) : q];
   return Cx<R>{(R)w.x, (R)(sg * w.y)};
 }
 
 // Length-RAD DFT o[m] = sum_r v[r] e^{sgn 2 pi i r m / RAD}; radices 2 and 4
 // in closed form, others with roots from the table (index r m N/RAD mod N).
-template <typename R, int RAD>
+template <typename R, int RAD, bool PAD = false>
 __device__ __forceinline__ void small_dft(const Cx<R>* v, Cx<R>* o, const Cx<double>* __restrict__ W, int N,
                                           double sg) {
   if constexpr (RAD == 2) {
@@ -86,7 +91,7 @@ __device__ __forceinline__ void small_dft(const Cx<R>* v, Cx<R>* o, const Cx<dou
       double sx = (double)v[0].x, sy = (double)v[0].y;
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
-        const Cx<R> w = twiddle<R>(W, ((r * m) % RAD) * (N / RAD), sg);
+        const Cx<R> w = twiddle<R, PAD>(W, ((r * m) % RAD) * (N / RAD), sg);
         sx += (double)v[r].x * (double)w.x - (double)v[r].y * (double)w.y;
         sy += (double)v[r].x * (double)w.y + (double)v[r].y * (double)w.x;
       }
@@ -146,12 +151,39 @@ __device__ void fft_stage_any(const Cx<R>* in, Cx<R>* out, const Cx<double>* __r
   }
 }
 
+// Quotient and remainder by d; P2: d is a power of two (shift and mask
+// instead of an integer division).
+template <bool P2>
+__device__ __forceinline__ int idiv(int x, int d) {
+  if constexpr (P2) return x >> __builtin_ctz((unsigned)d);
+  else return x / d;
+}
+template <bool P2>
+__device__ __forceinline__ int imod(int x, int d) {
+  if constexpr (P2) return x & (d - 1);
+  else return x % d;
+}
+
+// LDS position of element x of line b in the single-buffer kernel: one
+// complex of padding after every 16 and lines lane_stride(N) apart.  A 16-byte
+// element per lane and 64 banks of 4 bytes make 16 slots per bank row; the
+// Stockham writes of the first stages go out at strides of 4 and 16
+// elements, which without the padding put 16 lanes on one slot.  The
+// gathers of the strided axes take 8 lines at once: with gather = true the
+// line stride is 4 slots (mod 16), which spreads them over the bank row (not
+// in the binning pass, whose histogram would then push a block past a
+// quarter of the CU's LDS).
+__host__ __device__ constexpr int lane_stride(int N, bool gather = false) {
+  return N + (N + 15) / 16 + (gather ? 4 : 0);
+}
+__device__ __forceinline__ int lpos(int b, int x, int LS) { return b * LS + x + (x >> 4); }
+
 // In-place variant of a stage for the single-buffer kernel: every thread
 // takes up to PMAX butterflies' inputs (twiddled) into registers, the block
 // synchronises, then the outputs overwrite the same LDS lines.  The launch
-// guarantees B N / RAD <= PMAX blockDim.x.
-template <typename R, int RAD, int PMAX>
-__device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* Wl, int N, int B, int Ns,
+// guarantees B N / RAD <= PMAX blockDim.x.  P2: N and B are powers of two.
+template <typename R, int RAD, int PMAX, bool P2 = false>
+__device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* Wl, int N, int B, int LS, int Ns,
                                                   double sg) {
   const int M = N / RAD;
   const int stride = N / (Ns * RAD);
@@ -161,11 +193,11 @@ __device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* 
   for (int p = 0; p < PMAX; ++p) {
     const int t = threadIdx.x + p * blockDim.x;
     if (t < nbf) {
-      const int b = t / M, j = t - b * M, k = j % Ns;
+      const int b = idiv<P2>(t, M), j = t - b * M, k = imod<P2>(j, Ns);
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
-        Cx<R> x = buf[b * N + j + r * M];
-        if (r > 0 && k > 0) x = cmul(x, twiddle<R>(Wl, k * r * stride, sg));
+        Cx<R> x = buf[lpos(b, j + r * M, LS)];
+        if (r > 0 && k > 0) x = cmul(x, twiddle<R, true>(Wl, k * r * stride, sg));
         v[p][r] = x;
       }
     }
@@ -175,12 +207,12 @@ __device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* 
   for (int p = 0; p < PMAX; ++p) {
     const int t = threadIdx.x + p * blockDim.x;
     if (t < nbf) {
-      const int b = t / M, j = t - b * M, k = j % Ns;
+      const int b = idiv<P2>(t, M), j = t - b * M, k = imod<P2>(j, Ns);
       Cx<R> o[RAD];
-      small_dft<R, RAD>(v[p], o, Wl, N, sg);
-      const int idxD = (j / Ns) * Ns * RAD + k;
+      small_dft<R, RAD, true>(v[p], o, Wl, N, sg);
+      const int idxD = idiv<P2>(j, Ns) * Ns * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[b * N + idxD + r * Ns] = o[r];
+      for (int r = 0; r < RAD; ++r) buf[lpos(b, idxD + r * Ns, LS)] = o[r];
     }
   }
   __syncthreads();
@@ -189,57 +221,127 @@ __device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* 
 // Butterflies per thread the in-place stages hold in registers, by radix.
 __host__ __device__ constexpr int inplace_pmax(int rad) { return rad == 2 ? 4 : rad == 3 ? 3 : 2; }
 
+// signed mode number of index i (Sec. 3.1: n~ in (-N/2, N/2])
+__device__ __forceinline__ int wrapk(int i, int N) { return i <= N / 2 ? i : i - N; }
+
+// shell floor(|n~|) of a mode with |n~|^2 = n2s (exact integer square root)
+__device__ __forceinline__ int shell_of(int64_t n2s) {
+  int b = (int)sqrt((double)n2s);
+  while ((int64_t)(b + 1) * (b + 1) <= n2s) ++b;
+  while ((int64_t)b * b > n2s) --b;
+  return b;
+}
+
+// Input and output of a line pass: the plain pass reads and writes the
+// complex array; the first (z) pass of a power spectrum reads the real field
+// in storage precision instead, and its last (x) pass adds |f(n~)|^2 to
+// per-block shell histograms instead of storing the transform.
+enum LineMode { kLinePlain = 0, kLineRealIn = 1, kLineBinOut = 2 };
+struct LineIO {
+  const void* rin;  // kLineRealIn: the real field
+  double* pS;       // kLineBinOut: nbins sums per block
+  int nbins;
+  int per_block;    // kLineBinOut: line batches per block
+};
+
 // Sizes whose factors are all 2, 3, 4 or 5: one LDS buffer of B lines plus
 // the N roots of unity, so that more blocks fit on a compute unit.
-template <typename R, bool POW2>
+template <typename R, bool POW2, int MODE = kLinePlain, typename TIN = float>
 __global__ __launch_bounds__(256) void fft_lines_inplace_kernel(Cx<R>* data, const Cx<double>* __restrict__ W,
                                                                  FFTPlan P, int axis, int B, double sgn,
-                                                                 double scale) {
+                                                                 double scale, LineIO io) {
   extern __shared__ unsigned char smem_raw[];
   const int N = P.N;
   Cx<double>* Wl = reinterpret_cast<Cx<double>*>(smem_raw);
-  Cx<R>* buf = reinterpret_cast<Cx<R>*>(Wl + N);
+  const int LS = lane_stride(N, axis != 2 && MODE != kLineBinOut);
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(Wl + lane_stride(N));  // the padded root table
+  double* hist = reinterpret_cast<double*>(buf + (size_t)B * LS);  // kLineBinOut
   const size_t NN = (size_t)N * N;
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int lb = blockIdx.x;
-  const int nzb = N / B;
-  auto addr = [&](int b, int i) -> size_t {
-    if (axis == 2) return ((size_t)lb * B + b) * N + i;
-    const int o = lb / nzb, z0 = (lb % nzb) * B;
-    if (axis == 1) return (size_t)o * NN + (size_t)i * N + z0 + b;
-    return (size_t)i * NN + (size_t)o * N + z0 + b;
-  };
-  for (int m = tid; m < N; m += NT) Wl[m] = W[m];
-  for (int e = tid; e < B * N; e += NT) {
-    int b, i;
-    if (axis == 2) { b = e / N; i = e % N; } else { i = e / B; b = e % B; }
-    buf[b * N + i] = data[addr(b, i)];
+  const int nzb = idiv<POW2>(N, B);
+  int lb0 = blockIdx.x, lb1 = blockIdx.x + 1;
+  if constexpr (MODE == kLineBinOut) {
+    lb0 = blockIdx.x * io.per_block;
+    lb1 = min((int)(NN / B), lb0 + io.per_block);
+    for (int h = tid; h < io.nbins; h += NT) hist[h] = 0.0;
   }
-  __syncthreads();
-  int Ns = 1;
-  const double sg = sgn < 0.0 ? -1.0 : 1.0;
-  for (int f = 0; f < P.nfac; ++f) {
-    const int Rr = P.fac[f];
-    if constexpr (POW2) {  // power-of-two sizes: only radices 4 and 2 (fewer registers)
-      if (Rr == 4) fft_stage_inplace<R, 4, inplace_pmax(4)>(buf, Wl, N, B, Ns, sg);
-      else fft_stage_inplace<R, 2, inplace_pmax(2)>(buf, Wl, N, B, Ns, sg);
+  for (int m = tid; m < N; m += NT) Wl[m + (m >> 4)] = W[m];
+  for (int lb = lb0; lb < lb1; ++lb) {
+    const int o = idiv<POW2>(lb, nzb), z0 = imod<POW2>(lb, nzb) * B;
+    auto addr = [&](int b, int i) -> size_t {
+      if (axis == 2) return ((size_t)lb * B + b) * N + i;
+      if (axis == 1) return (size_t)o * NN + (size_t)i * N + z0 + b;
+      return (size_t)i * NN + (size_t)o * N + z0 + b;
+    };
+    if (lb != lb0) __syncthreads();  // every thread is done with the previous batch
+    for (int e = tid; e < B * N; e += NT) {
+      int b, i;
+      if (axis == 2) { b = idiv<POW2>(e, N); i = imod<POW2>(e, N); } else { i = idiv<POW2>(e, B); b = imod<POW2>(e, B); }
+      if constexpr (MODE == kLineRealIn)
+        buf[lpos(b, i, LS)] = Cx<R>{(R) static_cast<const TIN*>(io.rin)[addr(b, i)], R(0)};
+      else
+        buf[lpos(b, i, LS)] = data[addr(b, i)];
+    }
+    __syncthreads();
+    int Ns = 1;
+    const double sg = sgn < 0.0 ? -1.0 : 1.0;
+    for (int f = 0; f < P.nfac; ++f) {
+      const int Rr = P.fac[f];
+      if constexpr (POW2) {  // power-of-two sizes: only radices 4 and 2 (fewer registers)
+        if (Rr == 4) fft_stage_inplace<R, 4, inplace_pmax(4), true>(buf, Wl, N, B, LS, Ns, sg);
+        else fft_stage_inplace<R, 2, inplace_pmax(2), true>(buf, Wl, N, B, LS, Ns, sg);
+      } else {
+        switch (Rr) {
+          case 2: fft_stage_inplace<R, 2, inplace_pmax(2)>(buf, Wl, N, B, LS, Ns, sg); break;
+          case 3: fft_stage_inplace<R, 3, inplace_pmax(3)>(buf, Wl, N, B, LS, Ns, sg); break;
+          case 4: fft_stage_inplace<R, 4, inplace_pmax(4)>(buf, Wl, N, B, LS, Ns, sg); break;
+          default: fft_stage_inplace<R, 5, inplace_pmax(5)>(buf, Wl, N, B, LS, Ns, sg); break;
+        }
+      }
+      Ns *= Rr;
+    }
+    if constexpr (MODE == kLineBinOut) {
+      // x pass, unscaled forward transform: mode (n1, n2, n3) = (x, line's y,
+      // line's z).  Each thread takes a run of consecutive x on one line,
+      // tracks the shell as n1 steps, and adds to the histogram once per
+      // shell it meets rather than once per mode.
+      const int tpl = NT / B, b = tid / tpl;
+      if (b < B) {
+        const int run = (N + tpl - 1) / tpl, i0 = (tid - b * tpl) * run, i1 = min(N, i0 + run);
+        const int n2 = wrapk(o, N), n3 = wrapk(z0 + b, N);
+        const int64_t r23 = (int64_t)n2 * n2 + (int64_t)n3 * n3;
+        int sh = -1;
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) {
+          const int n1 = wrapk(i, N);
+          const int64_t n2s = (int64_t)n1 * n1 + r23;
+          int s2 = sh < 0 ? shell_of(n2s) : sh;
+          while ((int64_t)(s2 + 1) * (s2 + 1) <= n2s) ++s2;
+          while ((int64_t)s2 * s2 > n2s) --s2;
+          if (s2 != sh) {
+            if (sh >= 0) atomicAdd(&hist[sh], acc);
+            sh = s2;
+            acc = 0.0;
+          }
+          const Cx<R> v = buf[lpos(b, i, LS)];
+          acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        if (sh >= 0) atomicAdd(&hist[sh], acc);
+      }
     } else {
-      switch (Rr) {
-        case 2: fft_stage_inplace<R, 2, inplace_pmax(2)>(buf, Wl, N, B, Ns, sg); break;
-        case 3: fft_stage_inplace<R, 3, inplace_pmax(3)>(buf, Wl, N, B, Ns, sg); break;
-        case 4: fft_stage_inplace<R, 4, inplace_pmax(4)>(buf, Wl, N, B, Ns, sg); break;
-        default: fft_stage_inplace<R, 5, inplace_pmax(5)>(buf, Wl, N, B, Ns, sg); break;
+      for (int e = tid; e < B * N; e += NT) {
+        int b, i;
+        if (axis == 2) { b = idiv<POW2>(e, N); i = imod<POW2>(e, N); } else { i = idiv<POW2>(e, B); b = imod<POW2>(e, B); }
+        Cx<R> v = buf[lpos(b, i, LS)];
+        v.x = (R)(v.x * scale);
+        v.y = (R)(v.y * scale);
+        data[addr(b, i)] = v;
       }
     }
-    Ns *= Rr;
   }
-  for (int e = tid; e < B * N; e += NT) {
-    int b, i;
-    if (axis == 2) { b = e / N; i = e % N; } else { i = e / B; b = e % B; }
-    Cx<R> v = buf[b * N + i];
-    v.x = (R)(v.x * scale);
-    v.y = (R)(v.y * scale);
-    data[addr(b, i)] = v;
+  if constexpr (MODE == kLineBinOut) {
+    __syncthreads();
+    for (int h = tid; h < io.nbins; h += NT) io.pS[(size_t)blockIdx.x * io.nbins + h] = hist[h];
   }
 }
 
@@ -336,16 +438,78 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
           set_error("FFT: in-place stage does not cover the batch");
           return LAT_EINVAL;
         }
-      const size_t shm = (size_t)N * sizeof(Cx<double>) + (size_t)B * N * sizeof(Cx<R>);
+      const size_t shm =
+          (size_t)lane_stride(N) * sizeof(Cx<double>) + (size_t)B * lane_stride(N, axis != 2) * sizeof(Cx<R>);
       if ((N & (N - 1)) == 0)
         hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
-                           sgn, sc);
+                           sgn, sc, LineIO{});
       else
         hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
-                           sgn, sc);
+                           sgn, sc, LineIO{});
     }
     CL_HIP(hipGetLastError());
   }
+  return LAT_OK;
+}
+
+// Forward transform of a real field for its power spectrum: the z pass reads
+// the field itself (no complex copy), the x pass bins |f(n~)|^2 into nblk
+// per-block histograms pS (nbins each) instead of storing the transform.
+// *nblk = 0 (nothing launched) where these passes do not apply: a radix
+// above 5, or the x pass's buffer, roots and histogram above 64 KiB of LDS.
+template <typename TIN>
+static int fft3d_bins(const TIN* f, Cx<double>* data, const Cx<double>* W, int N, int nbins, double* pS,
+                      int max_blocks, int* nblk, hipStream_t s) {
+  *nblk = 0;
+  const FFTPlan P = make_plan(N);
+  for (int k = 0; k < P.nfac; ++k)
+    if (P.fac[k] > 5) return LAT_OK;
+  int Bmax = 32;
+  while (Bmax > 1 && Bmax * N > 2048) Bmax >>= 1;
+  while (Bmax > 1 && N % Bmax) Bmax >>= 1;
+  // lines per batch and threads per block of each pass, as in fft3d
+  int Bs[3], nts[3];
+  for (int axis = 2; axis >= 0; --axis) {
+    const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
+    int B = Bmax;
+    while (B > minB && (size_t)N * N / B < 2048) B >>= 1;
+    Bs[axis] = B;
+    nts[axis] = std::min(256, std::max(64, (B * N / 4 + 63) / 64 * 64));
+    for (int k = 0; k < P.nfac; ++k)
+      if ((B * N / P.fac[k] + nts[axis] - 1) / nts[axis] > inplace_pmax(P.fac[k])) {
+        set_error("FFT: in-place stage does not cover the batch");
+        return LAT_EINVAL;
+      }
+  }
+  auto shm_of = [&](int axis) {
+    return (size_t)lane_stride(N) * sizeof(Cx<double>) +
+           (size_t)Bs[axis] * lane_stride(N, axis == 1) * sizeof(Cx<double>) +
+           (axis == 0 ? (size_t)nbins * sizeof(double) : 0);
+  };
+  if (shm_of(0) > 65536) return LAT_OK;
+  const int nbatch0 = (int)((size_t)N * N / Bs[0]);
+  const int per = (nbatch0 + max_blocks - 1) / max_blocks;
+  const int nb_bin = (nbatch0 + per - 1) / per;
+  const LineIO io{f, pS, nbins, per};
+  const bool pow2 = (N & (N - 1)) == 0;
+#define CL_LINES(MODE, ...)                                                                                     \
+  do {                                                                                                          \
+    if (pow2)                                                                                                   \
+      hipLaunchKernelGGL((fft_lines_inplace_kernel<double, true, MODE, ##__VA_ARGS__>), dim3(grid), dim3(nts[axis]), \
+                         shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);                            \
+    else                                                                                                        \
+      hipLaunchKernelGGL((fft_lines_inplace_kernel<double, false, MODE, ##__VA_ARGS__>), dim3(grid),             \
+                         dim3(nts[axis]), shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);           \
+  } while (0)
+  for (int axis = 2; axis >= 0; --axis) {
+    const int grid = axis == 0 ? nb_bin : (int)((size_t)N * N / Bs[axis]);
+    if (axis == 2) CL_LINES(kLineRealIn, TIN);
+    else if (axis == 1) CL_LINES(kLinePlain);
+    else CL_LINES(kLineBinOut);
+    CL_HIP(hipGetLastError());
+  }
+#undef CL_LINES
+  *nblk = nb_bin;
   return LAT_OK;
 }
 
@@ -358,11 +522,10 @@ __global__ void real_to_complex_kernel(const T* f, Cx<R>* c, int64_t V) {
   if (i < V) c[i] = Cx<R>{(R)f[i], (R)0};
 }
 
-__device__ __forceinline__ int wrapk(int i, int N) { return i <= N / 2 ? i : i - N; }
-
-// Per-block shell histograms of |f(n~)|^2 and, with GEOM, of the shell
-// geometry (sum of |n~| and mode counts), which does not depend on the field.
-template <typename R, bool GEOM>
+// Per-block shell histograms of |f(n~)|^2 (FIELD) and, with GEOM, of the
+// shell geometry (sum of |n~| and mode counts), which does not depend on the
+// field.
+template <typename R, bool GEOM, bool FIELD = true>
 __global__ __launch_bounds__(256) void bin_kernel(const Cx<R>* F, int N, int nbins, int64_t per_block,
                                                   double* pS, double* pK, unsigned long long* pC) {
   extern __shared__ unsigned char smem_raw[];
@@ -381,12 +544,11 @@ __global__ __launch_bounds__(256) void bin_kernel(const Cx<R>* F, int N, int nbi
     const int i3 = (int)(i % N), i2 = (int)((i / N) % N), i1x = (int)(i / ((int64_t)N * N));
     const int n1 = wrapk(i1x, N), n2 = wrapk(i2, N), n3 = wrapk(i3, N);
     const int64_t n2s = (int64_t)n1 * n1 + (int64_t)n2 * n2 + (int64_t)n3 * n3;
-    int b = (int)sqrt((double)n2s);
-    while ((int64_t)(b + 1) * (b + 1) <= n2s) ++b;
-    while ((int64_t)b * b > n2s) --b;
-    const Cx<R> v = F[i];
-    const double p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-    atomicAdd(&hS[b], p);
+    const int b = shell_of(n2s);
+    if (FIELD) {
+      const Cx<R> v = F[i];
+      atomicAdd(&hS[b], (double)v.x * (double)v.x + (double)v.y * (double)v.y);
+    }
     if (GEOM) {
       atomicAdd(&hK[b], sqrt((double)n2s));
       atomicAdd(&hC[b], 1ull);
@@ -655,15 +817,6 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
   const int blocks = (int)((V + threads - 1) / threads);
   Cx<double>* F = reinterpret_cast<Cx<double>*>(h->fft);
   const void* src = h->buf[h->cur][comp];
-  if (h->p.precision == LAT_FP32)
-    hipLaunchKernelGGL((real_to_complex_kernel<float, double>), dim3(blocks), dim3(threads), 0, h->stream,
-                       (const float*)src, F, V);
-  else
-    hipLaunchKernelGGL((real_to_complex_kernel<double, double>), dim3(blocks), dim3(threads), 0, h->stream,
-                       (const double*)src, F, V);
-  CL_HIP(hipGetLastError());
-  int rc = run_fft3d(h, +1, 1.0);
-  if (rc) return rc;
   const int nblk = kSpecBlocks;
   const int64_t per = (V + nblk - 1) / nblk;
   double* pS = (double*)h->spec;
@@ -675,23 +828,52 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
   unsigned long long* C = (unsigned long long*)(D + nb);
   const size_t shm = (size_t)nb * 24;
   const double norm = std::pow(h->dx / N, 3.0) / (2.0 * M_PI * M_PI);
-  // the shell geometry (K, C) is binned on the first spectrum only; later
-  // calls find it in place (nothing else writes this region)
+  // Sizes with radices up to 5: the transform reads the field and bins its
+  // last pass itself; the shell geometry (K, C) is binned once, from the mode
+  // indices alone, and found in place by later calls (nothing else writes it).
+  Cx<double>* W = reinterpret_cast<Cx<double>*>(h->twiddle);
+  if (!h->twiddle_ready) {
+    hipLaunchKernelGGL(twiddle_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream, W, N);
+    CL_HIP(hipGetLastError());
+    h->twiddle_ready = true;
+  }
+  int fused_blk = 0;
   if (!h->spec_geom_ready) {
-    hipLaunchKernelGGL((bin_kernel<double, true>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK, pC);
+    // geometry only (no field reads); S is overwritten below
+    hipLaunchKernelGGL((bin_kernel<double, true, false>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS,
+                       pK, pC);
     CL_HIP(hipGetLastError());
     hipLaunchKernelGGL(bin_sum_kernel<true>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, nblk, nb, h->p.kIR,
                        norm, S, K, D, C);
     CL_HIP(hipGetLastError());
     h->spec_geom_ready = true;
-  } else {
-    hipLaunchKernelGGL((bin_kernel<double, false>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK,
-                       pC);
-    CL_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bin_sum_kernel<false>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, nblk, nb, h->p.kIR,
-                       norm, S, K, D, C);
-    CL_HIP(hipGetLastError());
   }
+  int rc = h->p.precision == LAT_FP32
+               ? fft3d_bins((const float*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream)
+               : fft3d_bins((const double*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream);
+  if (rc) return rc;
+  if (fused_blk > 0) {
+    hipLaunchKernelGGL(bin_sum_kernel<false>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, fused_blk, nb,
+                       h->p.kIR, norm, S, K, D, C);
+    CL_HIP(hipGetLastError());
+    *out = Bins{S, K, D, C, nb};
+    return LAT_OK;
+  }
+  // other sizes: complex copy, the general transform, then the binning kernel
+  if (h->p.precision == LAT_FP32)
+    hipLaunchKernelGGL((real_to_complex_kernel<float, double>), dim3(blocks), dim3(threads), 0, h->stream,
+                       (const float*)src, F, V);
+  else
+    hipLaunchKernelGGL((real_to_complex_kernel<double, double>), dim3(blocks), dim3(threads), 0, h->stream,
+                       (const double*)src, F, V);
+  CL_HIP(hipGetLastError());
+  rc = run_fft3d(h, +1, 1.0);
+  if (rc) return rc;
+  hipLaunchKernelGGL((bin_kernel<double, false>), dim3(nblk), dim3(256), shm, h->stream, F, N, nb, per, pS, pK, pC);
+  CL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(bin_sum_kernel<false>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, nblk, nb, h->p.kIR,
+                     norm, S, K, D, C);
+  CL_HIP(hipGetLastError());
   *out = Bins{S, K, D, C, nb};
   return LAT_OK;
 }
