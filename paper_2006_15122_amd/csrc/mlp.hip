@@ -59,9 +59,34 @@ __device__ __forceinline__ bf16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(bf16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+// erfc(z) for z >= 0 by the Chebyshev fit of Press et al., Numerical Recipes
+// (Sec. 6.2, erfcc): t exp(-z^2 + P(t)) with t = 1 / (1 + z/2), fractional
+// error below 1.2e-7 in exact arithmetic (about 1e-6 in FP32 for z < 9).
+__device__ __forceinline__ float erfc_pos(float z) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  return t * __expf(fmaf(t, p, fmaf(-z, z, -1.26551223f)));
+}
+// 1 + erf(z): 2 - erfc(z) for z >= 0 and erfc(-z) below, so that the left
+// tail keeps its relative precision (1 + erf(z) cancels there), which is what
+// the BF16 rounding of the activation sees.
+__device__ __forceinline__ float one_plus_erf(float z) {
+  const float ec = erfc_pos(fabsf(z));
+  return z >= 0.0f ? 2.0f - ec : ec;
+}
+// GELU(a) = a Phi(a) = a (1 + erf(a / sqrt 2)) / 2 and its derivative
+// Phi(a) + a exp(-a^2/2) / sqrt(2 pi)
+__device__ __forceinline__ float gelu(float a) { return 0.5f * a * one_plus_erf(a * 0.70710678118654752f); }
 __device__ __forceinline__ float gelu_grad(float a) {
-  return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * expf(-0.5f * a * a);
+  return 0.5f * one_plus_erf(a * 0.70710678118654752f) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
 }
 
 __device__ __forceinline__ bf16x8 load8(const bf16_t* p) {
