@@ -413,6 +413,9 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   block_partials<T, NF, FULL, NT>(A, acc, pidx);
 }
 
+// Up to four rows per thread the kernel is held to four waves per SIMD (128
+// VGPRs): the first plane's loads in flight across the chained finish would
+// otherwise push it past that and halve the blocks per CU.
 template <typename T, int NF, bool FULL, int TZ, int BY, int RY>
 __global__ __launch_bounds__(TZ* BY, RY <= 4 ? 4 : 1) void scalar_pass_kernel(ScalarArgs<T> A) {
   int bid = blockIdx.x;
