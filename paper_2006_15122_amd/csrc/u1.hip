@@ -90,8 +90,8 @@ __device__ __forceinline__ float atan_t(float x) { return atanf(x); }
 __device__ __forceinline__ double atan_t(double x) { return atan(x); }
 // a / b; FP32 through the hardware reciprocal (1 ulp), which is below the
 // rounding already in a and b
-__device__ __forceinline__ float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double div_t(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double quot_t(double a, double b) { return a / b; }
 
 template <typename T>
 __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       sn[k] = P[k].y;
-      om[k] = P[k].x >= T(0) ? div_t(P[k].y * P[k].y, T(1) + P[k].x) : T(1) - P[k].x;
+      om[k] = P[k].x >= T(0) ? quot_t(P[k].y * P[k].y, T(1) + P[k].x) : T(1) - P[k].x;
     }
   };
 
