@@ -196,10 +196,11 @@ def time_spectrum(N: int = 256, reps: int = 10) -> dict:
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    # algorithmic HBM bytes per spectrum of the three line passes: the z pass
-    # reads the FP32 field (4) and writes the complex FP64 volume (16), the y
-    # pass reads and writes it (32), the x pass reads it (16) and bins in LDS
-    per_site = 4 + 16 + 32 + 16
+    # algorithmic HBM bytes per spectrum of the three line passes, which run
+    # in the field's FP32 precision: the z pass reads the field (4) and writes
+    # the complex volume (8), the y pass reads and writes it (16), the x pass
+    # reads it (8) and bins in LDS (FP64 sums)
+    per_site = 4 + 8 + 16 + 8
     return {"N": N, "ms_per_spectrum": ms, "spectra_per_s": 1e3 / ms, "bytes_per_site": per_site,
             "hbm_frac": N ** 3 * per_site / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 

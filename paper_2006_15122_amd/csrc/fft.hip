@@ -452,13 +452,14 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
   return LAT_OK;
 }
 
-// Forward transform of a real field for its power spectrum: the z pass reads
-// the field itself (no complex copy), the x pass bins |f(n~)|^2 into nblk
+// Forward transform of a real field for its power spectrum, in the field's
+// storage precision R (FP64 roots; FP64 histograms): the z pass reads the
+// field itself (no complex copy), the x pass bins |f(n~)|^2 into nblk
 // per-block histograms pS (nbins each) instead of storing the transform.
 // *nblk = 0 (nothing launched) where these passes do not apply: a radix
 // above 5, or the x pass's buffer, roots and histogram above 64 KiB of LDS.
-template <typename TIN>
-static int fft3d_bins(const TIN* f, Cx<double>* data, const Cx<double>* W, int N, int nbins, double* pS,
+template <typename R>
+static int fft3d_bins(const R* f, Cx<R>* data, const Cx<double>* W, int N, int nbins, double* pS,
                       int max_blocks, int* nblk, hipStream_t s) {
   *nblk = 0;
   const FFTPlan P = make_plan(N);
@@ -467,7 +468,8 @@ static int fft3d_bins(const TIN* f, Cx<double>* data, const Cx<double>* W, int N
   int Bmax = 32;
   while (Bmax > 1 && Bmax * N > 2048) Bmax >>= 1;
   while (Bmax > 1 && N % Bmax) Bmax >>= 1;
-  // lines per batch and threads per block of each pass, as in fft3d
+  // lines per batch and threads per block of each pass, as in fft3d (an FP32
+  // batch takes half the LDS of an FP64 one, so more blocks share a CU)
   int Bs[3], nts[3];
   for (int axis = 2; axis >= 0; --axis) {
     const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
@@ -483,7 +485,7 @@ static int fft3d_bins(const TIN* f, Cx<double>* data, const Cx<double>* W, int N
   }
   auto shm_of = [&](int axis) {
     return (size_t)lane_stride(N) * sizeof(Cx<double>) +
-           (size_t)Bs[axis] * lane_stride(N, axis == 1) * sizeof(Cx<double>) +
+           (size_t)Bs[axis] * lane_stride(N, axis == 1) * sizeof(Cx<R>) +
            (axis == 0 ? (size_t)nbins * sizeof(double) : 0);
   };
   if (shm_of(0) > 65536) return LAT_OK;
@@ -495,15 +497,15 @@ static int fft3d_bins(const TIN* f, Cx<double>* data, const Cx<double>* W, int N
 #define CL_LINES(MODE, ...)                                                                                     \
   do {                                                                                                          \
     if (pow2)                                                                                                   \
-      hipLaunchKernelGGL((fft_lines_inplace_kernel<double, true, MODE, ##__VA_ARGS__>), dim3(grid), dim3(nts[axis]), \
+      hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true, MODE, ##__VA_ARGS__>), dim3(grid), dim3(nts[axis]), \
                          shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);                            \
     else                                                                                                        \
-      hipLaunchKernelGGL((fft_lines_inplace_kernel<double, false, MODE, ##__VA_ARGS__>), dim3(grid),             \
+      hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false, MODE, ##__VA_ARGS__>), dim3(grid),                  \
                          dim3(nts[axis]), shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);           \
   } while (0)
   for (int axis = 2; axis >= 0; --axis) {
     const int grid = axis == 0 ? nb_bin : (int)((size_t)N * N / Bs[axis]);
-    if (axis == 2) CL_LINES(kLineRealIn, TIN);
+    if (axis == 2) CL_LINES(kLineRealIn, R);
     else if (axis == 1) CL_LINES(kLinePlain);
     else CL_LINES(kLineBinOut);
     CL_HIP(hipGetLastError());
@@ -849,7 +851,8 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
     h->spec_geom_ready = true;
   }
   int rc = h->p.precision == LAT_FP32
-               ? fft3d_bins((const float*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream)
+               ? fft3d_bins((const float*)src, reinterpret_cast<Cx<float>*>(h->fft), W, N, nb, pS, nblk, &fused_blk,
+                            h->stream)
                : fft3d_bins((const double*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream);
   if (rc) return rc;
   if (fused_blk > 0) {
