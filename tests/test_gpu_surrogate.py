@@ -71,10 +71,10 @@ def test_predict_matches_oracle_forward(n):
     yn, _ = mlp.forward(w, xn, bf16=True)
     ref = yn / _f32(osc) + _f32(osh)
     # Both sides round to BF16 from an FP32 value, but the GPU's FP32 sums and
-    # the oracle's FP64 ones differ in the last bits, so about 3 in 10^4
-    # activations round the other way; each such case moves an output by one
-    # BF16 step of one activation times a weight (~1e-4 in normalised units;
-    # an FP32 emulation of the kernels on the CPU peaks at 2.5e-4 over these
+    # the oracle's FP64 ones differ in the last bits, so a few activations in
+    # 10^4 round the other way; each such case moves an output by one BF16
+    # step of one activation times a weight (~1e-4 in normalised units; an
+    # FP32 emulation of the kernels on the CPU peaks at 2.5e-4 over these
     # rows).  Without the BF16 emulation the difference is 1e-3.
     d = (y - ref) * _f32(osc)
     assert np.max(np.abs(d)) < 6e-4, np.max(np.abs(d))
