@@ -819,7 +819,7 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
   const int blocks = (int)((V + threads - 1) / threads);
   Cx<double>* F = reinterpret_cast<Cx<double>*>(h->fft);
   const void* src = h->buf[h->cur][comp];
-  const int nblk = kSpecBlocks;
+  const int nblk = spec_blocks(N);
   const int64_t per = (V + nblk - 1) / nblk;
   double* pS = (double*)h->spec;
   double* pK = pS + (size_t)nblk * nb;

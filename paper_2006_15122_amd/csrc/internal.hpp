@@ -10,7 +10,11 @@
 
 namespace cl {
 
-constexpr int kSpecBlocks = 1024;  // blocks of the spectrum binning kernel
+// Per-block shell histograms of a spectrum: the binning kernel's blocks, or
+// the blocks of the transform's binning pass, at most spec_blocks(N); large
+// lattices take more so that each block bins fewer line batches.
+constexpr int kSpecBlocks = 1024;
+inline int spec_blocks(int N) { return N >= 256 ? 4 * kSpecBlocks : kSpecBlocks; }
 
 struct Tiling {
   int tz, by, ry, xc;

@@ -101,7 +101,7 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_part2,
   *off_part2 = o;
   o = align_up(o + (size_t)mb * 16 * sizeof(double), 256);
   *off_spec = o;
-  o = align_up(o + (size_t)(kSpecBlocks + 2) * spec_bins((int)N) * 24, 256);
+  o = align_up(o + (size_t)(spec_blocks((int)N) + 2) * spec_bins((int)N) * 24, 256);
   *off_buf0 = o;
   *comp_bytes = align_up((size_t)V * elem, 256);
   o += (size_t)nc * (*comp_bytes);
