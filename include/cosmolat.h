@@ -172,9 +172,13 @@ int lattice_energies(lattice_t* h, lattice_obs* out);
    k_IR |n~|, sum_sq[b] = sum |f(n~)|^2 with f(n~) = sum_n e^{+2 pi i n~.n/N}
    f(n), counts[b], and delta[b] = (k_IR b)^3/(2 pi^2) (dx/N)^3 sum_sq[b] /
    (4 pi b^2) for b >= 1 (0 for b = 0).  which: for scalar models 0..nf-1 =
-   field f, 16+f = momentum f.  Caller-owned host arrays of nbins_cap
-   entries; *nbins receives the number of shells.  Synchronises the stream.
-   Errors: LAT_EINVAL (which), LAT_ENOMEM (nbins_cap too small), LAT_EHIP. */
+   field f, 16+f = momentum f.  The transform runs in the storage precision
+   (FP32 lattices: FP32 butterflies, relative error about 1e-6 per mode) and
+   the shell sums in FP64; within a block they are added in no fixed order, so
+   results are reproducible to FP64 rounding.  Caller-owned host arrays of
+   nbins_cap entries; *nbins receives the number of shells.  Synchronises the
+   stream.  Errors: LAT_EINVAL (which), LAT_ENOMEM (nbins_cap too small),
+   LAT_EHIP. */
 int lattice_spectrum(lattice_t* h, int which, int nbins_cap, double* k, double* delta,
                      double* sum_sq, int64_t* counts, int* nbins);
 
