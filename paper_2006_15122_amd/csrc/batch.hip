@@ -26,7 +26,11 @@ namespace cl {
 template <typename T, int NF, int TZ, int BY, int RY>
 __global__ __launch_bounds__(TZ* BY) void batch_pass_kernel(const ScalarArgs<T>* runs, const int* tile_run,
                                                             const int* tile_local, double* partials, PassDesc pd) {
-  const int b = blockIdx.x;
+  // blocks are dealt to the XCDs in turn; this gives each XCD a contiguous
+  // range of the tile table (neighbouring tiles of a run), so the halo rows
+  // two tiles share are read through the same L2
+  int b = blockIdx.x;
+  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
   ScalarArgs<T> A = runs[tile_run[b]];
   A.pd = pd;
   A.partials = partials;
