@@ -259,9 +259,15 @@ __global__ __launch_bounds__(256) void fft_lines_inplace_kernel(Cx<R>* data, con
   const size_t NN = (size_t)N * N;
   const int tid = threadIdx.x, NT = blockDim.x;
   const int nzb = idiv<POW2>(N, B);
-  int lb0 = blockIdx.x, lb1 = blockIdx.x + 1;
+  // Blocks are dealt to the XCDs in turn; on the strided axes give each XCD
+  // a contiguous range of batches instead, so that the row segments of
+  // neighbouring batches (B elements each, under a cache line in FP32) are
+  // fetched through one L2.
+  int blk = blockIdx.x;
+  if (axis != 2 && (gridDim.x & 7) == 0) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+  int lb0 = blk, lb1 = blk + 1;
   if constexpr (MODE == kLineBinOut) {
-    lb0 = blockIdx.x * io.per_block;
+    lb0 = blk * io.per_block;
     lb1 = min((int)(NN / B), lb0 + io.per_block);
     for (int h = tid; h < io.nbins; h += NT) hist[h] = 0.0;
   }
