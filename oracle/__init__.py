@@ -589,7 +589,10 @@ def u1_vacuum_ic(cfg: dict) -> dict:
     sj = [(1.0 - np.exp(2j * math.pi * nn / N)) / dx for nn in (n1, n2, n3)]
     den = sum(np.abs(x) ** 2 for x in sj)
     zero = den == 0
-    piA = np.stack([a ** (1.0 - alpha) * paper_idft(np.where(zero, 0.0, np.conj(x) * Rh / np.where(zero, 1.0, den))).real
+    # The leapfrog and Verlet kicks conserve G = sum_i D-_i piA_i - rho(phi, pi)
+    # exactly, with no power of a in it (Sec. 5.3 kernels), so the link momenta
+    # themselves solve the discrete Gauss law for any a0 and alpha.
+    piA = np.stack([paper_idft(np.where(zero, 0.0, np.conj(x) * Rh / np.where(zero, 1.0, den))).real
                     for x in sj])
     if cfg.get("model") == "u1nc":
         links = np.zeros((3, N, N, N))

@@ -254,3 +254,158 @@ def test_u1_vv_and_leapfrog_agree_to_second_order():
         oracle.u1_lf_steps(m, lf, h, n)
         diffs.append(np.max(np.abs(v["phi"] - lf["phi"])))
     assert 3.2 < diffs[0] / diffs[1] < 5.0, diffs
+
+
+# --------------------------------------------------------------------------
+# Initial state of the charged scalar (Sec. 7.1, 7.2), pinned from its output
+# --------------------------------------------------------------------------
+def _u1_potential_curvature(lam, m2, pb, n, eps=1e-4):
+    """d^2 V / d phi_n^2 of V = lam |phi|^4 + m2 |phi|^2, |phi|^2 = (phi_0^2 + phi_1^2)/2,
+    by a central difference of the potential itself (not of a closed form)."""
+    def V(p0, p1):
+        r2 = 0.5 * (p0 * p0 + p1 * p1)
+        return lam * r2 * r2 + m2 * r2
+
+    p = list(pb)
+    vals = []
+    for d in (-eps, 0.0, eps):
+        q = list(p)
+        q[n] += d
+        vals.append(V(*q))
+    return (vals[0] - 2 * vals[1] + vals[2]) / (eps * eps)
+
+
+def _modes_of(field, N):
+    """f(n~) = sum_n exp(+2 pi i n~.n/N) f(n) through numpy's inverse FFT."""
+    return np.fft.ifftn(field) * N ** 3
+
+
+def _half_space(N):
+    """One member of every +-n~ pair that is not its own partner, by a rule of
+    this test (smaller linear index of the two)."""
+    idx = np.arange(N)
+    I, J, K = np.meshgrid(idx, idx, idx, indexing="ij")
+    lin = (I * N + J) * N + K
+    par = ((-I) % N * N + (-J) % N) * N + (-K) % N
+    return lin < par
+
+
+def _u1_ic_decompose(cfg, st):
+    """Left/right movers L_n, R_n of each real component (Sec. 7.2 form
+    df = (L + R)/sqrt 2, df' = c i w (L - R)/sqrt 2 - H df) recovered from the
+    output state, with every ingredient computed here: w_k^2 = k^2 + a^2 d2V,
+    H from the homogeneous Friedmann equation, c = a^{-(1-alpha)}."""
+    N = cfg["N"]
+    kIR, al, a = cfg["kIR"], cfg["alpha"], cfg["a0"]
+    dx = 2 * math.pi / (kIR * N)
+    lam, m2 = cfg["lam"], cfg["m2"][0]
+    pb, db = cfg["phi0"], cfg["dphi0"]
+    r2 = 0.5 * (pb[0] ** 2 + pb[1] ** 2)
+    rho_h = (db[0] ** 2 + db[1] ** 2) / (2 * a ** (2 * al)) + lam * r2 * r2 + m2 * r2
+    H = math.sqrt(cfg["fstar_over_mp"] ** 2 / 3 * a ** (2 * al + 2) * rho_h) / a
+    f = np.fft.fftfreq(N) * N
+    F1, F2, F3 = np.meshgrid(f, f, f, indexing="ij")
+    k = kIR * np.sqrt(F1 ** 2 + F2 ** 2 + F3 ** 2)
+    P0 = cfg["omega_over_f"] ** 2 * (N / dx) ** 3
+    out = []
+    for n in range(2):
+        comp = math.sqrt(2.0) * st["phi"][n] - pb[n]          # phi = (phi_0 + i phi_1)/sqrt 2
+        dcomp = math.sqrt(2.0) * st["pi"][n] / a ** (3 - al) - db[n]   # pi = a^{3-alpha} phi'
+        Fm, Fd = _modes_of(comp, N), _modes_of(dcomp, N)
+        w = np.sqrt(k * k + a * a * _u1_potential_curvature(lam, m2, pb, n))
+        P = P0 / (2 * a * a * w)
+        G = (Fd + H * Fm) / (a ** (-(1 - al)) * 1j * np.where(w > 0, w, 1.0))
+        out.append(dict(F=Fm, Fd=Fd, L=(Fm + G) / math.sqrt(2), R=(Fm - G) / math.sqrt(2), P=P, w=w, H=H))
+    return out
+
+
+def _u1_ic_cfg(seed, N=12):
+    return dict(model="u1", nf=2, N=N, kIR=0.3, dt=0.01, alpha=1.0, fstar_over_mp=2.0, omega_over_f=0.05,
+                m2=(0.0, 0.0), lam=1.0, q=0.0, e=0.5, phi0=(0.9, 0.4), dphi0=(0.0, 0.0), expansion=True,
+                seed=seed, a0=1.0)
+
+
+@pytest.mark.parametrize("a0", [1.0, 2.0])
+def test_u1_vacuum_ic_movers_obey_the_charge_constraints_mode_by_mode(a0):
+    # |l_n| = |r_n| and th_1^r = th_0^r + th_1^l - th_0^l at every mode (Sec. 7.2): only
+    # true if the test's w_k (with m2_eff,n = d2V/dphi_n^2), H, the 1/sqrt 2 of the complex
+    # field and pi = a^{3-alpha} phi' all match what the generator used.  alpha = 1, so that
+    # a0 = 2 tests the powers of a without the a^{+-(1-alpha)} of the derivative modes,
+    # which the paper writes both ways (Sec. 7.1 against Sec. 7.2) and which is 1 here.
+    cfg = dict(_u1_ic_cfg(5), a0=a0)
+    d = _u1_ic_decompose(cfg, oracle.u1_vacuum_ic(cfg))
+    hs = _half_space(cfg["N"])
+    scale = np.sqrt(d[0]["P"][hs]).max()
+    for n in range(2):
+        L, R = d[n]["L"][hs], d[n]["R"][hs]
+        assert np.max(np.abs(np.abs(L) - np.abs(R))) < 1e-9 * scale, n
+        assert np.abs(L).min() > 0
+    ph = d[1]["R"][hs] * d[0]["L"][hs] / (d[0]["R"][hs] * d[1]["L"][hs])   # e^{i(th1r - th0r - th1l + th0l)}
+    assert np.max(np.abs(ph - 1.0)) < 1e-8
+
+
+def test_u1_vacuum_ic_mode_statistics():
+    # Ensemble over 48 seeds of |df_n|^2 / P_n (Rayleigh moduli: mean 1), of the derivative
+    # modes |df'_n|^2 / ((c^2 w^2 + H^2) P_n), and of the fourth moment of Re df_n.
+    # With |l| = |r| a mode is |l| (e^{i th_l} + e^{i th_r})/sqrt 2, whose real part has
+    # kurtosis 9/2 (E|l|^4 = 2 P^2, E(Re Z)^2 = 1, E(Re Z)^4 = 9/4 for Z = e^{ia} + e^{ib}),
+    # not the 3 of independent Gaussian movers.
+    N = 12
+    hs = _half_space(N)
+    r = [[], []]
+    rd = [[], []]
+    z = [[], []]
+    for s in range(48):
+        cfg = _u1_ic_cfg(1000 + s, N)
+        d = _u1_ic_decompose(cfg, oracle.u1_vacuum_ic(cfg))
+        for n in range(2):
+            P, w, H = d[n]["P"][hs], d[n]["w"][hs], d[n]["H"]
+            r[n].append(np.abs(d[n]["F"][hs]) ** 2 / P)
+            rd[n].append(np.abs(d[n]["Fd"][hs]) ** 2 / ((w * w + H * H) * P))
+            z[n].append(d[n]["F"][hs].real / np.sqrt(P / 2))
+    for n in range(2):
+        for arr in (np.concatenate(r[n]), np.concatenate(rd[n])):
+            assert abs(arr.mean() - 1) < 3 * arr.std() / math.sqrt(arr.size), (n, arr.mean())
+        zz = np.concatenate(z[n])
+        assert abs(np.mean(zz ** 2) - 1) < 0.03
+        kurt = np.mean(zz ** 4) / np.mean(zz ** 2) ** 2
+        assert abs(kurt - 4.5) < 0.3, (n, kurt)
+
+
+def test_u1_vacuum_ic_statistics_see_a_wrong_effective_mass():
+    # the statistics above are sensitive to m2_eff: the low shells of component 0 at
+    # m2_eff = lam (s + 2 phi_0^2) against lam s (the curvature of |phi|^4 along |phi| only)
+    N = 12
+    hs = _half_space(N)
+    f = np.fft.fftfreq(N) * N
+    F1, F2, F3 = np.meshgrid(f, f, f, indexing="ij")
+    low = (np.sqrt(F1 ** 2 + F2 ** 2 + F3 ** 2) <= 2.0)[hs]
+    good, bad = [], []
+    for s in range(48):
+        cfg = _u1_ic_cfg(2000 + s, N)
+        d = _u1_ic_decompose(cfg, oracle.u1_vacuum_ic(cfg))[0]
+        P = d["P"][hs][low]
+        k2 = (d["w"][hs][low]) ** 2 - _u1_potential_curvature(1.0, 0.0, cfg["phi0"], 0)
+        Pbad = P * d["w"][hs][low] / np.sqrt(k2 + 1.0 * (0.9 ** 2 + 0.4 ** 2))
+        good.append(np.abs(d["F"][hs][low]) ** 2 / P)
+        bad.append(np.abs(d["F"][hs][low]) ** 2 / Pbad)
+    g, b = np.concatenate(good), np.concatenate(bad)
+    assert abs(g.mean() - 1) < 3 * g.std() / math.sqrt(g.size)
+    assert abs(b.mean() - 1) > 6 * b.std() / math.sqrt(b.size)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5])
+def test_u1_initial_gauss_law_at_a0_not_one(alpha):
+    # the kicks conserve sum_i D-_i piA_i - 2e (f/w)^2 Im[conj phi pi] with no power of a,
+    # so the initial link momenta must solve exactly that at any a0 (Sec. 7.2 with a0 != 1)
+    cfg = dict(_cfg(N=8, alpha=alpha), a0=2.0)
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    assert oracle.u1_sync_observe(m, st)["gauss"] < 1e-12
+    h = 0.01
+    vv = _copy(st)
+    oracle.u1_vv_steps(m, vv, h, "vv2", 20)
+    assert oracle.u1_sync_observe(m, vv)["gauss"] < 1e-12
+    oracle.u1_lf_startup(m, st, h)
+    oracle.u1_lf_steps(m, st, h, 20)
+    assert oracle.u1_lf_observe(m, st, h)["gauss"] < 1e-12
