@@ -384,6 +384,69 @@ def spectrum(f: np.ndarray, kIR: float) -> dict:
     return {"count": cnt, "S": S, "k": kbar, "delta": delta, "delta_avg": delta_avg}
 
 
+def _renorm(sp: dict, kIR: float) -> dict:
+    S, cnt, kbar = sp["S"], sp["count"], sp["k"]
+    N = sp["N"]
+    dx = lattice_dx(N, kIR)
+    nb = len(S)
+    bb = np.arange(nb, dtype=np.float64)
+    norm = (dx / N) ** 3 / (2.0 * math.pi ** 2)
+    sp["delta"] = np.zeros(nb)
+    sp["delta"][1:] = (kIR * bb[1:]) ** 3 * norm * S[1:] / (4.0 * math.pi * bb[1:] ** 2)
+    sp["delta_avg"] = np.where(cnt > 0, kbar ** 3 * norm * S / np.maximum(cnt, 1), 0.0)
+    return sp
+
+
+def u1_magnetic_field(cfg: dict, links: np.ndarray) -> np.ndarray:
+    """Magnetic field of the U(1) model on the sites (Sec. 5.4 observables),
+    B_i for (i, j, k) cyclic:
+      compact:      B_i = Im V_jk / (e dx^2), with the plaquette
+                    V_jk(n) = V_j(n) V_k(n+j) conj V_j(n+k) conj V_k(n);
+      non-compact:  B_i = sum_jk eps_ijk D+_j A_k = D+_j A_k - D+_k A_j.
+    The factor i printed before Im V_jk is read as a typo (B is real)."""
+    N = int(cfg["N"])
+    dx = lattice_dx(N, cfg["kIR"])
+    e = float(cfg["e"])
+    B = np.empty((3, N, N, N))
+    for i in range(3):
+        j, k = (i + 1) % 3, (i + 2) % 3
+        if cfg.get("model") == "u1nc":
+            A = links
+            B[i] = ((np.roll(A[k], -1, axis=j) - A[k]) - (np.roll(A[j], -1, axis=k) - A[j])) / dx
+        else:
+            V = links[:, 0] + 1j * links[:, 1]
+            P = V[j] * np.roll(V[k], -1, axis=j) * np.conj(np.roll(V[j], -1, axis=k)) * np.conj(V[k])
+            B[i] = P.imag / (e * dx * dx)
+    return B
+
+
+def u1_spectrum(cfg: dict, st: dict, which: str) -> dict:
+    """Spectra of the U(1) model (Sec. 5.4.2), binned as spectrum():
+      "phi": |Re phi(n~)|^2 + |Im phi(n~)|^2,  "pi": the same for pi_phi,
+      "E":   sum_i |E_i(n~)|^2 with E_i = pi_A,i / a^{1-alpha},
+      "B":   sum_i |B_i(n~)|^2 with B_i from u1_magnetic_field.
+    For "E" the scale factor is st["a"]."""
+    kIR = float(cfg["kIR"])
+    if which == "phi":
+        fields = [st["phi"][0], st["phi"][1]]
+    elif which == "pi":
+        fields = [st["pi"][0], st["pi"][1]]
+    elif which == "E":
+        c = st["a"] ** (-(1.0 - float(cfg.get("alpha", 1.0))))
+        fields = [c * st["piA"][i] for i in range(3)]
+    elif which == "B":
+        Bf = u1_magnetic_field(cfg, st["links"])
+        fields = [Bf[i] for i in range(3)]
+    else:
+        raise ValueError(which)
+    parts = [spectrum(f, kIR) for f in fields]
+    out = {k: v.copy() for k, v in parts[0].items()}
+    for p in parts[1:]:
+        out["S"] = out["S"] + p["S"]
+    out["N"] = fields[0].shape[0]
+    return _renorm(out, kIR)
+
+
 def logk_grid(N: int, kIR: float, nk: int = 64) -> np.ndarray:
     """nk log-spaced wavenumbers from kIR to kIR floor(sqrt(3) N / 2), the
     lowest and highest shells of the lattice (Sec. 3.1 binning)."""
@@ -602,6 +665,203 @@ def u1_vacuum_ic(cfg: dict) -> dict:
     st = {"phi": phi, "pi": pi, "links": links, "piA": piA, "a": a, "b": 1.0}
     if expand:
         o = u1_sync_observe(u1_model(cfg), st)
+        st["b"] = math.sqrt(fmp2 / 3.0 * a ** (2 * (alpha + 1)) * o["rho"])
+    else:
+        st["b"] = 0.0
+    return st
+
+
+# ---------------------------------------------------------------------------
+# Doublet with SU(2) x U(1) links (Sec. 6; ICs Sec. 7.2)
+# ---------------------------------------------------------------------------
+class SU2(ctypes.Structure):
+    """Parameters of the SU(2) x U(1) doublet model: V = lam |Phi|^4 + m2 |Phi|^2,
+    U(1) coupling e = g_A Q_A, SU(2) coupling g = g_B Q_B."""
+    _fields_ = [("N", ctypes.c_int32), ("expand", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("pad1", ctypes.c_int32), ("dx", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("fmp2", ctypes.c_double), ("lam", ctypes.c_double), ("m2", ctypes.c_double),
+                ("e", ctypes.c_double), ("g", ctypes.c_double), ("wf2", ctypes.c_double)]
+
+
+def su2_model(cfg: dict) -> SU2:
+    m = SU2()
+    m.N = int(cfg["N"])
+    m.expand = 1 if cfg.get("expansion", True) else 0
+    m.dx = lattice_dx(m.N, cfg["kIR"])
+    m.alpha = float(cfg.get("alpha", 1.0))
+    m.fmp2 = float(cfg.get("fstar_over_mp", 1.0)) ** 2
+    m.lam = float(cfg.get("lam", 0.0))
+    m.m2 = float(list(cfg.get("m2", (0.0, 0.0)))[0])
+    m.e = float(cfg["e"])
+    m.g = float(cfg["g"])
+    m.wf2 = float(cfg.get("omega_over_f", 1.0)) ** 2
+    return m
+
+
+def _su2_args(st):
+    return (_p(st["phi"]), _p(st["pi"]), _p(st["links"]), _p(st["su2"]), _p(st["piA"]), _p(st["piB"]))
+
+
+def su2_kernels(m: SU2, a, st):
+    N = m.N
+    Kp, KA, KB = np.empty((4, N, N, N)), np.empty((3, N, N, N)), np.empty((3, 3, N, N, N))
+    lib().orc_su2_kernels(ctypes.byref(m), ctypes.c_double(a), _p(st["phi"]), _p(st["links"]), _p(st["su2"]),
+                          _p(Kp), _p(KA), _p(KB))
+    return Kp, KA, KB
+
+
+def su2_lf_startup(m: SU2, st: dict, h: float):
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib().orc_su2_lf_startup(ctypes.byref(m), *_su2_args(st), ctypes.byref(ca), ctypes.byref(cb), ctypes.c_double(h))
+    st["a"], st["b"] = ca.value, cb.value
+
+
+def su2_lf_steps(m: SU2, st: dict, h: float, nsteps: int, omp: bool = False):
+    """nsteps SU(N) staggered-leapfrog steps (Sec. 6.2.1), in place on st."""
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib(omp).orc_su2_lf_steps(ctypes.byref(m), *_su2_args(st), ctypes.byref(ca), ctypes.byref(cb),
+                              ctypes.c_double(h), ctypes.c_int64(nsteps))
+    st["a"], st["b"] = ca.value, cb.value
+
+
+def su2_vv_steps(m: SU2, st: dict, h: float, integrator: str = "vv2", nsteps: int = 1, omp: bool = False):
+    """nsteps velocity-Verlet / Yoshida steps (Sec. 6.2.2, 6.2.3), in place on st."""
+    w = np.ascontiguousarray(VV_WEIGHTS[integrator], dtype=np.float64)
+    ca, cb = ctypes.c_double(st["a"]), ctypes.c_double(st["b"])
+    lib(omp).orc_su2_vv_steps(ctypes.byref(m), *_su2_args(st), ctypes.byref(ca), ctypes.byref(cb),
+                              ctypes.c_double(h), _p(w), ctypes.c_int(len(w)), ctypes.c_int64(nsteps))
+    st["a"], st["b"] = ca.value, cb.value
+
+
+def _su2_obs(e, a):
+    d = {"a": a, "EK": e[0], "EG": e[1], "EV": e[2], "EK_A": e[3], "EG_A": e[4], "EK_B": e[5], "EG_B": e[6],
+         "EV_quartic": e[7], "EV_mass": e[8], "b": e[9], "hc": e[10], "gauss": e[11], "gauss_B": e[12],
+         "mean": [e[13], e[14], e[15], e[16]], "meansq": e[17]}
+    d["rho"] = sum(e[k] for k in range(7))
+    d["p"] = e[0] - e[1] / 3.0 - e[2] + (e[3] + e[4] + e[5] + e[6]) / 3.0
+    d["w"] = d["p"] / d["rho"] if d["rho"] != 0 else 0.0
+    return d
+
+
+def su2_lf_observe(m: SU2, st: dict, h: float) -> dict:
+    e = np.zeros(18)
+    lib().orc_su2_lf_observe(ctypes.byref(m), *_su2_args(st), ctypes.c_double(st["a"]), ctypes.c_double(st["b"]),
+                             ctypes.c_double(h), _p(e))
+    return _su2_obs(e, st["a"])
+
+
+def su2_sync_observe(m: SU2, st: dict) -> dict:
+    e = np.zeros(18)
+    lib().orc_su2_sync_observe(ctypes.byref(m), *_su2_args(st), ctypes.c_double(st["a"]), ctypes.c_double(st["b"]),
+                               _p(e))
+    return _su2_obs(e, st["a"])
+
+
+def su2_gauss(m: SU2, st: dict) -> np.ndarray:
+    out = np.zeros(10)
+    lib().orc_su2_gauss(ctypes.byref(m), _p(st["phi"]), _p(st["pi"]), _p(st["su2"]), _p(st["piA"]), _p(st["piB"]),
+                        _p(out))
+    return out
+
+
+def su2_charges(cfg: dict, phi: np.ndarray, pi: np.ndarray):
+    """Charge densities of the doublet (Sec. 6.2 Gauss laws):
+    rho_A = 2e (f/w)^2 Im[Phi^dag pi],  rho_B^a = g (f/w)^2 Im[Phi^dag sigma_a pi]."""
+    w2 = float(cfg.get("omega_over_f", 1.0)) ** 2
+    P = [phi[0] + 1j * phi[1], phi[2] + 1j * phi[3]]
+    Q = [pi[0] + 1j * pi[1], pi[2] + 1j * pi[3]]
+    rhoA = 2.0 * float(cfg["e"]) / w2 * (np.conj(P[0]) * Q[0] + np.conj(P[1]) * Q[1]).imag
+    s = [np.conj(P[0]) * Q[1] + np.conj(P[1]) * Q[0],                 # Phi^dag sigma_1 pi
+         -1j * np.conj(P[0]) * Q[1] + 1j * np.conj(P[1]) * Q[0],       # Phi^dag sigma_2 pi
+         np.conj(P[0]) * Q[0] - np.conj(P[1]) * Q[1]]                  # Phi^dag sigma_3 pi
+    rhoB = np.stack([float(cfg["g"]) / w2 * x.imag for x in s])
+    return rhoA, rhoB
+
+
+def _gauss_solve(rho: np.ndarray, N: int, dx: float) -> np.ndarray:
+    """Minimum-norm solution E_i of sum_i D-_i E_i = rho (Sec. 7.2):
+    E_i(n~) = conj(s_i) rho(n~) / sum_j |s_j|^2, s_j = (1 - exp(+2 pi i n~_j/N))/dx, E(0) = 0."""
+    n1, n2, n3, _ = reciprocal(N)
+    Rh = paper_dft(rho)
+    sj = [(1.0 - np.exp(2j * math.pi * nn / N)) / dx for nn in (n1, n2, n3)]
+    den = sum(np.abs(x) ** 2 for x in sj)
+    zero = den == 0
+    return np.stack([paper_idft(np.where(zero, 0.0, np.conj(x) * Rh / np.where(zero, 1.0, den))).real for x in sj])
+
+
+def su2_vacuum_ic(cfg: dict) -> dict:
+    """Initial state of the SU(2) x U(1) doublet (Sec. 7.2).
+
+    Real components phi_n (n = 0..3) of Phi = (phi_0 + i phi_1, phi_2 + i phi_3)/sqrt 2
+    get the homogeneous values phi0[n] plus vacuum modes (Sec. 7.1) with
+    |l_n| = |r_n| and th_m^r = th_0^r + th_m^l - th_0^l (m = 1, 2, 3); with equal
+    homogeneous values (equal effective masses) every charge then vanishes mode by
+    mode.  Random numbers: Philox(counter=(lin, n, 0), key=seed); u0 -> |l_n|,
+    u2 -> th_n^l, u3 of component 0 -> th_0^r.  Links V = 1 and U = 1 (A = B = 0);
+    the electric fields solve both Gauss laws with the minimum-norm Fourier
+    solution; b from the Hubble constraint.  Shapes: phi, pi (4, N, N, N); links
+    (3, 2, N, N, N); su2 (3, 4, N, N, N) as (c0, c1, c2, c3); piA (3, N, N, N);
+    piB (3, 3, N, N, N)."""
+    N = int(cfg["N"])
+    kIR = float(cfg["kIR"])
+    dx = lattice_dx(N, kIR)
+    alpha = float(cfg.get("alpha", 1.0))
+    a = float(cfg.get("a0", 1.0))
+    w2 = float(cfg.get("omega_over_f", 1.0)) ** 2
+    lam = float(cfg.get("lam", 0.0))
+    m2 = float(list(cfg.get("m2", (0.0, 0.0)))[0])
+    fmp2 = float(cfg.get("fstar_over_mp", 1.0)) ** 2
+    expand = bool(cfg.get("expansion", True))
+    pb = list(cfg.get("phi0", (0.5, 0.5, 0.5, 0.5)))
+    db = list(cfg.get("dphi0", (0.0, 0.0, 0.0, 0.0)))
+    s = sum(x * x for x in pb)
+    r2 = 0.5 * s
+    rho_hom = sum(x * x for x in db) / (2.0 * a ** (2 * alpha)) + lam * r2 * r2 + m2 * r2
+    Hh = math.sqrt(fmp2 / 3.0 * a ** (2 * (alpha + 1)) * rho_hom) / a if expand else 0.0
+    m2eff = [lam * (s + 2.0 * pb[n] ** 2) + m2 for n in range(4)]
+    _, _, _, nabs = reciprocal(N)
+    k = kIR * nabs
+    lin, par = conjugate_partner(N)
+    rep = lin < par
+    kcut = float(cfg.get("kcut", 0.0) or 0.0)
+    two32 = 4294967296.0
+    U = [philox(int(cfg["seed"]), n, 0, N ** 3).reshape(N, N, N, 4).astype(np.float64) for n in range(4)]
+    th_l = [2.0 * math.pi * (U[n][..., 2] + 0.5) / two32 for n in range(4)]
+    th0r = 2.0 * math.pi * (U[0][..., 3] + 0.5) / two32
+    th_r = [th0r] + [th0r + th_l[n] - th_l[0] for n in range(1, 4)]
+    fields, derivs = [], []
+    for n in range(4):
+        om2 = k * k + a * a * m2eff[n]
+        ok = rep & (om2 > 0)
+        if kcut > 0:
+            ok &= k <= kcut
+        om = np.sqrt(np.where(ok, om2, 1.0))
+        P = np.where(ok, w2 * (N / dx) ** 3 / (2.0 * a * a * om), 0.0)
+        R = np.sqrt(-P * np.log((U[n][..., 0] + 0.5) / two32))
+        L = R * np.exp(1j * th_l[n])
+        Rt = R * np.exp(1j * th_r[n])
+        F = np.where(ok, (L + Rt) / math.sqrt(2.0), 0.0).ravel()
+        Fd = np.where(ok, a ** (-(1.0 - alpha)) * 1j * om * (L - Rt) / math.sqrt(2.0)
+                      - Hh * (L + Rt) / math.sqrt(2.0), 0.0).ravel()
+        okf, linf, parf = ok.ravel(), lin.ravel(), par.ravel()
+        F[parf[okf]] = np.conj(F[linf[okf]])
+        Fd[parf[okf]] = np.conj(Fd[linf[okf]])
+        fields.append(pb[n] + paper_idft(F.reshape(N, N, N)).real)
+        derivs.append(db[n] + paper_idft(Fd.reshape(N, N, N)).real)
+    r = 1.0 / math.sqrt(2.0)
+    phi = np.stack([f * r for f in fields])
+    pi = a ** (3.0 - alpha) * np.stack([d * r for d in derivs])
+    rhoA, rhoB = su2_charges(cfg, phi, pi)
+    links = np.zeros((3, 2, N, N, N))
+    links[:, 0] = 1.0
+    su2 = np.zeros((3, 4, N, N, N))
+    su2[:, 0] = 1.0
+    piA = _gauss_solve(rhoA, N, dx)
+    piB = np.stack([_gauss_solve(rhoB[c], N, dx) for c in range(3)], axis=1)   # (i, a, ...)
+    st = {"phi": phi, "pi": pi, "links": links, "su2": su2, "piA": np.ascontiguousarray(piA),
+          "piB": np.ascontiguousarray(piB), "a": a, "b": 1.0}
+    if expand:
+        o = su2_sync_observe(su2_model(cfg), st)
         st["b"] = math.sqrt(fmp2 / 3.0 * a ** (2 * (alpha + 1)) * o["rho"])
     else:
         st["b"] = 0.0

@@ -797,3 +797,492 @@ void orc_u1_sync_observe(const orc_u1* m, const double* phi, const double* pi, c
   e[11] = s[7];
   e[12] = s[8];
 }
+
+/* ------------------------------------------------------------------ */
+/* Doublet with SU(2) x U(1) gauge links (Sec. 6; SU(N) toolkit of     */
+/* Sec. 3.2.2).  Phi = (Phi_0, Phi_1), Phi_c = (phi_2c + i phi_2c+1)    */
+/* /sqrt 2, stored as four reals (Re Phi_0, Im Phi_0, Re Phi_1,        */
+/* Im Phi_1).  U(1) link V_i = exp(i th_i) stored (Re, Im); SU(2) link  */
+/* U_i = c0 + i c.sigma stored (c0, c1, c2, c3), in matrix form        */
+/*   [[c0 + i c3, c2 + i c1], [-c2 + i c1, c0 - i c3]].                */
+/* pi_A,i: one real per link; pi_B,i: three reals per link, the        */
+/* components along T_a = sigma_a/2.  The equations are those of the   */
+/* lattice Hamiltonian whose energies the paper lists (Sec. 6.3.1):    */
+/*   E_K^Phi = <pi^dag pi>/a^6, E_G^Phi = sum_i <|V_i U_i Phi_{+i}     */
+/*   - Phi|^2>/(a^2 dx^2), E_K^B = (w/f)^2 sum <pi_B^2>/(2 a^4),        */
+/*   E_G^B = 2 (w/f)^2/(a^4 dx^4 g^2) sum_{i<j} <2 - Tr U_ij>,          */
+/* with U(1) as in Sec. 5; the electric fields generate left          */
+/* multiplication of the links (U' = -i g dx pi_B U / a^{1-alpha},      */
+/* Sec. 6.2), so each force is minus the derivative of the energy     */
+/* along that motion.  Arithmetic: explicit 2x2 complex matrices.      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t N, expand, pad0, pad1;
+  double dx, alpha, fmp2;
+  double lambda;   /* V = lambda |Phi|^4 + m2 |Phi|^2, |Phi|^2 = Phi^dag Phi */
+  double m2;
+  double e;        /* U(1) coupling of the doublet, g_A Q_A */
+  double g;        /* SU(2) coupling, g_B Q_B */
+  double wf2;      /* (w_star/f_star)^2 */
+} orc_su2;
+
+typedef struct { cpx m[2][2]; } mat2;
+
+static mat2 mat_of_c(double c0, double c1, double c2, double c3) {
+  mat2 r;
+  r.m[0][0] = cmk(c0, c3);
+  r.m[0][1] = cmk(c2, c1);
+  r.m[1][0] = cmk(-c2, c1);
+  r.m[1][1] = cmk(c0, -c3);
+  return r;
+}
+static mat2 mat_mul(mat2 a, mat2 b) {
+  mat2 r;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const cpx p = cmul_(a.m[i][0], b.m[0][j]), q = cmul_(a.m[i][1], b.m[1][j]);
+      r.m[i][j] = cmk(p.re + q.re, p.im + q.im);
+    }
+  return r;
+}
+static mat2 mat_dag(mat2 a) {
+  mat2 r;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) r.m[i][j] = cconj_(a.m[j][i]);
+  return r;
+}
+static mat2 mat_scale(mat2 a, cpx s) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) a.m[i][j] = cmul_(s, a.m[i][j]);
+  return a;
+}
+/* Pauli matrices sigma_1..3 */
+static mat2 pauli(int a) {
+  mat2 r;
+  r.m[0][0] = r.m[0][1] = r.m[1][0] = r.m[1][1] = cmk(0.0, 0.0);
+  if (a == 1) { r.m[0][1] = cmk(1.0, 0.0); r.m[1][0] = cmk(1.0, 0.0); }
+  else if (a == 2) { r.m[0][1] = cmk(0.0, -1.0); r.m[1][0] = cmk(0.0, 1.0); }
+  else { r.m[0][0] = cmk(1.0, 0.0); r.m[1][1] = cmk(-1.0, 0.0); }
+  return r;
+}
+static cpx mat_trace(mat2 a) { return cmk(a.m[0][0].re + a.m[1][1].re, a.m[0][0].im + a.m[1][1].im); }
+/* c_a of an SU(2) element M = c0 + i c.sigma: Tr(sigma_a M) = 2 i c_a */
+static double su2_coef(mat2 M, int a) { return 0.5 * mat_trace(mat_mul(pauli(a), M)).im; }
+/* matrix of the algebra element sum_a x^a T_a, T_a = sigma_a/2 */
+static mat2 alg_mat(const double x[3]) {
+  mat2 r;
+  r.m[0][0] = cmk(0.5 * x[2], 0.0);
+  r.m[0][1] = cmk(0.5 * x[0], -0.5 * x[1]);
+  r.m[1][0] = cmk(0.5 * x[0], 0.5 * x[1]);
+  r.m[1][1] = cmk(-0.5 * x[2], 0.0);
+  return r;
+}
+/* components x^a of a Hermitian traceless X = x^a T_a: x^a = Tr(sigma_a X) */
+static void alg_comp(mat2 X, double x[3]) {
+  for (int a = 1; a <= 3; ++a) x[a - 1] = mat_trace(mat_mul(pauli(a), X)).re;
+}
+
+typedef struct { cpx v[2]; } vec2;
+static vec2 mat_vec(mat2 A, vec2 x) {
+  vec2 r;
+  for (int i = 0; i < 2; ++i) {
+    const cpx p = cmul_(A.m[i][0], x.v[0]), q = cmul_(A.m[i][1], x.v[1]);
+    r.v[i] = cmk(p.re + q.re, p.im + q.im);
+  }
+  return r;
+}
+/* x^dag y */
+static cpx vdot(vec2 x, vec2 y) {
+  const cpx p = cmul_(cconj_(x.v[0]), y.v[0]), q = cmul_(cconj_(x.v[1]), y.v[1]);
+  return cmk(p.re + q.re, p.im + q.im);
+}
+
+static vec2 dbl_at(const double* phi, int64_t V, int64_t s) {
+  vec2 r;
+  r.v[0] = cmk(phi[s], phi[V + s]);
+  r.v[1] = cmk(phi[2 * V + s], phi[3 * V + s]);
+  return r;
+}
+static mat2 su2_link(const double* UL, int64_t V, int i, int64_t s) {
+  const double* b = UL + (size_t)4 * i * V;
+  return mat_of_c(b[s], b[V + s], b[2 * V + s], b[3 * V + s]);
+}
+/* W_i(n) = V_i(n) U_i(n), the combined link acting on the doublet */
+static mat2 dbl_link(const double* VL, const double* UL, int64_t V, int i, int64_t s) {
+  return mat_scale(su2_link(UL, V, i, s), link_c(VL, V, i, s));
+}
+static mat2 su2_plaquette(const orc_su2* m, const double* UL, int i, int j, int64_t s) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  return mat_mul(mat_mul(su2_link(UL, V, i, s), su2_link(UL, V, j, shift(N, s, i, 1))),
+                 mat_mul(mat_dag(su2_link(UL, V, i, shift(N, s, j, 1))), mat_dag(su2_link(UL, V, j, s))));
+}
+static cpx u1_plaquette_c(const orc_su2* m, const double* VL, int i, int j, int64_t s) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const cpx a = link_c(VL, V, i, s), b = link_c(VL, V, j, shift(N, s, i, 1));
+  const cpx c = cconj_(link_c(VL, V, i, shift(N, s, j, 1))), d = cconj_(link_c(VL, V, j, s));
+  return cmul_(cmul_(a, b), cmul_(c, d));
+}
+
+/* Kernels (Sec. 6.2, written as the forces of the energies above):
+   K_Phi    = a^{1+alpha} sum_i (W_i Phi_{+i} - 2 Phi + W_i(n-i)^dag Phi_{-i}) / dx^2
+              - a^{3+alpha} (2 lambda |Phi|^2 + m2) Phi
+   K_A,i    = a^{1+alpha} (2e/dx)(f/w)^2 Im[Phi^dag W_i Phi_{+i}]
+              + a^{alpha-1}/(e dx^3) sum_{j!=i} (Im V_ij(n) - Im V_ij(n-j))
+   K_B,i^a  = a^{1+alpha} (g/dx)(f/w)^2 Im[Phi^dag sigma_a W_i Phi_{+i}]
+              + a^{alpha-1} 2/(g dx^3) sum_{j!=i} (c_a[U_ij(n)] - c_a[U_j(n-j)^dag U_ij(n-j) U_j(n-j)]) */
+void orc_su2_kernels(const orc_su2* m, double a, const double* phi, const double* VL, const double* UL,
+                     double* Kphi, double* KA, double* KB) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  const double cl = pow(a, 1.0 + m->alpha) / (m->dx * m->dx);
+  const double cp = pow(a, 3.0 + m->alpha);
+  const double cjA = pow(a, 1.0 + m->alpha) * 2.0 * m->e / m->dx / m->wf2;
+  const double cjB = pow(a, 1.0 + m->alpha) * m->g / m->dx / m->wf2;
+  const double cbA = pow(a, m->alpha - 1.0) / (m->e * m->dx * m->dx * m->dx);
+  const double cbB = pow(a, m->alpha - 1.0) * 2.0 / (m->g * m->dx * m->dx * m->dx);
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < N; ++x)
+    for (int y = 0; y < N; ++y)
+      for (int z = 0; z < N; ++z) {
+        const int64_t s = site(N, x, y, z);
+        const vec2 p = dbl_at(phi, V, s);
+        vec2 lap;
+        for (int c = 0; c < 2; ++c) lap.v[c] = cmk(-6.0 * p.v[c].re, -6.0 * p.v[c].im);
+        vec2 fw[3];
+        for (int i = 0; i < 3; ++i) {
+          const int64_t sp = shift(N, s, i, 1), sm = shift(N, s, i, -1);
+          fw[i] = mat_vec(dbl_link(VL, UL, V, i, s), dbl_at(phi, V, sp));
+          const vec2 bw = mat_vec(mat_dag(dbl_link(VL, UL, V, i, sm)), dbl_at(phi, V, sm));
+          for (int c = 0; c < 2; ++c) {
+            lap.v[c].re += fw[i].v[c].re + bw.v[c].re;
+            lap.v[c].im += fw[i].v[c].im + bw.v[c].im;
+          }
+        }
+        const double r2 = vdot(p, p).re;
+        const double dv = 2.0 * m->lambda * r2 + m->m2;
+        for (int c = 0; c < 2; ++c) {
+          Kphi[(2 * c) * V + s] = cl * lap.v[c].re - cp * dv * p.v[c].re;
+          Kphi[(2 * c + 1) * V + s] = cl * lap.v[c].im - cp * dv * p.v[c].im;
+        }
+        for (int i = 0; i < 3; ++i) {
+          double magA = 0.0, magB[3] = {0.0, 0.0, 0.0};
+          for (int j = 0; j < 3; ++j) {
+            if (j == i) continue;
+            const int64_t sjm = shift(N, s, j, -1);
+            magA += u1_plaquette_c(m, VL, i, j, s).im - u1_plaquette_c(m, VL, i, j, sjm).im;
+            const mat2 Pn = su2_plaquette(m, UL, i, j, s);
+            const mat2 Uj = su2_link(UL, V, j, sjm);
+            const mat2 Pm = mat_mul(mat_mul(mat_dag(Uj), su2_plaquette(m, UL, i, j, sjm)), Uj);
+            for (int a = 1; a <= 3; ++a) magB[a - 1] += su2_coef(Pn, a) - su2_coef(Pm, a);
+          }
+          KA[i * V + s] = cjA * vdot(p, fw[i]).im + cbA * magA;
+          for (int a = 1; a <= 3; ++a)
+            KB[(3 * i + a - 1) * V + s] = cjB * vdot(p, mat_vec(pauli(a), fw[i])).im + cbB * magB[a - 1];
+        }
+      }
+}
+
+/* Raw volume averages: out[0] = <pi^dag pi>, out[1] = <sum_i |W_i Phi_{+i} - Phi|^2>,
+   out[2] = <lambda |Phi|^4>, out[3] = <m2 |Phi|^2>, out[4] = <sum_i piA_i^2>,
+   out[5] = <sum_{i<j} (1 - Re V_ij)>, out[6] = <sum_{i,a} piB_i^a^2>, out[7] = <sum_{i<j} (2 - Tr U_ij)>,
+   out[8..11] = <the four real components of Phi>, out[12] = <|Phi|^2>. */
+#define ORC_SU2_NS 13
+void orc_su2_sums(const orc_su2* m, const double* phi, const double* pi, const double* VL, const double* UL,
+                  const double* piA, const double* piB, double* out) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  double* part = (double*)calloc((size_t)N * ORC_SU2_NS, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < N; ++x) {
+    double* acc = part + (size_t)x * ORC_SU2_NS;
+    for (int y = 0; y < N; ++y)
+      for (int z = 0; z < N; ++z) {
+        const int64_t s = site(N, x, y, z);
+        const vec2 p = dbl_at(phi, V, s);
+        if (pi)
+          for (int k = 0; k < 4; ++k) acc[0] += pi[k * V + s] * pi[k * V + s];
+        for (int i = 0; i < 3; ++i) {
+          const vec2 f = mat_vec(dbl_link(VL, UL, V, i, s), dbl_at(phi, V, shift(N, s, i, 1)));
+          for (int c = 0; c < 2; ++c) {
+            const double dr = f.v[c].re - p.v[c].re, di = f.v[c].im - p.v[c].im;
+            acc[1] += dr * dr + di * di;
+          }
+          if (piA) acc[4] += piA[i * V + s] * piA[i * V + s];
+          if (piB)
+            for (int a = 0; a < 3; ++a) acc[6] += piB[(3 * i + a) * V + s] * piB[(3 * i + a) * V + s];
+        }
+        const double r2 = vdot(p, p).re;
+        acc[2] += m->lambda * r2 * r2;
+        acc[3] += m->m2 * r2;
+        for (int i = 0; i < 3; ++i)
+          for (int j = i + 1; j < 3; ++j) {
+            acc[5] += 1.0 - u1_plaquette_c(m, VL, i, j, s).re;
+            acc[7] += 2.0 - mat_trace(su2_plaquette(m, UL, i, j, s)).re;
+          }
+        for (int k = 0; k < 4; ++k) acc[8 + k] += phi[k * V + s];
+        acc[12] += r2;
+      }
+  }
+  for (int k = 0; k < ORC_SU2_NS; ++k) {
+    double sacc = 0.0;
+    for (int x = 0; x < N; ++x) sacc += part[(size_t)x * ORC_SU2_NS + k];
+    out[k] = sacc / (double)V;
+  }
+  free(part);
+}
+
+/* Energies: e[0] E_K^Phi, e[1] E_G^Phi, e[2] E_V, e[3] E_K^A, e[4] E_G^A, e[5] E_K^B, e[6] E_G^B,
+   e[7] <lambda|Phi|^4>, e[8] <m2|Phi|^2>.  kin_* >= 0 override the kinetic averages. */
+static void su2_energies(const orc_su2* m, double a, const double* s, double kin_phi, double kin_A, double kin_B,
+                         double* e) {
+  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2, dx2 = m->dx * m->dx, dx4 = dx2 * dx2;
+  e[0] = (kin_phi >= 0.0 ? kin_phi : s[0]) / a6;
+  e[1] = s[1] / (a2 * dx2);
+  e[2] = s[2] + s[3];
+  e[3] = m->wf2 * (kin_A >= 0.0 ? kin_A : s[4]) / (2.0 * a4);
+  e[4] = m->wf2 * s[5] / (a4 * dx4 * m->e * m->e);
+  e[5] = m->wf2 * (kin_B >= 0.0 ? kin_B : s[6]) / (2.0 * a4);
+  e[6] = 2.0 * m->wf2 * s[7] / (a4 * dx4 * m->g * m->g);
+  e[7] = s[2];
+  e[8] = s[3];
+}
+
+/* K_a with both gauge sectors, radiation-like: (alpha-1)(E_K^A + E_G^A + E_K^B + E_G^B) */
+double orc_su2_Ka(const orc_su2* m, double a, const double* e) {
+  const double al = m->alpha;
+  return m->fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+         ((al - 2.0) * e[0] + al * e[1] + (al + 1.0) * e[2] + (al - 1.0) * (e[3] + e[4] + e[5] + e[6]));
+}
+
+/* Link drifts (Sec. 6.2 drift from momenta, Cayley form):
+   V <- (1 - i u)/(1 + i u) V,   u = e h dx piA / (2 a_mid^{1-alpha});
+   U <- (1 - i X)(1 + i X)^{-1} U, X = w^a sigma_a, w^a = g h dx piB^a / (4 a_mid^{1-alpha})
+   (the Cayley transform of -i g h dx piB^a T_a / a_mid^{1-alpha}; unitary, det 1). */
+static void su2_link_drift(const orc_su2* m, double* VL, double* UL, const double* piA, const double* piB, double h,
+                           double amid) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  const double cA = m->e * h * m->dx / (2.0 * pow(amid, 1.0 - m->alpha));
+  const double cB = m->g * h * m->dx / (4.0 * pow(amid, 1.0 - m->alpha));
+  for (int i = 0; i < 3; ++i)
+    for (int64_t s = 0; s < V; ++s) {
+      const double u = cA * piA[i * V + s];
+      const double d = 1.0 + u * u;
+      const cpx r = cmk((1.0 - u * u) / d, -2.0 * u / d);
+      const cpx v = cmul_(r, link_c(VL, V, i, s));
+      VL[(2 * i) * V + s] = v.re;
+      VL[(2 * i + 1) * V + s] = v.im;
+      /* (1 - iX)(1 + iX)^{-1} = (1 - iX)^2 / (1 + |w|^2) since X^2 = |w|^2 */
+      double w[3];
+      for (int a = 0; a < 3; ++a) w[a] = cB * piB[(3 * i + a) * V + s];
+      const double w2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+      const mat2 C = mat_of_c((1.0 - w2) / (1.0 + w2), -2.0 * w[0] / (1.0 + w2), -2.0 * w[1] / (1.0 + w2),
+                              -2.0 * w[2] / (1.0 + w2));
+      const mat2 Un = mat_mul(C, su2_link(UL, V, i, s));
+      double* b = UL + (size_t)4 * i * V;
+      b[s] = Un.m[0][0].re;
+      b[V + s] = Un.m[0][1].im;
+      b[2 * V + s] = Un.m[0][1].re;
+      b[3 * V + s] = Un.m[0][0].im;
+    }
+}
+
+/* Start-up of the staggered leapfrog from a synchronised state (as orc_u1_lf_startup). */
+void orc_su2_lf_startup(const orc_su2* m, double* phi, double* pi, double* VL, double* UL, double* piA,
+                        double* piB, double* a, double* b, double h) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 4 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double* KB = (double*)malloc(sizeof(double) * 9 * V);
+  double s[ORC_SU2_NS], e[9];
+  if (m->expand) {
+    orc_su2_sums(m, phi, pi, VL, UL, piA, piB, s);
+    su2_energies(m, *a, s, -1.0, -1.0, -1.0, e);
+    *b = *b - 0.5 * h * orc_su2_Ka(m, *a, e);
+  }
+  orc_su2_kernels(m, *a, phi, VL, UL, Kp, KA, KB);
+  for (int64_t i = 0; i < 4 * V; ++i) pi[i] -= 0.5 * h * Kp[i];
+  for (int64_t i = 0; i < 3 * V; ++i) piA[i] -= 0.5 * h * KA[i];
+  for (int64_t i = 0; i < 9 * V; ++i) piB[i] -= 0.5 * h * KB[i];
+  free(Kp);
+  free(KA);
+  free(KB);
+}
+
+/* SU(N) staggered leapfrog (Sec. 6.2.1), per step:
+     pi_{+1/2} = pi_{-1/2} + h K_Phi;  piA, piB likewise
+     b_{+1/2}  = b_{-1/2} + h K_a[a, semi-sums of the kinetic energies, E_G, E_V]
+     a_{+1}    = a + h b_{+1/2};  Phi += h pi_{+1/2} / a_{+1/2}^{3-alpha};  links drifted */
+void orc_su2_lf_steps(const orc_su2* m, double* phi, double* pi, double* VL, double* UL, double* piA, double* piB,
+                      double* a, double* b, double h, int64_t nsteps) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 4 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double* KB = (double*)malloc(sizeof(double) * 9 * V);
+  double s[ORC_SU2_NS], e[9];
+  for (int64_t it = 0; it < nsteps; ++it) {
+    orc_su2_kernels(m, *a, phi, VL, UL, Kp, KA, KB);
+    const double kp0 = sum_sq(pi, 4 * V), ka0 = sum_sq(piA, 3 * V), kb0 = sum_sq(piB, 9 * V);
+    for (int64_t i = 0; i < 4 * V; ++i) pi[i] += h * Kp[i];
+    for (int64_t i = 0; i < 3 * V; ++i) piA[i] += h * KA[i];
+    for (int64_t i = 0; i < 9 * V; ++i) piB[i] += h * KB[i];
+    double anew = *a, amid = *a;
+    if (m->expand) {
+      const double kp1 = sum_sq(pi, 4 * V), ka1 = sum_sq(piA, 3 * V), kb1 = sum_sq(piB, 9 * V);
+      orc_su2_sums(m, phi, NULL, VL, UL, NULL, NULL, s);
+      su2_energies(m, *a, s, 0.5 * (kp0 + kp1) / (double)V, 0.5 * (ka0 + ka1) / (double)V,
+                   0.5 * (kb0 + kb1) / (double)V, e);
+      *b = *b + h * orc_su2_Ka(m, *a, e);
+      anew = *a + h * (*b);
+      amid = 0.5 * (*a + anew);
+    }
+    const double cd = h * pow(amid, -(3.0 - m->alpha));
+    for (int64_t i = 0; i < 4 * V; ++i) phi[i] += cd * pi[i];
+    su2_link_drift(m, VL, UL, piA, piB, h, amid);
+    *a = anew;
+  }
+  free(Kp);
+  free(KA);
+  free(KB);
+}
+
+/* Velocity Verlet and its Yoshida compositions (Sec. 6.2.2, 6.2.3), in the
+   order of orc_u1_vv_steps. */
+void orc_su2_vv_steps(const orc_su2* m, double* phi, double* pi, double* VL, double* UL, double* piA, double* piB,
+                      double* a, double* b, double h, const double* w, int nw, int64_t nsteps) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double* Kp = (double*)malloc(sizeof(double) * 4 * V);
+  double* KA = (double*)malloc(sizeof(double) * 3 * V);
+  double* KB = (double*)malloc(sizeof(double) * 9 * V);
+  double s[ORC_SU2_NS], e[9];
+  for (int64_t it = 0; it < nsteps; ++it) {
+    for (int p = 0; p < nw; ++p) {
+      const double hw = w[p] * h;
+      if (m->expand) {
+        orc_su2_sums(m, phi, pi, VL, UL, piA, piB, s);
+        su2_energies(m, *a, s, -1.0, -1.0, -1.0, e);
+        *b += 0.5 * hw * orc_su2_Ka(m, *a, e);
+      }
+      orc_su2_kernels(m, *a, phi, VL, UL, Kp, KA, KB);
+      for (int64_t i = 0; i < 4 * V; ++i) pi[i] += 0.5 * hw * Kp[i];
+      for (int64_t i = 0; i < 3 * V; ++i) piA[i] += 0.5 * hw * KA[i];
+      for (int64_t i = 0; i < 9 * V; ++i) piB[i] += 0.5 * hw * KB[i];
+      double anew = *a, amid = *a;
+      if (m->expand) {
+        anew = *a + hw * (*b);
+        amid = 0.5 * (*a + anew);
+      }
+      const double cd = hw * pow(amid, -(3.0 - m->alpha));
+      for (int64_t i = 0; i < 4 * V; ++i) phi[i] += cd * pi[i];
+      su2_link_drift(m, VL, UL, piA, piB, hw, amid);
+      *a = anew;
+      orc_su2_kernels(m, *a, phi, VL, UL, Kp, KA, KB);
+      for (int64_t i = 0; i < 4 * V; ++i) pi[i] += 0.5 * hw * Kp[i];
+      for (int64_t i = 0; i < 3 * V; ++i) piA[i] += 0.5 * hw * KA[i];
+      for (int64_t i = 0; i < 9 * V; ++i) piB[i] += 0.5 * hw * KB[i];
+      if (m->expand) {
+        orc_su2_sums(m, phi, pi, VL, UL, piA, piB, s);
+        su2_energies(m, *a, s, -1.0, -1.0, -1.0, e);
+        *b += 0.5 * hw * orc_su2_Ka(m, *a, e);
+      }
+    }
+  }
+  free(Kp);
+  free(KA);
+  free(KB);
+}
+
+/* Gauss residuals (Sec. 5.2 for U(1); Sec. 6.2, discrete SU(N) Gauss law with the
+   electric field at n - i parallel-transported to n):
+   G_A(n)   = sum_i (piA_i(n) - piA_i(n-i))/dx - 2e (f/w)^2 Im[Phi^dag pi]
+   G_B^a(n) = sum_i (piB_i(n) - U_i(n-i)^dag piB_i(n-i) U_i(n-i))^a / dx - g (f/w)^2 Im[Phi^dag sigma_a pi]
+   out[0..2] = sum G_A^2, sum div_A^2, sum rho_A^2; out[3..5] the same for SU(2) (over a);
+   out[6] = sum rho_A, out[7..9] = sum rho_B^a. */
+void orc_su2_gauss(const orc_su2* m, const double* phi, const double* pi, const double* UL, const double* piA,
+                   const double* piB, double* out) {
+  const int N = m->N;
+  const int64_t V = (int64_t)N * N * N;
+  for (int k = 0; k < 10; ++k) out[k] = 0.0;
+  for (int64_t s = 0; s < V; ++s) {
+    const vec2 p = dbl_at(phi, V, s), q = dbl_at(pi, V, s);
+    double divA = 0.0, divB[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 3; ++i) {
+      const int64_t sm = shift(N, s, i, -1);
+      divA += (piA[i * V + s] - piA[i * V + sm]) / m->dx;
+      double xm[3], xt[3];
+      for (int a = 0; a < 3; ++a) xm[a] = piB[(3 * i + a) * V + sm];
+      const mat2 U = su2_link(UL, V, i, sm);
+      alg_comp(mat_mul(mat_mul(mat_dag(U), alg_mat(xm)), U), xt);
+      for (int a = 0; a < 3; ++a) divB[a] += (piB[(3 * i + a) * V + s] - xt[a]) / m->dx;
+    }
+    const double rhoA = 2.0 * m->e / m->wf2 * vdot(p, q).im;
+    out[0] += (divA - rhoA) * (divA - rhoA);
+    out[1] += divA * divA;
+    out[2] += rhoA * rhoA;
+    out[6] += rhoA;
+    for (int a = 1; a <= 3; ++a) {
+      const double rhoB = m->g / m->wf2 * vdot(p, mat_vec(pauli(a), q)).im;
+      out[3] += (divB[a - 1] - rhoB) * (divB[a - 1] - rhoB);
+      out[4] += divB[a - 1] * divB[a - 1];
+      out[5] += rhoB * rhoB;
+      out[6 + a] += rhoB;
+    }
+  }
+}
+
+/* Observables; e[0..8] as su2_energies, e[9] = b, e[10] = Hubble-constraint residual,
+   e[11] = Gauss residual of U(1), e[12] = of SU(2), e[13..16] = <components of Phi>,
+   e[17] = <|Phi|^2>.  Staggered (lf = 1): kinetic semi-sums, b_n the mean of the two
+   half-step values, as orc_u1_lf_observe. */
+static void su2_observe(const orc_su2* m, const double* phi, const double* pi, const double* VL, const double* UL,
+                        const double* piA, const double* piB, double a, double b, double h, int lf, double* e) {
+  const int64_t V = (int64_t)m->N * m->N * m->N;
+  double s[ORC_SU2_NS];
+  double bn = b;
+  if (lf) {
+    double* Kp = (double*)malloc(sizeof(double) * 4 * V);
+    double* KA = (double*)malloc(sizeof(double) * 3 * V);
+    double* KB = (double*)malloc(sizeof(double) * 9 * V);
+    orc_su2_kernels(m, a, phi, VL, UL, Kp, KA, KB);
+    double kp1 = 0.0, ka1 = 0.0, kb1 = 0.0;
+    for (int64_t i = 0; i < 4 * V; ++i) { const double v = pi[i] + h * Kp[i]; kp1 += v * v; }
+    for (int64_t i = 0; i < 3 * V; ++i) { const double v = piA[i] + h * KA[i]; ka1 += v * v; }
+    for (int64_t i = 0; i < 9 * V; ++i) { const double v = piB[i] + h * KB[i]; kb1 += v * v; }
+    const double kp0 = sum_sq(pi, 4 * V), ka0 = sum_sq(piA, 3 * V), kb0 = sum_sq(piB, 9 * V);
+    orc_su2_sums(m, phi, NULL, VL, UL, NULL, NULL, s);
+    su2_energies(m, a, s, 0.5 * (kp0 + kp1) / (double)V, 0.5 * (ka0 + ka1) / (double)V,
+                 0.5 * (kb0 + kb1) / (double)V, e);
+    if (m->expand) bn = 0.5 * (b + b + h * orc_su2_Ka(m, a, e));
+    free(Kp);
+    free(KA);
+    free(KB);
+  } else {
+    orc_su2_sums(m, phi, pi, VL, UL, piA, piB, s);
+    su2_energies(m, a, s, -1.0, -1.0, -1.0, e);
+  }
+  double hc = 0.0;
+  if (m->expand) {
+    const double rho = e[0] + e[1] + e[2] + e[3] + e[4] + e[5] + e[6];
+    const double rhs = m->fmp2 / 3.0 * pow(a, 2.0 * (m->alpha + 1.0)) * rho;
+    hc = fabs(bn * bn - rhs) / (bn * bn);
+  }
+  double g[10];
+  orc_su2_gauss(m, phi, pi, UL, piA, piB, g);
+  e[9] = bn;
+  e[10] = hc;
+  e[11] = sqrt(g[0]) / (sqrt(g[1]) + sqrt(g[2]));
+  e[12] = sqrt(g[3]) / (sqrt(g[4]) + sqrt(g[5]));
+  for (int k = 0; k < 4; ++k) e[13 + k] = s[8 + k];
+  e[17] = s[12];
+}
+
+void orc_su2_lf_observe(const orc_su2* m, const double* phi, const double* pi, const double* VL, const double* UL,
+                        const double* piA, const double* piB, double a, double b, double h, double* e) {
+  su2_observe(m, phi, pi, VL, UL, piA, piB, a, b, h, 1, e);
+}
+
+void orc_su2_sync_observe(const orc_su2* m, const double* phi, const double* pi, const double* VL,
+                          const double* UL, const double* piA, const double* piB, double a, double b, double* e) {
+  su2_observe(m, phi, pi, VL, UL, piA, piB, a, b, 0.0, 0, e);
+}

@@ -409,3 +409,70 @@ def test_u1_initial_gauss_law_at_a0_not_one(alpha):
     oracle.u1_lf_startup(m, st, h)
     oracle.u1_lf_steps(m, st, h, 20)
     assert oracle.u1_lf_observe(m, st, h)["gauss"] < 1e-12
+
+
+# --------------------------------------------------------------------------
+# U(1) spectra (Sec. 5.4.2)
+# --------------------------------------------------------------------------
+def test_u1_spectra_parseval():
+    # sum_b S_b = N^3 sum_n sum_c f_c(n)^2 for the complex scalar, its momentum, E and B
+    cfg = _cfg(N=10)
+    rs = synth.random_u1_state(10, seed=4, amp=0.3, link_angle=1.2, emom=0.4)
+    st = dict(rs, a=1.7, b=0.2)
+    N = 10
+    for which, parts in (("phi", st["phi"]), ("pi", st["pi"]), ("E", st["piA"] * 1.7 ** (-(1 - cfg["alpha"])))):
+        sp = oracle.u1_spectrum(cfg, st, which)
+        assert abs(sp["S"].sum() - N ** 3 * np.sum(parts ** 2)) < 1e-10 * sp["S"].sum(), which
+    # B from the plaquettes, built here with complex numbers from the phases
+    th = np.arctan2(st["links"][:, 1], st["links"][:, 0])
+    dx = 2 * math.pi / (cfg["kIR"] * N)
+    Bsq = 0.0
+    for i in range(3):
+        j, k = (i + 1) % 3, (i + 2) % 3
+        phi_jk = th[j] + np.roll(th[k], -1, axis=j) - np.roll(th[j], -1, axis=k) - th[k]
+        Bsq += np.sum((np.sin(phi_jk) / (cfg["e"] * dx * dx)) ** 2)
+    sp = oracle.u1_spectrum(cfg, st, "B")
+    assert abs(sp["S"].sum() - N ** 3 * Bsq) < 1e-10 * sp["S"].sum()
+
+
+@pytest.mark.parametrize("model", ["u1", "u1nc"])
+def test_u1_magnetic_spectrum_single_mode(model):
+    # A_y = eps cos(2 pi m x/N + psi): B_z = D+_x A_y is one lattice wave, all its power in
+    # shell m with S_m = N^6 eps^2 k_lat^2 / 2, k_lat = 2 sin(pi m/N)/dx (compact: up to
+    # the O((e dx^2 eps k)^2) of sin(Phi) against Phi)
+    N, m, eps = 12, 3, 1e-4
+    cfg = dict(_cfg(N=N), model=model)
+    dx = 2 * math.pi / (cfg["kIR"] * N)
+    x = np.arange(N)[:, None, None] * np.ones((1, N, N))
+    A = np.zeros((3, N, N, N))
+    A[1] = eps * np.cos(2 * math.pi * m * x / N + 0.4)
+    if model == "u1":
+        links = np.zeros((3, 2, N, N, N))
+        th = -cfg["e"] * dx * A
+        links[:, 0], links[:, 1] = np.cos(th), np.sin(th)
+    else:
+        links = A
+    st = {"phi": np.zeros((2, N, N, N)), "pi": np.zeros((2, N, N, N)), "links": links,
+          "piA": np.zeros((3, N, N, N)), "a": 1.0, "b": 0.0}
+    sp = oracle.u1_spectrum(cfg, st, "B")
+    klat = 2 * math.sin(math.pi * m / N) / dx
+    expect = N ** 6 * eps ** 2 * klat ** 2 / 2
+    tol = 1e-10 if model == "u1nc" else 1e-6
+    assert abs(sp["S"][m] - expect) < tol * expect
+    others = np.delete(sp["S"], m)
+    assert np.max(others) < tol * expect
+
+
+def test_u1_electric_spectrum_single_mode_and_scale_factor():
+    # pi_A,x = eps cos(2 pi m y/N): shell m holds N^6 eps^2/2, times a^{-2(1-alpha)}
+    N, m, eps = 12, 4, 0.3
+    cfg = _cfg(N=N, alpha=0.5)
+    y = np.arange(N)[None, :, None] * np.ones((N, 1, N))
+    piA = np.zeros((3, N, N, N))
+    piA[0] = eps * np.cos(2 * math.pi * m * y / N)
+    st = {"phi": np.zeros((2, N, N, N)), "pi": np.zeros((2, N, N, N)),
+          "links": np.zeros((3, 2, N, N, N)), "piA": piA, "a": 2.0, "b": 0.0}
+    sp = oracle.u1_spectrum(cfg, st, "E")
+    expect = N ** 6 * eps ** 2 / 2 / 2.0
+    assert abs(sp["S"][m] - expect) < 1e-12 * expect
+    assert np.max(np.delete(sp["S"], m)) < 1e-12 * expect
