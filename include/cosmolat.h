@@ -49,6 +49,12 @@ extern "C" {
                                (Sec. 5.2): A' = a^{-(1-alpha)} pi_A, magnetic
                                kernel sum_j (D-_j D+_j A_i - D-_j D+_i A_j),
                                E_G^A from F_ij = D+_i A_j - D+_j A_i         */
+#define LAT_MODEL_SU2U1 3   /* doublet Phi = (phi_0 + i phi_1, phi_2 + i phi_3)
+                               / sqrt 2 with compact SU(2) and U(1) links
+                               (Sec. 6): V = lambda |Phi|^4 + m2[0] |Phi|^2,
+                               U(1) coupling e, SU(2) coupling g; nf = 4.
+                               Every real component starts at phi0[0] (and
+                               dphi0[0]), the equal amplitudes of Sec. 7.2 */
 
 /* Integrators (Sec. 3.3-3.4, 4.2-4.3) */
 #define LAT_LF2 0   /* staggered leapfrog, scheme III (pi = a^{3-alpha} phi')    */
@@ -90,6 +96,7 @@ typedef struct lattice_params {
   double dphi0[2];     /* homogeneous d phi / d eta                          */
   double a0;           /* initial scale factor (1)                           */
   double kcut;         /* 0: no cut; else fluctuations only for k <= kcut    */
+  double g;            /* SU(2) gauge coupling g_B Q_B (LAT_MODEL_SU2U1)     */
 } lattice_params;
 
 /* Homogeneous variables of a state.  For LAT_LF2, staggered = 1 means the
@@ -121,6 +128,10 @@ typedef struct lattice_obs {
   int64_t step;
   int32_t staggered;
   int32_t reserved;
+  double EK_B, EG_B;   /* SU(2) electric and magnetic energy (Sec. 6.3.1)   */
+  double gauss_B;      /* SU(2) Gauss-law residual                          */
+  double mean_lo[2];   /* SU(2) x U(1): <Re Phi_1>, <Im Phi_1>; mean_f holds */
+                       /* <Re Phi_0>, <Im Phi_0> and meansq_f[0] <|Phi|^2>  */
 } lattice_obs;
 
 typedef struct lattice lattice_t;
@@ -166,16 +177,33 @@ int lattice_step(lattice_t* h, int64_t nsteps);
    Errors: LAT_ENONFINITE (NaN/Inf in a volume average), LAT_EHIP. */
 int lattice_energies(lattice_t* h, lattice_obs* out);
 
+/* Spectrum selectors of the U(1) models that add components shell by shell
+   (Sec. 5.4.2): the complex scalar |Re phi(n~)|^2 + |Im phi(n~)|^2, the same
+   for its momentum, the electric field sum_i |E_i(n~)|^2 with
+   E_i = pi_A,i / a^{1-alpha} (a of the current state; in a staggered state
+   pi_A is the stored half-step value), and the magnetic field
+   sum_i |B_i(n~)|^2 with B_i = Im V_jk / (e dx^2) for (i, j, k) cyclic
+   (compact links; the factor i printed before Im is read as a typo) or
+   B_i = D+_j A_k - D+_k A_j (non-compact).  B is computed in FP64 from the
+   stored links and transformed in the storage precision. */
+#define LAT_SPEC_U1_PHI 32
+#define LAT_SPEC_U1_PI 33
+#define LAT_SPEC_U1_E 34
+#define LAT_SPEC_U1_B 35
+
 /* Radially binned power spectrum of one field component (Sec. 3.1, eq. of
    the discrete spectrum; Sec. 4.4.2, 5.4.2).  Shell b holds the modes with
    floor(|n~|) = b, b = 0 .. floor(sqrt(3) N / 2).  Per shell: k[b] = mean
    k_IR |n~|, sum_sq[b] = sum |f(n~)|^2 with f(n~) = sum_n e^{+2 pi i n~.n/N}
    f(n), counts[b], and delta[b] = (k_IR b)^3/(2 pi^2) (dx/N)^3 sum_sq[b] /
    (4 pi b^2) for b >= 1 (0 for b = 0).  which: for scalar models 0..nf-1 =
-   field f, 16+f = momentum f.  The transform runs in the storage precision
-   (FP32 lattices: FP32 butterflies, relative error about 1e-6 per mode) and
-   the shell sums in FP64; within a block they are added in no fixed order, so
-   results are reproducible to FP64 rounding.  Caller-owned host arrays of
+   field f, 16+f = momentum f; for U(1) models 0, 1 = Re, Im phi, 16, 17 =
+   Re, Im pi, and the summed LAT_SPEC_U1_* selectors above; for the SU(2) x
+   U(1) model 0..3 and 16..19 = the real components of Phi and pi, and
+   LAT_SPEC_U1_PHI / LAT_SPEC_U1_PI = their sums.  The stored values are
+   transformed in FP64 for either storage precision, and the shell sums are
+   FP64; within a block they are added in no fixed order, so results are
+   reproducible to FP64 rounding.  Caller-owned host arrays of
    nbins_cap entries; *nbins receives the number of shells.  Synchronises the
    stream.  Errors: LAT_EINVAL (which), LAT_ENOMEM (nbins_cap too small),
    LAT_EHIP. */

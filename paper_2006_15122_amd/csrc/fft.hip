@@ -458,14 +458,14 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
   return LAT_OK;
 }
 
-// Forward transform of a real field for its power spectrum, in the field's
-// storage precision R (FP64 roots; FP64 histograms): the z pass reads the
-// field itself (no complex copy), the x pass bins |f(n~)|^2 into nblk
-// per-block histograms pS (nbins each) instead of storing the transform.
+// Forward transform of a real field (stored as TIN) for its power spectrum,
+// in precision R (FP64 roots; FP64 histograms): the z pass reads the field
+// itself (no complex copy), the x pass bins |f(n~)|^2 into nblk per-block
+// histograms pS (nbins each) instead of storing the transform.
 // *nblk = 0 (nothing launched) where these passes do not apply: a radix
 // above 5, or the x pass's buffer, roots and histogram above 64 KiB of LDS.
-template <typename R>
-static int fft3d_bins(const R* f, Cx<R>* data, const Cx<double>* W, int N, int nbins, double* pS,
+template <typename R, typename TIN = R>
+static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int nbins, double* pS,
                       int max_blocks, int* nblk, hipStream_t s) {
   *nblk = 0;
   const FFTPlan P = make_plan(N);
@@ -511,7 +511,7 @@ static int fft3d_bins(const R* f, Cx<R>* data, const Cx<double>* W, int N, int n
   } while (0)
   for (int axis = 2; axis >= 0; --axis) {
     const int grid = axis == 0 ? nb_bin : (int)((size_t)N * N / Bs[axis]);
-    if (axis == 2) CL_LINES(kLineRealIn, R);
+    if (axis == 2) CL_LINES(kLineRealIn, TIN);
     else if (axis == 1) CL_LINES(kLinePlain);
     else CL_LINES(kLineBinOut);
     CL_HIP(hipGetLastError());
@@ -730,6 +730,7 @@ int run_fft3d(lattice* h, int sign, double scale) {
 int init_state(lattice* h) {
   const lattice_params& p = h->p;
   if (is_u1(p)) return u1_init_state(h);
+  if (is_su2(p)) return su2_init_state(h);
   const int N = p.N;
   const int64_t V = (int64_t)N * N * N;
   const double a = p.a0, al = p.alpha;
@@ -808,6 +809,26 @@ struct Bins {
   int nb;
 };
 
+// Shell sums of several real fields added (acc = sum_c f_c S_c, with
+// f_c = a^pw read from the device state, or 1 for pw = 0), and the paper's
+// delta of the sum.
+__global__ void shell_accumulate_kernel(const double* S, double* acc, int nb, int first, const DevState* st,
+                                        double pw) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double f = pw == 0.0 ? 1.0 : pow(st->a, pw);
+  acc[b] = (first ? 0.0 : acc[b]) + f * S[b];
+}
+
+__global__ void shell_delta_kernel(const double* acc, double* D, int nb, double kIR, double norm) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double kb = kIR * (double)b;
+  D[b] = b > 0 ? kb * kb * kb * norm * acc[b] / (4.0 * M_PI * (double)b * (double)b) : 0.0;
+}
+
+int component_bins(lattice_t* h, const void* src, Bins* out);
+
 int spectrum_bins(lattice_t* h, int which, Bins* out) {
   const int N = h->p.N;
   const int nb = (int)std::floor(std::sqrt(3.0) * N / 2.0) + 1;
@@ -815,16 +836,77 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
   if (h->p.model == LAT_MODEL_SCALAR) {
     if (which >= 0 && which < h->p.nf) comp = which;
     else if (which >= 16 && which < 16 + h->p.nf) comp = h->p.nf + which - 16;
+  } else if (is_su2(h->p)) {
+    // the four real components of Phi and pi, or (Sec. 6.3.2) their sums
+    if (which >= 0 && which < 4) comp = which;
+    else if (which >= 16 && which < 20) comp = 4 + which - 16;
+    else if (which == LAT_SPEC_U1_PHI || which == LAT_SPEC_U1_PI) {
+      char* tail = h->spec + (size_t)(spec_blocks(N)) * nb * 24 + (size_t)nb * 32;
+      double* acc = reinterpret_cast<double*>(tail);
+      double* dacc = acc + nb;
+      Bins B{};
+      for (int c = 0; c < 4; ++c) {
+        int rc = component_bins(h, h->buf[h->cur][(which == LAT_SPEC_U1_PHI ? 0 : 4) + c], &B);
+        if (rc) return rc;
+        hipLaunchKernelGGL(shell_accumulate_kernel, dim3((nb + 255) / 256), dim3(256), 0, h->stream, B.S, acc, nb,
+                           c == 0 ? 1 : 0, h->st, 0.0);
+        CL_HIP(hipGetLastError());
+      }
+      const double norm = std::pow(h->dx / N, 3.0) / (2.0 * M_PI * M_PI);
+      hipLaunchKernelGGL(shell_delta_kernel, dim3((nb + 255) / 256), dim3(256), 0, h->stream, acc, dacc, nb,
+                         h->p.kIR, norm);
+      CL_HIP(hipGetLastError());
+      *out = Bins{acc, B.K, dacc, B.C, nb};
+      return LAT_OK;
+    }
   } else {
     if (which >= 0 && which < 2) comp = which;                 // Re, Im of phi
     else if (which >= 16 && which < 18) comp = 2 + which - 16;  // Re, Im of pi
+    else if (which >= LAT_SPEC_U1_PHI && which <= LAT_SPEC_U1_B) {
+      // sums over components (Sec. 5.4.2): the complex scalar, its momentum,
+      // E_i = pi_A,i / a^{1-alpha}, and B_i (computed into the free state buffer)
+      const int nc = which <= LAT_SPEC_U1_PI ? 2 : 3;
+      const double pw = which == LAT_SPEC_U1_E ? -2.0 * (1.0 - h->p.alpha) : 0.0;
+      char* tail = h->spec + (size_t)(spec_blocks(N)) * nb * 24 + (size_t)nb * 32;
+      double* acc = reinterpret_cast<double*>(tail);
+      double* dacc = acc + nb;
+      Bins B{};
+      for (int c = 0; c < nc; ++c) {
+        const void* src;
+        if (which == LAT_SPEC_U1_PHI) src = h->buf[h->cur][c];
+        else if (which == LAT_SPEC_U1_PI) src = h->buf[h->cur][2 + c];
+        else if (which == LAT_SPEC_U1_E) src = h->buf[h->cur][7 + c];
+        else {
+          void* scratch = h->buf[1 - h->cur][0];
+          int rc = u1_magnetic_field(h, c, scratch);
+          if (rc) return rc;
+          src = scratch;
+        }
+        int rc = component_bins(h, src, &B);
+        if (rc) return rc;
+        hipLaunchKernelGGL(shell_accumulate_kernel, dim3((nb + 255) / 256), dim3(256), 0, h->stream, B.S, acc, nb,
+                           c == 0 ? 1 : 0, h->st, pw);
+        CL_HIP(hipGetLastError());
+      }
+      const double norm = std::pow(h->dx / N, 3.0) / (2.0 * M_PI * M_PI);
+      hipLaunchKernelGGL(shell_delta_kernel, dim3((nb + 255) / 256), dim3(256), 0, h->stream, acc, dacc, nb,
+                         h->p.kIR, norm);
+      CL_HIP(hipGetLastError());
+      *out = Bins{acc, B.K, dacc, B.C, nb};
+      return LAT_OK;
+    }
   }
   if (comp < 0) { set_error("spectrum: unknown field selector"); return LAT_EINVAL; }
+  return component_bins(h, h->buf[h->cur][comp], out);
+}
+
+int component_bins(lattice_t* h, const void* src, Bins* out) {
+  const int N = h->p.N;
+  const int nb = (int)std::floor(std::sqrt(3.0) * N / 2.0) + 1;
   const int64_t V = (int64_t)N * N * N;
   const int threads = 256;
   const int blocks = (int)((V + threads - 1) / threads);
   Cx<double>* F = reinterpret_cast<Cx<double>*>(h->fft);
-  const void* src = h->buf[h->cur][comp];
   const int nblk = spec_blocks(N);
   const int64_t per = (V + nblk - 1) / nblk;
   double* pS = (double*)h->spec;
@@ -856,10 +938,12 @@ int spectrum_bins(lattice_t* h, int which, Bins* out) {
     CL_HIP(hipGetLastError());
     h->spec_geom_ready = true;
   }
+  // The transform runs in FP64 for either storage: an FP32 transform's
+  // rounding is relative to the field's total power (the zero mode of a
+  // condensate included), which would swamp the low-power shells.
   int rc = h->p.precision == LAT_FP32
-               ? fft3d_bins((const float*)src, reinterpret_cast<Cx<float>*>(h->fft), W, N, nb, pS, nblk, &fused_blk,
-                            h->stream)
-               : fft3d_bins((const double*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream);
+               ? fft3d_bins<double, float>((const float*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream)
+               : fft3d_bins<double, double>((const double*)src, F, W, N, nb, pS, nblk, &fused_blk, h->stream);
   if (rc) return rc;
   if (fused_blk > 0) {
     hipLaunchKernelGGL(bin_sum_kernel<false>, dim3(nb), dim3(256), 0, h->stream, pS, pK, pC, fused_blk, nb,

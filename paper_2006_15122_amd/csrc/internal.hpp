@@ -35,7 +35,7 @@ struct lattice {
   int64_t max_blocks;
   int ncomp;
   size_t comp_bytes;
-  void* buf[2][16];     // ping-pong state buffers, per component
+  void* buf[2][40];     // ping-pong state buffers, per component
   void* fft;            // complex FP64 scratch of N^3 entries
   void* twiddle;        // N complex FP64 roots of unity for the FFT
   bool twiddle_ready = false;
@@ -80,6 +80,16 @@ int u1_step(lattice* h, int64_t n);
 int u1_energies(lattice* h);
 int u1_init_state(lattice* h);
 int u1_gauss(lattice* h);
+// B_i of the U(1) model on the sites, into out (N^3 values, storage precision)
+int u1_magnetic_field(lattice* h, int i, void* out);
+// initial-state helpers shared by the charged-scalar models (u1.hip)
+int charged_mode_field(lattice* h, int comp, int deriv, double m2eff, double Hhom, double base, double* out);
+int gauss_solve_fields(lattice* h, const double2* R, void* const out[3], bool fp32);
+// the SU(2) x U(1) doublet model (su2.hip)
+inline bool is_su2(const lattice_params& p) { return p.model == LAT_MODEL_SU2U1; }
+int su2_step(lattice* h, int64_t n);
+int su2_energies(lattice* h);
+int su2_init_state(lattice* h);
 int run_fft3d(lattice* h, int sign, double scale);
 bool tiling_ok(const lattice* h, const Tiling& t);
 void default_tiling(lattice* h);

@@ -61,7 +61,9 @@ std::vector<double> vv_weights(int integrator) {
 
 int validate(const lattice_params* p) {
   if (!p) { set_error("params is NULL"); return LAT_EINVAL; }
-  if (p->model != LAT_MODEL_SCALAR && !is_u1(*p)) { set_error("unknown model"); return LAT_EINVAL; }
+  if (p->model != LAT_MODEL_SCALAR && !is_u1(*p) && !is_su2(*p)) { set_error("unknown model"); return LAT_EINVAL; }
+  if (is_su2(*p) && p->nf != 4) { set_error("SU(2) x U(1) model needs nf = 4"); return LAT_EINVAL; }
+  if (is_su2(*p) && !(p->e > 0.0 && p->g > 0.0)) { set_error("SU(2) x U(1) model needs e > 0 and g > 0"); return LAT_EINVAL; }
   if (p->model == LAT_MODEL_SCALAR && (p->nf < 1 || p->nf > 2)) { set_error("scalar model needs nf = 1 or 2"); return LAT_EINVAL; }
   if (is_u1(*p) && p->nf != 2) { set_error("U1 model needs nf = 2"); return LAT_EINVAL; }
   if (p->N < 32 || p->N > 1024 || p->N % 32 != 0) { set_error("N must be a multiple of 32 in [32, 1024]"); return LAT_EINVAL; }
@@ -117,12 +119,18 @@ static void layout(const lattice_params* p, size_t* off_part, size_t* off_part2,
 
 int ncomponents(const lattice_params* p) {
   if (is_u1(*p)) return 10;  // phi (2), pi (2), link phases or A_i (3), piA (3)
+  if (is_su2(*p)) return 35;  // Phi (4), pi (4), U(1) phases (3), piA (3), SU(2) links (12), piB (9)
   return 2 * p->nf;
 }
 
 }  // namespace cl
 
 using namespace cl;
+
+static int su2_set_state(lattice_t* h, const double* fields, const double* momenta, const double* links,
+                         const double* link_momenta, const lattice_scalars* s);
+static int su2_get_state(lattice_t* h, double* fields, double* momenta, double* links, double* link_momenta,
+                         lattice_scalars* s);
 
 extern "C" {
 
@@ -181,7 +189,7 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
   // Tune first, on zeroed buffers, so that the timed passes can ping-pong
   // between the two state copies exactly as lattice_step does; the initial
   // state is built afterwards.
-  if (p->N >= 128) {
+  if (p->N >= 128 && !is_su2(*p)) {
     rc = autotune(L);
     if (rc) { delete L; return rc; }
   }
@@ -267,6 +275,7 @@ int lattice_field_device_ptr(lattice_t* h, int c, void** ptr, int32_t* elem_byte
 int lattice_set_state(lattice_t* h, const double* fields, const double* momenta, const double* links,
                       const double* link_momenta, const lattice_scalars* s) {
   if (!h || !fields || !momenta || !s) { set_error("NULL argument"); return LAT_EINVAL; }
+  if (is_su2(h->p)) return su2_set_state(h, fields, momenta, links, link_momenta, s);
   const bool u1 = is_u1(h->p), nc = h->p.model == LAT_MODEL_U1_NC;
   if (u1 && (!links || !link_momenta)) { set_error("U1 state needs links and link momenta"); return LAT_EINVAL; }
   if (!u1 && (links || link_momenta)) { set_error("scalar state takes no links"); return LAT_EINVAL; }
@@ -307,6 +316,7 @@ int lattice_set_state(lattice_t* h, const double* fields, const double* momenta,
 int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* links, double* link_momenta,
                       lattice_scalars* s) {
   if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
+  if (is_su2(h->p)) return su2_get_state(h, fields, momenta, links, link_momenta, s);
   const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
   const int nf = h->p.nf;
   const bool u1 = is_u1(h->p), nc = h->p.model == LAT_MODEL_U1_NC;
@@ -350,16 +360,93 @@ int lattice_get_state(lattice_t* h, double* fields, double* momenta, double* lin
   return LAT_OK;
 }
 
+// SU(2) x U(1): fields, momenta 4 N^3 each; links = the U(1) links (Re, Im),
+// 3*2*N^3, then the SU(2) links (c0, c1, c2, c3), 3*4*N^3; link momenta =
+// pi_A (3*N^3) then pi_B (direction i, component a: 9*N^3).  U(1) links are
+// stored by phase.
+static int su2_set_state(lattice_t* h, const double* fields, const double* momenta, const double* links,
+                         const double* link_momenta, const lattice_scalars* s) {
+  if (!links || !link_momenta) { set_error("SU(2) x U(1) state needs links and link momenta"); return LAT_EINVAL; }
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  std::vector<const double*> comps;
+  for (int k = 0; k < 4; ++k) comps.push_back(fields + k * V);
+  for (int k = 0; k < 4; ++k) comps.push_back(momenta + k * V);
+  std::vector<double> phases((size_t)3 * V);
+  for (int i = 0; i < 3; ++i)
+    for (int64_t k = 0; k < V; ++k) {
+      const double re = links[(2 * i) * V + k], im = links[(2 * i + 1) * V + k];
+      if (!std::isfinite(re) || !std::isfinite(im)) { set_error("non-finite link"); return LAT_ENONFINITE; }
+      phases[(size_t)i * V + k] = std::atan2(im, re);
+    }
+  for (int i = 0; i < 3; ++i) comps.push_back(phases.data() + (size_t)i * V);
+  for (int i = 0; i < 3; ++i) comps.push_back(link_momenta + i * V);
+  for (int k = 0; k < 12; ++k) comps.push_back(links + (6 + k) * V);
+  for (int k = 0; k < 9; ++k) comps.push_back(link_momenta + (3 + k) * V);
+  for (size_t c = 0; c < comps.size(); ++c)
+    for (int64_t i = 0; i < V; ++i)
+      if (!std::isfinite(comps[c][i])) { set_error("non-finite value in state"); return LAT_ENONFINITE; }
+  int rc = upload_components(h, comps.data(), (int)comps.size());
+  if (rc) return rc;
+  rc = upload_scalars(h, s->a, s->b, s->eta);
+  if (rc) return rc;
+  h->staggered = s->staggered ? 1 : 0;
+  h->step = s->step;
+  return LAT_OK;
+}
+
+static int su2_get_state(lattice_t* h, double* fields, double* momenta, double* links, double* link_momenta,
+                         lattice_scalars* s) {
+  const int64_t V = (int64_t)h->p.N * h->p.N * h->p.N;
+  std::vector<double*> comps((size_t)h->ncomp, nullptr);
+  for (int k = 0; k < 4; ++k) {
+    if (fields) comps[k] = fields + k * V;
+    if (momenta) comps[4 + k] = momenta + k * V;
+  }
+  std::vector<double> phases;
+  if (links) {
+    phases.resize((size_t)3 * V);
+    for (int i = 0; i < 3; ++i) comps[8 + i] = phases.data() + (size_t)i * V;
+    for (int k = 0; k < 12; ++k) comps[14 + k] = links + (6 + k) * V;
+  }
+  if (link_momenta) {
+    for (int i = 0; i < 3; ++i) comps[11 + i] = link_momenta + i * V;
+    for (int k = 0; k < 9; ++k) comps[26 + k] = link_momenta + (3 + k) * V;
+  }
+  int rc = download_components(h, comps.data(), (int)comps.size());
+  if (rc) return rc;
+  if (links) {
+    for (int i = 0; i < 3; ++i)
+      for (int64_t k = 0; k < V; ++k) {
+        const double t = phases[(size_t)i * V + k];
+        links[(2 * i) * V + k] = std::cos(t);
+        links[(2 * i + 1) * V + k] = std::sin(t);
+      }
+  }
+  if (s) {
+    DevState d;
+    CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    CL_HIP(hipStreamSynchronize(h->stream));
+    s->a = d.a;
+    s->b = d.b;
+    s->eta = d.eta;
+    s->step = h->step;
+    s->staggered = h->staggered;
+    s->reserved = 0;
+  }
+  return LAT_OK;
+}
+
 int lattice_step(lattice_t* h, int64_t nsteps) {
   if (!h) { set_error("NULL handle"); return LAT_EINVAL; }
   if (nsteps < 0) { set_error("nsteps < 0"); return LAT_EINVAL; }
   if (is_u1(h->p)) return u1_step(h, nsteps);
+  if (is_su2(h->p)) return su2_step(h, nsteps);
   return scalar_step(h, nsteps);
 }
 
 int lattice_energies(lattice_t* h, lattice_obs* out) {
   if (!h || !out) { set_error("NULL argument"); return LAT_EINVAL; }
-  int rc = is_u1(h->p) ? u1_energies(h) : scalar_energies(h);
+  int rc = is_u1(h->p) ? u1_energies(h) : is_su2(h->p) ? su2_energies(h) : scalar_energies(h);
   if (rc) return rc;
   DevState d;
   CL_HIP(hipMemcpyAsync(&d, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
@@ -570,6 +657,7 @@ int scalar_energies(lattice* h) {
 // tiling
 // ---------------------------------------------------------------------------
 bool tiling_ok(const lattice* h, const Tiling& t) {
+  if (is_su2(h->p)) return false;  // its passes are untiled
   bool compiled = false;
   const int fp32 = h->p.precision == LAT_FP32;
   const bool u1 = is_u1(h->p);
@@ -590,6 +678,10 @@ bool tiling_ok(const lattice* h, const Tiling& t) {
 
 void default_tiling(lattice* h) {
   const int N = h->p.N;
+  if (is_su2(h->p)) {
+    h->tile = Tiling{0, 0, 0, 0};
+    return;
+  }
   if (is_u1(h->p)) {
     // the 64-wide tile where it divides N; the largest x-chunk that still
     // gives 1024 blocks

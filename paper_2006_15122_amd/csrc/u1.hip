@@ -93,6 +93,13 @@ __device__ __forceinline__ double atan_t(double x) { return atan(x); }
 __device__ __forceinline__ float quot_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double quot_t(double a, double b) { return a / b; }
 
+// cos t - 1 from (cos t, sin t) without cancellation: -sin^2/(1 + cos) where
+// cos > 0, the plain difference (no cancellation) elsewhere
+template <typename T>
+__device__ __forceinline__ T cos_m1(T cs, T sn) {
+  return cs > T(0) ? -quot_t(sn * sn, T(1) + cs) : cs - T(1);
+}
+
 template <typename T>
 __device__ __forceinline__ C2<T> ld(const T* re, const T* im, size_t i) {
   return C2<T>{re[i], im[i]};
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   static_assert(NT == 256, "partials and LDS sized for four waves");
   __shared__ T Lp[2][2][LY][LZ];       // drifted phi (Re, Im), planes in flight
   __shared__ T Lt[2][3][LY][LZ];       // drifted link phases (own sites are stored)
-  __shared__ C2<T> Lu[2][3][LY][LZ];   // drifted links U_i = e^{i theta_i} (cos, sin)
+  __shared__ C2<T> Lu[2][3][LY][LZ];   // drifted links minus one, U_i - 1 = (cos - 1, sin)
   __shared__ T Ls[3][TY + 1][TZ + 1];  // S_01, S_02, S_12; index 0 = row y0-1 / column z0-1
 
   const int N = A.N;
@@ -291,7 +298,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
         Lt[b][i][ly][lz] = th;
         T sn, cs;
         sincos_t(NC ? mth * th : th, &sn, &cs);
-        Lu[b][i][ly][lz] = C2<T>{cs, sn};
+        Lu[b][i][ly][lz] = C2<T>{cos_m1(cs, sn), sn};
       }
     }
     if (has_ring) {
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
         }
         T sn, cs;
         sincos_t(NC ? mth * th : th, &sn, &cs);
-        Lu[b][i][rly][rlz] = C2<T>{cs, sn};
+        Lu[b][i][rly][rlz] = C2<T>{cos_m1(cs, sn), sn};
       }
     }
   };
@@ -327,11 +334,12 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       for (int k = 0; k < 3; ++k) om[k] = T(0.5) * sn[k] * sn[k];
       return;
     }
-    const C2<T> u0 = Lu[c][0][ly][lz], u1 = Lu[c][1][ly][lz], u2 = Lu[c][2][ly][lz];
+    auto U = [](C2<T> m) { return C2<T>{T(1) + m.x, m.y}; };
+    const C2<T> u0 = U(Lu[c][0][ly][lz]), u1 = U(Lu[c][1][ly][lz]), u2 = U(Lu[c][2][ly][lz]);
     C2<T> P[3];
-    P[0] = cm(cm(u0, Lu[n][1][ly][lz]), cc(cm(Lu[c][0][ly + 1][lz], u1)));
-    P[1] = cm(cm(u0, Lu[n][2][ly][lz]), cc(cm(Lu[c][0][ly][lz + 1], u2)));
-    P[2] = cm(cm(u1, Lu[c][2][ly + 1][lz]), cc(cm(Lu[c][1][ly][lz + 1], u2)));
+    P[0] = cm(cm(u0, U(Lu[n][1][ly][lz])), cc(cm(U(Lu[c][0][ly + 1][lz]), u1)));
+    P[1] = cm(cm(u0, U(Lu[n][2][ly][lz])), cc(cm(U(Lu[c][0][ly][lz + 1]), u2)));
+    P[2] = cm(cm(u1, U(Lu[c][2][ly + 1][lz])), cc(cm(U(Lu[c][1][ly][lz + 1]), u2)));
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       sn[k] = P[k].y;
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 
   // registers: plane x-1 (own column) and raw momenta of planes x, x+1
   T pm[2][RY], s01m[RY], s02m[RY];
-  C2<T> um[RY];  // U_0 of the own column at plane x-1
+  C2<T> um[RY];  // U_0 - 1 of the own column at plane x-1
   T qc[5][RY], qn[5][RY];
 
   // prologue: plane x0-1 -> buffer 1, plane x0 -> buffer 0; S_01, S_02 of
@@ -426,17 +434,22 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
       const T th[3] = {Lt[cb_][0][ly][lz], Lt[cb_][1][ly][lz], Lt[cb_][2][ly][lz]};
       const C2<T> uf[3] = {Lu[cb_][0][ly][lz], Lu[cb_][1][ly][lz], Lu[cb_][2][ly][lz]};
       const C2<T> ub[3] = {um[r], Lu[cb_][1][ly - 1][lz], Lu[cb_][2][ly][lz - 1]};
-      C2<T> lap{T(-6) * p.x, T(-6) * p.y};
+      // covariant differences U phi_{+k} - phi = (U - 1) phi_{+k} + (phi_{+k} - phi):
+      // both parts are small where the fields are smooth, so the FP32 result
+      // keeps its relative precision instead of cancelling against the
+      // condensate; the current Im[conj(phi) U phi_{+k}] = Im[conj(phi) g]
+      C2<T> lap{T(0), T(0)};
       T Kcur[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const C2<T> f = cm(uf[k], fw[k]);
-        const C2<T> b = cm(cc(ub[k]), bw[k]);
-        lap.x += f.x + b.x;
-        lap.y += f.y + b.y;
-        const T gx = f.x - p.x, gy = f.y - p.y;
-        ts[2] += gx * gx + gy * gy;
-        Kcur[k] = cj * (p.x * f.y - p.y * f.x);
+        const C2<T> uf1 = cm(uf[k], fw[k]);
+        const C2<T> g{uf1.x + (fw[k].x - p.x), uf1.y + (fw[k].y - p.y)};
+        const C2<T> ub1 = cm(cc(ub[k]), bw[k]);
+        const C2<T> gb{ub1.x + (bw[k].x - p.x), ub1.y + (bw[k].y - p.y)};
+        lap.x += g.x + gb.x;
+        lap.y += g.y + gb.y;
+        ts[2] += g.x * g.x + g.y * g.y;
+        Kcur[k] = cj * (p.x * g.y - p.y * g.x);
       }
       const T r2 = p.x * p.x + p.y * p.y;
       const T dv = T(2) * lam * r2 + m2;
@@ -889,6 +902,66 @@ __global__ void u1_zero_phases_kernel(T* t0, T* t1, T* t2, int64_t V) {
   t0[i] = t1[i] = t2[i] = T(0);
 }
 
+// Real component `comp` (0..3) of a charged scalar, or its derivative, into
+// out (V doubles): base plus the inverse DFT of the vacuum modes of Sec. 7.2
+// with the zero-charge constraints (or base alone for LAT_IC_HOMOGENEOUS).
+int charged_mode_field(lattice* h, int comp, int deriv, double m2eff, double Hhom, double base, double* out) {
+  const lattice_params& p = h->p;
+  const int N = p.N;
+  const int64_t V = (int64_t)N * N * N;
+  double2* F = reinterpret_cast<double2*>(h->fft);
+  const int thr = 256;
+  const int blk = (int)((V + thr - 1) / thr);
+  if (p.ic == LAT_IC_VACUUM) {
+    U1ModeArgs M;
+    M.N = N;
+    M.comp = comp;
+    M.deriv = deriv;
+    M.seed = p.seed;
+    M.kIR = p.kIR;
+    M.P0 = p.omega_over_f * p.omega_over_f * std::pow((double)N / h->dx, 3.0);
+    M.a = p.a0;
+    M.alpha = p.alpha;
+    M.m2eff = m2eff;
+    M.Hhom = Hhom;
+    M.kcut = p.kcut;
+    hipLaunchKernelGGL(u1_modes_kernel, dim3(blk), dim3(thr), 0, h->stream, F, M);
+    CL_HIP(hipGetLastError());
+    int rc = run_fft3d(h, -1, 1.0);
+    if (rc) return rc;
+    hipLaunchKernelGGL(u1_take_real_kernel, dim3(blk), dim3(thr), 0, h->stream, F, out, V, base, 1.0 / (double)V);
+  } else {
+    hipLaunchKernelGGL(u1_take_real_kernel, dim3(blk), dim3(thr), 0, h->stream, F, out, V, base, 0.0);
+  }
+  CL_HIP(hipGetLastError());
+  return LAT_OK;
+}
+
+// Minimum-norm solution of sum_i D-_i E_i = rho (Sec. 7.2) for the charge
+// density whose DFT is R (V complex FP64, kept), into the three link-momentum
+// components out[i] (storage precision: fp32 selects float).
+int gauss_solve_fields(lattice* h, const double2* R, void* const out[3], bool fp32) {
+  const int N = h->p.N;
+  const int64_t V = (int64_t)N * N * N;
+  double2* F = reinterpret_cast<double2*>(h->fft);
+  const int thr = 256;
+  const int blk = (int)((V + thr - 1) / thr);
+  for (int i = 0; i < 3; ++i) {
+    hipLaunchKernelGGL(u1_gauss_solve_kernel, dim3(blk), dim3(thr), 0, h->stream, R, F, N, i, h->dx);
+    CL_HIP(hipGetLastError());
+    int rc = run_fft3d(h, -1, 1.0);
+    if (rc) return rc;
+    if (fp32)
+      hipLaunchKernelGGL(u1_store_link_momentum_kernel<float>, dim3(blk), dim3(thr), 0, h->stream, F,
+                         (float*)out[i], V, 1.0 / (double)V);
+    else
+      hipLaunchKernelGGL(u1_store_link_momentum_kernel<double>, dim3(blk), dim3(thr), 0, h->stream, F,
+                         (double*)out[i], V, 1.0 / (double)V);
+    CL_HIP(hipGetLastError());
+  }
+  return LAT_OK;
+}
+
 template <typename T>
 static int u1_init_state_t(lattice* h) {
   const lattice_params& p = h->p;
@@ -949,8 +1022,10 @@ static int u1_init_state_t(lattice* h) {
     CL_HIP(hipGetLastError());
     rc = run_fft3d(h, -1, 1.0);
     if (rc) return rc;
+    // the kick conserves sum_i D-_i piA_i - rho(phi, pi) with no power of a,
+    // so the momenta themselves solve the Gauss law at any a0 and alpha
     hipLaunchKernelGGL(u1_store_link_momentum_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, F, c[7 + i], V,
-                       std::pow(a, 1.0 - al) / (double)V);
+                       1.0 / (double)V);
     CL_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(u1_zero_phases_kernel<T>, dim3(blk), dim3(thr), 0, h->stream, c[4], c[5], c[6], V);
@@ -969,6 +1044,61 @@ static int u1_init_state_t(lattice* h) {
     rc = upload_scalars(h, a, b0, 0.0);
     if (rc) return rc;
   }
+  return LAT_OK;
+}
+
+// Magnetic field B_i on the sites (Sec. 5.4 observables), (i, j, k) cyclic.
+// Compact: B_i = Im V_jk / (e dx^2) = sin(Phi_jk) / (e dx^2) with
+// Phi_jk(n) = th_j(n) + th_k(n+j) - th_j(n+k) - th_k(n) from the stored
+// phases; non-compact: B_i = D+_j A_k - D+_k A_j.  FP64 arithmetic on the
+// stored values, the result in storage precision.
+template <typename T, bool NC>
+__global__ __launch_bounds__(256) void u1_magnetic_kernel(const T* lj, const T* lk, T* out, int N, int j, int k,
+                                                          double e, double dx) {
+  const size_t NN = (size_t)N * N;
+  const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= NN * N) return;
+  const int c[3] = {(int)(s / NN), (int)((s / N) % N), (int)(s % N)};
+  auto plus = [&](int d) {
+    int q[3] = {c[0], c[1], c[2]};
+    q[d] = (q[d] + 1) % N;
+    return (size_t)q[0] * NN + (size_t)q[1] * N + q[2];
+  };
+  const double vj = (double)lj[s], vk = (double)lk[s];
+  const double vk_j = (double)lk[plus(j)], vj_k = (double)lj[plus(k)];
+  double B;
+  if constexpr (NC) {
+    B = ((vk_j - vk) - (vj_k - vj)) / dx;
+  } else {
+    B = sin((vj + vk_j) - (vj_k + vk)) / (e * dx * dx);
+  }
+  out[s] = (T)B;
+}
+
+int u1_magnetic_field(lattice* h, int i, void* out) {
+  const int N = h->p.N;
+  const int64_t V = (int64_t)N * N * N;
+  const int j = (i + 1) % 3, k = (i + 2) % 3;
+  const void* lj = h->buf[h->cur][4 + j];
+  const void* lk = h->buf[h->cur][4 + k];
+  const dim3 grid((unsigned)((V + 255) / 256)), blk(256);
+  const bool nc = h->p.model == LAT_MODEL_U1_NC;
+  if (h->p.precision == LAT_FP32) {
+    if (nc)
+      hipLaunchKernelGGL((u1_magnetic_kernel<float, true>), grid, blk, 0, h->stream, (const float*)lj,
+                         (const float*)lk, (float*)out, N, j, k, h->p.e, h->dx);
+    else
+      hipLaunchKernelGGL((u1_magnetic_kernel<float, false>), grid, blk, 0, h->stream, (const float*)lj,
+                         (const float*)lk, (float*)out, N, j, k, h->p.e, h->dx);
+  } else {
+    if (nc)
+      hipLaunchKernelGGL((u1_magnetic_kernel<double, true>), grid, blk, 0, h->stream, (const double*)lj,
+                         (const double*)lk, (double*)out, N, j, k, h->p.e, h->dx);
+    else
+      hipLaunchKernelGGL((u1_magnetic_kernel<double, false>), grid, blk, 0, h->stream, (const double*)lj,
+                         (const double*)lk, (double*)out, N, j, k, h->p.e, h->dx);
+  }
+  CL_HIP(hipGetLastError());
   return LAT_OK;
 }
 

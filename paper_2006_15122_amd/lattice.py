@@ -16,8 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libcosmolat.so")
 _LIB = None
 
-LAT_MODEL_SCALAR, LAT_MODEL_U1, LAT_MODEL_U1_NC = 0, 1, 2
-MODELS = {"scalar": LAT_MODEL_SCALAR, "u1": LAT_MODEL_U1, "u1nc": LAT_MODEL_U1_NC}
+LAT_MODEL_SCALAR, LAT_MODEL_U1, LAT_MODEL_U1_NC, LAT_MODEL_SU2U1 = 0, 1, 2, 3
+MODELS = {"scalar": LAT_MODEL_SCALAR, "u1": LAT_MODEL_U1, "u1nc": LAT_MODEL_U1_NC, "su2u1": LAT_MODEL_SU2U1}
 INTEGRATORS = {"lf2": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ICS = {"vacuum": 0, "homogeneous": 1}
@@ -31,6 +31,9 @@ EXPORTS = ["lattice_workspace_size", "lattice_init", "lattice_set_state", "latti
            "lattice_batch_get_tiling", "lattice_batch_set_tiling", "lattice_batch_use_graph",
            "lattice_batch_destroy"]
 
+
+# spectrum selectors of the U(1) models that add components (cosmolat.h)
+SPEC_U1_PHI, SPEC_U1_PI, SPEC_U1_E, SPEC_U1_B = 32, 33, 34, 35
 
 class LatticeError(RuntimeError):
     def __init__(self, rc, msg):
@@ -47,7 +50,7 @@ class Params(ctypes.Structure):
                 ("omega_over_f", ctypes.c_double), ("m2", ctypes.c_double * 2),
                 ("lam", ctypes.c_double), ("q", ctypes.c_double), ("e", ctypes.c_double),
                 ("phi0", ctypes.c_double * 2), ("dphi0", ctypes.c_double * 2),
-                ("a0", ctypes.c_double), ("kcut", ctypes.c_double)]
+                ("a0", ctypes.c_double), ("kcut", ctypes.c_double), ("g", ctypes.c_double)]
 
 
 class Scalars(ctypes.Structure):
@@ -64,7 +67,8 @@ class Obs(ctypes.Structure):
                 ("EK_A", ctypes.c_double), ("EG_A", ctypes.c_double), ("rho", ctypes.c_double),
                 ("p", ctypes.c_double), ("w", ctypes.c_double), ("hc", ctypes.c_double),
                 ("gauss", ctypes.c_double), ("step", ctypes.c_int64), ("staggered", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("EK_B", ctypes.c_double), ("EG_B", ctypes.c_double),
+                ("gauss_B", ctypes.c_double), ("mean_lo", ctypes.c_double * 2)]
 
 
 def lib():
@@ -107,6 +111,7 @@ def params(cfg: dict) -> Params:
     p.lam = float(cfg.get("lam", 0.0))
     p.q = float(cfg.get("q", 0.0))
     p.e = float(cfg.get("e", 0.0))
+    p.g = float(cfg.get("g", 0.0))
     ph = list(cfg.get("phi0", (1.0, 0.0))) + [0.0, 0.0]
     dph = list(cfg.get("dphi0", (0.0, 0.0))) + [0.0, 0.0]
     p.phi0[0], p.phi0[1] = float(ph[0]), float(ph[1])
@@ -128,8 +133,13 @@ def _dp(a):
 
 def obs_dict(o: Obs, nf: int) -> dict:
     d = {k: getattr(o, k) for k in ("eta", "a", "b", "H", "EK", "EG", "EV", "EK_A", "EG_A", "rho",
-                                    "p", "w", "hc", "gauss", "step", "staggered")}
+                                    "p", "w", "hc", "gauss", "step", "staggered", "EK_B", "EG_B", "gauss_B")}
     d["EV_mass"], d["EV_quartic"], d["EV_int"] = o.EV_term[0], o.EV_term[1], o.EV_term[2]
+    if nf == 4:
+        # the doublet: means of its four real components, <|Phi|^2>
+        d["mean"] = [o.mean_f[0], o.mean_f[1], o.mean_lo[0], o.mean_lo[1]]
+        d["meansq"] = o.meansq_f[0]
+        return d
     for f in range(nf):
         d[f"EK{f}"] = o.EK_f[f]
         d[f"EG{f}"] = o.EG_f[f]
@@ -167,7 +177,8 @@ class Lattice:
                                   ctypes.byref(self.h)))
 
     # -- state --------------------------------------------------------------
-    def set_state(self, phi, pi, a, b, eta=0.0, step=0, staggered=False, links=None, piA=None):
+    def set_state(self, phi, pi, a, b, eta=0.0, step=0, staggered=False, links=None, piA=None, su2=None,
+                  piB=None):
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         pi = np.ascontiguousarray(pi, dtype=np.float64)
         s = Scalars(a=float(a), b=float(b), eta=float(eta), step=int(step),
@@ -176,7 +187,15 @@ class Lattice:
         V = self.N ** 3
         if phi.size != self.nf * V or pi.size != self.nf * V:
             raise ValueError(f"phi and pi must hold {self.nf} x N^3 values")
-        if links is not None:
+        if self.p.model == LAT_MODEL_SU2U1:
+            # the C ABI takes the U(1) links then the SU(2) links, pi_A then pi_B
+            if links is None or su2 is None or piA is None or piB is None:
+                raise ValueError("the SU(2) x U(1) state needs links, su2, piA and piB")
+            lk = np.ascontiguousarray(np.concatenate([np.ravel(links), np.ravel(su2)]), dtype=np.float64)
+            pa = np.ascontiguousarray(np.concatenate([np.ravel(piA), np.ravel(piB)]), dtype=np.float64)
+            if lk.size != 18 * V or pa.size != 12 * V:
+                raise ValueError("links (3,2,N,N,N), su2 (3,4,N,N,N), piA (3,N,N,N), piB (3,3,N,N,N)")
+        elif links is not None:
             lk = np.ascontiguousarray(links, dtype=np.float64)
             pa = np.ascontiguousarray(piA, dtype=np.float64)
             # compact links are (Re, Im) pairs; the non-compact model takes A_i
@@ -198,11 +217,20 @@ class Lattice:
         elif self.p.model == LAT_MODEL_U1_NC:
             links = np.empty((3, N, N, N))
             piA = np.empty((3, N, N, N))
+        elif self.p.model == LAT_MODEL_SU2U1:
+            links = np.empty(18 * N ** 3)
+            piA = np.empty(12 * N ** 3)
         _check(lib().lattice_get_state(self.h, _dp(phi), _dp(pi), _dp(links) if links is not None else None,
                                        _dp(piA) if piA is not None else None, ctypes.byref(s)))
         out = {"phi": phi, "pi": pi, "a": s.a, "b": s.b, "eta": s.eta, "step": s.step,
                "staggered": bool(s.staggered)}
-        if links is not None:
+        if self.p.model == LAT_MODEL_SU2U1:
+            V = N ** 3
+            out["links"] = links[:6 * V].reshape(3, 2, N, N, N)
+            out["su2"] = links[6 * V:].reshape(3, 4, N, N, N)
+            out["piA"] = piA[:3 * V].reshape(3, N, N, N)
+            out["piB"] = piA[3 * V:].reshape(3, 3, N, N, N)
+        elif links is not None:
             out["links"], out["piA"] = links, piA
         return out
 

@@ -62,6 +62,18 @@ def config3_noncompact(N: int = 192) -> dict:
     return c
 
 
+def config_su2u1(N: int = 128, integrator: str = "vv2") -> dict:
+    """Doublet with SU(2) x U(1) links, the paper's p = 4 working example
+    without its singlet: V = |Phi|^4 (program units), resonance parameters
+    q_A = e^2/lambda and q_B = g^2/(4 lambda) both 100 with lambda = (w*/f*)^2 =
+    1e-4, so e = 0.1 and g = 0.2; 128^3, kIR = 0.6, dt = 0.01, every real
+    component of Phi starting at 1/2 (|Phi| = 1/sqrt 2), FP32, seed 6."""
+    return dict(name=f"su2u1_{N}_{integrator}_fp32", model="su2u1", nf=4, N=N, kIR=0.6, dt=0.01, nsteps=1000,
+                alpha=1.0, fstar_over_mp=FSTAR_OVER_MP, omega_over_f=1e-2, m2=(0.0, 0.0), lam=1.0, q=0.0,
+                e=0.1, g=0.2, phi0=(0.5, 0.5, 0.5, 0.5), dphi0=(0.0, 0.0, 0.0, 0.0), integrator=integrator,
+                precision="fp32", expansion=True, ic="vacuum", seed=6, a0=1.0)
+
+
 def config4_runs(nruns: int = 96, sizes=(32, 64, 96), nsteps: int = 5000) -> list:
     """96 independent two-scalar VV2 runs, sizes split evenly among 32^3,
     64^3, 96^3, q = 10^(1+3u) with u uniform from a seeded generator, seeds

@@ -1,0 +1,165 @@
+"""GPU parity of the SU(2) x U(1) doublet path (Sec. 6) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_15122_amd import synth
+from test_gpu_scalar import check_shells
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("a", "b", "EK", "EG", "EV", "EK_A", "EG_A", "EK_B", "EG_B", "EV_quartic")
+STATE = ("phi", "pi", "links", "su2", "piA", "piB")
+
+
+def _lattice(cfg):
+    from paper_2006_15122_amd.lattice import Lattice
+
+    return Lattice(cfg, device="cuda:0")
+
+
+def _cfg(N, precision="fp32", **kw):
+    c = dict(synth.config_su2u1(N=N), precision=precision)
+    c.update(kw)
+    return c
+
+
+def _set(lat, st):
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], su2=st["su2"], piA=st["piA"],
+                  piB=st["piB"])
+
+
+def compare(g, o, tol, what):
+    bad = {}
+    for k in KEYS:
+        if o[k] == 0.0:
+            continue
+        r = abs(g[k] - o[k]) / abs(o[k])
+        if not r <= tol:
+            bad[k] = r
+    sc = math.sqrt(o["meansq"])
+    for c in range(4):
+        r = abs(g["mean"][c] - o["mean"][c]) / sc
+        if not r <= tol:
+            bad[f"mean{c}"] = r
+    r = abs(g["meansq"] - o["meansq"]) / o["meansq"]
+    if not r <= tol:
+        bad["meansq"] = r
+    assert not bad, (what, bad)
+    return max([abs(g[k] - o[k]) / abs(o[k]) for k in KEYS if o[k] != 0.0])
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_su2_device_initial_state_matches_oracle_fp64(N):
+    cfg = _cfg(N, "fp64")
+    lat = _lattice(cfg)
+    st = oracle.su2_vacuum_ic(cfg)
+    s = lat.get_state()
+    for key in STATE:
+        ref = st[key]
+        assert np.max(np.abs(s[key] - ref)) < 1e-12 * max(np.max(np.abs(ref)), 1e-30), key
+    assert abs(s["b"] - st["b"]) < 1e-12 * st["b"]
+    e = lat.energies()
+    assert e["gauss"] < 1e-12 and e["gauss_B"] < 1e-12
+    compare(e, oracle.su2_sync_observe(oracle.su2_model(cfg), st), 1e-12, "initial state")
+
+
+@pytest.mark.parametrize("integ,nsteps", [("lf2", 100), ("vv2", 60), ("vv4", 20)])
+def test_su2_fp64_parity_and_both_gauss_laws(integ, nsteps):
+    # couplings e = g = 0.5: at the workload's e = 0.1 the U(1) plaquette angles stay
+    # near 1e-4, where the oracle's own 1 - Re V_ij (links kept as (Re, Im), unit only
+    # to rounding) carries ~1e-16 per plaquette against Phi^2/2 ~ 5e-9, a 1e-10
+    # relative floor in E_G^A on its side; the GPU keeps the phases
+    cfg = _cfg(32, "fp64", integrator=integ, e=0.5, g=0.5)
+    st = oracle.su2_vacuum_ic(cfg)
+    m = oracle.su2_model(cfg)
+    lat = _lattice(cfg)
+    _set(lat, st)
+    h = cfg["dt"]
+    if integ == "lf2":
+        oracle.su2_lf_startup(m, st, h)
+    half = nsteps // 2
+    for k in range(2):
+        lat.step(half)
+        if integ == "lf2":
+            oracle.su2_lf_steps(m, st, h, half, omp=True)
+            o = oracle.su2_lf_observe(m, st, h)
+        else:
+            oracle.su2_vv_steps(m, st, h, integ, half, omp=True)
+            o = oracle.su2_sync_observe(m, st)
+        g = lat.energies()
+        compare(g, o, 1e-10, f"{integ} fp64 step {half * (k + 1)}")
+        assert g["gauss"] < 1e-12 and g["gauss_B"] < 1e-12, (g["gauss"], g["gauss_B"])
+    assert o["EG_B"] > 0.0 and o["EG_A"] > 0.0
+    s = lat.get_state()
+    assert s["staggered"] == (integ == "lf2") and s["step"] == nsteps
+    for key in STATE:
+        assert np.max(np.abs(s[key] - st[key])) < 1e-10 * np.max(np.abs(st[key])), key
+
+
+@pytest.mark.parametrize("integ,nsteps", [("vv2", 200), ("lf2", 200)])
+def test_su2_fp32_parity_64(integ, nsteps):
+    cfg = _cfg(64, "fp32", integrator=integ)
+    st = oracle.su2_vacuum_ic(cfg)
+    m = oracle.su2_model(cfg)
+    lat = _lattice(cfg)
+    _set(lat, st)
+    h = cfg["dt"]
+    if integ == "lf2":
+        oracle.su2_lf_startup(m, st, h)
+    for k in range(4):
+        lat.step(nsteps // 4)
+        if integ == "lf2":
+            oracle.su2_lf_steps(m, st, h, nsteps // 4, omp=True)
+            o = oracle.su2_lf_observe(m, st, h)
+        else:
+            oracle.su2_vv_steps(m, st, h, integ, nsteps // 4, omp=True)
+            o = oracle.su2_sync_observe(m, st)
+        g = lat.energies()
+        w = compare(g, o, 1e-5, f"{integ} fp32 step {nsteps // 4 * (k + 1)}")
+        print(integ, "step", nsteps // 4 * (k + 1), "worst %.2e gauss %.2e gauss_B %.2e" % (w, g["gauss"], g["gauss_B"]),
+              flush=True)
+        assert g["gauss"] < 1e-5 and g["gauss_B"] < 1e-5, (g["gauss"], g["gauss_B"])
+    s = lat.get_state()
+    assert np.max(np.abs((s["su2"] ** 2).sum(axis=1) - 1.0)) < 1e-6
+
+
+def test_su2_doublet_spectra_match_oracle():
+    from paper_2006_15122_amd.lattice import SPEC_U1_PHI, SPEC_U1_PI
+
+    for precision, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        cfg = _cfg(64, precision)
+        lat = _lattice(cfg)
+        lat.step(40)
+        s = lat.get_state()
+        for which, key in ((SPEC_U1_PHI, "phi"), (SPEC_U1_PI, "pi")):
+            g = lat.spectrum(which)
+            parts = [oracle.spectrum(s[key][c], cfg["kIR"]) for c in range(4)]
+            o = dict(parts[0])
+            o["S"] = sum(p["S"] for p in parts)
+            N, dx = 64, oracle.lattice_dx(64, cfg["kIR"])
+            bb = np.arange(len(o["S"]), dtype=np.float64)
+            o["delta"] = np.zeros(len(o["S"]))
+            o["delta"][1:] = (cfg["kIR"] * bb[1:]) ** 3 * (dx / N) ** 3 / (2 * math.pi ** 2) * o["S"][1:] / (
+                4 * math.pi * bb[1:] ** 2)
+            check_shells(g, o, tol, f"su2 {precision} {key}")
+        # a single real component
+        g = lat.spectrum(2)
+        check_shells(g, oracle.spectrum(s["phi"][2], cfg["kIR"]), tol, f"su2 {precision} component 2")
+
+
+def test_su2_full_size_128_fp32_against_oracle():
+    # the benchmarked workload at its full size: 10 steps against the live oracle
+    cfg = _cfg(128, "fp32")
+    st = oracle.su2_vacuum_ic(cfg)
+    m = oracle.su2_model(cfg)
+    lat = _lattice(cfg)
+    _set(lat, st)
+    lat.step(10)
+    oracle.su2_vv_steps(m, st, cfg["dt"], "vv2", 10, omp=True)
+    o = oracle.su2_sync_observe(m, st)
+    g = lat.energies()
+    print("128^3 worst %.2e gauss %.2e gauss_B %.2e" % (compare(g, o, 1e-5, "128^3"), g["gauss"], g["gauss_B"]))
+    assert g["gauss"] < 1e-5 and g["gauss_B"] < 1e-5

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from paper_2006_15122_amd import synth
+from test_gpu_scalar import check_shells
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +86,28 @@ def test_u1_fp64_parity_and_gauss_200_steps():
         assert np.max(np.abs(s[key] - st[key])) < 1e-10 * np.max(np.abs(st[key])), key
 
 
-def test_u1_fp32_parity_64_400_steps():
+def _control(case):
+    """Per-checkpoint errors of FP32 storage alone (FP64 oracle, state rounded
+    to FP32 after every step) and of one FP32 rounding of the initial state,
+    written by tests/golden/make_fp32_control.py."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fp32_control_{case}.json")
+    with open(path) as f:
+        return {cp["step"]: cp for cp in json.load(f)["checkpoints"]}
+
+
+def in_window(ctl_step):
+    """Trajectory parity is gated at 1e-5 where FP32 storage alone (the
+    control) stays below 1e-6 on every observable: a decade below the gate,
+    since the FP32 arithmetic of a kernel adds rounding of the same order.
+    Past that point the resonant growth of the fields amplifies any rounding
+    a hundredfold per 100 steps and no FP32 run can follow the FP64 one."""
+    return max(v for k, v in ctl_step["storage"].items() if k != "gauss") < 1e-6
+
+
+def test_config3_fp32_64_parity_window_and_gauss_every_100_steps():
     cfg = _cfg(64, "fp32")
     st = oracle.u1_vacuum_ic(cfg)
     m = oracle.u1_model(cfg)
@@ -93,20 +115,28 @@ def test_u1_fp32_parity_64_400_steps():
     lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
     h = cfg["dt"]
     oracle.u1_lf_startup(m, st, h)
-    # Every observable within 1e-5 through 300 steps.  By step 400 expansion has
-    # redshifted the fluctuations so far that the covariant differences
-    # V phi_{+i} - phi and the current Im[conj(phi) V phi_{+i}] cancel against
-    # the homogeneous condensate: FP32 rounding of the stored phi (6e-8 |phi|)
-    # then shows as ~1e-5 relative error in E_G^phi (measured 1.2e-5) and in
-    # E_K^A, E_G^A (measured 2.7e-5).  At that checkpoint the tolerances are
-    # 2e-5 (scalar sector) and 5e-5 (gauge energies).
-    for k in range(4):
+    ctl = _control("u1higgs_64_lf2")
+    gmax, gated = 0.0, 0
+    for k in range(10):
+        step = 100 * (k + 1)
         lat.step(100)
         oracle.u1_lf_steps(m, st, h, 100, omp=True)
         o = oracle.u1_lf_observe(m, st, h)
         g = lat.energies()
-        compare(g, o, 1e-5 if k < 3 else 2e-5, f"fp32 step {100 * (k + 1)}", gauge_tol=1e-5 if k < 3 else 5e-5)
-        assert g["gauss"] < 1e-5, g["gauss"]
+        errs = {key: abs(g[key] - o[key]) / abs(o[key]) for key in KEYS if o[key] != 0.0}
+        print(f"step {step}: gauss {g['gauss']:.2e} (FP32-storage control {ctl[step]['storage']['gauss']:.2e}); "
+              + " ".join(f"{key} {v:.1e}" for key, v in errs.items()), flush=True)
+        if in_window(ctl[step]):
+            compare(g, o, 1e-5, f"fp32 step {step}")
+            gated += 1
+        assert errs["a"] < 1e-6, (step, errs["a"])
+        # the Gauss residual of an FP32 state cannot fall below what storing
+        # phi, pi, pi_A and the link phases in FP32 leaves; FP32 storage alone
+        # (FP64 arithmetic) gives the control's residual, and the GPU path
+        # must stay within 2x of its largest value so far
+        gmax = max(gmax, ctl[step]["storage"]["gauss"])
+        assert g["gauss"] < 2.0 * gmax, (step, g["gauss"], gmax)
+    assert gated >= 3
 
 
 def test_u1_every_tiling_agrees():
@@ -133,26 +163,59 @@ def test_u1_every_tiling_agrees():
     assert n == 8
 
 
-def test_u1_full_size_192_sampled_sites():
+def _golden(case):
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"full_size_{case}.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_config3_full_size_192_1000_steps():
+    # config 3 at its full size and length against the oracle's stored run
+    # (tests/golden/make_full_size.py), re-checked here with the live oracle at
+    # its initial state and step 5.  At 192^3 the vacuum energy drives a fast
+    # expansion and the resonance amplifies rounding sooner than at 64^3: FP32
+    # storage alone departs from the FP64 run by 4.3e-7 at step 80 and 1.2e-5
+    # at step 100 (tests/golden/fp32_control_u1higgs_192_lf2.json), so the
+    # observables are gated while that control stays below 1e-6, and a and
+    # the Gauss residual at every checkpoint to step 1000.
+    gold = _golden("u1higgs_192_lf2")
+    ctl = _control("u1higgs_192_lf2")
     cfg = _cfg(192, "fp32")
+    assert gold["config"]["N"] == 192 and gold["config"]["seed"] == cfg["seed"]
     st = oracle.u1_vacuum_ic(cfg)
     m = oracle.u1_model(cfg)
+    o0 = oracle.u1_sync_observe(m, st)
+    cps = {cp["step"]: cp["obs"] for cp in gold["checkpoints"]}
+    for key in KEYS:
+        assert abs(o0[key] - cps[0][key]) <= 1e-12 * abs(cps[0][key]), key
     lat = _lattice(cfg)
     lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
     h = cfg["dt"]
-    lat.step(3)
     oracle.u1_lf_startup(m, st, h)
-    oracle.u1_lf_steps(m, st, h, 3, omp=True)
-    o = oracle.u1_lf_observe(m, st, h)
-    g = lat.energies()
-    compare(g, o, 1e-5, "192^3")
-    assert g["gauss"] < 1e-5
-    s = lat.get_state()
-    rng = np.random.default_rng(1)
-    for key, nc in (("phi", 2), ("pi", 2), ("piA", 3)):
-        idx = (rng.integers(0, nc, 4096),) + tuple(rng.integers(0, 192, (3, 4096)))
-        d = np.abs(s[key][idx] - st[key][idx])
-        assert np.max(d) < 2e-5 * np.max(np.abs(st[key][idx])), key
+    oracle.u1_lf_steps(m, st, h, 5, omp=True)
+    o5 = oracle.u1_lf_observe(m, st, h)
+    for key in KEYS:
+        if cps[5][key] != 0.0:
+            assert abs(o5[key] - cps[5][key]) <= 1e-12 * abs(cps[5][key]), key
+    lat.step(5)
+    compare(lat.energies(), o5, 1e-5, "192^3 step 5")
+    done, gated, gmax = 5, 0, max(cp["storage"]["gauss"] for cp in ctl.values())
+    for step in sorted(k for k in cps if k > 5):
+        lat.step(step - done)
+        done = step
+        g, o = lat.energies(), cps[step]
+        errs = {key: abs(g[key] - o[key]) / abs(o[key]) for key in KEYS if o[key] != 0.0}
+        print(f"192^3 step {step}: gauss {g['gauss']:.2e} "
+              + " ".join(f"{key} {v:.1e}" for key, v in errs.items()), flush=True)
+        if step in ctl and in_window(ctl[step]):
+            compare(g, o, 1e-5, f"192^3 step {step}")
+            gated += 1
+        assert errs["a"] < 1e-6, (step, errs["a"])
+        assert g["gauss"] < 2.0 * gmax, (step, g["gauss"], gmax)
+    assert gated >= 4 and done == 1000
 
 
 def test_u1_device_init_fp32_gauss_and_energy_budget():
@@ -173,8 +236,7 @@ def test_u1_spectrum_matches_oracle():
     for which, arr in ((0, s["phi"][0]), (1, s["phi"][1]), (16, s["pi"][0])):
         g = lat.spectrum(which)
         o = oracle.spectrum(arr, cfg["kIR"])
-        assert np.array_equal(g["count"], o["count"])
-        assert np.max(np.abs(g["S"] - o["S"])) < 1e-10 * np.max(o["S"])
+        check_shells(g, o, 1e-10, f"u1 fp64 which={which}")
 
 
 @pytest.mark.parametrize("N,precision,tol", [(32, "fp64", 1e-12), (64, "fp32", 1e-5), (96, "fp32", 1e-5)])
@@ -238,3 +300,60 @@ def test_u1_velocity_verlet_parity(integ, N, precision, tol, nsteps):
     if precision == "fp64":
         for key in ("phi", "pi", "links", "piA"):
             assert np.max(np.abs(s[key] - st[key])) < tol * np.max(np.abs(st[key])), key
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5])
+def test_u1_initial_gauss_law_at_a0_not_one(alpha):
+    # the kicks conserve sum_i D-_i piA_i - rho(phi, pi) with no power of a, so
+    # the device initial state must solve exactly that at a0 != 1 (Sec. 7.2)
+    cfg = _cfg(32, "fp64", alpha=alpha, a0=2.0)
+    lat = _lattice(cfg)
+    st = oracle.u1_vacuum_ic(cfg)
+    s = lat.get_state()
+    for key in ("phi", "pi", "piA"):
+        assert np.max(np.abs(s[key] - st[key])) < 1e-12 * np.max(np.abs(st[key])), key
+    assert lat.energies()["gauss"] < 1e-12
+    lat.step(20)
+    assert lat.energies()["gauss"] < 1e-12
+    v = _lattice(dict(cfg, integrator="vv2"))
+    v.step(20)
+    assert v.energies()["gauss"] < 1e-12
+
+
+@pytest.mark.parametrize("integ", ["vv6", "vv8", "vv10"])
+def test_u1_high_order_yoshida_fp64_parity(integ):
+    # compact U(1) Yoshida VV6, VV8, VV10 (Sec. 5.3.3): 7, 15, 31 fused passes per step
+    cfg = _cfg(32, "fp64", integrator=integ)
+    st = oracle.u1_vacuum_ic(cfg)
+    m = oracle.u1_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"], links=st["links"], piA=st["piA"])
+    n = {"vv6": 12, "vv8": 6, "vv10": 3}[integ]
+    lat.step(n)
+    oracle.u1_vv_steps(m, st, cfg["dt"], integ, n, omp=True)
+    compare(lat.energies(), oracle.u1_sync_observe(m, st), 1e-10, integ)
+    assert lat.energies()["gauss"] < 1e-12
+    s = lat.get_state()
+    for key in ("phi", "pi", "links", "piA"):
+        assert np.max(np.abs(s[key] - st[key])) < 1e-10 * np.max(np.abs(st[key])), key
+
+
+@pytest.mark.parametrize("model,precision", [("u1", "fp64"), ("u1", "fp32"), ("u1nc", "fp64"), ("u1nc", "fp32")])
+def test_u1_field_spectra_match_oracle(model, precision):
+    # the complex scalar, its momentum, E and B spectra (Sec. 5.4.2) of a
+    # state 150 steps in (B != 0), against the oracle on the same stored
+    # state, shell by shell
+    from paper_2006_15122_amd.lattice import SPEC_U1_B, SPEC_U1_E, SPEC_U1_PHI, SPEC_U1_PI
+
+    cfg = _cfg(64, precision, model=model, alpha=0.5)
+    lat = _lattice(cfg)
+    lat.step(150)
+    s = lat.get_state()
+    st = {k: s[k] for k in ("phi", "pi", "links", "piA")}
+    st["a"] = s["a"]
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for which, name in ((SPEC_U1_PHI, "phi"), (SPEC_U1_PI, "pi"), (SPEC_U1_E, "E"), (SPEC_U1_B, "B")):
+        g = lat.spectrum(which)
+        o = oracle.u1_spectrum(cfg, st, name)
+        check_shells(g, o, tol, f"{model} {precision} {name}")
+    assert o["S"][1:].max() > 0  # B has power by then
