@@ -114,7 +114,7 @@ def time_batch(steps: int) -> dict:
     e1.record(B.stream)
     B.synchronize()
     ms_b = e0.elapsed_time(e1)
-    seq_steps = max(steps // 5, 4)
+    seq_steps = steps                  # the same steps per run as the batched leg
     with torch.cuda.stream(B.stream):
         for r in B.runs:               # warm the single-lattice kernels
             r.step(1)
@@ -172,9 +172,9 @@ def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
 
 
 def time_spectrum(N: int = 256, reps: int = 10) -> dict:
-    """One power spectrum of a 256^3 FP32 field (Sec. 3.1): complex FP64 3D FFT,
-    shell binning and the log-k interpolation, all queued on the lattice's
-    stream and timed there with HIP events."""
+    """One power spectrum of a 256^3 FP32 field (Sec. 3.1): the stored FP32
+    values through an FP64 3D FFT, shell binning and the log-k interpolation,
+    all queued on the lattice's stream and timed there with HIP events."""
     import torch
 
     from paper_2006_15122_amd import synth
@@ -196,29 +196,48 @@ def time_spectrum(N: int = 256, reps: int = 10) -> dict:
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    # algorithmic HBM bytes per spectrum of the three line passes, which run
-    # in the field's FP32 precision: the z pass reads the field (4) and writes
-    # the complex volume (8), the y pass reads and writes it (16), the x pass
-    # reads it (8) and bins in LDS (FP64 sums)
-    per_site = 4 + 8 + 16 + 8
+    # algorithmic HBM bytes per spectrum of the three line passes (complex
+    # FP64): the z pass reads the FP32 field (4) and writes the complex volume
+    # (16), the y pass reads and writes it (32), the x pass reads it (16) and
+    # bins in LDS (FP64 sums)
+    per_site = 4 + 16 + 32 + 16
     return {"N": N, "ms_per_spectrum": ms, "spectra_per_s": 1e3 / ms, "bytes_per_site": per_site,
             "hbm_frac": N ** 3 * per_site / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
-def cpu_baseline(cfg: dict, nsteps: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg: dict, nsteps: int, st_steps: int) -> dict:
+    """The FP64 oracle on the host cores: its OpenMP build over nsteps and its
+    single-thread build over st_steps of the same workload."""
     import oracle
 
     st = oracle.vacuum_ic(cfg)
     m = oracle.scalar_model(cfg)
-    phi, pi = st["phi"], st["pi"]
+    N = cfg["N"]
+    phi, pi = st["phi"].copy(), st["pi"].copy()
     t0 = time.perf_counter()
     oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], cfg["integrator"], nsteps, omp=True)
     dt = time.perf_counter() - t0
-    N = cfg["N"]
+    phi, pi = st["phi"], st["pi"]
+    t1 = time.perf_counter()
+    oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], cfg["integrator"], st_steps, omp=False)
+    dt1 = time.perf_counter() - t1
     return {"value": N ** 3 * nsteps / dt, "unit": "site-updates/s", "cores": int(oracle.lib(True).orc_num_threads()),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"FP64 oracle (C, OpenMP over x-planes), {cfg['integrator'].upper()}, {N}^3, two fields, "
-                      f"{nsteps} steps from the seeded initial state, {dt:.1f} s"}
+                      f"{nsteps} steps from the seeded initial state, {dt:.1f} s",
+            "single_thread": {"value": N ** 3 * st_steps / dt1, "unit": "site-updates/s", "cores": 1,
+                              "sample": f"the same oracle built without OpenMP, {st_steps} steps, {dt1:.1f} s"}}
 
 
 def main():
@@ -229,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps-single", type=int, default=8)
     ap.add_argument("--tile", default=None,
                     help="tz,by,ry,xc of the main run instead of the autotuner's choice (for counter runs, "
                          "where profiling overhead can change the tuner's pick)")
@@ -340,12 +360,35 @@ def main():
                                   "hbm_frac": n3 * 80 / (ms4 / st3 / 1e3) / 1e9 / HBM_PEAK_GBS,
                                   "ms_per_pass": ms4 / st3, "ms_per_pass_ext_events": k4,
                                   "bytes_per_site_update": 80, "steps": st3, "gauss": obs4["gauss"]}
+        # FP64 storage of the headline workload (the paper's implied precision):
+        # 64 B per site-update
+        c64 = dict(synth.config2(q=100.0, integrator="vv2"), precision="fp64")
+        st64 = max(args.steps // 10, 10)
+        ms64, _, _, t64, k64 = time_lattice(c64, st64, 10, st64 + 1)
+        n64 = c64["N"] ** 3
+        extras["vv2_256_fp64"] = {"site_updates_per_s": n64 * st64 / (ms64 / 1e3),
+                                  "hbm_frac": n64 * 64 / (ms64 / (st64 + 1) / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "ms_per_pass": ms64 / (st64 + 1), "ms_per_pass_ext_events": k64, "tile": t64,
+                                  "bytes_per_site_update": 64, "steps": st64}
+        # SU(2) x U(1) doublet, 128^3, FP32, velocity Verlet: 35 FP32 per site
+        # (Phi 4, pi 4, U(1) phases 3, pi_A 3, SU(2) links 12, pi_B 9) read and
+        # written once per pass = 280 B per site-update; each pass is a drift,
+        # a kick and a finish kernel
+        c5 = synth.config_su2u1()
+        st5 = max(args.steps // 20, 10)
+        ms5, _, obs5, _, k5 = time_lattice(c5, st5, 5, st5 + 1)
+        n5 = c5["N"] ** 3
+        extras["su2u1_128_vv2"] = {"site_updates_per_s": n5 * st5 / (ms5 / 1e3),
+                                   "hbm_frac": n5 * 280 / (ms5 / (st5 + 1) / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                   "ms_per_pass": ms5 / (st5 + 1), "ms_per_kick_kernel": k5,
+                                   "bytes_per_site_update": 280, "steps": st5, "gauss": obs5["gauss"],
+                                   "gauss_B": obs5["gauss_B"]}
         extras["batch_96"] = time_batch(max(args.steps // 10, 20))
         extras["surrogate_predict_65536"] = time_surrogate()
         extras["spectrum_256"] = time_spectrum()
         out["extras"] = extras
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps, args.cpu_steps_single)
     print(json.dumps(out), flush=True)
 
 

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void su2_drift_kernel(Su2Args<T> A) {
 // 4 m2|Phi|^2, 5,6 pi_A, 7 sum_{i<j}(1 - cos Phi_ij), 8,9 pi_B,
 // 10 sum_{i<j}(1 - Re/Tr-half U_ij), 11..14 the four components of Phi, 15 |Phi|^2.
 template <typename T>
-__global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
+__global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
   const int N = A.N;
   const size_t NN = (size_t)N * N, V = NN * N;
   const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -192,24 +192,36 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
   for (int k = 0; k < kSu2Acc; ++k) acc[k] = 0.0;
   if (s < V) {
     const T* const* F = A.fields_in_dst ? const_cast<const T* const*>(A.dst) : A.src;
-    const int c[3] = {(int)(s / NN), (int)((s / N) % N), (int)(s % N)};
-    const size_t str[3] = {NN, (size_t)N, 1};
-    // s + step e_d (periodic)
-    auto nb = [&](size_t base, int d, int step) -> size_t {
-      int cd = (int)((base / str[d]) % N);
-      int nd = cd + step;
-      nd = nd < 0 ? nd + N : (nd >= N ? nd - N : nd);
-      return base + (size_t)((long)(nd - cd) * (long)str[d]);
-    };
-    auto LP = [&](size_t t, Cx2<T> (&p)[2]) {
+    // periodic neighbour offsets, once per thread: sp[d] = n + e_d, sm[d] = n - e_d,
+    // and dg[a][b] = n - e_b + e_a (a != b)
+    // (sites fit in 32 bits: N^3 <= 2^30)
+    const unsigned su = (unsigned)s, n = (unsigned)N, nn = (unsigned)NN;
+    const unsigned c[3] = {su / nn, (su / n) % n, su % n};
+    const unsigned str[3] = {nn, n, 1u};
+    int op[3], om[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      op[d] = c[d] == n - 1 ? -(int)((n - 1) * str[d]) : (int)str[d];
+      om[d] = c[d] == 0 ? (int)((n - 1) * str[d]) : -(int)str[d];
+    }
+    unsigned sp[3], sm[3], dg[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sp[d] = su + op[d];
+      sm[d] = su + om[d];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) dg[a][b] = su + om[b] + op[a];
+    auto LP = [&](unsigned t, Cx2<T> (&p)[2]) {
       p[0] = Cx2<T>{F[kPH][t], F[kPH + 1][t]};
       p[1] = Cx2<T>{F[kPH + 2][t], F[kPH + 3][t]};
     };
-    auto LQ = [&](int i, size_t t) -> Q4<T> {
+    auto LQ = [&](int i, unsigned t) -> Q4<T> {
       return Q4<T>{F[kUL + 4 * i][t], F[kUL + 4 * i + 1][t], F[kUL + 4 * i + 2][t], F[kUL + 4 * i + 3][t]};
     };
-    auto LT = [&](int i, size_t t) -> T { return F[kTH + i][t]; };
-    (void)c;
+    auto LT = [&](int i, unsigned t) -> T { return F[kTH + i][t]; };
 
     const double a_in = A.st->a, b_in = A.st->b;
     const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
@@ -224,7 +236,7 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
     const T lam = (T)A.lam, m2 = (T)A.m2;
 
     Cx2<T> p[2];
-    LP(s, p);
+    LP(su, p);
     // ---- matter: covariant differences in the cancellation-free form
     //   W Phi_+ - Phi = (V - 1) y + (U - 1) Phi_+ + (Phi_+ - Phi),  y = U Phi_+
     //   W(n-i)^dag Phi_- - Phi = (U^dag - 1) y' + (conj V - 1) Phi_- + (Phi_- - Phi),  y' = conj(V) Phi_-
@@ -232,16 +244,15 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
     T eg = T(0), curA[3], curB[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const size_t sp = nb(s, i, 1), sm = nb(s, i, -1);
       Cx2<T> fp[2], fm[2];
-      LP(sp, fp);
-      LP(sm, fm);
+      LP(sp[i], fp);
+      LP(sm[i], fm);
       // forward
-      const Q4<T> u = LQ(i, s);
+      const Q4<T> u = LQ(i, su);
       Cx2<T> um1f[2];
       qapply(u, qw_m1(u), fp, um1f);  // (U - 1) Phi_+
       T sn, cs;
-      sincos_s(LT(i, s), &sn, &cs);
+      sincos_s(LT(i, su), &sn, &cs);
       const Cx2<T> vm1{cs > T(0) ? -sn * sn / (T(1) + cs) : cs - T(1), sn};
       Cx2<T> g[2];
 #pragma unroll
@@ -250,9 +261,9 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
         g[k] = cadd2(cadd2(cmul2(vm1, y), um1f[k]), csub2(fp[k], p[k]));
       }
       // backward
-      const Q4<T> ub = qdag(LQ(i, sm));
+      const Q4<T> ub = qdag(LQ(i, sm[i]));
       T snb, csb;
-      sincos_s(LT(i, sm), &snb, &csb);
+      sincos_s(LT(i, sm[i]), &snb, &csb);
       const Cx2<T> vbm1{csb > T(0) ? -snb * snb / (T(1) + csb) : csb - T(1), -snb};  // conj(V) - 1
       Cx2<T> vf[2], yb[2], ubm1[2];
 #pragma unroll
@@ -276,25 +287,28 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
     const T r2 = p[0].re * p[0].re + p[0].im * p[0].im + p[1].re * p[1].re + p[1].im * p[1].im;
     const T dv = T(2) * lam * r2 + m2;
 
-    // ---- U(1) plaquettes: sin Phi_ab(m), Phi_ab(m) = th_a(m) + th_b(m+a) - th_a(m+b) - th_b(m)
-    auto plA = [&](int a, int b, size_t m, T* om) -> T {
-      const T ph = (LT(a, m) + LT(b, nb(m, a, 1))) - (LT(a, nb(m, b, 1)) + LT(b, m));
+    // ---- U(1) plaquettes: sin Phi_ab(m), Phi_ab(m) = th_a(m) + th_b(m+a) - th_a(m+b) - th_b(m),
+    // at m = n and at m = n - e_q (m + e_a = n when a = q)
+    auto pos = [&](int q, int a) -> unsigned { return a == q ? su : dg[a][q]; };
+    auto plA = [&](int a, int b, int q, T* om1) -> T {
+      const unsigned m = q < 0 ? su : sm[q];
+      const unsigned ma = q < 0 ? sp[a] : pos(q, a), mb = q < 0 ? sp[b] : pos(q, b);
+      const T ph = (LT(a, m) + LT(b, ma)) - (LT(a, mb) + LT(b, m));
       T sh, ch;
       sincos_s(T(0.5) * ph, &sh, &ch);
-      if (om) *om = T(2) * sh * sh;  // 1 - cos Phi
+      if (om1) *om1 = T(2) * sh * sh;  // 1 - cos Phi
       return T(2) * sh * ch;
     };
     T omA[3];
-    const T S01 = plA(0, 1, s, &omA[0]), S02 = plA(0, 2, s, &omA[1]), S12 = plA(1, 2, s, &omA[2]);
-    const size_t sxm = nb(s, 0, -1), sym = nb(s, 1, -1), szm = nb(s, 2, -1);
-    const T curlA[3] = {(S01 - plA(0, 1, sym, nullptr)) + (S02 - plA(0, 2, szm, nullptr)),
-                        (-S01 + plA(0, 1, sxm, nullptr)) + (S12 - plA(1, 2, szm, nullptr)),
-                        (-S02 + plA(0, 2, sxm, nullptr)) + (-S12 + plA(1, 2, sym, nullptr))};
+    const T S01 = plA(0, 1, -1, &omA[0]), S02 = plA(0, 2, -1, &omA[1]), S12 = plA(1, 2, -1, &omA[2]);
+    const T curlA[3] = {(S01 - plA(0, 1, 1, nullptr)) + (S02 - plA(0, 2, 2, nullptr)),
+                        (-S01 + plA(0, 1, 0, nullptr)) + (S12 - plA(1, 2, 2, nullptr)),
+                        (-S02 + plA(0, 2, 0, nullptr)) + (-S12 + plA(1, 2, 1, nullptr))};
 
     // ---- SU(2) plaquettes U_ab(n) = U_a(n) U_b(n+a) U_a(n+b)^dag U_b(n)^dag and the
     // backward ones transported to n (products of three links)
     auto plB = [&](int a, int b) -> Q4<T> {
-      return qmul(qmul(LQ(a, s), LQ(b, nb(s, a, 1))), qdag(qmul(LQ(b, s), LQ(a, nb(s, b, 1)))));
+      return qmul(qmul(LQ(a, su), LQ(b, sp[a])), qdag(qmul(LQ(b, su), LQ(a, sp[b]))));
     };
     const Q4<T> P01 = plB(0, 1), P02 = plB(0, 2), P12 = plB(1, 2);
     T omB = T(0);
@@ -303,18 +317,18 @@ __global__ __launch_bounds__(256) void su2_kick_kernel(Su2Args<T> A) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) omB += -qw_m1(*P[k]);  // 1 - w = (2 - Tr)/2
     }
-    // i = a, plane (a, b), base n - b: U_b(m)^dag U_a(m) U_b(m+a) U_a(n)^dag, m = n - b
-    auto tA = [&](int a, int b, size_t m) -> Q4<T> {
-      return qmul(qmul(qdag(LQ(b, m)), LQ(a, m)), qmul(LQ(b, nb(m, a, 1)), qdag(LQ(a, s))));
+    // i = a, plane (a, b), base m = n - b: U_b(m)^dag U_a(m) U_b(m+a) U_a(n)^dag
+    auto tA = [&](int a, int b) -> Q4<T> {
+      return qmul(qmul(qdag(LQ(b, sm[b])), LQ(a, sm[b])), qmul(LQ(b, dg[a][b]), qdag(LQ(a, su))));
     };
-    // i = b, plane (a, b), base n - a: U_b(n) U_a(m+b)^dag U_b(m)^dag U_a(m), m = n - a
-    auto tB = [&](int a, int b, size_t m) -> Q4<T> {
-      return qmul(qmul(LQ(b, s), qdag(LQ(a, nb(m, b, 1)))), qmul(qdag(LQ(b, m)), LQ(a, m)));
+    // i = b, plane (a, b), base m = n - a: U_b(n) U_a(m+b)^dag U_b(m)^dag U_a(m)
+    auto tB = [&](int a, int b) -> Q4<T> {
+      return qmul(qmul(LQ(b, su), qdag(LQ(a, dg[b][a]))), qmul(qdag(LQ(b, sm[a])), LQ(a, sm[a])));
     };
     T magB[3][3];
     {
-      const Q4<T> t01 = tA(0, 1, sym), t02 = tA(0, 2, szm), t12 = tA(1, 2, szm);
-      const Q4<T> r01 = tB(0, 1, sxm), r02 = tB(0, 2, sxm), r12 = tB(1, 2, sym);
+      const Q4<T> t01 = tA(0, 1), t02 = tA(0, 2), t12 = tA(1, 2);
+      const Q4<T> r01 = tB(0, 1), r02 = tB(0, 2), r12 = tB(1, 2);
       // i = 0: [c(P01) - c(t01)] + [c(P02) - c(t02)]
       magB[0][0] = (P01.x - t01.x) + (P02.x - t02.x);
       magB[0][1] = (P01.y - t01.y) + (P02.y - t02.y);
