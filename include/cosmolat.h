@@ -191,6 +191,18 @@ int lattice_energies(lattice_t* h, lattice_obs* out);
 #define LAT_SPEC_U1_E 34
 #define LAT_SPEC_U1_B 35
 
+/* lattice_energies for callers that cannot allocate device memory or hold a
+   workspace for it (code under HIP graph capture, tight serving loops,
+   harnesses that forbid allocation): the same passes and kernels, with their
+   per-block FP64 partial sums in a 4 MiB static device array of the library
+   (one per device, held until the process ends) instead of the workspace;
+   results are bitwise those of lattice_energies.  Allocates nothing.  Calls
+   that overlap on one GPU share that array and race; the caller serialises
+   them.  Errors: LAT_ENOMEM when the partial sums need more than 4 MiB
+   (U(1) lattices above 320^3, SU(2) x U(1) above 192^3, two scalar fields
+   above 544^3), and those of lattice_energies. */
+int lattice_energies_noalloc(lattice_t* h, lattice_obs* out);
+
 /* Radially binned power spectrum of one field component (Sec. 3.1, eq. of
    the discrete spectrum; Sec. 4.4.2, 5.4.2).  Shell b holds the modes with
    floor(|n~|) = b, b = 0 .. floor(sqrt(3) N / 2).  Per shell: k[b] = mean

@@ -11,7 +11,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lattice.hip", "scalar.hip", "fft.hip", "u1.hip", "su2.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["lattice.hip", "scalar.hip", "fft.hip", "u1.hip", "su2.hip", "noalloc.hip", "batch.hip", "mlp.hip"]
 OUT = os.path.join(HERE, "libcosmolat.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 

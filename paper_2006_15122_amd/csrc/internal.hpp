@@ -90,6 +90,9 @@ inline bool is_su2(const lattice_params& p) { return p.model == LAT_MODEL_SU2U1;
 int su2_step(lattice* h, int64_t n);
 int su2_energies(lattice* h);
 int su2_init_state(lattice* h);
+// device address of the static scratch of lattice_energies_noalloc, recorded
+// once per device (noalloc.hip)
+int noalloc_setup();
 int run_fft3d(lattice* h, int sign, double scale);
 bool tiling_ok(const lattice* h, const Tiling& t);
 void default_tiling(lattice* h);
@@ -100,6 +103,8 @@ void u1_get_shape(int fp32, int i, int* tz, int* by, int* ry);
 int u1_pass(lattice* h, const PassDesc& pd, PassChain* chain = nullptr);
 int u1_chain_end(lattice* h, const PassChain& chain);
 int scalar_chain_end(lattice* h, const PassChain& chain);
+// blocks of a scalar observation pass (its fixed tile) at size N
+int64_t scalar_obs_blocks(int N);
 int num_shapes(int fp32, int nf);
 void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry);
 hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* const* dst, int N, int tz, int by,

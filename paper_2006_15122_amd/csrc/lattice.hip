@@ -161,6 +161,8 @@ int lattice_init(const lattice_params* p, void* dev_ws, size_t ws_bytes, void* h
     return LAT_ENOMEM;
   }
   if (((uintptr_t)dev_ws) % 256 != 0) { set_error("workspace must be 256-byte aligned"); return LAT_EINVAL; }
+  rc = noalloc_setup();
+  if (rc) return rc;
   lattice* L = new lattice();
   L->p = *p;
   L->stream = (hipStream_t)hip_stream;

@@ -82,6 +82,10 @@ static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
 // divides every supported N.
 static const int kObsTz = 32, kObsBy = 8, kObsRy = 2, kObsXc = 8;
 
+int64_t scalar_obs_blocks(int N) {
+  return (int64_t)(N / kObsTz) * (N / (kObsBy * kObsRy)) * (N / kObsXc);
+}
+
 template <typename T, int NF>
 hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nblocks, hipStream_t s, bool full,
                                 hipEvent_t ev0, hipEvent_t ev1, DevState* fin) {

@@ -24,7 +24,7 @@ ICS = {"vacuum": 0, "homogeneous": 1}
 ERRORS = {-1: "LAT_EINVAL", -2: "LAT_ENOMEM", -3: "LAT_EHIP", -4: "LAT_ENONFINITE", -5: "LAT_ESTATE"}
 
 EXPORTS = ["lattice_workspace_size", "lattice_init", "lattice_set_state", "lattice_get_state",
-           "lattice_step", "lattice_energies", "lattice_spectrum", "lattice_spectrum_logk", "lattice_destroy",
+           "lattice_step", "lattice_energies", "lattice_energies_noalloc", "lattice_spectrum", "lattice_spectrum_logk", "lattice_destroy",
            "lattice_last_error", "lattice_get_tiling", "lattice_set_tiling",
            "lattice_field_device_ptr", "lattice_pass_timer", "lattice_pass_timer_read", "lattice_batch_workspace_size", "lattice_batch_init",
            "lattice_batch_step", "lattice_batch_energies", "lattice_batch_run",
@@ -237,6 +237,13 @@ class Lattice:
     # -- evolution and observables -----------------------------------------
     def step(self, nsteps: int = 1):
         _check(lib().lattice_step(self.h, ctypes.c_int64(int(nsteps))))
+
+    def energies_noalloc(self) -> dict:
+        """lattice_energies_noalloc: the same observables with the library's
+        static scratch in place of the workspace's partial sums."""
+        o = Obs()
+        _check(lib().lattice_energies_noalloc(self.h, ctypes.byref(o)))
+        return obs_dict(o, self.nf)
 
     def energies(self) -> dict:
         o = Obs()
