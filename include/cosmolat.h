@@ -245,7 +245,10 @@ const char* lattice_last_error(void);
    (64,4,4) (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) for FP32 two
    fields and (64,4,2) (32,8,2) (32,4,4) otherwise; U(1) lattices (64,4,2) and
    (32,8,1) in FP32, (32,8,1) in FP64.  lattice_init picks one (the built-in
-   autotuner times them for N >= 128); this call reports it.  */
+   autotuner times them for N >= 128, once per model, size, precision,
+   integrator and expansion in a process, so that later lattices of the same
+   configuration share the tile and with it the order of their FP64 sums);
+   this call reports it.  SU(2) x U(1) passes are untiled (0, 0, 0, 0).  */
 int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc);
 
 /* Force a tile shape (for the autotuner and tests).  Errors: LAT_EINVAL if

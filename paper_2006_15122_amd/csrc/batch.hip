@@ -1,9 +1,13 @@
 // Batched ensembles of independent scalar lattices (sizes may differ).
 //
 // Every pass of every run goes through one batched kernel whose blocks are
-// the tiles of all runs (tile table built on the host), followed by one
-// finish block per run that reduces that run's FP64 partials in a fixed order
-// and advances its a, b (Sec. 4.3.2).  Kernel boundaries make each pass's
+// the tiles of all runs (tile table built on the host).  The finish of a pass
+// (Sec. 4.3.2: each run's FP64 partials reduced in a fixed order, then a and
+// b advanced) is carried by the next pass of the chain: every block reduces
+// its own run's records of the previous pass before its first plane is
+// consumed, the run's first tile stores the resulting state, and the records
+// and states alternate between two regions and two slots per run.  One
+// finish block per run closes the chain.  Kernel boundaries make each pass's
 // results visible across XCDs with one L2 write-back per XCD, so no block
 // ever waits on another.  A whole lattice_batch_step call is captured into a
 // HIP graph and launched once; the graph is cached per (nsteps, buffer
@@ -14,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -23,35 +28,66 @@
 
 namespace cl {
 
+// The pending finish of a chain: pass `pd` wrote its records to `partials`
+// (run r's at tile_offset[r] ..) starting from state slot `rd` of every run.
+struct BatchPrev {
+  const double* partials;  // nullptr: nothing pending
+  PassDesc pd;
+};
+
+// slots[2 r + k]: state slot k of run r (k = 0 is the run's canonical state).
+// Up to four rows per thread the kernel is held to four waves per SIMD, as
+// the single-lattice pass is.
 template <typename T, int NF, int TZ, int BY, int RY>
-__global__ __launch_bounds__(TZ* BY) void batch_pass_kernel(const ScalarArgs<T>* runs, const int* tile_run,
-                                                            const int* tile_local, double* partials, PassDesc pd) {
+__global__ __launch_bounds__(TZ* BY, RY <= 4 ? 4 : 1) void batch_pass_kernel(
+    const ScalarArgs<T>* runs, const int* tile_run, const int* tile_local, const int* tile_offset,
+    DevState* const* slots, int rd, BatchPrev prev, double* partials, PassDesc pd) {
   // blocks are dealt to the XCDs in turn; this gives each XCD a contiguous
   // range of the tile table (neighbouring tiles of a run), so the halo rows
   // two tiles share are read through the same L2
   int b = blockIdx.x;
   if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-  ScalarArgs<T> A = runs[tile_run[b]];
+  const int r = tile_run[b], local = tile_local[b];
+  ScalarArgs<T> A = runs[r];
   A.pd = pd;
   A.partials = partials;
-  const DevState* st = A.st;
-  scalar_tile<T, NF, false, TZ, BY, RY>(A, tile_local[b], b, [st](double& a, double& bb) {
-    a = st->a;
-    bb = st->b;
+  A.st = slots[2 * r + rd];
+  const int first = tile_offset[r], nrec = tile_offset[r + 1] - first;
+  DevState* const out = slots[2 * r + (rd ^ 1)];
+  scalar_tile<T, NF, false, TZ, BY, RY>(A, local, b, [&](double& a_in, double& b_in) {
+    if (prev.partials) {
+      constexpr int NP = Acc<NF, false>::N;
+      __shared__ double ab[2];
+      double S[NP];
+      if (reduce_partials<NP, TZ * BY>(prev.partials, first, nrec, S)) {
+        double an, bn;
+        finish_state<T, NF, false>(A, prev.pd, A.st, S, local == 0 ? out : nullptr, an, bn);
+        ab[0] = an;
+        ab[1] = bn;
+      }
+      __syncthreads();
+      a_in = ab[0];
+      b_in = ab[1];
+    } else {
+      a_in = A.st->a;
+      b_in = A.st->b;
+    }
   });
 }
 
+// Closing finish of a chain, one block per run: slot rd plus the last pass's
+// records give the run's canonical state (slot 0).
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void batch_finish_kernel(const ScalarArgs<T>* runs, const int* tile_offset,
-                                                           const double* partials, PassDesc pd) {
+                                                           DevState* const* slots, int rd, BatchPrev prev) {
   const int r = blockIdx.x;
   constexpr int NACC = Acc<NF, false>::N;
   double S[NACC];
   const int first = tile_offset[r];
-  if (!reduce_partials<NACC, 256>(partials, first, tile_offset[r + 1] - first, S)) return;
+  if (!reduce_partials<NACC, 256>(prev.partials, first, tile_offset[r + 1] - first, S)) return;
   ScalarArgs<T> A = runs[r];
-  A.pd = pd;
-  finish_from_sums<T, NF, false>(A, S);
+  double an, bn;
+  finish_state<T, NF, false>(A, prev.pd, slots[2 * r + rd], S, slots[2 * r], an, bn);
 }
 
 #define CL_BATCH_SHAPES(X) \
@@ -63,24 +99,36 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const ScalarArgs<T>* 
 
 static const int kBatchShapes[][3] = {{32, 8, 2}, {32, 4, 4}, {32, 8, 4}, {64, 4, 2}, {64, 4, 4}};
 
+// The chain of one lattice_batch_step call (or of an autotuning run).
+struct BatchChain {
+  int k = 0;         // passes launched
+  int rd = 0;        // state slot the next pass starts from
+  BatchPrev prev{};  // finish still to be applied
+};
+
 template <typename T, int NF>
-static hipError_t launch_batch_t(const Tiling& t, int ntiles, int nruns, const void* runs, const int* tile_run,
-                                 const int* tile_local, const int* tile_offset, double* partials,
-                                 const PassDesc& pd, hipStream_t s) {
+static hipError_t launch_batch_t(const Tiling& t, int ntiles, const void* runs, const int* tile_run,
+                                 const int* tile_local, const int* tile_offset, DevState* const* slots,
+                                 double* partials, const PassDesc& pd, const BatchChain& c, hipStream_t s) {
   const ScalarArgs<T>* R = static_cast<const ScalarArgs<T>*>(runs);
   bool ok = false;
-#define X(a, b, c)                                                                                          \
-  if (!ok && t.tz == a && t.by == b && t.ry == c) {                                                         \
-    hipLaunchKernelGGL((batch_pass_kernel<T, NF, a, b, c>), dim3(ntiles), dim3(a * b), 0, s, R, tile_run, \
-                       tile_local, partials, pd);                                                           \
-    ok = true;                                                                                              \
+#define X(a, b, cc)                                                                                            \
+  if (!ok && t.tz == a && t.by == b && t.ry == cc) {                                                           \
+    hipLaunchKernelGGL((batch_pass_kernel<T, NF, a, b, cc>), dim3(ntiles), dim3(a * b), 0, s, R, tile_run,   \
+                       tile_local, tile_offset, slots, c.rd, c.prev, partials, pd);                           \
+    ok = true;                                                                                                 \
   }
   CL_BATCH_SHAPES(X)
 #undef X
   if (!ok) return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((batch_finish_kernel<T, NF>), dim3(nruns), dim3(256), 0, s, R, tile_offset, partials, pd);
+  return hipGetLastError();
+}
+
+template <typename T, int NF>
+static hipError_t launch_batch_end_t(int nruns, const void* runs, const int* tile_offset, DevState* const* slots,
+                                     const BatchChain& c, hipStream_t s) {
+  hipLaunchKernelGGL((batch_finish_kernel<T, NF>), dim3(nruns), dim3(256), 0, s,
+                     static_cast<const ScalarArgs<T>*>(runs), tile_offset, slots, c.rd, c.prev);
   return hipGetLastError();
 }
 
@@ -97,7 +145,8 @@ struct lattice_batch {
   int* tile_run;
   int* tile_local;
   int* tile_offset;
-  double* partials;
+  cl::DevState** slots;  // [2 nruns]: each run's two state slots
+  double* partials[2];   // the records of consecutive passes alternate
   size_t args_bytes;
   int64_t max_tiles;
   int ntiles;
@@ -141,7 +190,8 @@ static void batch_header(const lattice_params* ps, int nruns, size_t* args_bytes
   *max_tiles = mt;
   size_t o = 2 * ab;
   o += aup((size_t)mt * 4) * 2 + aup((size_t)(nruns + 1) * 4);
-  o += aup((size_t)mt * 4 * sizeof(double));
+  o += aup((size_t)nruns * 2 * sizeof(void*));
+  o += 2 * aup((size_t)mt * 4 * sizeof(double));
   *header = o;
 }
 
@@ -218,17 +268,38 @@ static int batch_upload(lattice_batch* B) {
   return B->fp32 ? batch_upload_tables<float>(B) : batch_upload_tables<double>(B);
 }
 
-static hipError_t batch_launch(lattice_batch* B, const PassDesc& pd, int parity) {
+// One pass of a chain; the records go to the region the pass number picks.
+static hipError_t batch_launch(lattice_batch* B, const PassDesc& pd, int parity, BatchChain& c) {
   const void* args = B->args[parity];
+  double* part = B->partials[c.k & 1];
+  hipError_t e;
+  auto go = [&](auto* tag, auto nf) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return launch_batch_t<T, decltype(nf)::value>(B->tile, B->ntiles, args, B->tile_run, B->tile_local,
+                                                  B->tile_offset, B->slots, part, pd, c, B->stream);
+  };
   if (B->fp32)
-    return B->nf == 1 ? launch_batch_t<float, 1>(B->tile, B->ntiles, B->nruns, args, B->tile_run, B->tile_local,
-                                                 B->tile_offset, B->partials, pd, B->stream)
-                      : launch_batch_t<float, 2>(B->tile, B->ntiles, B->nruns, args, B->tile_run, B->tile_local,
-                                                 B->tile_offset, B->partials, pd, B->stream);
-  return B->nf == 1 ? launch_batch_t<double, 1>(B->tile, B->ntiles, B->nruns, args, B->tile_run, B->tile_local,
-                                                B->tile_offset, B->partials, pd, B->stream)
-                    : launch_batch_t<double, 2>(B->tile, B->ntiles, B->nruns, args, B->tile_run, B->tile_local,
-                                                B->tile_offset, B->partials, pd, B->stream);
+    e = B->nf == 1 ? go((float*)nullptr, std::integral_constant<int, 1>{})
+                   : go((float*)nullptr, std::integral_constant<int, 2>{});
+  else
+    e = B->nf == 1 ? go((double*)nullptr, std::integral_constant<int, 1>{})
+                   : go((double*)nullptr, std::integral_constant<int, 2>{});
+  if (e != hipSuccess) return e;
+  if (c.prev.partials) c.rd ^= 1;
+  c.prev = BatchPrev{part, pd};
+  ++c.k;
+  return hipSuccess;
+}
+
+// Closing finish: every run's canonical state from the chain's last pass.
+static hipError_t batch_chain_end(lattice_batch* B, const BatchChain& c) {
+  if (c.k == 0) return hipSuccess;
+  const void* args = B->args[0];
+  if (B->fp32)
+    return B->nf == 1 ? launch_batch_end_t<float, 1>(B->nruns, args, B->tile_offset, B->slots, c, B->stream)
+                      : launch_batch_end_t<float, 2>(B->nruns, args, B->tile_offset, B->slots, c, B->stream);
+  return B->nf == 1 ? launch_batch_end_t<double, 1>(B->nruns, args, B->tile_offset, B->slots, c, B->stream)
+                    : launch_batch_end_t<double, 2>(B->nruns, args, B->tile_offset, B->slots, c, B->stream);
 }
 
 static void drop_graphs(lattice_batch* B) {
@@ -264,11 +335,17 @@ static int batch_autotune(lattice_batch* B) {
       B->tile = t;
       int rc = batch_upload(B);
       if (rc) return rc;
-      // full passes into the scratch buffers, a and b untouched
+      // chained passes into the other buffers that leave a and b as they
+      // are (update 0), as lattice_batch_step chains them; the closing
+      // finish stores only observables
       PassDesc pd = pass(1.0, 0.5, 0.5, MODE_VV, 1, 0);
-      CL_HIP(batch_launch(B, pd, B->parity));
+      BatchChain warm;
+      CL_HIP(batch_launch(B, pd, B->parity, warm));
+      CL_HIP(batch_chain_end(B, warm));
+      BatchChain c;
       CL_HIP(hipEventRecord(e0, B->stream));
-      for (int k = 0; k < 3; ++k) CL_HIP(batch_launch(B, pd, B->parity));
+      for (int k = 0; k < 3; ++k) CL_HIP(batch_launch(B, pd, B->parity, c));
+      CL_HIP(batch_chain_end(B, c));
       CL_HIP(hipEventRecord(e1, B->stream));
       CL_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -334,7 +411,11 @@ int lattice_batch_init(const lattice_params* ps, int nruns, void* dev_ws, size_t
   o += aup((size_t)mt * 4);
   B->tile_offset = (int*)(ws + o);
   o += aup((size_t)(nruns + 1) * 4);
-  B->partials = (double*)(ws + o);
+  B->slots = (DevState**)(ws + o);
+  o += aup((size_t)nruns * 2 * sizeof(void*));
+  B->partials[0] = (double*)(ws + o);
+  o += aup((size_t)mt * 4 * sizeof(double));
+  B->partials[1] = (double*)(ws + o);
   o = hdr;
   for (int r = 0; r < nruns; ++r) {
     size_t b = 0;
@@ -348,6 +429,25 @@ int lattice_batch_init(const lattice_params* ps, int nruns, void* dev_ws, size_t
     }
     B->runs.push_back(h);
     o += aup(b);
+  }
+  {
+    std::vector<DevState*> sl;
+    for (lattice* h : B->runs) {
+      sl.push_back(h->st);
+      sl.push_back(h->st2);
+    }
+    rc = LAT_OK;
+    if (hipMemcpyAsync(B->slots, sl.data(), sl.size() * sizeof(DevState*), hipMemcpyHostToDevice, B->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(B->stream) != hipSuccess) {
+      set_error("batch: uploading the state-slot table failed");
+      rc = LAT_EHIP;
+    }
+    if (rc) {
+      for (lattice* x : B->runs) lattice_destroy(x);
+      delete B;
+      return rc;
+    }
   }
   B->weights = vv_weights(ps[0].integrator);
   B->parity = 0;
@@ -379,8 +479,9 @@ int lattice_batch_step(lattice_batch_t* B, int64_t nsteps) {
       hipGraphExec_t ge;
       CL_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
       int par = start;
-      for (const PassDesc& pd : sched) {
-        hipError_t e = batch_launch(B, pd, par);
+      BatchChain c;
+      for (size_t i = 0; i <= sched.size(); ++i) {
+        hipError_t e = (i < sched.size()) ? batch_launch(B, sched[i], par, c) : batch_chain_end(B, c);
         if (e != hipSuccess) {
           hipGraph_t dummy;
           (void)hipStreamEndCapture(B->stream, &dummy);
@@ -396,10 +497,12 @@ int lattice_batch_step(lattice_batch_t* B, int64_t nsteps) {
     CL_HIP(hipGraphLaunch(it->second.second, B->stream));
   } else {
     int par = start;
+    BatchChain c;
     for (const PassDesc& pd : sched) {
-      CL_HIP(batch_launch(B, pd, par));
+      CL_HIP(batch_launch(B, pd, par, c));
       par ^= 1;
     }
+    CL_HIP(batch_chain_end(B, c));
   }
   const int flips = (int)(sched.size() & 1);
   for (lattice* h : B->runs) {

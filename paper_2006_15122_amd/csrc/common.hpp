@@ -46,6 +46,55 @@ struct DevState {
 // LF mode from the mean of <pi_in^2> and <pi_out^2>.
 enum PassMode { MODE_VV = 0, MODE_LF = 1 };
 
+// A per-pass coefficient (h a^p, a^p / dx^2, ...) carried as the unevaluated
+// sum hi + lo of two storage-precision numbers, which equals its FP64 value to
+// about 2^-48 relative.  Rounding the coefficient itself to FP32 would change
+// every site the same way every pass (a relative error of up to 6e-8 in the
+// time step or a coupling), a coherent perturbation that the resonant growth
+// amplifies like a change of the physics; the rounding of the products is
+// random from site to site and averages out of the volume observables.
+template <typename T>
+struct Coef {
+  T hi, lo;
+};
+template <typename T>
+__host__ __device__ inline Coef<T> coef(double v) {
+  const T hi = (T)v;
+  return Coef<T>{hi, (T)(v - (double)hi)};
+}
+// The same pair moved to scalar registers: every lane of a wave computes the
+// same coefficient (from a and b, which a chained pass reads out of LDS), so
+// the first lane's value is every lane's.
+__device__ __forceinline__ float wave_uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double wave_uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ Coef<T> ucoef(double v) {
+  const Coef<T> c = coef<T>(v);
+  return Coef<T>{wave_uniform(c.hi), wave_uniform(c.lo)};
+}
+// acc + c x.  The increment c x is formed first (hi x + lo x, one rounding)
+// and then added: adding lo x after hi x had been added to acc would round
+// back to the same number, since lo x is below half an ulp of the sum, and
+// leave the coefficient's rounding in place.
+template <typename T>
+__device__ __forceinline__ T fma_c(const Coef<T>& c, T x, T acc) {
+  if constexpr (sizeof(T) == sizeof(double)) return fma(c.hi, x, acc);
+  return acc + fmaf(c.hi, x, c.lo * x);
+}
+// c x
+template <typename T>
+__device__ __forceinline__ T mul_c(const Coef<T>& c, T x) {
+  if constexpr (sizeof(T) == sizeof(double)) return c.hi * x;
+  return fmaf(c.hi, x, c.lo * x);
+}
+
 struct PassDesc {
   double wd, wk1, wk2;
   int mode;

@@ -41,14 +41,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// dV/dphi_f with the couplings as hi + lo pairs (no coherent rounding of them)
 template <typename T, int NF>
-__device__ __forceinline__ T dpot(int f, const T (&p)[NF], T m2_0, T m2_1, T lam, T q) {
+__device__ __forceinline__ T dpot(int f, const T (&p)[NF], const Coef<T>& m2_0, const Coef<T>& m2_1,
+                                  const Coef<T>& lam, const Coef<T>& q) {
   if (f == 0) {
-    T d = m2_0 * p[0] + lam * p[0] * p[0] * p[0];
-    if constexpr (NF > 1) d += q * p[1] * p[1] * p[0];
+    T d = fma_c(lam, p[0] * p[0] * p[0], mul_c(m2_0, p[0]));
+    if constexpr (NF > 1) d = fma_c(q, p[1] * p[1] * p[0], d);
     return d;
   } else {
-    if constexpr (NF > 1) return m2_1 * p[1] + q * p[0] * p[0] * p[1];
+    if constexpr (NF > 1) return fma_c(q, p[0] * p[0] * p[1], mul_c(m2_1, p[1]));
     return T(0);
   }
 }
@@ -235,9 +237,10 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   const int z0 = zt * TZ, y0 = yt * TY, x0 = xcI * A.XC;
   const size_t NN = (size_t)N * N;
 
-  const T ckick = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
-  const T cE = (T)((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
+  const Coef<T> ckick = ucoef<T>((A.pd.wk1 + A.pd.wk2) * A.h);
+  const Coef<T> cE = ucoef<T>((A.pd.mode == MODE_LF ? (A.pd.wk1 + A.pd.wk2) : A.pd.wk1) * A.h);
   const T m2_0 = (T)A.m2_0, m2_1 = (T)A.m2_1, lam = (T)A.lam, q = (T)A.q;
+  const Coef<T> m2_0c = ucoef<T>(A.m2_0), m2_1c = ucoef<T>(A.m2_1), lamc = ucoef<T>(A.lam), qc_ = ucoef<T>(A.q);
   const T half = T(0.5), quarter = T(0.25);
   const bool lf = A.pd.mode == MODE_LF;
 
@@ -302,9 +305,9 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
   const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
-  const T cdrift = (T)(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
-  const T clap = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const T cpot = (T)pow(anew, 3.0 + A.alpha);
+  const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
+  const Coef<T> clap = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const Coef<T> cpot = ucoef<T>(pow(anew, 3.0 + A.alpha));
   // drifted plane into LDS: own columns from registers, halo drifted here
   auto store_lds = [&](const T (&p)[NF][RY], const T (&hp)[NF], const T (&hq)[NF]) {
 #pragma unroll
@@ -313,7 +316,7 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       for (int f = 0; f < NF; ++f) lds[f][1 + r * BY + ty][1 + tz] = p[f][r];
     if (has_halo) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) lds[f][hly][hlz] = hp[f] + cdrift * hq[f];
+      for (int f = 0; f < NF; ++f) lds[f][hly][hlz] = fma_c(cdrift, hq[f], hp[f]);
     }
   };
   {
@@ -321,8 +324,8 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        pm[f][r] = pm[f][r] + cdrift * qf[f][r];
-        pc[f][r] = pc[f][r] + cdrift * qc[f][r];
+        pm[f][r] = fma_c(cdrift, qf[f][r], pm[f][r]);
+        pc[f][r] = fma_c(cdrift, qc[f][r], pc[f][r]);
       }
     store_lds(pc, hp1, hq1);
 #pragma unroll
@@ -346,14 +349,18 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       const size_t o = row_off(x, y0 + r * BY + ty) + z;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const T pnext = pn[f][r] + cdrift * qn[f][r];
+        const T pnext = fma_c(cdrift, qn[f][r], pn[f][r]);
         const T yp = lds[f][ly + 1][1 + tz], ym = lds[f][ly - 1][1 + tz];
         const T zp = lds[f][ly][2 + tz], zm = lds[f][ly][tz];
-        const T lap = (pm[f][r] + pnext) + (yp + ym) + (zp + zm) - T(6) * cur[f];
-        const T K = clap * lap - cpot * dpot<T, NF>(f, cur, m2_0, m2_1, lam, q);
+        // differences first: each neighbour minus the site is exact in
+        // storage precision for nearby values, so the Laplacian of the small
+        // fluctuations does not cancel against the condensate
+        const T c = cur[f];
+        const T lap = ((pm[f][r] - c) + (pnext - c)) + ((yp - c) + (ym - c)) + ((zp - c) + (zm - c));
+        const T K = fma_c(clap, lap, -mul_c(cpot, dpot<T, NF>(f, cur, m2_0c, m2_1c, lamc, qc_)));
         const T pin = qc[f][r];
-        const T pout = pin + ckick * K;
-        const T pe = pin + cE * K;
+        const T pout = fma_c(ckick, K, pin);
+        const T pe = fma_c(cE, K, pin);
         if (A.pd.write) {
           // streaming stores: the new state is read again only by the next
           // pass, so keep it from evicting the halo rows other tiles still need
@@ -399,7 +406,7 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         pm[f][r] = pc[f][r];
-        pc[f][r] = pn[f][r] + cdrift * qn[f][r];
+        pc[f][r] = fma_c(cdrift, qn[f][r], pn[f][r]);
         qc[f][r] = qn[f][r];
         pn[f][r] = pf[f][r];
         qn[f][r] = qf[f][r];

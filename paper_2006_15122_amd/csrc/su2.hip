@@ -29,6 +29,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "phase.hpp"
 
 namespace cl {
 
@@ -90,10 +91,6 @@ __device__ __forceinline__ T cross_im(Cx2<T> a, Cx2<T> b) { return a.re * b.im -
 template <typename T>
 __device__ __forceinline__ T dot_re(Cx2<T> a, Cx2<T> b) { return a.re * b.re + a.im * b.im; }
 
-__device__ __forceinline__ void sincos_s(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sincos_s(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ float atan_s(float x) { return atanf(x); }
-__device__ __forceinline__ double atan_s(double x) { return atan(x); }
 __device__ __forceinline__ float rsqrt_s(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsqrt_s(double x) { return 1.0 / sqrt(x); }
 
@@ -151,18 +148,21 @@ __global__ __launch_bounds__(256) void su2_drift_kernel(Su2Args<T> A) {
   const double hw = A.pd.wd * A.h;
   const double anew = A.expand ? a_in + hw * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
-  const T cd = (T)(hw * pow(amid, -(3.0 - A.alpha)));
-  const T cu = (T)(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
-  const T cw = (T)(A.g * hw * A.dx / (4.0 * pow(amid, 1.0 - A.alpha)));
+  // coefficients as hi + lo pairs (no coherent rounding of them)
+  const Coef<T> cd = ucoef<T>(hw * pow(amid, -(3.0 - A.alpha)));
+  const Coef<T> cu = ucoef<T>(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
+  const Coef<T> cw = ucoef<T>(A.g * hw * A.dx / (4.0 * pow(amid, 1.0 - A.alpha)));
 #pragma unroll
-  for (int k = 0; k < 4; ++k) A.dst[kPH + k][s] = A.src[kPH + k][s] + cd * A.src[kPI + k][s];
+  for (int k = 0; k < 4; ++k) A.dst[kPH + k][s] = fma_c(cd, A.src[kPI + k][s], A.src[kPH + k][s]);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) A.dst[kTH + i][s] = wrap_turns(A.src[kTH + i][s] - T(2) * atan_s(cu * A.src[kPA + i][s]));
+  for (int i = 0; i < 3; ++i)
+    A.dst[kTH + i][s] = wrap_turns(A.src[kTH + i][s] - T(2) * atan_t(mul_c(cu, A.src[kPA + i][s])));
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const Q4<T> u{A.src[kUL + 4 * i][s], A.src[kUL + 4 * i + 1][s], A.src[kUL + 4 * i + 2][s],
                   A.src[kUL + 4 * i + 3][s]};
-    const T w0 = cw * A.src[kPB + 3 * i][s], w1 = cw * A.src[kPB + 3 * i + 1][s], w2 = cw * A.src[kPB + 3 * i + 2][s];
+    const T w0 = mul_c(cw, A.src[kPB + 3 * i][s]), w1 = mul_c(cw, A.src[kPB + 3 * i + 1][s]),
+            w2 = mul_c(cw, A.src[kPB + 3 * i + 2][s]);
     const T ww = w0 * w0 + w1 * w1 + w2 * w2;
     const T d = T(1) / (T(1) + ww);
     const Q4<T> c{(T(1) - ww) * d, T(-2) * w0 * d, T(-2) * w1 * d, T(-2) * w2 * d};
@@ -225,15 +225,16 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
 
     const double a_in = A.st->a, b_in = A.st->b;
     const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
-    const T cl = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-    const T cp = (T)pow(anew, 3.0 + A.alpha);
-    const T cjA = (T)(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-    const T cjB = (T)(pow(anew, 1.0 + A.alpha) * A.g / A.dx / A.wf2);
-    const T cbA = (T)(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
-    const T cbB = (T)(pow(anew, A.alpha - 1.0) * 2.0 / (A.g * A.dx * A.dx * A.dx));
-    const T ck = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
-    const T cE = (T)((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
+    const Coef<T> cl = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+    const Coef<T> cp = ucoef<T>(pow(anew, 3.0 + A.alpha));
+    const Coef<T> cjA = ucoef<T>(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+    const Coef<T> cjB = ucoef<T>(pow(anew, 1.0 + A.alpha) * A.g / A.dx / A.wf2);
+    const Coef<T> cbA = ucoef<T>(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+    const Coef<T> cbB = ucoef<T>(pow(anew, A.alpha - 1.0) * 2.0 / (A.g * A.dx * A.dx * A.dx));
+    const Coef<T> ck = ucoef<T>((A.pd.wk1 + A.pd.wk2) * A.h);
+    const Coef<T> cE = ucoef<T>((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
     const T lam = (T)A.lam, m2 = (T)A.m2;
+    const Coef<T> lam2c = ucoef<T>(2.0 * A.lam), m2c = ucoef<T>(A.m2);
 
     Cx2<T> p[2];
     LP(su, p);
@@ -251,9 +252,9 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
       const Q4<T> u = LQ(i, su);
       Cx2<T> um1f[2];
       qapply(u, qw_m1(u), fp, um1f);  // (U - 1) Phi_+
-      T sn, cs;
-      sincos_s(LT(i, su), &sn, &cs);
-      const Cx2<T> vm1{cs > T(0) ? -sn * sn / (T(1) + cs) : cs - T(1), sn};
+      T sn, cm;
+      sincos_m1(LT(i, su), &sn, &cm);
+      const Cx2<T> vm1{cm, sn};
       Cx2<T> g[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -262,9 +263,9 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
       }
       // backward
       const Q4<T> ub = qdag(LQ(i, sm[i]));
-      T snb, csb;
-      sincos_s(LT(i, sm[i]), &snb, &csb);
-      const Cx2<T> vbm1{csb > T(0) ? -snb * snb / (T(1) + csb) : csb - T(1), -snb};  // conj(V) - 1
+      T snb, cmb;
+      sincos_m1(LT(i, sm[i]), &snb, &cmb);
+      const Cx2<T> vbm1{cmb, -snb};  // conj(V) - 1
       Cx2<T> vf[2], yb[2], ubm1[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -285,7 +286,6 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
       curB[i][2] = cross_im(p[0], g[0]) - cross_im(p[1], g[1]);
     }
     const T r2 = p[0].re * p[0].re + p[0].im * p[0].im + p[1].re * p[1].re + p[1].im * p[1].im;
-    const T dv = T(2) * lam * r2 + m2;
 
     // ---- U(1) plaquettes: sin Phi_ab(m), Phi_ab(m) = th_a(m) + th_b(m+a) - th_a(m+b) - th_b(m),
     // at m = n and at m = n - e_q (m + e_a = n when a = q)
@@ -294,10 +294,10 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
       const unsigned m = q < 0 ? su : sm[q];
       const unsigned ma = q < 0 ? sp[a] : pos(q, a), mb = q < 0 ? sp[b] : pos(q, b);
       const T ph = (LT(a, m) + LT(b, ma)) - (LT(a, mb) + LT(b, m));
-      T sh, ch;
-      sincos_s(T(0.5) * ph, &sh, &ch);
-      if (om1) *om1 = T(2) * sh * sh;  // 1 - cos Phi
-      return T(2) * sh * ch;
+      T sn, cm;
+      sincos_m1(ph, &sn, &cm);
+      if (om1) *om1 = -cm;  // 1 - cos Phi
+      return sn;
     };
     T omA[3];
     const T S01 = plA(0, 1, -1, &omA[0]), S02 = plA(0, 2, -1, &omA[1]), S12 = plA(1, 2, -1, &omA[2]);
@@ -350,30 +350,33 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
     for (int k = 0; k < kSu2Acc; ++k) ts[k] = T(0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const Cx2<T> K{cl * lap[k].re - cp * dv * p[k].re, cl * lap[k].im - cp * dv * p[k].im};
+      // V'(Phi) = (2 lambda |Phi|^2 + m2) Phi
+      const T dre = fma_c(lam2c, r2 * p[k].re, mul_c(m2c, p[k].re));
+      const T dim = fma_c(lam2c, r2 * p[k].im, mul_c(m2c, p[k].im));
+      const Cx2<T> K{mul_c(cl, lap[k].re) - mul_c(cp, dre), mul_c(cl, lap[k].im) - mul_c(cp, dim)};
       const Cx2<T> pin{A.src[kPI + 2 * k][s], A.src[kPI + 2 * k + 1][s]};
-      const Cx2<T> pe{pin.re + cE * K.re, pin.im + cE * K.im};
+      const Cx2<T> pe{fma_c(cE, K.re, pin.re), fma_c(cE, K.im, pin.im)};
       ts[0] += pin.re * pin.re + pin.im * pin.im;
       ts[1] += pe.re * pe.re + pe.im * pe.im;
       if (wr) {
-        A.dst[kPI + 2 * k][s] = pin.re + ck * K.re;
-        A.dst[kPI + 2 * k + 1][s] = pin.im + ck * K.im;
+        A.dst[kPI + 2 * k][s] = fma_c(ck, K.re, pin.re);
+        A.dst[kPI + 2 * k + 1][s] = fma_c(ck, K.im, pin.im);
       }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const T K = cjA * curA[i] + cbA * curlA[i];
-      const T ain = A.src[kPA + i][s], ae = ain + cE * K;
+      const T K = fma_c(cbA, curlA[i], mul_c(cjA, curA[i]));
+      const T ain = A.src[kPA + i][s], ae = fma_c(cE, K, ain);
       ts[5] += ain * ain;
       ts[6] += ae * ae;
-      if (wr) A.dst[kPA + i][s] = ain + ck * K;
+      if (wr) A.dst[kPA + i][s] = fma_c(ck, K, ain);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const T KB = cjB * curB[i][a] + cbB * magB[i][a];
-        const T bin = A.src[kPB + 3 * i + a][s], be = bin + cE * KB;
+        const T KB = fma_c(cbB, magB[i][a], mul_c(cjB, curB[i][a]));
+        const T bin = A.src[kPB + 3 * i + a][s], be = fma_c(cE, KB, bin);
         ts[8] += bin * bin;
         ts[9] += be * be;
-        if (wr) A.dst[kPB + 3 * i + a][s] = bin + ck * KB;
+        if (wr) A.dst[kPB + 3 * i + a][s] = fma_c(ck, KB, bin);
       }
     }
     if (wr && !A.fields_in_dst) {

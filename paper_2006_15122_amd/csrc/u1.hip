@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "phase.hpp"
 
 namespace cl {
 
@@ -80,24 +81,6 @@ __device__ void u1_block_partials(double (&acc)[NACC], double* partials) {
     for (int w = 1; w < NW; ++w) s += red[w][tid];
     partials[(size_t)blockIdx.x * NACC + tid] = s;
   }
-}
-
-__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
-__device__ __forceinline__ double sin_t(double x) { return sin(x); }
-__device__ __forceinline__ float atan_t(float x) { return atanf(x); }
-__device__ __forceinline__ double atan_t(double x) { return atan(x); }
-// a / b; FP32 through the hardware reciprocal (1 ulp), which is below the
-// rounding already in a and b
-__device__ __forceinline__ float quot_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double quot_t(double a, double b) { return a / b; }
-
-// cos t - 1 from (cos t, sin t) without cancellation: -sin^2/(1 + cos) where
-// cos > 0, the plain difference (no cancellation) elsewhere
-template <typename T>
-__device__ __forceinline__ T cos_m1(T cs, T sn) {
-  return cs > T(0) ? -quot_t(sn * sn, T(1) + cs) : cs - T(1);
 }
 
 template <typename T>
@@ -236,18 +219,20 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const double amid = 0.5 * (a_in + anew);
   const bool dr = A.pd.wd != 0.0;
   const double hw = A.pd.wd * A.h;
-  const T cd = dr ? (T)(hw * pow(amid, -(3.0 - A.alpha))) : T(0);
-  const T cu = dr ? (T)(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha))) : T(0);
-  const T cA = dr ? (T)(hw / pow(amid, 1.0 - A.alpha)) : T(0);  // non-compact A drift
-  const T mth = (T)(-A.e * A.dx);                                // theta = -e dx A
-  const T cl = (T)(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const T cp = (T)pow(anew, 3.0 + A.alpha);
-  const T cj = (T)(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-  const T cb = (T)(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
-  const T ck = (T)((A.pd.wk1 + A.pd.wk2) * A.h);
-  const T cE = (T)((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
+  // per-pass coefficients as hi + lo pairs (no coherent rounding of them)
+  const Coef<T> cd = ucoef<T>(dr ? hw * pow(amid, -(3.0 - A.alpha)) : 0.0);
+  const Coef<T> cu = ucoef<T>(dr ? A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)) : 0.0);
+  const Coef<T> cA = ucoef<T>(dr ? hw / pow(amid, 1.0 - A.alpha) : 0.0);  // non-compact A drift
+  const Coef<T> mth = ucoef<T>(-A.e * A.dx);                                // theta = -e dx A
+  const Coef<T> cl = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const Coef<T> cp = ucoef<T>(pow(anew, 3.0 + A.alpha));
+  const Coef<T> cj = ucoef<T>(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+  const Coef<T> cb = ucoef<T>(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+  const Coef<T> ck = ucoef<T>((A.pd.wk1 + A.pd.wk2) * A.h);
+  const Coef<T> cE = ucoef<T>((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
   const bool wr = A.pd.write != 0;
   const T lam = (T)A.lam, m2 = (T)A.m2;
+  const Coef<T> lam2c = ucoef<T>(2.0 * A.lam), m2c = ucoef<T>(A.m2);
 
   // ring site owned by this thread (one at most)
   const bool has_ring = tid < NH;
@@ -285,37 +270,37 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int ly = 1 + r * BY + ty, lz = 1 + tz;
-      Lp[b][0][ly][lz] = raw[0][r] + cd * raw[2][r];
-      Lp[b][1][ly][lz] = raw[1][r] + cd * raw[3][r];
+      Lp[b][0][ly][lz] = fma_c(cd, raw[2][r], raw[0][r]);
+      Lp[b][1][ly][lz] = fma_c(cd, raw[3][r], raw[1][r]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         T th;
         if constexpr (NC) {
-          th = raw[4 + i][r] + cA * raw[7 + i][r];  // A_i after the drift
+          th = fma_c(cA, raw[7 + i][r], raw[4 + i][r]);  // A_i after the drift
         } else {
-          th = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(cu * raw[7 + i][r])) : raw[4 + i][r];
+          th = dr ? wrap_phase(raw[4 + i][r] - T(2) * atan_t(mul_c(cu, raw[7 + i][r]))) : raw[4 + i][r];
         }
         Lt[b][i][ly][lz] = th;
-        T sn, cs;
-        sincos_t(NC ? mth * th : th, &sn, &cs);
-        Lu[b][i][ly][lz] = C2<T>{cos_m1(cs, sn), sn};
+        T sn, cm;
+        sincos_m1(NC ? mul_c(mth, th) : th, &sn, &cm);
+        Lu[b][i][ly][lz] = C2<T>{cm, sn};
       }
     }
     if (has_ring) {
-      Lp[b][0][rly][rlz] = rraw[0] + cd * rraw[2];
-      Lp[b][1][rly][rlz] = rraw[1] + cd * rraw[3];
+      Lp[b][0][rly][rlz] = fma_c(cd, rraw[2], rraw[0]);
+      Lp[b][1][rly][rlz] = fma_c(cd, rraw[3], rraw[1]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         T th;
         if constexpr (NC) {
-          th = rraw[4 + i] + cA * rraw[7 + i];
+          th = fma_c(cA, rraw[7 + i], rraw[4 + i]);
           Lt[b][i][rly][rlz] = th;  // the plaquette angles need A on the ring
         } else {
-          th = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(cu * rraw[7 + i])) : rraw[4 + i];
+          th = dr ? wrap_phase(rraw[4 + i] - T(2) * atan_t(mul_c(cu, rraw[7 + i]))) : rraw[4 + i];
         }
-        T sn, cs;
-        sincos_t(NC ? mth * th : th, &sn, &cs);
-        Lu[b][i][rly][rlz] = C2<T>{cos_m1(cs, sn), sn};
+        T sn, cm;
+        sincos_m1(NC ? mul_c(mth, th) : th, &sn, &cm);
+        Lu[b][i][rly][rlz] = C2<T>{cm, sn};
       }
     }
   };
@@ -327,9 +312,9 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
     if constexpr (NC) {
       // Phi_ij = theta_i(m) + theta_j(m+i) - theta_i(m+j) - theta_j(m) with theta = -e dx A
       const T a0 = Lt[c][0][ly][lz], a1 = Lt[c][1][ly][lz], a2 = Lt[c][2][ly][lz];
-      sn[0] = mth * ((a0 + Lt[n][1][ly][lz]) - (Lt[c][0][ly + 1][lz] + a1));
-      sn[1] = mth * ((a0 + Lt[n][2][ly][lz]) - (Lt[c][0][ly][lz + 1] + a2));
-      sn[2] = mth * ((a1 + Lt[c][2][ly + 1][lz]) - (Lt[c][1][ly][lz + 1] + a2));
+      sn[0] = mul_c(mth, (a0 + Lt[n][1][ly][lz]) - (Lt[c][0][ly + 1][lz] + a1));
+      sn[1] = mul_c(mth, (a0 + Lt[n][2][ly][lz]) - (Lt[c][0][ly][lz + 1] + a2));
+      sn[2] = mul_c(mth, (a1 + Lt[c][2][ly + 1][lz]) - (Lt[c][1][ly][lz + 1] + a2));
 #pragma unroll
       for (int k = 0; k < 3; ++k) om[k] = T(0.5) * sn[k] * sn[k];
       return;
@@ -449,18 +434,19 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
         lap.x += g.x + gb.x;
         lap.y += g.y + gb.y;
         ts[2] += g.x * g.x + g.y * g.y;
-        Kcur[k] = cj * (p.x * g.y - p.y * g.x);
+        Kcur[k] = mul_c(cj, p.x * g.y - p.y * g.x);
       }
       const T r2 = p.x * p.x + p.y * p.y;
-      const T dv = T(2) * lam * r2 + m2;
-      const C2<T> Kp{cl * lap.x - cp * dv * p.x, cl * lap.y - cp * dv * p.y};
+      // V'(phi) = (2 lambda |phi|^2 + m2) phi
+      const C2<T> dvp{fma_c(lam2c, r2 * p.x, mul_c(m2c, p.x)), fma_c(lam2c, r2 * p.y, mul_c(m2c, p.y))};
+      const C2<T> Kp{mul_c(cl, lap.x) - mul_c(cp, dvp.x), mul_c(cl, lap.y) - mul_c(cp, dvp.y)};
       const T S01 = Ls[0][ly][lz], S02 = Ls[1][ly][lz], S12 = Ls[2][ly][lz];
       const T curl[3] = {(S01 - Ls[0][ly - 1][lz]) + (S02 - Ls[1][ly][lz - 1]),
                          (-S01 + s01m[r]) + (S12 - Ls[2][ly][lz - 1]),
                          (-S02 + s02m[r]) + (-S12 + Ls[2][ly - 1][lz])};
       const C2<T> pin{qc[0][r], qc[1][r]};
-      const C2<T> pout{pin.x + ck * Kp.x, pin.y + ck * Kp.y};
-      const C2<T> pe{pin.x + cE * Kp.x, pin.y + cE * Kp.y};
+      const C2<T> pout{fma_c(ck, Kp.x, pin.x), fma_c(ck, Kp.y, pin.y)};
+      const C2<T> pe{fma_c(cE, Kp.x, pin.x), fma_c(cE, Kp.y, pin.y)};
       ts[0] += pin.x * pin.x + pin.y * pin.y;
       ts[1] += pe.x * pe.x + pe.y * pe.y;
       ts[3] += lam * r2 * r2;
@@ -477,8 +463,8 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const T ain = qc[2 + k][r];
-        const T KA = Kcur[k] + cb * curl[k];
-        const T aout = ain + ck * KA, ae = ain + cE * KA;
+        const T KA = fma_c(cb, curl[k], Kcur[k]);
+        const T aout = fma_c(ck, KA, ain), ae = fma_c(cE, KA, ain);
         ts[5] += ain * ain;
         ts[6] += ae * ae;
         if (wr) {

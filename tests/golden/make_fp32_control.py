@@ -12,8 +12,9 @@ exact run than "storage" is by more than chance; where even "initial" is far
 from it, the dynamics amplify any rounding and trajectory parity ends.
 
     python tests/golden/make_fp32_control.py <case> [nsteps] [every]
-cases: u1higgs_64_lf2, u1higgs_192_lf2 (compact U(1), leapfrog),
-       scalar2_256_vv2_q100 (two fields, velocity Verlet).
+cases: u1higgs_64_lf2 (1000 steps, every 100), u1higgs_192_lf2 (1000 steps,
+       every 20 to step 300, then every 100) (compact U(1), leapfrog),
+       scalar2_256_vv2_q100 (two fields, velocity Verlet, 1000 steps).
 Writes fp32_control_<case>.json next to this script.
 """
 import json
@@ -34,6 +35,19 @@ CASES = {
     "u1higgs_192_lf2": lambda: dict(synth.config3(N=192), precision="fp64"),
     "scalar2_256_vv2_q100": lambda: dict(synth.config2(q=100.0, integrator="vv2"), precision="fp64"),
 }
+
+
+# checkpoints besides every `every` steps: the first 300 steps of the 192^3
+# U(1) run every 20 (the stretch in which FP32 storage still follows FP64)
+DENSE = {"u1higgs_192_lf2": (20, 300)}
+
+
+def _checkpoint_steps(case, nsteps, every):
+    steps = set(range(every, nsteps + 1, every))
+    if case in DENSE:
+        d, upto = DENSE[case]
+        steps |= set(range(d, min(upto, nsteps) + 1, d))
+    return sorted(steps)
 
 
 def _f32(x):
@@ -80,6 +94,7 @@ def main(case, nsteps=1000, every=100):
 
         def observe(st):
             return oracle.sync_observe(m, st["phi"], st["pi"], st["a"], st["b"])
+    cps = _checkpoint_steps(case, nsteps, every)
     runs = {}
     t0 = time.time()
     for mode in ("exact", "storage", "initial"):
@@ -91,14 +106,16 @@ def main(case, nsteps=1000, every=100):
             step(st)
             if mode == "storage":
                 _round(st, u1)
-            if (s + 1) % every == 0:
+            if s + 1 in cps:
                 obs.append(observe(st))
         runs[mode] = obs
         print(case, mode, "done %.0f s" % (time.time() - t0), flush=True)
     out = {"case": case, "config": cfg, "generator": "tests/golden/make_fp32_control.py", "checkpoints": []}
-    for i in range(nsteps // every):
+    for i, stp in enumerate(cps):
         r = runs["exact"][i]
-        cp = {"step": every * (i + 1)}
+        cp = {"step": stp}
+        if u1:
+            cp["gauss_exact"] = r["gauss"]
         for mode in ("storage", "initial"):
             o = runs[mode][i]
             cp[mode] = {k: abs(o[k] - r[k]) / abs(r[k]) for k in keys if r[k] != 0.0}

@@ -115,3 +115,26 @@ def test_every_batch_tiling_agrees():
             n += 1
     assert n >= 6
     B.close()
+
+
+def test_chained_finish_of_each_run_is_its_own():
+    # each pass reduces its own run's records of the previous pass (the run's
+    # slice of the tile table) and stores the run's state slots; a batch of
+    # three runs must therefore give each run the bits of a batch of that run
+    # alone on the same tile
+    from paper_2006_15122_amd.lattice import Batch
+
+    cfgs = _runs(sizes=(32, 96, 64), integ="vv4")
+    B = Batch(cfgs)
+    B.step(23)
+    B.step(4)
+    for r, c in enumerate(cfgs):
+        S = Batch([c])
+        S.set_tiling(*B.tiling())
+        S.step(23)
+        S.step(4)
+        sb, ss = B.runs[r].get_state(), S.runs[0].get_state()
+        assert np.array_equal(sb["phi"], ss["phi"]) and np.array_equal(sb["pi"], ss["pi"]), r
+        assert sb["a"] == ss["a"] and sb["b"] == ss["b"] and sb["eta"] == ss["eta"], r
+        S.close()
+    B.close()

@@ -181,13 +181,45 @@ def _golden(case):
         return json.load(f)
 
 
+def fp32_control(case):
+    """Per-checkpoint errors of FP32 storage alone (FP64 oracle, state rounded
+    to FP32 after every step) and of one FP32 rounding of the initial state,
+    written by tests/golden/make_fp32_control.py; None where no control exists."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fp32_control_{case}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return {cp["step"]: cp for cp in json.load(f)["checkpoints"]}
+
+
+def window_end(ctl):
+    """First checkpoint at which FP32 storage alone (the control) is 1e-6 or
+    more away from the FP64 run on some observable.  Trajectory parity is gated
+    at 1e-5 before it: a decade below the gate, since a kernel's FP32
+    arithmetic adds rounding of the same order.  From there on the resonant
+    growth of the fields amplifies any rounding a hundredfold per 100 steps or
+    so, and no FP32 run can follow the FP64 one."""
+    for step in sorted(ctl):
+        if max(v for k, v in ctl[step]["storage"].items() if k != "gauss") >= 1e-6:
+            return step
+    return math.inf
+
+
 @pytest.mark.parametrize("case", ["scalar2_256_vv2_q100", "scalar2_256_vv2_q1000", "scalar2_256_vv4_q1000"])
 def test_full_size_256_window_against_stored_oracle_run(case):
     """Config 2 at 256^3 on the autotuned tile over 1000 steps (VV2, q = 100
     and 1000) and 300 steps (VV4), every 100 steps against the oracle's stored
     run (tests/golden/make_full_size.py), which is re-checked here against the
-    live oracle at its initial state and at step 5."""
+    live oracle at its initial state and at step 5.  Where an FP32 control
+    exists (q = 100), the observables are gated at 1e-5 before its window end
+    and the scale factor at every checkpoint; the other two runs stay inside
+    the gate over their whole length."""
     gold = _golden(case)
+    ctl = fp32_control(case)
+    end = window_end(ctl) if ctl else math.inf
     cfg = dict(gold["config"])
     st = oracle.vacuum_ic(cfg)
     m = oracle.scalar_model(cfg)
@@ -205,14 +237,21 @@ def test_full_size_256_window_against_stored_oracle_run(case):
         assert abs(o5[key] - cps[5][key]) <= 1e-12 * abs(cps[5][key]), key
     lat.step(5)
     compare_obs(lat.energies(), o5, 2, 1e-5, f"{case} step 5")
-    done, worst = 5, 0.0
+    done, worst, gated = 5, 0.0, 0
     for step in sorted(k for k in cps if k >= 100):
         lat.step(step - done)
         done = step
-        w = compare_obs(lat.energies(), cps[step], 2, 1e-5, f"{case} step {step}")
-        worst = max(worst, w)
-        print(case, "step", step, "worst relative error %.2e" % w, flush=True)
-    assert done == gold["nsteps"]
+        g, o = lat.energies(), cps[step]
+        if step < end:
+            w = compare_obs(g, o, 2, 1e-5, f"{case} step {step}")
+            worst = max(worst, w)
+            gated += 1
+            print(case, "step", step, "worst relative error %.2e" % w, flush=True)
+        else:
+            ea = abs(g["a"] - o["a"]) / o["a"]
+            print(case, "step", step, "past the FP32 window: a %.1e" % ea, flush=True)
+            assert ea < 1e-6, (step, ea)
+    assert done == gold["nsteps"] and gated >= 3
     # pointwise values are not an observable of the method (late-time
     # fields are statistics, not gates): reported only
     s = lat.get_state()
@@ -463,3 +502,20 @@ def test_hubble_constraint_ladder_of_the_verlet_family():
         # previous one has already reached the round-off floor
         assert hc[hi] <= max(hc[lo] / 10.0, 10 * floor), (lo, hi, hc[lo], hc[hi])
     assert hc["vv2"] / max(hc["vv10"], floor) > 1e6
+
+
+def test_two_full_size_inits_are_bitwise_equal():
+    # the tuner's pick is kept per configuration, so a second 256^3 lattice of the
+    # same workload takes the same tile and reproduces the first bit for bit
+    cfg = synth.config2(q=100.0)
+    out = []
+    for _ in range(2):
+        lat = _lattice(cfg)
+        lat.step(20)
+        out.append((lat.tiling(), lat.energies(), lat.get_state()))
+        lat.close()
+    assert out[0][0] == out[1][0]
+    for k in ("a", "b", "EK", "EG", "EV"):
+        assert out[0][1][k] == out[1][1][k], k
+    assert np.array_equal(out[0][2]["phi"], out[1][2]["phi"])
+    assert np.array_equal(out[0][2]["pi"], out[1][2]["pi"])
