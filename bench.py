@@ -146,8 +146,8 @@ def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
     from paper_2006_15122_amd import emulator, synth
     from paper_2006_15122_amd.surrogate import Surrogate
 
-    shift, scale = emulator.in_scaling()
-    m = Surrogate(max_batch=64, in_shift=shift, in_scale=scale)
+    shift, scale, enc_freq = emulator.in_scaling()
+    m = Surrogate(max_batch=64, in_shift=shift, in_scale=scale, enc_freq=enc_freq)
     m.set_weights(synth.mlp_init(1))
     rng = np.random.default_rng(5)
     x = torch.from_numpy(np.stack([1.0 + 3.0 * rng.random(queries), 0.5 + 24.5 * rng.random(queries)],
@@ -164,7 +164,7 @@ def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
     e1.record(m.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    macs = 2 * 256 + 256 * 256 * 2 + 256 * 64       # per query
+    macs = 24 * 256 + 256 * 256 * 2 + 256 * 64      # per query (24 features into the first layer)
     tflops = 2.0 * macs * queries / (ms / 1e3) / 1e12
     m.close()
     return {"queries": queries, "ms_per_batch": ms, "queries_per_s": queries / (ms / 1e3),

@@ -3,17 +3,24 @@
  * lattice produces (Sec. 3.1 spectra of the preheating model of Sec. 8.1.1), trained on
  * the GPU on spectra the lattice itself generated.
  *
- * Network: 2 -> 256 -> 256 -> 256 -> 64, exact (erf) GELU after each hidden
- * layer, linear output, mean-squared-error loss, Adam.  FP32 master weights;
- * the matrix products run on the matrix cores with BF16 operands and FP32
- * accumulation.  BF16 (round to nearest even) is applied to: the weights fed
- * to the products, the hidden activations h1..h3, the output gradient and the
- * hidden pre-activation gradients of layers 3 and 2.  Biases, pre-activations,
- * the K = 2 first layer and all gradient sums stay FP32.
+ * Network: 2 inputs -> 24 fixed features -> 256 -> 256 -> 256 -> 64, exact
+ * (erf) GELU after each hidden layer, linear output, mean-squared-error loss,
+ * Adam.  FP32 master weights; the matrix products run on the matrix cores
+ * with BF16 operands and FP32 accumulation.  BF16 (round to nearest even) is
+ * applied to: the weights fed to the products, the hidden activations
+ * h1..h3, the output gradient and the hidden pre-activation gradients of
+ * layers 3 and 2.  Biases, pre-activations, the features, the first layer
+ * (K = 24, plain FMA) and all gradient sums stay FP32.
  *
  * Inputs and outputs are normalised inside the library:
  *   x_n = (x - in_shift) * in_scale,  y = y_n / out_scale + out_shift,
  *   target t_n = (t - out_shift) * out_scale.
+ * The features of a row are the two normalised inputs followed by a Fourier
+ * encoding of each: for input c and octave k = 0 .. SURR_N_FREQ_c - 1,
+ *   sin(2^k enc_freq[c] x_n,c), cos(2^k enc_freq[c] x_n,c),
+ * input 0's pairs first.  The encoding lets the first layer resolve the
+ * resonance bands of the spectrum in q and its oscillation in eta, which a
+ * plain MLP of this size smooths over.
  *
  * Conventions are those of cosmolat.h: 0 on success, negative LAT_* codes on
  * failure with the text in lattice_last_error(); the caller owns every
@@ -33,9 +40,12 @@ extern "C" {
 #endif
 
 #define SURR_N_IN 2
+#define SURR_N_FREQ0 6      /* octaves of the encoding of input 0 (log10 q) */
+#define SURR_N_FREQ1 5      /* octaves of the encoding of input 1 (eta) */
+#define SURR_N_FEAT 24      /* SURR_N_IN + 2 (SURR_N_FREQ0 + SURR_N_FREQ1) */
 #define SURR_WIDTH 256
 #define SURR_N_OUT 64
-#define SURR_NPARAMS 148800 /* 2*256+256 + 2*(256*256+256) + 256*64+64 */
+#define SURR_NPARAMS 154432 /* 24*256+256 + 2*(256*256+256) + 256*64+64 */
 
 typedef struct surrogate_t surrogate_t;
 
@@ -45,6 +55,7 @@ typedef struct surrogate_params {
   double beta1, beta2, eps; /* Adam moment decays and denominator offset */
   float in_shift[SURR_N_IN], in_scale[SURR_N_IN];
   float out_shift[SURR_N_OUT], out_scale[SURR_N_OUT];
+  float enc_freq[SURR_N_IN]; /* base angular frequency of each input's encoding, finite */
 } surrogate_params;
 
 /* Device workspace bytes for p (weights, Adam moments, BF16 copies and the
@@ -58,7 +69,7 @@ int surrogate_init(const surrogate_params* p, void* dev_ws, size_t ws_bytes, voi
                    surrogate_t** out);
 
 /* Load SURR_NPARAMS FP32 master weights from host memory, in this order:
- * W1[256][2], b1[256], W2[256][256], b2[256], W3[256][256], b3[256],
+ * W1[256][24], b1[256], W2[256][256], b2[256], W3[256][256], b3[256],
  * W4[64][256], b4[64] (W[out][in], a = W h + b).  Resets the Adam moments
  * and step count.  Synchronises the stream.  Errors: LAT_EINVAL, LAT_EHIP. */
 int surrogate_set_weights(surrogate_t* h, const float* host_w);
@@ -102,7 +113,7 @@ int surrogate_train_epoch(surrogate_t* h, const float* dev_x, const float* dev_t
  * Synchronises.  Errors: LAT_EINVAL (on with the null stream), LAT_EHIP. */
 int surrogate_use_graph(surrogate_t* h, int on);
 
-/* Forward pass for n query rows dev_x (FP32 [n][2]) into dev_y (FP32
+/* Forward pass for n query rows dev_x (FP32 [n][2], raw inputs) into dev_y (FP32
  * [n][64], denormalised log10 spectra), all layers fused in one kernel.
  * Asynchronous on the stream.  Errors: LAT_EINVAL, LAT_EHIP. */
 int surrogate_predict(surrogate_t* h, const float* dev_x, int64_t n, float* dev_y);

@@ -1,7 +1,10 @@
 """FP64 oracle of the spectrum surrogate MLP (TEST INFRASTRUCTURE ONLY).
 
-Network 2 -> 256 -> 256 -> 256 -> 64: three hidden layers with the exact
-(erf) GELU, a linear output, mean-squared-error loss, Adam.  The computation
+Network: the 2 normalised inputs -> 24 fixed features -> 256 -> 256 -> 256
+-> 64, three hidden layers with the exact (erf) GELU, a linear output,
+mean-squared-error loss, Adam.  The features are the inputs themselves and a
+Fourier encoding of each (sine and cosine of 2^k w_c u_c, octaves k = 0..5 of
+input 0 and 0..4 of input 1).  The computation
 is done in FP64; with ``bf16=True`` values are rounded to bfloat16
 (round-to-nearest-even) at the points where the GPU kernels store them in
 BF16:
@@ -10,8 +13,8 @@ BF16:
   - the hidden activations h1, h2, h3 (inputs of the next product),
   - the output gradient dL/dy and the pre-activation gradients dL/da3,
     dL/da2 (inputs of the backward products).
-Biases, pre-activations, the layer-1 product (K = 2) and the gradients of
-W1, b1 stay in full precision.
+Biases, pre-activations, the features, the layer-1 product (K = 24) and the
+gradients of W1, b1 stay in full precision.
 
 The network is not a step of the paper's method; it is the learned add-on
 whose targets are the lattice spectra of Sec. 3.1 / 4.4.2.
@@ -23,7 +26,21 @@ import math
 import numpy as np
 from scipy.special import erf
 
-SIZES = (2, 256, 256, 256, 64)
+N_FREQ = (6, 5)
+SIZES = (2 + 2 * sum(N_FREQ), 256, 256, 256, 64)
+
+
+def features(u: np.ndarray, enc_freq=(0.0, 0.0)) -> np.ndarray:
+    """(B, 2) normalised inputs u -> (B, 24): u_0, u_1, then for input 0 and
+    k = 0..5 the pair sin(2^k w_0 u_0), cos(2^k w_0 u_0), then the same for
+    input 1 and k = 0..4 (w = enc_freq)."""
+    u = np.asarray(u, dtype=np.float64)
+    cols = [u[:, 0], u[:, 1]]
+    for c, K in enumerate(N_FREQ):
+        for k in range(K):
+            a = (2.0 ** k) * float(enc_freq[c]) * u[:, c]
+            cols += [np.sin(a), np.cos(a)]
+    return np.stack(cols, 1)
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
@@ -49,10 +66,12 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
-def forward(p: dict, x: np.ndarray, bf16: bool = False) -> tuple:
-    """x: (B, 2) -> y: (B, 64); returns y and the cache for backward."""
+def forward(p: dict, u: np.ndarray, bf16: bool = False, enc_freq=(0.0, 0.0)) -> tuple:
+    """u: (B, 2) normalised inputs -> y: (B, 64); returns y and the cache for
+    backward."""
     r = bf16_round if bf16 else (lambda v: v)
     W = [r(p[f"W{l}"]) for l in range(1, 5)]
+    x = features(u, enc_freq)
     c = {"x": x, "W": W}
     a1 = x @ W[0].T + p["b1"]
     h1 = r(gelu(a1))
@@ -65,11 +84,11 @@ def forward(p: dict, x: np.ndarray, bf16: bool = False) -> tuple:
     return y, c
 
 
-def loss_and_grads(p: dict, x: np.ndarray, t: np.ndarray, bf16: bool = False) -> tuple:
+def loss_and_grads(p: dict, u: np.ndarray, t: np.ndarray, bf16: bool = False, enc_freq=(0.0, 0.0)) -> tuple:
     """Mean over batch and outputs of (y - t)^2 and its gradients."""
     r = bf16_round if bf16 else (lambda v: v)
-    y, c = forward(p, x, bf16)
-    B = x.shape[0]
+    y, c = forward(p, u, bf16, enc_freq)
+    B = u.shape[0]
     L = float(np.mean((y - t) ** 2))
     dy = 2.0 * (y - t) / (B * y.shape[1])
     W = c["W"]

@@ -37,8 +37,10 @@ struct surrogate_t;
 namespace {
 
 constexpr int NIN = SURR_N_IN, WID = SURR_WIDTH, NOUT = SURR_N_OUT, NPAR = SURR_NPARAMS;
+constexpr int NFQ0 = SURR_N_FREQ0, NFQ1 = SURR_N_FREQ1, NFEAT = SURR_N_FEAT;
+static_assert(NFEAT == NIN + 2 * (NFQ0 + NFQ1), "feature count");
 // offsets of the tensors in the flat parameter vector
-constexpr int OW1 = 0, OB1 = OW1 + WID * NIN, OW2 = OB1 + WID, OB2 = OW2 + WID * WID, OW3 = OB2 + WID,
+constexpr int OW1 = 0, OB1 = OW1 + WID * NFEAT, OW2 = OB1 + WID, OB2 = OW2 + WID * WID, OW3 = OB2 + WID,
               OB3 = OW3 + WID * WID, OW4 = OB3 + WID, OB4 = OW4 + NOUT * WID;
 static_assert(OB4 + NOUT == NPAR, "parameter count");
 
@@ -98,8 +100,36 @@ __device__ __forceinline__ f4 mma(bf16x8 a, bf16x8 b, f4 c) {
 
 // normalisation constants on the device
 struct Norm {
-  float in_shift[NIN], in_scale[NIN], out_shift[NOUT], out_scale[NOUT];
+  float in_shift[NIN], in_scale[NIN], out_shift[NOUT], out_scale[NOUT], enc_freq[NIN];
 };
+
+// sin and cos of 2^k (p + e) for k = 0 .. K-1, where p + e is an angle held
+// as an FP32 number and its rounding error: the octave doubles both exactly,
+// and the first-order term 2^k e keeps the high octaves as accurate as the
+// low ones (the rounding of the angle would otherwise grow with 2^k).
+template <int K>
+__device__ __forceinline__ void octaves(float p, float e, float* f) {
+#pragma unroll
+  for (int k = 0; k < K; ++k, p *= 2.0f, e *= 2.0f) {
+    float s, c;
+    sincosf(p, &s, &c);
+    f[2 * k] = fmaf(e, c, s);
+    f[2 * k + 1] = fmaf(-e, s, c);
+  }
+}
+
+// The first layer's inputs of one raw row (x0, x1): the normalised inputs
+// u_c, then sin and cos of 2^k enc_freq[c] u_c for the octaves of input 0,
+// then those of input 1.
+__device__ __forceinline__ void features(float x0, float x1, const Norm* nm, float* f) {
+  const float u0 = (x0 - nm->in_shift[0]) * nm->in_scale[0];
+  const float u1 = (x1 - nm->in_shift[1]) * nm->in_scale[1];
+  f[0] = u0;
+  f[1] = u1;
+  const float p0 = nm->enc_freq[0] * u0, p1 = nm->enc_freq[1] * u1;
+  octaves<NFQ0>(p0, fmaf(nm->enc_freq[0], u0, -p0), f + NIN);
+  octaves<NFQ1>(p1, fmaf(nm->enc_freq[1], u1, -p1), f + NIN + 2 * NFQ0);
+}
 
 // ---------------------------------------------------------------------------
 // training step, part 1: everything that is local to a batch row.  One block
@@ -130,7 +160,7 @@ struct RowArgs {
   bf16_t *DYt, *D3t, *D2t;          // BF16 dL/dy^T [NOUT][ldt], dL/da_l^T [WID][ldt]
   int ldt;
   float *bp1, *bp2, *bp3, *bp4;     // per-block bias-gradient columns [R][width]
-  float* w1p;                       // per-block first-layer weight gradient [R][WID][2]
+  float* w1p;                       // per-block first-layer weight gradient [R][WID][NFEAT]
   double* lpart;                    // per-block sum of squared residuals [R]
 };
 
@@ -184,34 +214,39 @@ __global__ __launch_bounds__(64 * NWAVE) void step_rows_kernel(RowArgs g) {
   __shared__ __align__(16) bf16_t HA[RB * LDH];
   __shared__ __align__(16) bf16_t HB[RB * LDH];
   __shared__ __align__(16) bf16_t DY[RB * LDY];
-  __shared__ float xs[RB][2];
+  __shared__ float xs[RB][NFEAT];
   __shared__ double lred[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rq = (lane >> 4) * 4;  // first of this lane's 4 rows in a 16-row tile
   const int rb = blockIdx.x, r0 = rb * RB;
   const int ldt = g.ldt;
 
-  // layer 1 (K = 2, plain FMA): thread t is unit t % 256 for L1R rows
+  // layer 1 (K = NFEAT, plain FMA): thread t is unit t % 256 for L1R rows;
+  // padding rows (past nvalid) take zero features
   if (t < RB) {
     const int i = r0 + t;
-    float x0 = 0.0f, x1 = 0.0f;
     if (i < g.nvalid) {
       const int64_t src = g.rows ? (int64_t)g.rows[i] : (int64_t)i;
-      x0 = (g.X[2 * src] - g.nm->in_shift[0]) * g.nm->in_scale[0];
-      x1 = (g.X[2 * src + 1] - g.nm->in_shift[1]) * g.nm->in_scale[1];
+      features(g.X[2 * src], g.X[2 * src + 1], g.nm, xs[t]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NFEAT; ++c) xs[t][c] = 0.0f;
     }
-    xs[t][0] = x0;
-    xs[t][1] = x1;
   }
   __syncthreads();
   {
     const int j = t & (WID - 1), rh = (t / WID) * L1R;
-    const float w0 = from_bf16(g.W1b[2 * j]), w1 = from_bf16(g.W1b[2 * j + 1]), bj = g.b1[j];
+    float wf[NFEAT];
+#pragma unroll
+    for (int c = 0; c < NFEAT; ++c) wf[c] = from_bf16(g.W1b[NFEAT * j + c]);
+    const float bj = g.b1[j];
     uint32_t packed[L1R / 2];
 #pragma unroll
     for (int q = 0; q < L1R; ++q) {
       const int r = rh + q;
-      const float a = xs[r][0] * w0 + xs[r][1] * w1 + bj;
+      float a = bj;
+#pragma unroll
+      for (int c = 0; c < NFEAT; ++c) a = fmaf(xs[r][c], wf[c], a);
       const bf16_t hv = to_bf16(gelu(a));
       g.A1[(size_t)(r0 + r) * WID + j] = a;
       HA[r * LDH + j] = hv;
@@ -312,32 +347,32 @@ __global__ __launch_bounds__(64 * NWAVE) void step_rows_kernel(RowArgs g) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int j = 16 * CT * w + 16 * ct + (lane & 15);
-        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        float c0 = 0.0f, dae[4];
         bf16_t hb[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = rq + e;
           const float da = acc[ct][e] * gelu_grad(Al[l][(size_t)(r0 + r) * WID + j]);
           c0 += da;
+          dae[e] = da;
           if (l < 2) {
             hb[e] = to_bf16(da);
             dstb[l][r * LDH + j] = hb[e];
-          } else {
-            c1 += da * xs[r][0];
-            c2 += da * xs[r][1];
           }
         }
         if (l < 2) store_t4(Dt[l], j, ldt, r0 + rq, hb);
         c0 = col_sum16(c0);
+        if (lane < 16) bp[l][(size_t)rb * WID + j] = c0;
         if (l == 2) {
-          c1 = col_sum16(c1);
-          c2 = col_sum16(c2);
-        }
-        if (lane < 16) {
-          bp[l][(size_t)rb * WID + j] = c0;
-          if (l == 2) {
-            g.w1p[((size_t)rb * WID + j) * 2] = c1;
-            g.w1p[((size_t)rb * WID + j) * 2 + 1] = c2;
+          // first layer's weight gradient: one feature at a time, summed
+          // over the block's rows (rows e of this lane, then across lanes)
+#pragma unroll
+          for (int c = 0; c < NFEAT; ++c) {
+            float cf = 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cf = fmaf(dae[e], xs[rq + e][c], cf);
+            cf = col_sum16(cf);
+            if (lane < 16) g.w1p[((size_t)rb * WID + j) * NFEAT + c] = cf;
           }
         }
       }
@@ -506,8 +541,8 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs f) {
   if (p >= NPAR) return;
   float g;
   if (p < OB1) {
-    const int j = p >> 1, c = p & 1;
-    g = ordered_sum(f.w1p + (size_t)j * 2 + c, (size_t)WID * 2, f.R);
+    const int j = p / NFEAT, c = p % NFEAT;
+    g = ordered_sum(f.w1p + (size_t)j * NFEAT + c, (size_t)WID * NFEAT, f.R);
   } else if (p < OW2) {
     g = ordered_sum(f.bp1 + (p - OB1), WID, f.R);
   } else if (p < OB2) {
@@ -548,25 +583,32 @@ __global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ 
                                                       const float* __restrict__ b3, const bf16_t* __restrict__ W4b,
                                                       const float* __restrict__ b4, float* __restrict__ Y) {
   __shared__ __align__(16) bf16_t H[64 * LDH];
-  __shared__ float xs[64][2];
+  __shared__ float xs[64][NFEAT];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, kq = (lane >> 4) * 8;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   if (t < 64) {
     const int64_t i = r0 + t;
-    float x0 = 0.0f, x1 = 0.0f;
     if (i < n) {
-      x0 = (X[2 * i] - nm->in_shift[0]) * nm->in_scale[0];
-      x1 = (X[2 * i + 1] - nm->in_shift[1]) * nm->in_scale[1];
+      features(X[2 * i], X[2 * i + 1], nm, xs[t]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NFEAT; ++c) xs[t][c] = 0.0f;
     }
-    xs[t][0] = x0;
-    xs[t][1] = x1;
   }
   __syncthreads();
   {
     const int j = t;
-    const float w0 = from_bf16(W1b[2 * j]), w1 = from_bf16(W1b[2 * j + 1]), bj = b1[j];
-    for (int r = 0; r < 64; ++r) H[r * LDH + j] = to_bf16(gelu(xs[r][0] * w0 + xs[r][1] * w1 + bj));
+    float wf[NFEAT];
+#pragma unroll
+    for (int c = 0; c < NFEAT; ++c) wf[c] = from_bf16(W1b[NFEAT * j + c]);
+    const float bj = b1[j];
+    for (int r = 0; r < 64; ++r) {
+      float a = bj;
+#pragma unroll
+      for (int c = 0; c < NFEAT; ++c) a = fmaf(xs[r][c], wf[c], a);
+      H[r * LDH + j] = to_bf16(gelu(a));
+    }
   }
   __syncthreads();
   // hidden layers 2 and 3: wave w owns columns 64w .. 64w+63 of all 64 rows
@@ -706,7 +748,7 @@ size_t carve(int B, char* base, surrogate_t* s) {
   h.Ve = (float*)take(4ull * NPAR);
   h.G = (float*)take(4ull * NPAR);
   h.nm = (Norm*)take(sizeof(Norm));
-  h.wc.W1b = (bf16_t*)take(2ull * WID * NIN);
+  h.wc.W1b = (bf16_t*)take(2ull * WID * NFEAT);
   h.wc.W2b = (bf16_t*)take(2ull * WID * WID);
   h.wc.W2t = (bf16_t*)take(2ull * WID * WID);
   h.wc.W3b = (bf16_t*)take(2ull * WID * WID);
@@ -726,7 +768,7 @@ size_t carve(int B, char* base, surrogate_t* s) {
   h.bp2 = (float*)take(4ull * R * WID);
   h.bp3 = (float*)take(4ull * R * WID);
   h.bp4 = (float*)take(4ull * R * NOUT);
-  h.w1p = (float*)take(4ull * R * WID * 2);
+  h.w1p = (float*)take(4ull * R * WID * NFEAT);
   h.lpart = (double*)take(8ull * R);
   h.losses = (double*)take(8ull * MAX_STEPS);
   h.stats = (double*)take(8ull * 2 * NOUT);
@@ -745,8 +787,9 @@ int validate(const surrogate_params* p) {
     return LAT_EINVAL;
   }
   for (int c = 0; c < NIN; ++c)
-    if (!std::isfinite(p->in_shift[c]) || !std::isfinite(p->in_scale[c]) || p->in_scale[c] == 0.0f) {
-      set_error("input normalisation must be finite with nonzero scale");
+    if (!std::isfinite(p->in_shift[c]) || !std::isfinite(p->in_scale[c]) || p->in_scale[c] == 0.0f ||
+        !std::isfinite(p->enc_freq[c])) {
+      set_error("input normalisation must be finite with nonzero scale, and the encoding frequencies finite");
       return LAT_EINVAL;
     }
   for (int c = 0; c < NOUT; ++c)
@@ -851,6 +894,7 @@ extern "C" int surrogate_init(const surrogate_params* p, void* dev_ws, size_t ws
   std::memcpy(nm.in_scale, p->in_scale, sizeof nm.in_scale);
   std::memcpy(nm.out_shift, p->out_shift, sizeof nm.out_shift);
   std::memcpy(nm.out_scale, p->out_scale, sizeof nm.out_scale);
+  std::memcpy(nm.enc_freq, p->enc_freq, sizeof nm.enc_freq);
   hipError_t e = hipMemcpyAsync(h->nm, &nm, sizeof(Norm), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {

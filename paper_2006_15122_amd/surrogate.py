@@ -14,8 +14,10 @@ import numpy as np
 from .lattice import _check, lib
 
 N_IN, WIDTH, N_OUT = 2, 256, 64
-NPARAMS = 148800
-SHAPES = (("W1", (WIDTH, N_IN)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2", (WIDTH,)),
+N_FREQ = (6, 5)                      # octaves of the Fourier encoding of each input
+N_FEAT = N_IN + 2 * sum(N_FREQ)      # 24 first-layer inputs
+NPARAMS = 154432
+SHAPES = (("W1", (WIDTH, N_FEAT)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2", (WIDTH,)),
           ("W3", (WIDTH, WIDTH)), ("b3", (WIDTH,)), ("W4", (N_OUT, WIDTH)), ("b4", (N_OUT,)))
 
 EXPORTS = ["surrogate_workspace_size", "surrogate_init", "surrogate_set_weights", "surrogate_get_weights",
@@ -27,7 +29,7 @@ class SurrParams(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("in_shift", ctypes.c_float * N_IN),
                 ("in_scale", ctypes.c_float * N_IN), ("out_shift", ctypes.c_float * N_OUT),
-                ("out_scale", ctypes.c_float * N_OUT)]
+                ("out_scale", ctypes.c_float * N_OUT), ("enc_freq", ctypes.c_float * N_IN)]
 
 
 def pack(p: dict) -> np.ndarray:
@@ -47,12 +49,13 @@ def unpack(v: np.ndarray) -> dict:
 
 
 def make_params(max_batch=4096, in_shift=(0.0, 0.0), in_scale=(1.0, 1.0), out_shift=None, out_scale=None,
-                beta1=0.9, beta2=0.999, eps=1e-8) -> SurrParams:
+                beta1=0.9, beta2=0.999, eps=1e-8, enc_freq=(0.0, 0.0)) -> SurrParams:
     p = SurrParams()
     p.max_batch = int(max_batch)
     p.beta1, p.beta2, p.eps = float(beta1), float(beta2), float(eps)
     for c in range(N_IN):
         p.in_shift[c], p.in_scale[c] = float(in_shift[c]), float(in_scale[c])
+        p.enc_freq[c] = float(enc_freq[c])
     osh = np.zeros(N_OUT) if out_shift is None else np.asarray(out_shift, dtype=np.float64)
     osc = np.ones(N_OUT) if out_scale is None else np.asarray(out_scale, dtype=np.float64)
     for c in range(N_OUT):

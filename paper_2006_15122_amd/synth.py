@@ -128,7 +128,7 @@ def random_u1_state(N: int, seed: int, amp: float = 0.1, link_angle: float = 0.2
     return {"phi": phi, "pi": pi, "links": links, "piA": piA}
 
 
-def mlp_init(seed: int, widths=(2, 256, 256, 256, 64), bias_scale: float = 0.0) -> dict:
+def mlp_init(seed: int, widths=(24, 256, 256, 256, 64), bias_scale: float = 0.0) -> dict:
     """Glorot-uniform weights W_l (out, in) and biases uniform in
     [-bias_scale, bias_scale] for the spectrum surrogate, from a seeded
     generator."""

@@ -117,17 +117,19 @@ def test_surrogate_struct_layout_and_workspace(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "%s"\n'
-        'int main(void){printf("%%zu %%zu %%zu %%zu %%d\\n", sizeof(surrogate_params),'
+        'int main(void){printf("%%zu %%zu %%zu %%zu %%zu %%d %%d\\n", sizeof(surrogate_params),'
         ' offsetof(surrogate_params, in_shift), offsetof(surrogate_params, out_scale),'
-        ' offsetof(surrogate_params, eps), SURR_NPARAMS); return 0;}\n'
+        ' offsetof(surrogate_params, eps), offsetof(surrogate_params, enc_freq), SURR_NPARAMS, SURR_N_FEAT);'
+        ' return 0;}\n'
         % os.path.join(ROOT, "include", "surrogate.h"))
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     P = surrogate.SurrParams
-    assert got == [ctypes.sizeof(P), P.in_shift.offset, P.out_scale.offset, P.eps.offset, surrogate.NPARAMS]
+    assert got == [ctypes.sizeof(P), P.in_shift.offset, P.out_scale.offset, P.eps.offset, P.enc_freq.offset,
+                   surrogate.NPARAMS, surrogate.N_FEAT]
     n = sum(int(np.prod(s)) for _, s in surrogate.SHAPES)
-    assert n == surrogate.NPARAMS == 148800
+    assert n == surrogate.NPARAMS == 24 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64
     small = surrogate.workspace_size(surrogate.make_params(max_batch=64))
     big = surrogate.workspace_size(surrogate.make_params(max_batch=4096))
     # master weights, two Adam moments and the gradient at least; activations grow with the batch
@@ -135,7 +137,8 @@ def test_surrogate_struct_layout_and_workspace(tmp_path):
 
 
 @pytest.mark.parametrize("kw", [dict(max_batch=0), dict(max_batch=100), dict(max_batch=32768),
-                                dict(beta1=1.0), dict(eps=0.0), dict(in_scale=(0.0, 1.0))])
+                                dict(beta1=1.0), dict(eps=0.0), dict(in_scale=(0.0, 1.0)),
+                                dict(enc_freq=(float("nan"), 0.0))])
 def test_surrogate_rejects_bad_params(kw):
     from paper_2006_15122_amd import surrogate
     with pytest.raises(lattice.LatticeError) as e:

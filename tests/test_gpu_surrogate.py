@@ -12,6 +12,7 @@ from paper_2006_15122_amd import synth
 pytestmark = pytest.mark.gpu
 
 IN_SHIFT, IN_SCALE = (2.5, 12.5), (1.0 / 1.5, 1.0 / 12.5)
+ENC = (0.9, 0.4)   # base angular frequencies of the Fourier features
 
 
 def _torch():
@@ -38,7 +39,7 @@ def _out_norm(seed):
 def _model(max_batch, out_shift, out_scale):
     from paper_2006_15122_amd.surrogate import Surrogate
     return Surrogate(max_batch=max_batch, in_shift=IN_SHIFT, in_scale=IN_SCALE, out_shift=out_shift,
-                     out_scale=out_scale)
+                     out_scale=out_scale, enc_freq=ENC)
 
 
 def _f32(v):
@@ -46,9 +47,13 @@ def _f32(v):
 
 
 def _normalise(x, t, osh, osc):
-    """The library's normalisation, evaluated in FP64 from the FP32 inputs and
-    the FP32 constants it holds."""
-    xn = (_f32(x) - _f32(IN_SHIFT)) * _f32(IN_SCALE)
+    """The library's normalisation: the inputs as the kernels form them (FP32
+    difference, then FP32 product: the Fourier features multiply any
+    discrepancy in them by up to 2^5), the targets in FP64 from the FP32
+    values and constants it holds."""
+    f32 = np.float32
+    xn = ((np.asarray(x, f32) - np.asarray(IN_SHIFT, f32)).astype(f32) * np.asarray(IN_SCALE, f32)).astype(f32)
+    xn = xn.astype(np.float64)
     tn = None if t is None else (_f32(t) - _f32(osh)) * _f32(osc)
     return xn, tn
 
@@ -68,16 +73,17 @@ def test_predict_matches_oracle_forward(n):
     x, _ = _inputs(3, n)
     y = m.predict(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
     xn, _ = _normalise(x, None, osh, osc)
-    yn, _ = mlp.forward(w, xn, bf16=True)
+    yn, _ = mlp.forward(w, xn, bf16=True, enc_freq=_f32(ENC))
     ref = yn / _f32(osc) + _f32(osh)
-    # Both sides round to BF16 from an FP32 value, but the GPU's FP32 sums and
-    # the oracle's FP64 ones differ in the last bits, so a few activations in
-    # 10^4 round the other way; each such case moves an output by one BF16
-    # step of one activation times a weight (~1e-4 in normalised units; an
-    # FP32 emulation of the kernels on the CPU peaks at 2.5e-4 over these
-    # rows).  Without the BF16 emulation the difference is 1e-3.
+    # Both sides round to BF16 from an FP32 value, but the GPU's FP32 sums (and
+    # FP32 features) and the oracle's FP64 ones differ in the last bits, so a
+    # few activations in 10^4 round the other way; each such case moves an
+    # output by one BF16 step of one activation times a weight: at most
+    # 2^-8 * |h3| * |W4| ~ 2^-8 * 2 * 0.14 ~ 1.1e-3 in normalised units for
+    # one flip of a last-layer activation near 2 (Glorot bound of W4: 0.14).
+    # The norm below is the systematic check.
     d = (y - ref) * _f32(osc)
-    assert np.max(np.abs(d)) < 6e-4, np.max(np.abs(d))
+    assert np.max(np.abs(d)) < 1.5e-3, np.max(np.abs(d))
     assert np.linalg.norm(d) < 1e-4 * np.linalg.norm(yn), np.linalg.norm(d) / np.linalg.norm(yn)
 
 
@@ -92,7 +98,7 @@ def test_loss_and_gradients_match_oracle_with_bf16_rounding():
     loss, g = m.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), torch.from_numpy(rows).cuda())
     g = g.cpu().numpy().astype(np.float64)
     xn, tn = _normalise(x[rows], t[rows], osh, osc)
-    L, go = mlp.loss_and_grads(w, xn, tn, bf16=True)
+    L, go = mlp.loss_and_grads(w, xn, tn, bf16=True, enc_freq=_f32(ENC))
     assert abs(loss - L) < 1e-5 * L, (loss, L)
     from paper_2006_15122_amd.surrogate import unpack
     gg = unpack(g)
@@ -101,7 +107,7 @@ def test_loss_and_gradients_match_oracle_with_bf16_rounding():
         assert rel < 1e-4, (k, rel)
     # without BF16 emulation the same comparison is visibly worse: the
     # oracle's rounding points are the GPU's
-    _, g64 = mlp.loss_and_grads(w, xn, tn, bf16=False)
+    _, g64 = mlp.loss_and_grads(w, xn, tn, bf16=False, enc_freq=_f32(ENC))
     worse = max(np.max(np.abs(gg[k] - g64[k])) / np.max(np.abs(g64[k])) for k in ("W2", "W3", "W4"))
     assert worse > 1e-4
 
@@ -227,24 +233,38 @@ def test_graph_replayed_epochs_match_eager_epochs():
 
 def test_surrogate_trained_on_lattice_spectra_answers_held_out_q():
     """What the network adds to the method: spectra at new couplings without a
-    lattice run.  A reduced pipeline (256 training runs at 64^3 instead of
-    2000, 8 held-out couplings, 3000 epochs) must land within 25% mean
-    relative error of the 8-seed lattice mean on the judged points, while
-    answering 65536 queries at least 10^4 times faster than the batched
-    lattice produces spectra.  The full-size pipeline (python -m
-    paper_2006_15122_amd.emulator) is the one held to 5%."""
+    lattice run.  The full pipeline (2000 training runs at 64^3, 5000 VV2
+    steps each, 10^5 device spectra; the recipe chosen on a validation split
+    of the training runs; 64 held-out couplings x 8 seeds) must land within 5%
+    mean relative error of the 8-seed lattice mean on the judged points (seed
+    scatter below 2%), and within 6% under the looser judge (standard error
+    below 2%), while answering 65536 queries at least 10^4 times faster than
+    the batched lattice produces spectra.  Linear interpolation in log10 q
+    between the two nearest training runs is reported beside it: with 2000
+    runs over three decades it is the stronger predictor on the low-scatter
+    points (1.2% against 2.8%), while the network is the better one on
+    single-seed validation spectra (it averages over the seeds of neighbouring
+    couplings)."""
     torch = _torch()
     import time
     from paper_2006_15122_amd import emulator
-    tr = synth.config5_train_runs(256)
+    tr = synth.config5_train_runs(2000)
     X, T, tgen = emulator.generate(tr, nsnap=50, every=100)
     assert torch.isfinite(T).all()
-    m, hist, _ = emulator.train(X, T, epochs=3000)
-    assert hist[-1] < 0.5 * hist[0]
-    ho = synth.config5_heldout_runs(8, 8)
-    J = emulator.judge(m, ho, 8, nsnap=50, every=100)
-    assert J["n_judged"] > 1000
-    assert J["mean_rel_err"] < 0.25, J["mean_rel_err"]
+    m, hist, _ = emulator.train(X, T)
+    assert hist[-1] < 0.2 * hist[0]
+    ho = synth.config5_heldout_runs(64, 8)
+    _, TH, _ = emulator.generate(ho, nsnap=50, every=100)
+    J = emulator.judge(m, ho, 8, nsnap=50, every=100, T=TH)
+    pb = emulator.interpolate_in_q(tr, T.cpu().numpy(), [c["q"] for c in ho[::8]], 50)
+    B = emulator.score(pb, 10.0 ** TH.cpu().numpy().astype(np.float64).reshape(64, 8, 50, 64), 8)
+    print("network: judged %d, mean %.4f (looser %.4f); interpolation in q: %.4f (looser %.4f)"
+          % (J["n_judged"], J["mean_rel_err"], J["mean_rel_err_sem"], B["mean_rel_err"], B["mean_rel_err_sem"]),
+          flush=True)
+    assert J["n_judged"] > 20000
+    assert J["mean_rel_err"] < 0.05, J["mean_rel_err"]
+    assert J["mean_rel_err_sem"] < 0.06, J["mean_rel_err_sem"]
+    assert B["n_judged"] == J["n_judged"]
     x = torch.rand(65536, 2, device="cuda:0") * torch.tensor([3.0, 24.5], device="cuda:0") + \
         torch.tensor([1.0, 0.5], device="cuda:0")
     m.predict(x)
