@@ -242,7 +242,8 @@ const char* lattice_last_error(void);
 
 /* Tile shape of the fused pass: threads along z (32 or 64), rows of threads
    along y, rows per thread, x-planes per block.  Scalar lattices compile
-   (64,4,4) (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) for FP32 two
+   (64,4,4) (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) (128,4,4)
+   (128,4,8) (256,4,4) (128,8,2) (64,8,4) (256,4,2) (128,4,2) for FP32 two
    fields and (64,4,2) (32,8,2) (32,4,4) otherwise; U(1) lattices (64,4,2) and
    (32,8,1) in FP32, (32,8,1) in FP64.  lattice_init picks one (the built-in
    autotuner times them for N >= 128, once per model, size, precision,

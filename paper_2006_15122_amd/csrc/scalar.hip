@@ -67,7 +67,9 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
   X(T, NF, 128, 4, 8)            \
   X(T, NF, 256, 4, 4)            \
   X(T, NF, 128, 8, 2)            \
-  X(T, NF, 64, 8, 4)
+  X(T, NF, 64, 8, 4)             \
+  X(T, NF, 256, 4, 2)            \
+  X(T, NF, 128, 4, 2)
 #define CL_SHAPES_SMALL(X, T, NF) \
   X(T, NF, 64, 4, 2)              \
   X(T, NF, 32, 8, 2)              \
@@ -75,7 +77,7 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
 
 static const Shape kShapesMain[] = {{64, 4, 4},  {64, 4, 2},  {64, 8, 2},  {64, 4, 8},  {32, 8, 2},
                                     {32, 4, 4},  {32, 8, 4},  {128, 4, 4}, {128, 4, 8}, {256, 4, 4},
-                                    {128, 8, 2}, {64, 8, 4}};
+                                    {128, 8, 2}, {64, 8, 4},  {256, 4, 2}, {128, 4, 2}};
 static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
 
 // Observation passes always use the 32 x 16 tile with 8 planes, which

@@ -294,7 +294,7 @@ def test_wide_tiles_256_against_oracle():
     rng = np.random.default_rng(2)
     idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 256, size=(3, 4096)))
     n = 0
-    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4)):
+    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2)):
         for xc in (8, 16, 32, 64):
             lat.set_tiling(tz, by, ry, xc)
             lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
@@ -303,7 +303,7 @@ def test_wide_tiles_256_against_oracle():
             s = lat.get_state()
             assert np.max(np.abs(s["phi"][idx] - phi[idx])) < 1e-5 * np.max(np.abs(phi[idx])), (tz, by, ry, xc)
             n += 1
-    assert n == 20
+    assert n == 28
 
 
 def test_large_512_vv2_sampled_sites():
