@@ -151,7 +151,11 @@ def obs_dict(o: Obs, nf: int) -> dict:
 class Lattice:
     """One lattice on one GPU.  cfg: a workload dict (see synth.py)."""
 
-    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, _handle=None, _owner=None):
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, ws_fill=None, _handle=None,
+                 _owner=None):
+        """ws_fill: a byte (0..255) written over the whole workspace before
+        lattice_init, so that a test can show no result depends on what the
+        memory held (0xFF makes every FP32 and FP64 word a NaN)."""
         self.cfg = dict(cfg)
         self.p = params(cfg)
         self.nf = self.p.nf
@@ -168,6 +172,8 @@ class Lattice:
         nbytes = workspace_size(cfg)
         self.device = torch.device(device)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if ws_fill is not None:
+            self.ws.fill_(int(ws_fill))
         base = self.ws.data_ptr()
         off = (-base) % 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -305,7 +311,8 @@ class Batch:
     kernel per pass, whole step calls replayed from a HIP graph).  cfgs: list of
     workload dicts sharing nf, integrator, precision and dt."""
 
-    def __init__(self, cfgs, device: str = "cuda:0", stream=None):
+    def __init__(self, cfgs, device: str = "cuda:0", stream=None, ws_fill=None):
+        """ws_fill: as for Lattice, a byte written over the workspace first."""
         import torch
 
         self.cfgs = [dict(c) for c in cfgs]
@@ -316,6 +323,8 @@ class Batch:
         _check(lib().lattice_batch_workspace_size(P, ctypes.c_int(n), ctypes.byref(nb)))
         self.device = torch.device(device)
         self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        if ws_fill is not None:
+            self.ws.fill_(int(ws_fill))
         base = self.ws.data_ptr()
         off = (-base) % 256
         # graph capture needs a created (non-default) stream; default priority

@@ -84,12 +84,16 @@ class Surrogate:
     """The MLP with its device workspace.  x rows are (log10 q, eta); outputs
     are log10 mode-averaged spectra at 64 log-spaced k."""
 
-    def __init__(self, device="cuda:0", stream=None, **kw):
+    def __init__(self, device="cuda:0", stream=None, ws_fill=None, **kw):
+        """ws_fill: a byte written over the whole workspace before
+        surrogate_init (0xFF: every FP32 word a NaN); kw: make_params."""
         import torch
         self.p = make_params(**kw)
         self.device = torch.device(device)
         nbytes = workspace_size(self.p)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if ws_fill is not None:
+            self.ws.fill_(int(ws_fill))
         # a created stream (default priority), so that training epochs can be
         # captured and replayed as HIP graphs
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
