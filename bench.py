@@ -24,13 +24,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 # (tz, by, ry) shapes the library's autotuner times for FP32 two-field lattices
 TUNER_SHAPES = ((64, 4, 4), (64, 4, 2), (64, 8, 2), (64, 4, 8), (32, 8, 2), (32, 4, 4), (32, 8, 4),
-                (128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2))
+                (128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2),
+                (128, 16, 1), (256, 8, 1), (512, 4, 1))
 BYTES_PER_SITE_VV2_NF2_FP32 = 32  # read phi, chi, pi_phi, pi_chi; write the same (FP32)
 
 
 def _kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("scalar.hip", "scalar_tile.hpp", "common.hpp"):
+    for f in ("scalar.hip", "scalar_tile.hpp", "scalar_rows.hpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2006_15122_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -240,11 +240,14 @@ int lattice_destroy(lattice_t* h);
 /* Text of the calling thread's last error ("" if none). */
 const char* lattice_last_error(void);
 
-/* Tile shape of the fused pass: threads along z (32 or 64), rows of threads
-   along y, rows per thread, x-planes per block.  Scalar lattices compile
-   (64,4,4) (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) (128,4,4)
-   (128,4,8) (256,4,4) (128,8,2) (64,8,4) (256,4,2) (128,4,2) for FP32 two
-   fields and (64,4,2) (32,8,2) (32,4,4) otherwise; U(1) lattices (64,4,2) and
+/* Tile shape of the fused pass: threads along z, rows of threads along y,
+   rows per thread, x-planes per block.  Scalar lattices compile (64,4,4)
+   (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) (128,4,4) (128,4,8)
+   (256,4,4) (128,8,2) (64,8,4) (256,4,2) (128,4,2) for FP32 two fields, plus
+   the full-row tiles (128,16,1) (256,8,1) (512,4,1), valid only where the first
+   number equals N: a block holds whole z-rows, four sites per thread, and
+   each site's update is bit for bit the general tiles'.  Other scalar
+   storage and field counts compile (64,4,2) (32,8,2) (32,4,4); U(1) lattices (64,4,2) and
    (32,8,1) in FP32, (32,8,1) in FP64.  lattice_init picks one (the built-in
    autotuner times them for N >= 128, once per model, size, precision,
    integrator and expansion in a process, so that later lattices of the same
@@ -253,7 +256,8 @@ const char* lattice_last_error(void);
 int lattice_get_tiling(lattice_t* h, int32_t* tz, int32_t* by, int32_t* ry, int32_t* xc);
 
 /* Force a tile shape (for the autotuner and tests).  Errors: LAT_EINVAL if
-   the shape is not compiled or does not divide N. */
+   the shape is not compiled, does not divide N, or is a full-row tile of
+   another N. */
 int lattice_set_tiling(lattice_t* h, int32_t tz, int32_t by, int32_t ry, int32_t xc);
 
 /* Kernel timing of the fused pass (scalar or U(1)).  After lattice_pass_timer(h, n),

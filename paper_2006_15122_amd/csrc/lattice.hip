@@ -694,6 +694,7 @@ bool tiling_ok(const lattice* h, const Tiling& t) {
   }
   if (!compiled) return false;
   const int N = h->p.N;
+  if (!u1 && t.ry == 1 && t.tz != N) return false;  // full-row tiles hold whole z-rows
   const int ty = t.by * t.ry;
   if (N % t.tz || N % ty || t.xc < 1 || N % t.xc) return false;
   const int64_t nb = (int64_t)(N / t.tz) * (N / ty) * (N / t.xc);

@@ -24,6 +24,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "scalar_rows.hpp"
 #include "scalar_tile.hpp"
 
 namespace cl {
@@ -53,6 +54,20 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
   return hipGetLastError();
 }
 
+// Full-row tiles (FP32 stepping passes): tz = N, ry = 1, by y-rows per block.
+template <int NF, int NL, int BY>
+hipError_t launch_rows(const ScalarArgs<float>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                       DevState* fin) {
+  if (ev0)
+    hipExtLaunchKernelGGL((scalar_rows_kernel<NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, ev0, ev1, 0, A);
+  else
+    hipLaunchKernelGGL((scalar_rows_kernel<NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !fin) return e;
+  hipLaunchKernelGGL((scalar_finish_kernel<float, NF, false>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
+  return hipGetLastError();
+}
+
 // Stepping passes: every compiled tile shape (FP32 two-field is the
 // production case; the other storage/field combinations get a subset).
 #define CL_SHAPES_MAIN(X, T, NF) \
@@ -75,9 +90,17 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
   X(T, NF, 32, 8, 2)              \
   X(T, NF, 32, 4, 4)
 
+// full-row shapes (tz = N sites, by rows, ry = 1), 512 lanes, for N = 128,
+// 256 and 512 (1024-lane blocks of these spill)
+#define CL_ROWS_MAIN(X, NF) \
+  X(NF, 128, 16)            \
+  X(NF, 256, 8)             \
+  X(NF, 512, 4)
+
 static const Shape kShapesMain[] = {{64, 4, 4},  {64, 4, 2},  {64, 8, 2},  {64, 4, 8},  {32, 8, 2},
                                     {32, 4, 4},  {32, 8, 4},  {128, 4, 4}, {128, 4, 8}, {256, 4, 4},
-                                    {128, 8, 2}, {64, 8, 4},  {256, 4, 2}, {128, 4, 2}};
+                                    {128, 8, 2}, {64, 8, 4},  {256, 4, 2}, {128, 4, 2}, {128, 16, 1},
+                                    {256, 8, 1}, {512, 4, 1}};
 static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
 
 // Observation passes always use the 32 x 16 tile with 8 planes, which
@@ -97,6 +120,10 @@ hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nbl
     return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s, ev0, ev1, fin);
   if constexpr (std::is_same<T, float>::value && NF == 2) {
     CL_SHAPES_MAIN(X, T, NF)
+#define XR(NFF, n, b) \
+  if (sh.tz == n && sh.by == b && sh.ry == 1) return launch_rows<NFF, n / 4, b>(A, nblocks, s, ev0, ev1, fin);
+    CL_ROWS_MAIN(XR, NF)
+#undef XR
   } else {
     CL_SHAPES_SMALL(X, T, NF)
   }
@@ -122,6 +149,7 @@ hipError_t launch_scalar_pass(int fp32, int nf, const void* const* src, void* co
                               int* nblocks_out, int full, hipEvent_t ev0, hipEvent_t ev1, const PrevPass& prev,
                               DevState* fin) {
   if (full && (prev.partials || !fin)) return hipErrorInvalidValue;  // observation passes finish themselves
+  if ((pd.write != 0) == (full != 0)) return hipErrorInvalidValue;    // stepping passes store, observations do not
   if (full) {
     tz = kObsTz;
     by = kObsBy;

@@ -328,16 +328,20 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
         pc[f][r] = fma_c(cdrift, qc[f][r], pc[f][r]);
       }
     store_lds(pc, hp1, hq1);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
   }
 
-  for (int i = 0; i < A.XC; ++i) {
+  // One plane of the stencil.  (pn, qn) hold raw plane x+1 and (hpa, hqa) the
+  // halo of x+1; plane x+2 is loaded into (pf, qf) and (hpb, hqb).  The loop
+  // below calls this twice per trip with the two register sets swapped, so
+  // that no register copy has to wait for the loads just issued: they are
+  // first used one plane later.
+  auto plane = [&](int i, T (&pn)[NF][RY], T (&qn)[NF][RY], T (&pf)[NF][RY], T (&qf)[NF][RY],
+                   T (&hpa)[NF], T (&hqa)[NF], T (&hpb)[NF], T (&hqb)[NF]) {
     const int x = x0 + i;
     // issue loads of plane x+2, two planes ahead of the stencil
     if (i + 1 < A.XC) {
       load_own((x + 2) % N, pf, qf);
-      if (i + 2 < A.XC) load_halo((x + 2) % N, hp2, hq2);
+      if (i + 2 < A.XC) load_halo((x + 2) % N, hpb, hqb);
     }
     __syncthreads();
 #pragma unroll
@@ -361,9 +365,12 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
         const T pin = qc[f][r];
         const T pout = fma_c(ckick, K, pin);
         const T pe = fma_c(cE, K, pin);
-        if (A.pd.write) {
-          // streaming stores: the new state is read again only by the next
-          // pass, so keep it from evicting the halo rows other tiles still need
+        if constexpr (!FULL) {
+          // stepping passes always store and observation passes never do (the
+          // launcher checks pd.write against this), so no branch splits the
+          // count of memory operations in flight.  Streaming stores: the new
+          // state is read again only by the next pass, so keep it from
+          // evicting the halo rows other tiles still need
           __builtin_nontemporal_store(cur[f], &A.dst[f][o]);
           __builtin_nontemporal_store(pout, &A.dst[2 + f][o]);
         }
@@ -400,7 +407,7 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       }
     }
     __syncthreads();
-    // shift: plane x+1 becomes current, x+2 becomes next
+    // shift: plane x+1 becomes current (x+2 becomes next by the swap)
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -408,14 +415,12 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
         pm[f][r] = pc[f][r];
         pc[f][r] = fma_c(cdrift, qn[f][r], pn[f][r]);
         qc[f][r] = qn[f][r];
-        pn[f][r] = pf[f][r];
-        qn[f][r] = qf[f][r];
       }
-    if (i + 1 < A.XC) {
-      store_lds(pc, hp1, hq1);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) { hp1[f] = hp2[f]; hq1[f] = hq2[f]; }
-    }
+    if (i + 1 < A.XC) store_lds(pc, hpa, hqa);
+  };
+  for (int i = 0; i < A.XC; i += 2) {
+    plane(i, pn, qn, pf, qf, hp2, hq2, hp1, hq1);
+    if (i + 1 < A.XC) plane(i + 1, pf, qf, pn, qn, hp1, hq1, hp2, hq2);
   }
   block_partials<T, NF, FULL, NT>(A, acc, pidx);
 }

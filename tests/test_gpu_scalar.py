@@ -294,7 +294,8 @@ def test_wide_tiles_256_against_oracle():
     rng = np.random.default_rng(2)
     idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 256, size=(3, 4096)))
     n = 0
-    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2)):
+    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2),
+                         (256, 8, 1)):
         for xc in (8, 16, 32, 64):
             lat.set_tiling(tz, by, ry, xc)
             lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
@@ -303,7 +304,49 @@ def test_wide_tiles_256_against_oracle():
             s = lat.get_state()
             assert np.max(np.abs(s["phi"][idx] - phi[idx])) < 1e-5 * np.max(np.abs(phi[idx])), (tz, by, ry, xc)
             n += 1
-    assert n == 28
+    assert n == 32
+
+
+def test_full_row_tiles_128_against_oracle():
+    """The full-row tiles (a block holds whole z-rows, four sites per lane) at
+    128^3 over every x-chunk down to 2 planes, against the oracle after 6 steps."""
+    cfg = synth.small(synth.config2(q=100.0), 128)
+    st = synth.random_state(cfg, seed=21, amp=0.3, mom=0.3)
+    m = oracle.scalar_model(cfg)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    a, b = oracle.vv_steps(m, phi, pi, 1.0, 0.5, cfg["dt"], "vv2", 6, omp=True)
+    o = oracle.sync_observe(m, phi, pi, a, b)
+    lat = _lattice(cfg)
+    n = 0
+    for (tz, by, ry) in ((128, 16, 1),):
+        for xc in (2, 4, 8, 16, 32, 128):
+            lat.set_tiling(tz, by, ry, xc)
+            lat.set_state(st["phi"], st["pi"], 1.0, 0.5)
+            lat.step(6)
+            compare_obs(lat.energies(), o, 2, 1e-5, f"tile {tz},{by},{ry},{xc}")
+            s = lat.get_state()
+            assert np.max(np.abs(s["phi"] - phi)) < 1e-5 * np.max(np.abs(phi)), (tz, by, ry, xc)
+            assert np.max(np.abs(s["pi"] - pi)) < 1e-5 * np.max(np.abs(pi)), (tz, by, ry, xc)
+            n += 1
+    assert n == 6
+
+
+def test_full_row_tile_pass_is_bitwise_the_general_tiles():
+    """One pass from the uploaded a and b (the leapfrog start-up kick): the
+    full-row tiles do each site's arithmetic exactly as the general tile does,
+    so the new fields and momenta agree bit for bit."""
+    cfg = dict(synth.small(synth.config2(q=100.0), 256), integrator="lf2")
+    st = synth.random_state(cfg, seed=22, amp=0.3, mom=0.3)
+    lat = _lattice(cfg)
+    out = []
+    for t in ((128, 8, 2, 32), (256, 8, 1, 16), (256, 8, 1, 32), (256, 8, 1, 64)):
+        lat.set_tiling(*t)
+        lat.set_state(st["phi"], st["pi"], 1.0, 0.5)
+        lat.step(0)
+        out.append(lat.get_state())
+    for k, s in enumerate(out[1:]):
+        assert np.array_equal(s["phi"], out[0]["phi"]), k
+        assert np.array_equal(s["pi"], out[0]["pi"]), k
 
 
 def test_large_512_vv2_sampled_sites():
