@@ -90,12 +90,20 @@ def test_batch_vv4_and_run_handles():
     B.close()
 
 
-def test_every_batch_tiling_agrees():
+def test_every_batch_tiling_against_oracle():
+    """Every compiled batch tile shape and x-chunk that divides all three sizes,
+    each run against the FP64 oracle from the same state (6 VV2 steps)."""
     from paper_2006_15122_amd.lattice import Batch
 
     cfgs = _runs(sizes=(32, 64, 96))
+    states = [synth.random_state(c, seed=50 + r, amp=0.2, mom=0.2) for r, c in enumerate(cfgs)]
+    ref = []
+    for c, st in zip(cfgs, states):
+        m = oracle.scalar_model(c)
+        phi, pi = st["phi"].copy(), st["pi"].copy()
+        a, b = oracle.vv_steps(m, phi, pi, 1.0, 0.3, c["dt"], "vv2", 6, omp=True)
+        ref.append(oracle.sync_observe(m, phi, pi, a, b))
     B = Batch(cfgs)
-    ref = None
     n = 0
     for (tz, by, ry) in [(32, 8, 2), (32, 4, 4), (32, 8, 4), (64, 4, 2), (64, 4, 4)]:
         for xc in (8, 16, 32):
@@ -103,15 +111,12 @@ def test_every_batch_tiling_agrees():
                 B.set_tiling(tz, by, ry, xc)
             except Exception:
                 continue
-            for r, c in enumerate(cfgs):
-                st = synth.random_state(c, seed=50 + r, amp=0.2, mom=0.2)
+            for r, st in enumerate(states):
                 B.runs[r].set_state(st["phi"], st["pi"], 1.0, 0.3)
             B.step(6)
-            e = [x["EK"] + x["EG"] + x["EV"] for x in B.energies()]
-            if ref is None:
-                ref = e
-            for r in range(3):
-                assert _rel(e[r], ref[r]) < 1e-6, (tz, by, ry, xc, r)
+            for r, e in enumerate(B.energies()):
+                for k in ("a", "b", "EK", "EG", "EV"):
+                    assert _rel(e[k], ref[r][k]) < 1e-5, (tz, by, ry, xc, r, k, e[k], ref[r][k])
             n += 1
     assert n >= 6
     B.close()
