@@ -246,8 +246,10 @@ const char* lattice_last_error(void);
    (256,4,4) (128,8,2) (64,8,4) (256,4,2) (128,4,2) for FP32 two fields, plus
    the full-row tiles (128,16,1) (256,8,1) (512,4,1), valid only where the first
    number equals N: a block holds whole z-rows, four sites per thread, and
-   each site's update is bit for bit the general tiles'.  Other scalar
-   storage and field counts compile (64,4,2) (32,8,2) (32,4,4); U(1) lattices (64,4,2) and
+   each site's update is bit for bit the general tiles'.  FP64 two fields
+   compile (64,4,2) (32,8,2) (32,4,4) and the full-row tiles (128,8,1)
+   (256,4,1) (512,2,1) (two sites per thread); other scalar storage and field
+   counts (64,4,2) (32,8,2) (32,4,4); U(1) lattices (64,4,2) and
    (32,8,1) in FP32, (32,8,1) in FP64.  lattice_init picks one (the built-in
    autotuner times them for N >= 128, once per model, size, precision,
    integrator and expansion in a process, so that later lattices of the same

@@ -54,17 +54,17 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
   return hipGetLastError();
 }
 
-// Full-row tiles (FP32 stepping passes): tz = N, ry = 1, by y-rows per block.
-template <int NF, int NL, int BY>
-hipError_t launch_rows(const ScalarArgs<float>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+// Full-row tiles (stepping passes): tz = N, ry = 1, by y-rows per block.
+template <typename T, int NF, int NL, int BY>
+hipError_t launch_rows(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
                        DevState* fin) {
   if (ev0)
-    hipExtLaunchKernelGGL((scalar_rows_kernel<NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, ev0, ev1, 0, A);
+    hipExtLaunchKernelGGL((scalar_rows_kernel<T, NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, ev0, ev1, 0, A);
   else
-    hipLaunchKernelGGL((scalar_rows_kernel<NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, A);
+    hipLaunchKernelGGL((scalar_rows_kernel<T, NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !fin) return e;
-  hipLaunchKernelGGL((scalar_finish_kernel<float, NF, false>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
+  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, false>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
   return hipGetLastError();
 }
 
@@ -91,17 +91,23 @@ hipError_t launch_rows(const ScalarArgs<float>& A, int nblocks, hipStream_t s, h
   X(T, NF, 32, 4, 4)
 
 // full-row shapes (tz = N sites, by rows, ry = 1), 512 lanes, for N = 128,
-// 256 and 512 (1024-lane blocks of these spill)
+// 256 and 512 (1024-lane blocks of these spill): four sites per lane in
+// FP32 storage, two in FP64
 #define CL_ROWS_MAIN(X, NF) \
-  X(NF, 128, 16)            \
-  X(NF, 256, 8)             \
-  X(NF, 512, 4)
+  X(float, NF, 128, 16, 4)  \
+  X(float, NF, 256, 8, 4)   \
+  X(float, NF, 512, 4, 4)
+#define CL_ROWS_F64(X, NF)  \
+  X(double, NF, 128, 8, 2)  \
+  X(double, NF, 256, 4, 2)  \
+  X(double, NF, 512, 2, 2)
 
 static const Shape kShapesMain[] = {{64, 4, 4},  {64, 4, 2},  {64, 8, 2},  {64, 4, 8},  {32, 8, 2},
                                     {32, 4, 4},  {32, 8, 4},  {128, 4, 4}, {128, 4, 8}, {256, 4, 4},
                                     {128, 8, 2}, {64, 8, 4},  {256, 4, 2}, {128, 4, 2}, {128, 16, 1},
                                     {256, 8, 1}, {512, 4, 1}};
 static const Shape kShapesSmall[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}};
+static const Shape kShapesF64[] = {{64, 4, 2}, {32, 8, 2}, {32, 4, 4}, {128, 8, 1}, {256, 4, 1}, {512, 2, 1}};
 
 // Observation passes always use the 32 x 16 tile with 8 planes, which
 // divides every supported N.
@@ -120,22 +126,26 @@ hipError_t launch_scalar_pass_t(const ScalarArgs<T>& A, const Shape& sh, int nbl
     return launch_shape<TT, NFF, false, a, b, c>(A, nblocks, s, ev0, ev1, fin);
   if constexpr (std::is_same<T, float>::value && NF == 2) {
     CL_SHAPES_MAIN(X, T, NF)
-#define XR(NFF, n, b) \
-  if (sh.tz == n && sh.by == b && sh.ry == 1) return launch_rows<NFF, n / 4, b>(A, nblocks, s, ev0, ev1, fin);
+#define XR(TT, NFF, n, b, w) \
+  if (sh.tz == n && sh.by == b && sh.ry == 1) return launch_rows<TT, NFF, n / w, b>(A, nblocks, s, ev0, ev1, fin);
     CL_ROWS_MAIN(XR, NF)
-#undef XR
   } else {
     CL_SHAPES_SMALL(X, T, NF)
+    if constexpr (std::is_same<T, double>::value && NF == 2) {
+      CL_ROWS_F64(XR, NF)
+    }
+#undef XR
   }
 #undef X
   return hipErrorInvalidValue;
 }
 
 int num_shapes(int fp32, int nf) {
-  return (fp32 && nf == 2) ? (int)(sizeof(kShapesMain) / sizeof(Shape)) : (int)(sizeof(kShapesSmall) / sizeof(Shape));
+  if (nf == 2) return fp32 ? (int)(sizeof(kShapesMain) / sizeof(Shape)) : (int)(sizeof(kShapesF64) / sizeof(Shape));
+  return (int)(sizeof(kShapesSmall) / sizeof(Shape));
 }
 void get_shape(int fp32, int nf, int i, int* tz, int* by, int* ry) {
-  const Shape& sh = (fp32 && nf == 2) ? kShapesMain[i] : kShapesSmall[i];
+  const Shape& sh = nf == 2 ? (fp32 ? kShapesMain[i] : kShapesF64[i]) : kShapesSmall[i];
   *tz = sh.tz;
   *by = sh.by;
   *ry = sh.ry;

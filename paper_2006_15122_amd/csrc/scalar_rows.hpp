@@ -1,7 +1,8 @@
-// Full-row tile of the fused scalar pass, FP32 storage (stepping passes).
+// Full-row tile of the fused scalar pass (stepping passes).
 //
-// A block holds whole z-rows of the lattice: N = 4 NL sites per row, four
-// consecutive sites per lane, moved as one 16-byte access.  It owns BY
+// A block holds whole z-rows of the lattice: N = W NL sites per row, W
+// consecutive sites per lane moved as one 16-byte access (W = 4 in FP32
+// storage, 2 in FP64).  It owns BY
 // consecutive y-rows and marches along x over XC planes, like the general
 // tile, with the same arithmetic in the same order, so every site's new
 // field and momentum are bit-for-bit those of the general tile.  What
@@ -20,19 +21,42 @@
 
 namespace cl {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+// 16 bytes of consecutive sites: the vector a lane loads and stores
+template <typename T>
+struct RowVec;
+template <>
+struct RowVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <>
+struct RowVec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
 
-template <int NF, int NL, int BY, typename GetAB>
-__device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile, int pidx, GetAB get_ab) {
-  using T = float;
-  constexpr int N = 4 * NL;
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+// the W sites' terms of one lane, summed pairwise
+template <typename T, int W>
+__device__ __forceinline__ T lane_sum(const T (&v)[W]) {
+  if constexpr (W == 4) return (v[0] + v[1]) + (v[2] + v[3]);
+  return v[0] + v[1];
+}
+
+template <typename T, int NF, int NL, int BY, typename GetAB>
+__device__ __forceinline__ void scalar_rows(const ScalarArgs<T>& A, int tile, int pidx, GetAB get_ab) {
+  using VW = typename RowVec<T>::type;  // W consecutive sites
+  constexpr int W = RowVec<T>::W;
+  constexpr int N = W * NL;
   constexpr int NT = NL * BY;
   constexpr int NACC = Acc<NF, false>::N;
   static_assert(NT % 64 == 0 && NT <= 1024, "block of whole waves");
   // drifted planes in two buffers: plane x0 + i in buffer i & 1 (x0 - 1 in
   // buffer 1), rows y0-1 .. y0+BY, each a whole z-row; the x-1 neighbours of
   // the stencil are read from the other buffer
-  __shared__ f32x4 lds[2][NF][BY + 2][NL];
+  __shared__ VW lds[2][NF][BY + 2][NL];
 
   const int tid = threadIdx.x;
   const int tz = tid % NL, ty = tid / NL;
@@ -56,7 +80,7 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
   const int ly = 1 + ty;
   // register planes (four sites each): pc = drifted x, qc = momentum at x,
   // (pn, qn) = raw x+1, (pf, qf) = raw x+2 in flight
-  f32x4 pc[NF], qc[NF], pn[NF], qn[NF], pf[NF], qf[NF];
+  VW pc[NF], qc[NF], pn[NF], qn[NF], pf[NF], qf[NF];
 
   // halo rows y0-1 and y0+BY of plane x+1, loaded one plane ahead of their
   // use: 2 NF N single sites spread over all lanes, KH per lane
@@ -64,9 +88,9 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
   constexpr int KH = (NHI + NT - 1) / NT;
   T hp[KH], hq[KH];
 
-  auto at = [&](const T* base, size_t o) { return *reinterpret_cast<const f32x4*>(base + o); };
-  auto load_own = [&](int x, f32x4 (&p)[NF], f32x4 (&pq)[NF]) {
-    const size_t o = (size_t)x * NN + (size_t)y * N + 4 * tz;
+  auto at = [&](const T* base, size_t o) { return *reinterpret_cast<const VW*>(base + o); };
+  auto load_own = [&](int x, VW (&p)[NF], VW (&pq)[NF]) {
+    const size_t o = (size_t)x * NN + (size_t)y * N + W * tz;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       p[f] = at(A.src[f], o);
@@ -97,7 +121,7 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
   // prologue: planes x0-1 (drifted, into buffer 1), x0 (drifted, into
   // buffer 0 with its halo), x0+1 (raw, in flight)
   const int xm = (x0 - 1 + N) % N;
-  f32x4 pm[NF];
+  VW pm[NF];
   load_own(xm, pm, qf);  // qf: momentum of plane x0-1, only needed for its drift
   double a_in, b_in;
   get_ab(a_in, b_in);
@@ -109,10 +133,10 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
   const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
   const Coef<T> clap = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
   const Coef<T> cpot = ucoef<T>(pow(anew, 3.0 + A.alpha));
-  auto drift = [&](const f32x4& qv, const f32x4& pv) {
-    f32x4 r;
+  auto drift = [&](const VW& qv, const VW& pv) {
+    VW r;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = fma_c(cdrift, qv[e], pv[e]);
+    for (int e = 0; e < W; ++e) r[e] = fma_c(cdrift, qv[e], pv[e]);
     return r;
   };
   // the drifted plane into LDS buffer b: own rows from registers, halo rows
@@ -139,7 +163,7 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
   // One plane (x = x0 + i, in buffer B = i & 1); called twice per trip with
   // the register sets swapped (see the general tile): (pn, qn) hold raw plane
   // x+1, plane x+2 is loaded into (pf, qf), the halo rows of x+1 into (hp, hq).
-  auto plane = [&](int i, auto bsel, f32x4 (&pn)[NF], f32x4 (&qn)[NF], f32x4 (&pf)[NF], f32x4 (&qf)[NF]) {
+  auto plane = [&](int i, auto bsel, VW (&pn)[NF], VW (&qn)[NF], VW (&pf)[NF], VW (&qf)[NF]) {
     constexpr int B = decltype(bsel)::value;
     const int x = x0 + i;
     if (i + 1 < A.XC) {
@@ -147,42 +171,42 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
       load_halo((x + 1) % N);
     }
     __syncthreads();
-    const size_t o = (size_t)x * NN + (size_t)y * N + 4 * tz;
+    const size_t o = (size_t)x * NN + (size_t)y * N + W * tz;
     // plane x+1 drifted, in place
 #pragma unroll
     for (int f = 0; f < NF; ++f) pn[f] = drift(qn[f], pn[f]);
-    // the potential at the four sites, summed pairwise in FP32 and added to
-    // the FP64 total once per plane
+    // the potential at the lane's W sites, summed pairwise in storage
+    // precision and added to the FP64 total once per plane
     {
-      T v4[4];
+      T v4[W];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < W; ++e) {
         const T p2 = pc[0][e] * pc[0][e];
-        T v = p2 * fmaf(qlam, p2, hm2_0);
+        T v = p2 * fma_t(qlam, p2, hm2_0);
         if constexpr (NF > 1) {
           const T c2 = pc[1][e] * pc[1][e];
-          v = fmaf(c2, fmaf(hqq, p2, hm2_1), v);
+          v = fma_t(c2, fma_t(hqq, p2, hm2_1), v);
         }
         v4[e] = v;
       }
-      acc[3] += (double)((v4[0] + v4[1]) + (v4[2] + v4[3]));
+      acc[3] += (double)lane_sum<T, W>(v4);
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const f32x4 xm4 = lds[1 - B][f][ly][tz];
-      const f32x4 yp = lds[B][f][ly + 1][tz], ym = lds[B][f][ly - 1][tz];
+      const VW xm4 = lds[1 - B][f][ly][tz];
+      const VW yp = lds[B][f][ly + 1][tz], ym = lds[B][f][ly - 1][tz];
       // the z-neighbours outside the lane's four sites, periodic in the row
-      const T zlo = lds[B][f][ly][(tz + NL - 1) % NL][3];
+      const T zlo = lds[B][f][ly][(tz + NL - 1) % NL][W - 1];
       const T zhi = lds[B][f][ly][(tz + 1) % NL][0];
-      f32x4 pout;
+      VW pout;
       T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < W; ++e) {
         T cur[NF];
 #pragma unroll
         for (int g = 0; g < NF; ++g) cur[g] = pc[g][e];
         const T c = cur[f];
-        const T zp = e == 3 ? zhi : pc[f][e + 1];
+        const T zp = e == W - 1 ? zhi : pc[f][e + 1];
         const T zm = e == 0 ? zlo : pc[f][e - 1];
         // the general tile's Laplacian, term for term
         const T lap = ((xm4[e] - c) + (pn[f][e] - c)) + ((yp[e] - c) + (ym[e] - c)) + ((zp - c) + (zm - c));
@@ -191,17 +215,17 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
         pout[e] = fma_c(ckick, K, pin);
         const T pe = fma_c(cE, K, pin);
         const T gx = pn[f][e] - c, gy = yp[e] - c, gz = zp - c;
-        s0 = fmaf(pin, pin, s0);
-        s1 = fmaf(pe, pe, s1);
+        s0 = fma_t(pin, pin, s0);
+        s1 = fma_t(pe, pe, s1);
         s2 += gx * gx + gy * gy + gz * gz;
       }
-      // the four sites' terms summed in FP32, then into the FP64 totals
+      // the W sites' terms summed in storage precision, then into the FP64 totals
       if (lf) acc[0] += (double)s0;
       acc[1] += (double)s1;
       acc[2] += (double)s2;
       // streaming stores of the new state (read again only by the next pass)
-      __builtin_nontemporal_store(pc[f], reinterpret_cast<f32x4*>(A.dst[f] + o));
-      __builtin_nontemporal_store(pout, reinterpret_cast<f32x4*>(A.dst[2 + f] + o));
+      __builtin_nontemporal_store(pc[f], reinterpret_cast<VW*>(A.dst[f] + o));
+      __builtin_nontemporal_store(pout, reinterpret_cast<VW*>(A.dst[2 + f] + o));
     }
     __syncthreads();
 #pragma unroll
@@ -221,8 +245,8 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<float>& A, int tile
 
 // About 145 VGPRs: one 512-lane block per CU.  Holding it to 128 (two
 // blocks per CU) spills inside the plane loop and is slower.
-template <int NF, int NL, int BY>
-__global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<float> A) {
+template <typename T, int NF, int NL, int BY>
+__global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<T> A) {
   int bid = blockIdx.x;
   if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
   auto get_ab = [&](double& a_in, double& b_in) {
@@ -232,7 +256,7 @@ __global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<float> A
       double S[NP];
       if (reduce_partials<NP, NL * BY>(A.prev.partials, 0, A.prev.nblocks, S)) {
         double an, bn;
-        finish_state<float, NF, false>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
+        finish_state<T, NF, false>(A, A.prev.pd, A.st, S, blockIdx.x == 0 ? A.prev.out : nullptr, an, bn);
         ab[0] = an;
         ab[1] = bn;
       }
@@ -244,7 +268,7 @@ __global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<float> A
       b_in = A.st->b;
     }
   };
-  scalar_rows<NF, NL, BY>(A, bid, blockIdx.x, get_ab);
+  scalar_rows<T, NF, NL, BY>(A, bid, blockIdx.x, get_ab);
 }
 
 }  // namespace cl

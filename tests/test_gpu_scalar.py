@@ -349,6 +349,64 @@ def test_full_row_tile_pass_is_bitwise_the_general_tiles():
         assert np.array_equal(s["pi"], out[0]["pi"]), k
 
 
+def test_full_row_tiles_fp64_against_oracle():
+    """FP64 storage (two sites per lane) on the full-row tiles: 128^3 over
+    several x-chunks and 256^3 on the 256 x 4 tile, against the oracle at the
+    FP64 tolerance."""
+    for N, shape, xcs, nsteps in ((128, (128, 8, 1), (2, 8, 32, 128), 6), (256, (256, 4, 1), (32,), 3)):
+        cfg = dict(synth.small(synth.config2(q=100.0), N), precision="fp64")
+        st = synth.random_state(cfg, seed=23, amp=0.3, mom=0.3)
+        m = oracle.scalar_model(cfg)
+        phi, pi = st["phi"].copy(), st["pi"].copy()
+        a, b = oracle.vv_steps(m, phi, pi, 1.0, 0.5, cfg["dt"], "vv2", nsteps, omp=True)
+        o = oracle.sync_observe(m, phi, pi, a, b)
+        lat = _lattice(cfg)
+        for xc in xcs:
+            lat.set_tiling(*shape, xc)
+            lat.set_state(st["phi"], st["pi"], 1.0, 0.5)
+            lat.step(nsteps)
+            compare_obs(lat.energies(), o, 2, 1e-10, f"fp64 tile {shape},{xc}")
+            s = lat.get_state()
+            assert np.max(np.abs(s["phi"] - phi)) < 1e-10 * np.max(np.abs(phi)), (N, xc)
+            assert np.max(np.abs(s["pi"] - pi)) < 1e-10 * np.max(np.abs(pi)), (N, xc)
+        lat.close()
+
+
+def test_full_row_tile_fp64_512_sampled_sites():
+    # the 512 x 2 full-row tile (two rows per block, two sites per lane)
+    cfg = dict(synth.config2(q=100.0, N=512), precision="fp64")
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_tiling(512, 2, 1, 32)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+    lat.step(2)
+    phi, pi = st["phi"], st["pi"]
+    a, b = oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], "vv2", 2, omp=True)
+    compare_obs(lat.energies(), oracle.sync_observe(m, phi, pi, a, b), 2, 1e-10, "512^3 fp64 rows")
+    s = lat.get_state()
+    rng = np.random.default_rng(3)
+    idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 512, size=(3, 4096)))
+    for arr, ref in ((s["phi"], phi), (s["pi"], pi)):
+        assert np.max(np.abs(arr[idx] - ref[idx])) < 1e-10 * np.max(np.abs(ref[idx]))
+    lat.close()
+
+
+def test_full_row_tile_fp64_pass_is_bitwise_the_general_tiles():
+    cfg = dict(synth.small(synth.config2(q=100.0), 256), integrator="lf2", precision="fp64")
+    st = synth.random_state(cfg, seed=24, amp=0.3, mom=0.3)
+    lat = _lattice(cfg)
+    out = []
+    for t in ((32, 8, 2, 32), (256, 4, 1, 16), (256, 4, 1, 64)):
+        lat.set_tiling(*t)
+        lat.set_state(st["phi"], st["pi"], 1.0, 0.5)
+        lat.step(0)
+        out.append(lat.get_state())
+    for k, s in enumerate(out[1:]):
+        assert np.array_equal(s["phi"], out[0]["phi"]), k
+        assert np.array_equal(s["pi"], out[0]["pi"]), k
+
+
 def test_large_512_vv2_sampled_sites():
     cfg = synth.config2(q=100.0, N=512)
     st = oracle.vacuum_ic(cfg)
