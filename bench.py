@@ -23,10 +23,18 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 # (tz, by, ry) shapes the library's autotuner times for FP32 two-field lattices
-TUNER_SHAPES = ((64, 4, 4), (64, 4, 2), (64, 8, 2), (64, 4, 8), (32, 8, 2), (32, 4, 4), (32, 8, 4),
-                (128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2),
+TUNER_SHAPES = ((64, 4, 2), (64, 8, 2), (32, 8, 2), (128, 8, 2), (256, 4, 2), (128, 4, 2),
                 (128, 16, 1), (256, 8, 1), (512, 4, 1))
 BYTES_PER_SITE_VV2_NF2_FP32 = 32  # read phi, chi, pi_phi, pi_chi; write the same (FP32)
+
+
+def _pass_kernel_name(tile) -> str:
+    """The FP32 two-field stepping kernel a tile runs: full-row tiles (ry = 1,
+    tz = N, four sites per lane) or the general tile."""
+    tz, by, ry = tile[:3]
+    if ry == 1:
+        return "scalar_rows_kernel<float, 4, 2, %d, %d>" % (tz // 4, by)
+    return "scalar_pass_kernel<float, 2, false, %d, %d, %d>" % (tz, by, ry)
 
 
 def _kernel_hash() -> str:
@@ -322,7 +330,7 @@ def main():
                    "tile": {"tz": tile[0], "by": tile[1], "ry": tile[2], "xc": tile[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(sites, tile),
-                     "kernel": "scalar_pass_kernel<float, 2, false, %d, %d, %d>" % tile[:3],
+                     "kernel": _pass_kernel_name(tile),
                      "ms_per_launch": ms_per_pass, "launches": passes,
                      "kernel_timing": "HIP events around the timed region on the lattice's stream, divided by "
                                       "the pass launches in it (gaps and the one closing finish kernel included)",

@@ -241,9 +241,8 @@ int lattice_destroy(lattice_t* h);
 const char* lattice_last_error(void);
 
 /* Tile shape of the fused pass: threads along z, rows of threads along y,
-   rows per thread, x-planes per block.  Scalar lattices compile (64,4,4)
-   (64,4,2) (64,8,2) (64,4,8) (32,8,2) (32,4,4) (32,8,4) (128,4,4) (128,4,8)
-   (256,4,4) (128,8,2) (64,8,4) (256,4,2) (128,4,2) for FP32 two fields, plus
+   rows per thread, x-planes per block.  Scalar lattices compile (64,4,2)
+   (64,8,2) (32,8,2) (128,8,2) (256,4,2) (128,4,2) for FP32 two fields, plus
    the full-row tiles (128,16,1) (256,8,1) (512,4,1), valid only where the first
    number equals N: a block holds whole z-rows, four sites per thread, and
    each site's update is bit for bit the general tiles'.  FP64 two fields

@@ -21,18 +21,10 @@
 
 namespace cl {
 
-// 16 bytes of consecutive sites: the vector a lane loads and stores
-template <typename T>
-struct RowVec;
-template <>
-struct RowVec<float> {
-  typedef float type __attribute__((ext_vector_type(4)));
-  static constexpr int W = 4;
-};
-template <>
-struct RowVec<double> {
-  typedef double type __attribute__((ext_vector_type(2)));
-  static constexpr int W = 2;
+// W consecutive sites of one row: the vector a lane loads and stores
+template <typename T, int W>
+struct RowVec {
+  typedef T type __attribute__((ext_vector_type(W)));
 };
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
@@ -42,13 +34,13 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return f
 template <typename T, int W>
 __device__ __forceinline__ T lane_sum(const T (&v)[W]) {
   if constexpr (W == 4) return (v[0] + v[1]) + (v[2] + v[3]);
-  return v[0] + v[1];
+  if constexpr (W == 2) return v[0] + v[1];
+  return v[0];
 }
 
-template <typename T, int NF, int NL, int BY, typename GetAB>
+template <typename T, int W, int NF, int NL, int BY, typename GetAB>
 __device__ __forceinline__ void scalar_rows(const ScalarArgs<T>& A, int tile, int pidx, GetAB get_ab) {
-  using VW = typename RowVec<T>::type;  // W consecutive sites
-  constexpr int W = RowVec<T>::W;
+  using VW = typename RowVec<T, W>::type;  // W consecutive sites
   constexpr int N = W * NL;
   constexpr int NT = NL * BY;
   constexpr int NACC = Acc<NF, false>::N;
@@ -245,7 +237,7 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<T>& A, int tile, in
 
 // About 145 VGPRs: one 512-lane block per CU.  Holding it to 128 (two
 // blocks per CU) spills inside the plane loop and is slower.
-template <typename T, int NF, int NL, int BY>
+template <typename T, int W, int NF, int NL, int BY>
 __global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<T> A) {
   int bid = blockIdx.x;
   if (A.swizzle) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
@@ -268,7 +260,7 @@ __global__ __launch_bounds__(NL* BY) void scalar_rows_kernel(ScalarArgs<T> A) {
       b_in = A.st->b;
     }
   };
-  scalar_rows<T, NF, NL, BY>(A, bid, blockIdx.x, get_ab);
+  scalar_rows<T, W, NF, NL, BY>(A, bid, blockIdx.x, get_ab);
 }
 
 }  // namespace cl

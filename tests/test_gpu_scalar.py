@@ -282,8 +282,8 @@ def test_full_size_256_vv2_sampled_sites():
 
 
 def test_wide_tiles_256_against_oracle():
-    """The z-wide tile shapes (128 and 256 threads along z, one z-tile per
-    plane at 256^3) over every x-chunk, against the oracle after 5 steps."""
+    """The z-wide tile shapes (128 and 256 threads along z) and the full-row
+    tile over every x-chunk at 256^3, against the oracle after 5 steps."""
     cfg = synth.config2(q=100.0)
     st = oracle.vacuum_ic(cfg)
     m = oracle.scalar_model(cfg)
@@ -294,8 +294,7 @@ def test_wide_tiles_256_against_oracle():
     rng = np.random.default_rng(2)
     idx = (rng.integers(0, 2, size=4096),) + tuple(rng.integers(0, 256, size=(3, 4096)))
     n = 0
-    for (tz, by, ry) in ((128, 4, 4), (128, 4, 8), (256, 4, 4), (128, 8, 2), (64, 8, 4), (256, 4, 2), (128, 4, 2),
-                         (256, 8, 1)):
+    for (tz, by, ry) in ((128, 8, 2), (256, 4, 2), (128, 4, 2), (256, 8, 1)):
         for xc in (8, 16, 32, 64):
             lat.set_tiling(tz, by, ry, xc)
             lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
@@ -304,7 +303,7 @@ def test_wide_tiles_256_against_oracle():
             s = lat.get_state()
             assert np.max(np.abs(s["phi"][idx] - phi[idx])) < 1e-5 * np.max(np.abs(phi[idx])), (tz, by, ry, xc)
             n += 1
-    assert n == 32
+    assert n == 16
 
 
 def test_full_row_tiles_128_against_oracle():
@@ -461,7 +460,7 @@ def test_every_tiling_agrees():
     a, b = oracle.vv_steps(m, phi, pi, 1.0, 0.5, cfg["dt"], "vv2", 8, omp=True)
     o = oracle.sync_observe(m, phi, pi, a, b)
     lat = _lattice(cfg)
-    shapes = [(64, 4, 4), (64, 4, 2), (64, 8, 2), (64, 4, 8), (32, 8, 2), (32, 4, 4), (32, 8, 4)]
+    shapes = [(64, 4, 2), (64, 8, 2), (32, 8, 2)]
     n = 0
     for (tz, by, ry) in shapes:
         for xc in (4, 8, 16, 32):
@@ -475,7 +474,7 @@ def test_every_tiling_agrees():
             s = lat.get_state()
             assert np.max(np.abs(s["phi"] - phi)) < 1e-5 * np.max(np.abs(phi)), (tz, by, ry, xc)
             n += 1
-    assert n >= 20
+    assert n == 12
 
 
 def test_bitwise_determinism():
