@@ -38,9 +38,15 @@ def _pass_kernel_name(tile) -> str:
 
 
 def _kernel_hash() -> str:
+    """Hash of the scalar pass's sources with comments and blank lines left
+    out, so that a change to the code, not to its comments, marks the stored
+    traffic counters as stale."""
     h = hashlib.sha256()
     for f in ("scalar.hip", "scalar_tile.hpp", "scalar_rows.hpp", "common.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2006_15122_amd", "csrc", f), "rb").read())
+        for line in open(os.path.join(ROOT, "paper_2006_15122_amd", "csrc", f)):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

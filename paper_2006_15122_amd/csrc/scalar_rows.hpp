@@ -2,14 +2,17 @@
 //
 // A block holds whole z-rows of the lattice: N = W NL sites per row, W
 // consecutive sites per lane moved as one 16-byte access (W = 4 in FP32
-// storage, 2 in FP64).  It owns BY
-// consecutive y-rows and marches along x over XC planes, like the general
-// tile, with the same arithmetic in the same order, so every site's new
-// field and momentum are bit-for-bit those of the general tile.  What
-// changes is the memory side: the periodic z-neighbours of a row are in the
-// row itself (no z halo loads at all), every global access is a full
-// 16-byte-per-lane row segment, and one address serves four sites.  The only
-// halo left is the two y-rows above and below the block, read as whole rows.
+// storage, 2 in FP64).  It owns BY consecutive y-rows and marches along x
+// over XC planes like the general tile, with each site's drift and kick
+// written term for term as there: from the same a and b, a pass gives every
+// site the general tile's new field and momentum bit for bit.  The energy
+// terms of a lane's W sites are summed in storage precision before they join
+// the FP64 totals, so the sums (and with them a and b after the pass) agree
+// with the general tile's to rounding, not bit for bit.  What changes is the
+// memory side: the periodic z-neighbours of a row are in the row itself (no
+// z halo loads at all), every global access is a whole 16-byte lane segment
+// of a row, and one address serves W sites.  The only halo left is the two
+// y-rows above and below the block, spread over all lanes.
 #pragma once
 
 #include <hip/hip_runtime.h>
