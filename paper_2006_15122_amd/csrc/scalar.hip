@@ -50,7 +50,7 @@ hipError_t launch_shape(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipE
     hipLaunchKernelGGL((scalar_pass_kernel<T, NF, FULL, TZ, BY, RY>), dim3(nblocks), dim3(TZ * BY), 0, s, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !fin) return e;
-  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
+  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, FULL>), dim3(1), dim3(kFinishThreads), 0, s, A, nblocks, fin);
   return hipGetLastError();
 }
 
@@ -64,7 +64,7 @@ hipError_t launch_rows(const ScalarArgs<T>& A, int nblocks, hipStream_t s, hipEv
     hipLaunchKernelGGL((scalar_rows_kernel<T, W, NF, NL, BY>), dim3(nblocks), dim3(NL * BY), 0, s, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !fin) return e;
-  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, false>), dim3(1), dim3(1024), 0, s, A, nblocks, fin);
+  hipLaunchKernelGGL((scalar_finish_kernel<T, NF, false>), dim3(1), dim3(kFinishThreads), 0, s, A, nblocks, fin);
   return hipGetLastError();
 }
 
@@ -222,9 +222,9 @@ hipError_t launch_scalar_finish(int fp32, int nf, int N, const double* phys, int
     A.partials = partials;
     A.st = in;
     if (nf == 1)
-      hipLaunchKernelGGL((scalar_finish_kernel<TT, 1, false>), dim3(1), dim3(1024), 0, s, A, nblocks, out);
+      hipLaunchKernelGGL((scalar_finish_kernel<TT, 1, false>), dim3(1), dim3(kFinishThreads), 0, s, A, nblocks, out);
     else
-      hipLaunchKernelGGL((scalar_finish_kernel<TT, 2, false>), dim3(1), dim3(1024), 0, s, A, nblocks, out);
+      hipLaunchKernelGGL((scalar_finish_kernel<TT, 2, false>), dim3(1), dim3(kFinishThreads), 0, s, A, nblocks, out);
     return hipGetLastError();
   };
   return fp32 ? go((float*)nullptr) : go((double*)nullptr);

@@ -204,10 +204,14 @@ __device__ void finish_from_sums(const ScalarArgs<T>& A, const double (&S)[Acc<N
 
 // One block: combine the partials of all nblocks tiles in block order and
 // update the homogeneous state.
+// One block of kFinishThreads threads: four waves leave each thread the
+// registers for its FP64 sums (1024 threads, held to 128 VGPRs, spilled them).
+constexpr int kFinishThreads = 256;
+
 template <typename T, int NF, bool FULL>
-__global__ __launch_bounds__(1024) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks, DevState* out) {
+__global__ __launch_bounds__(kFinishThreads) void scalar_finish_kernel(ScalarArgs<T> A, int nblocks, DevState* out) {
   double S[Acc<NF, FULL>::N];
-  if (!reduce_partials<Acc<NF, FULL>::N, 1024>(A.partials, 0, nblocks, S)) return;
+  if (!reduce_partials<Acc<NF, FULL>::N, kFinishThreads>(A.partials, 0, nblocks, S)) return;
   double an, bn;
   finish_state<T, NF, FULL>(A, A.pd, A.st, S, out, an, bn);
 }

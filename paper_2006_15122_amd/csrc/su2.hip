@@ -407,14 +407,19 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
 // Energies (Sec. 5.4.1, Sec. 6.3.1) at a' and the scale-factor kernel with
 // both gauge sectors, K_a = (1/3)(f/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G
 // + (alpha+1)E_V + (alpha-1)(E_K^A + E_G^A + E_K^B + E_G^B)]; b_out = b + (wk1 + wk2) h K_a.
+// One block of kSu2FinishThreads threads: four waves leave each thread the
+// registers for its FP64 sums (1024 threads, held to 128 VGPRs, spilled them).
+constexpr int kSu2FinishThreads = 256;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void su2_finish_kernel(Su2Args<T> A, int nblocks) {
-  __shared__ double red[16][kSu2Acc];
+__global__ __launch_bounds__(kSu2FinishThreads) void su2_finish_kernel(Su2Args<T> A, int nblocks) {
+  constexpr int NW = kSu2FinishThreads / 64;
+  __shared__ double red[NW][kSu2Acc];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double tot[kSu2Acc];
 #pragma unroll
   for (int k = 0; k < kSu2Acc; ++k) tot[k] = 0.0;
-  for (int b = tid; b < nblocks; b += 1024)
+  for (int b = tid; b < nblocks; b += kSu2FinishThreads)
 #pragma unroll
     for (int k = 0; k < kSu2Acc; ++k) tot[k] += A.partials[(size_t)b * kSu2Acc + k];
 #pragma unroll
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(1024) void su2_finish_kernel(Su2Args<T> A, int nblo
   double S[kSu2Acc];
   for (int k = 0; k < kSu2Acc; ++k) {
     double v = 0.0;
-    for (int w = 0; w < 16; ++w) v += red[w][k];
+    for (int w = 0; w < NW; ++w) v += red[w][k];
     S[k] = v;
   }
   const PassDesc& pd = A.pd;
@@ -606,7 +611,7 @@ static int su2_pass_t(lattice* h, const PassDesc& pd) {
   hipLaunchKernelGGL(su2_kick_kernel<T>, dim3(nb), dim3(256), 0, h->stream, A);
   CL_HIP(hipGetLastError());
   if (ev1) CL_HIP(hipEventRecord(ev1, h->stream));
-  hipLaunchKernelGGL(su2_finish_kernel<T>, dim3(1), dim3(1024), 0, h->stream, A, nb);
+  hipLaunchKernelGGL(su2_finish_kernel<T>, dim3(1), dim3(kSu2FinishThreads), 0, h->stream, A, nb);
   CL_HIP(hipGetLastError());
   if (pd.write) h->cur ^= 1;
   return LAT_OK;

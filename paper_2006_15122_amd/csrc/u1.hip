@@ -597,11 +597,15 @@ __device__ bool u1_reduce_partials(const double* partials, int nb, double (&S)[k
   return true;
 }
 
-// The finish of the pass described by A, into `out`.
+// The finish of the pass described by A, into `out`: one block of
+// kU1FinishThreads threads (four waves leave each thread the registers for
+// its FP64 sums; 1024 threads, held to 128 VGPRs, spilled them).
+constexpr int kU1FinishThreads = 256;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void u1_pass_finish(U1PassArgs<T> A, int nblocks, DevState* out) {
+__global__ __launch_bounds__(kU1FinishThreads) void u1_pass_finish(U1PassArgs<T> A, int nblocks, DevState* out) {
   double S[kU1Acc];
-  if (!u1_reduce_partials<1024>(A.partials, nblocks, S)) return;
+  if (!u1_reduce_partials<kU1FinishThreads>(A.partials, nblocks, S)) return;
   double an, bn;
   u1_finish_state<T>(A, A.pd, A.st, S, out, an, bn);
 }
@@ -690,7 +694,7 @@ static int u1_pass_t(lattice* h, const PassDesc& pd, PassChain* chain) {
     chain->prev = PrevPass{A.partials, nb, pd, nullptr};
     ++chain->k;
   } else {
-    hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, nb, h->st);
+    hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(kU1FinishThreads), 0, h->stream, A, nb, h->st);
     CL_HIP(hipGetLastError());
   }
   if (pd.write) h->cur ^= 1;
@@ -715,7 +719,7 @@ static int u1_chain_finish(lattice* h, const PassChain& c) {
   A.pd = c.prev.pd;
   A.partials = const_cast<double*>(c.prev.partials);
   A.st = c.rd ? h->st2 : h->st;
-  hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(1024), 0, h->stream, A, c.prev.nblocks, h->st);
+  hipLaunchKernelGGL(u1_pass_finish<T>, dim3(1), dim3(kU1FinishThreads), 0, h->stream, A, c.prev.nblocks, h->st);
   CL_HIP(hipGetLastError());
   return LAT_OK;
 }
