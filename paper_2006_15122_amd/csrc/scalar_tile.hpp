@@ -26,6 +26,20 @@ struct ScalarArgs {
   PrevPass prev;     // single-lattice passes only; batched launches leave it empty
 };
 
+// Field loads and stores through global-address-space pointers.  The batched
+// pass takes its field pointers from a table in device memory, where the
+// compiler cannot tell they address global memory; it would emit flat
+// accesses, which count against the LDS wait counter as well, so that every
+// wait for the stencil's LDS reads would also wait for the prefetched planes.
+template <typename T>
+__device__ __forceinline__ T load_g(const T* base, size_t o) {
+  return ((const __attribute__((address_space(1))) T*)base)[o];
+}
+template <typename T>
+__device__ __forceinline__ void store_g_nt(T v, T* base, size_t o) {
+  __builtin_nontemporal_store(v, &((__attribute__((address_space(1))) T*)base)[o]);
+}
+
 // Accumulators of one pass.  FULL (observation passes): per field
 // <pi_in^2>, <pi_E^2>, <grad^2>, <phi>, <phi^2>, then the three potential
 // terms.  Stepping passes keep only what the scale-factor kernel needs:
@@ -279,8 +293,8 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       const size_t o = row_off(x, y0 + r * BY + ty) + z;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        p[f][r] = A.src[f][o];
-        pq[f][r] = A.src[2 + f][o];
+        p[f][r] = load_g(A.src[f], o);
+        pq[f][r] = load_g(A.src[2 + f], o);
       }
     }
   };
@@ -289,8 +303,8 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
       const size_t o = row_off(x, hy) + hz;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        p[f] = A.src[f][o];
-        pq[f] = A.src[2 + f][o];
+        p[f] = load_g(A.src[f], o);
+        pq[f] = load_g(A.src[2 + f], o);
       }
     }
   };
@@ -375,8 +389,8 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
           // count of memory operations in flight.  Streaming stores: the new
           // state is read again only by the next pass, so keep it from
           // evicting the halo rows other tiles still need
-          __builtin_nontemporal_store(cur[f], &A.dst[f][o]);
-          __builtin_nontemporal_store(pout, &A.dst[2 + f][o]);
+          store_g_nt(cur[f], A.dst[f], o);
+          store_g_nt(pout, A.dst[2 + f], o);
         }
         const T gx = pnext - cur[f], gy = yp - cur[f], gz = zp - cur[f];
         if constexpr (FULL) {
