@@ -25,6 +25,7 @@
 // as quaternions (w, x, y, z) = w + i(x sigma_1 + y sigma_2 + z sigma_3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -407,6 +408,34 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
 // Energies (Sec. 5.4.1, Sec. 6.3.1) at a' and the scale-factor kernel with
 // both gauge sectors, K_a = (1/3)(f/m_p)^2 a'^{1+2 alpha}[(alpha-2)E_K + alpha E_G
 // + (alpha+1)E_V + (alpha-1)(E_K^A + E_G^A + E_K^B + E_G^B)]; b_out = b + (wk1 + wk2) h K_a.
+// First stage of a pass's reduction: block g of R sums the contiguous range
+// g of the nb records (lanes in order, then the waves in order) into record g
+// of `out`, so that the one-block finish reads R records, not nb.  With one
+// block reading the 8192 records of a 128^3 pass the finish took 36 us.
+constexpr int kSu2FoldBlocks = 64;
+
+template <int NACC>
+__global__ __launch_bounds__(256) void su2_fold_records(const double* in, int nb, double* out) {
+  __shared__ double red[4][NACC];
+  const int R = gridDim.x, g = blockIdx.x;
+  const int chunk = (nb + R - 1) / R;
+  const int b0 = g * chunk, b1 = b0 + chunk < nb ? b0 + chunk : nb;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double t[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) t[k] = 0.0;
+  for (int b = b0 + tid; b < b1; b += 256)
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) t[k] += in[(size_t)b * NACC + k];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const double v = wsum64(t[k]);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (tid < NACC) out[(size_t)g * NACC + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
 // One block of kSu2FinishThreads threads: four waves leave each thread the
 // registers for its FP64 sums (1024 threads, held to 128 VGPRs, spilled them).
 constexpr int kSu2FinishThreads = 256;
@@ -611,7 +640,13 @@ static int su2_pass_t(lattice* h, const PassDesc& pd) {
   hipLaunchKernelGGL(su2_kick_kernel<T>, dim3(nb), dim3(256), 0, h->stream, A);
   CL_HIP(hipGetLastError());
   if (ev1) CL_HIP(hipEventRecord(ev1, h->stream));
-  hipLaunchKernelGGL(su2_finish_kernel<T>, dim3(1), dim3(kSu2FinishThreads), 0, h->stream, A, nb);
+  // the kick's nb records folded into R records in the second partials
+  // buffer (it holds max_blocks >= R records of 16 sums), then the finish
+  const int R = (int)std::min<int64_t>(kSu2FoldBlocks, h->max_blocks);
+  hipLaunchKernelGGL(su2_fold_records<kSu2Acc>, dim3(R), dim3(256), 0, h->stream, A.partials, nb, h->partials2);
+  CL_HIP(hipGetLastError());
+  A.partials = h->partials2;
+  hipLaunchKernelGGL(su2_finish_kernel<T>, dim3(1), dim3(kSu2FinishThreads), 0, h->stream, A, R);
   CL_HIP(hipGetLastError());
   if (pd.write) h->cur ^= 1;
   return LAT_OK;
