@@ -195,8 +195,10 @@ int lattice_energies(lattice_t* h, lattice_obs* out);
    workspace for it (code under HIP graph capture, tight serving loops,
    harnesses that forbid allocation): the same passes and kernels, with their
    per-block FP64 partial sums in a 4 MiB static device array of the library
-   (one per device, held until the process ends) instead of the workspace;
-   results are bitwise those of lattice_energies.  Allocates nothing.  Calls
+   (one per device, held until the process ends) instead of the workspace
+   (SU(2) x U(1) folds those records into 64 in the workspace's second record
+   buffer, as lattice_energies does); results are bitwise those of
+   lattice_energies.  Allocates nothing.  Calls
    that overlap on one GPU share that array and race; the caller serialises
    them.  Errors: LAT_ENOMEM when the partial sums need more than 4 MiB
    (U(1) lattices above 320^3, SU(2) x U(1) above 192^3, two scalar fields
