@@ -371,6 +371,30 @@ def test_full_row_tiles_fp64_against_oracle():
         lat.close()
 
 
+@pytest.mark.parametrize("precision, shape, tol", [("fp32", (128, 16, 1), 1e-5), ("fp64", (128, 8, 1), 1e-10)])
+def test_full_row_tiles_lf2_against_oracle(precision, shape, tol):
+    """Staggered leapfrog on the full-row tiles (the start-up kick, then
+    drift + kick passes with the kinetic term of the half-step momenta) at
+    128^3, against the oracle's scheme III at two checkpoints."""
+    cfg = dict(synth.small(synth.config2(q=100.0, integrator="lf2"), 128), precision=precision)
+    st = synth.random_state(cfg, seed=25, amp=0.3, mom=0.3)
+    m = oracle.scalar_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_tiling(*shape, 16)
+    lat.set_state(st["phi"], st["pi"], 1.0, 0.5)
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    h = cfg["dt"]
+    a, b = oracle.lf_startup(m, phi, pi, 1.0, 0.5, h)
+    for k in range(2):
+        lat.step(4)
+        a, b = oracle.lf_steps(m, phi, pi, a, b, h, 4, omp=True)
+        compare_obs(lat.energies(), oracle.lf_observe(m, phi, pi, a, b, h), 2, tol, f"{precision} lf2 {4 * (k + 1)}")
+    s = lat.get_state()
+    assert s["staggered"]
+    assert np.max(np.abs(s["phi"] - phi)) < tol * np.max(np.abs(phi))
+    assert np.max(np.abs(s["pi"] - pi)) < tol * np.max(np.abs(pi))
+
+
 def test_full_row_tile_fp64_512_sampled_sites():
     # the 512 x 2 full-row tile (two rows per block, two sites per lane)
     cfg = dict(synth.config2(q=100.0, N=512), precision="fp64")
