@@ -244,10 +244,27 @@ struct LineIO {
   int per_block;    // kLineBinOut: line batches per block
 };
 
+// Launch shape of the line passes, measured at 256^3 (a pass is held by the
+// latency of its loads and LDS stages, not by HBM bandwidth):
+// - a thread loads LU of its batch elements before it writes them to LDS:
+//   two on the contiguous z lines (best of 1, 2, 4 and 8), one at a time on
+//   the gathers of the strided axes, which got slower with more rows in
+//   flight (1.0 : 1.06 : 1.25 for one, two and four);
+// - at most 4 lines per z batch, so that more blocks share a CU (8 and 2
+//   were slower);
+// - up to 512 threads per block on the y pass (one butterfly per thread and
+//   stage), 256 elsewhere.
+// Radix-16 stages (two LDS round trips instead of four) and prefetching the
+// next batch into registers were both slower: their register use halves the
+// blocks per CU.
+constexpr int kLineLoadsZ = 2;
+constexpr int kLinesZ = 4;
+constexpr int kThreadsY = 512;
+
 // Sizes whose factors are all 2, 3, 4 or 5: one LDS buffer of B lines plus
 // the N roots of unity, so that more blocks fit on a compute unit.
-template <typename R, bool POW2, int MODE = kLinePlain, typename TIN = float>
-__global__ __launch_bounds__(256) void fft_lines_inplace_kernel(Cx<R>* data, const Cx<double>* __restrict__ W,
+template <typename R, bool POW2, int MODE = kLinePlain, typename TIN = float, int LU = 1>
+__global__ __launch_bounds__(512) void fft_lines_inplace_kernel(Cx<R>* data, const Cx<double>* __restrict__ W,
                                                                  FFTPlan P, int axis, int B, double sgn,
                                                                  double scale, LineIO io) {
   extern __shared__ unsigned char smem_raw[];
@@ -280,13 +297,30 @@ __global__ __launch_bounds__(256) void fft_lines_inplace_kernel(Cx<R>* data, con
       return (size_t)i * NN + (size_t)o * N + z0 + b;
     };
     if (lb != lb0) __syncthreads();  // every thread is done with the previous batch
-    for (int e = tid; e < B * N; e += NT) {
-      int b, i;
-      if (axis == 2) { b = idiv<POW2>(e, N); i = imod<POW2>(e, N); } else { i = idiv<POW2>(e, B); b = imod<POW2>(e, B); }
-      if constexpr (MODE == kLineRealIn)
-        buf[lpos(b, i, LS)] = Cx<R>{(R) static_cast<const TIN*>(io.rin)[addr(b, i)], R(0)};
-      else
-        buf[lpos(b, i, LS)] = data[addr(b, i)];
+    // LU of a thread's elements are loaded before the first of them goes to LDS
+    for (int e0 = tid; e0 < B * N; e0 += LU * NT) {
+      Cx<R> in[LU];
+#pragma unroll
+      for (int k = 0; k < LU; ++k) {
+        const int e = e0 + k * NT;
+        if (e < B * N) {
+          int b, i;
+          if (axis == 2) { b = idiv<POW2>(e, N); i = imod<POW2>(e, N); } else { i = idiv<POW2>(e, B); b = imod<POW2>(e, B); }
+          if constexpr (MODE == kLineRealIn)
+            in[k] = Cx<R>{(R) static_cast<const TIN*>(io.rin)[addr(b, i)], R(0)};
+          else
+            in[k] = data[addr(b, i)];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < LU; ++k) {
+        const int e = e0 + k * NT;
+        if (e < B * N) {
+          int b, i;
+          if (axis == 2) { b = idiv<POW2>(e, N); i = imod<POW2>(e, N); } else { i = idiv<POW2>(e, B); b = imod<POW2>(e, B); }
+          buf[lpos(b, i, LS)] = in[k];
+        }
+      }
     }
     __syncthreads();
     int Ns = 1;
@@ -411,9 +445,9 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(Cx<R>* data, const Cx<do
 
 // Three line passes (z, y, x).  Lines per block B: the most that fit (one
 // buffer of at most 2048 elements plus the roots for the in-place kernel,
-// two buffers within 64 KiB for the generic one), fewer where that leaves
-// under 2048 blocks, but at least 8 on the strided axes so that each
-// gathered row is 128 bytes.
+// two buffers within 64 KiB for the generic one), at most kLinesZ along z,
+// fewer where that leaves under 2048 blocks, but at least 8 on the strided
+// axes so that each gathered row is 128 bytes.
 template <typename R>
 static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double scale, hipStream_t s) {
   const FFTPlan P = make_plan(N);
@@ -430,10 +464,11 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
   while (Bmax > 1 && N % Bmax) Bmax >>= 1;
   for (int axis = 2; axis >= 0; --axis) {
     const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
-    int B = Bmax;
+    int B = axis == 2 ? std::min(Bmax, kLinesZ) : Bmax;
     while (B > minB && (size_t)N * N / B < 2048) B >>= 1;
     const int nblk = (int)((size_t)N * N / B);
-    const int nt = std::min(256, std::max(64, (B * N / 4 + 63) / 64 * 64));
+    // (the two-buffer kernel is built for 256 threads)
+    const int nt = std::min(axis == 1 && !any ? kThreadsY : 256, std::max(64, (B * N / 4 + 63) / 64 * 64));
     const double sc = axis == 0 ? scale : 1.0;
     if (any) {
       const size_t shm = (size_t)2 * B * N * sizeof(Cx<R>);
@@ -446,12 +481,21 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
         }
       const size_t shm =
           (size_t)lane_stride(N) * sizeof(Cx<double>) + (size_t)B * lane_stride(N, axis != 2) * sizeof(Cx<R>);
-      if ((N & (N - 1)) == 0)
+      const bool p2 = (N & (N - 1)) == 0;
+      if (axis == 2) {
+        if (p2)
+          hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true, kLinePlain, float, kLineLoadsZ>), dim3(nblk), dim3(nt),
+                             shm, s, data, W, P, axis, B, sgn, sc, LineIO{});
+        else
+          hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false, kLinePlain, float, kLineLoadsZ>), dim3(nblk),
+                             dim3(nt), shm, s, data, W, P, axis, B, sgn, sc, LineIO{});
+      } else if (p2) {
         hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
                            sgn, sc, LineIO{});
-      else
+      } else {
         hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false>), dim3(nblk), dim3(nt), shm, s, data, W, P, axis, B,
                            sgn, sc, LineIO{});
+      }
     }
     CL_HIP(hipGetLastError());
   }
@@ -479,10 +523,10 @@ static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int
   int Bs[3], nts[3];
   for (int axis = 2; axis >= 0; --axis) {
     const int minB = axis == 2 ? 1 : std::min(Bmax, 8);
-    int B = Bmax;
+    int B = axis == 2 ? std::min(Bmax, kLinesZ) : Bmax;
     while (B > minB && (size_t)N * N / B < 2048) B >>= 1;
     Bs[axis] = B;
-    nts[axis] = std::min(256, std::max(64, (B * N / 4 + 63) / 64 * 64));
+    nts[axis] = std::min(axis == 1 ? kThreadsY : 256, std::max(64, (B * N / 4 + 63) / 64 * 64));
     for (int k = 0; k < P.nfac; ++k)
       if ((B * N / P.fac[k] + nts[axis] - 1) / nts[axis] > inplace_pmax(P.fac[k])) {
         set_error("FFT: in-place stage does not cover the batch");
@@ -511,7 +555,7 @@ static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int
   } while (0)
   for (int axis = 2; axis >= 0; --axis) {
     const int grid = axis == 0 ? nb_bin : (int)((size_t)N * N / Bs[axis]);
-    if (axis == 2) CL_LINES(kLineRealIn, TIN);
+    if (axis == 2) CL_LINES(kLineRealIn, TIN, kLineLoadsZ);
     else if (axis == 1) CL_LINES(kLinePlain);
     else CL_LINES(kLineBinOut);
     CL_HIP(hipGetLastError());

@@ -11,10 +11,12 @@
 namespace cl {
 
 // Per-block shell histograms of a spectrum: the binning kernel's blocks, or
-// the blocks of the transform's binning pass, at most spec_blocks(N); large
-// lattices take more so that each block bins fewer line batches.
+// the blocks of the transform's binning pass, at most spec_blocks(N).  Up to
+// 256^3, 1024 (four per CU) make the quickest spectrum (at 256^3 the x pass
+// takes the same time with 4096 and the reduction of the histograms half);
+// larger lattices take more so that each block bins fewer line batches.
 constexpr int kSpecBlocks = 1024;
-inline int spec_blocks(int N) { return N >= 256 ? 4 * kSpecBlocks : kSpecBlocks; }
+inline int spec_blocks(int N) { return N > 256 ? 4 * kSpecBlocks : kSpecBlocks; }
 
 struct Tiling {
   int tz, by, ry, xc;
