@@ -29,11 +29,15 @@ struct FFTPlan {
   int fac[16];
 };
 
-static FFTPlan make_plan(int N) {
+// Factors of N: radix 8 first where r8 (the binning pass), then 4, 2 and
+// odd primes.
+static FFTPlan make_plan(int N, bool r8 = false) {
   FFTPlan P;
   P.N = N;
   P.nfac = 0;
   int n = N;
+  if (r8)
+    while (n % 8 == 0 && n != 16) { P.fac[P.nfac++] = 8; n /= 8; }
   while (n % 4 == 0) { P.fac[P.nfac++] = 4; n /= 4; }
   while (n % 2 == 0) { P.fac[P.nfac++] = 2; n /= 2; }
   for (int p = 3; n > 1; p += 2)
@@ -85,6 +89,23 @@ __device__ __forceinline__ void small_dft(const Cx<R>* v, Cx<R>* o, const Cx<dou
     o[2] = Cx<R>{a0.x - b0.x, a0.y - b0.y};
     o[1] = Cx<R>{a1.x - s * b1.y, a1.y + s * b1.x};
     o[3] = Cx<R>{a1.x + s * b1.y, a1.y - s * b1.x};
+  } else if constexpr (RAD == 8) {
+    // 8 = 2 x 4 with r = r2 + 2 r1 and m = m1 + 4 m2: length-4 DFTs of the
+    // even and the odd inputs, the odd ones times e^{sgn 2 pi i m1/8}, then
+    // o[m1] and o[m1 + 4] as their sum and difference
+    const R s = (R)sg, hf = (R)0.70710678118654752440084436210484904;
+    const Cx<R> ev[4] = {v[0], v[2], v[4], v[6]}, od[4] = {v[1], v[3], v[5], v[7]};
+    Cx<R> a[4], b[4];
+    small_dft<R, 4>(ev, a, W, N, sg);
+    small_dft<R, 4>(od, b, W, N, sg);
+    b[1] = Cx<R>{hf * (b[1].x - s * b[1].y), hf * (b[1].y + s * b[1].x)};
+    b[2] = Cx<R>{-s * b[2].y, s * b[2].x};
+    b[3] = Cx<R>{-hf * (b[3].x + s * b[3].y), hf * (s * b[3].x - b[3].y)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      o[m] = Cx<R>{a[m].x + b[m].x, a[m].y + b[m].y};
+      o[m + 4] = Cx<R>{a[m].x - b[m].x, a[m].y - b[m].y};
+    }
   } else {
 #pragma unroll
     for (int m = 0; m < RAD; ++m) {
@@ -219,7 +240,11 @@ __device__ __forceinline__ void fft_stage_inplace(Cx<R>* buf, const Cx<double>* 
 }
 
 // Butterflies per thread the in-place stages hold in registers, by radix.
-__host__ __device__ constexpr int inplace_pmax(int rad) { return rad == 2 ? 4 : rad == 3 ? 3 : 2; }
+__host__ __device__ constexpr int inplace_pmax(int rad) { return rad == 2 ? 4 : rad == 3 ? 3 : rad == 8 ? 1 : 2; }
+
+// radices the in-place kernel and the two-buffer kernel without the generic
+// stage take (8: the binning pass's in-place kernel only)
+__host__ __device__ constexpr bool fixed_radix(int rad) { return rad <= 5; }
 
 // signed mode number of index i (Sec. 3.1: n~ in (-N/2, N/2])
 __device__ __forceinline__ int wrapk(int i, int N) { return i <= N / 2 ? i : i - N; }
@@ -327,7 +352,13 @@ __global__ __launch_bounds__(512) void fft_lines_inplace_kernel(Cx<R>* data, con
     const double sg = sgn < 0.0 ? -1.0 : 1.0;
     for (int f = 0; f < P.nfac; ++f) {
       const int Rr = P.fac[f];
-      if constexpr (POW2) {  // power-of-two sizes: only radices 4 and 2 (fewer registers)
+      // radix 8 (three stages instead of four at 256) is built into the
+      // binning pass only, whose plan has it: its registers would cost the
+      // other passes blocks per CU
+      constexpr bool R8 = MODE == kLineBinOut;
+      if (R8 && Rr == 8) {
+        if constexpr (R8) fft_stage_inplace<R, 8, inplace_pmax(8), POW2>(buf, Wl, N, B, LS, Ns, sg);
+      } else if constexpr (POW2) {  // power-of-two sizes: only radices 4 and 2 (fewer registers)
         if (Rr == 4) fft_stage_inplace<R, 4, inplace_pmax(4), true>(buf, Wl, N, B, LS, Ns, sg);
         else fft_stage_inplace<R, 2, inplace_pmax(2), true>(buf, Wl, N, B, LS, Ns, sg);
       } else {
@@ -454,7 +485,7 @@ static int fft3d(Cx<R>* data, const Cx<double>* W, int N, double sgn, double sca
   bool any = false;
   for (int f = 0; f < P.nfac; ++f) {
     if (P.fac[f] > kMaxRadix) { set_error("FFT radix above 32"); return LAT_EINVAL; }
-    any = any || P.fac[f] > 5;
+    any = any || !fixed_radix(P.fac[f]);
   }
   int Bmax = 32;
   if (any)
@@ -512,9 +543,9 @@ template <typename R, typename TIN = R>
 static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int nbins, double* pS,
                       int max_blocks, int* nblk, hipStream_t s) {
   *nblk = 0;
-  const FFTPlan P = make_plan(N);
+  const FFTPlan P = make_plan(N), P8 = make_plan(N, true);  // P8: the x (binning) pass
   for (int k = 0; k < P.nfac; ++k)
-    if (P.fac[k] > 5) return LAT_OK;
+    if (!fixed_radix(P.fac[k])) return LAT_OK;
   int Bmax = 32;
   while (Bmax > 1 && Bmax * N > 2048) Bmax >>= 1;
   while (Bmax > 1 && N % Bmax) Bmax >>= 1;
@@ -527,8 +558,9 @@ static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int
     while (B > minB && (size_t)N * N / B < 2048) B >>= 1;
     Bs[axis] = B;
     nts[axis] = std::min(axis == 1 ? kThreadsY : 256, std::max(64, (B * N / 4 + 63) / 64 * 64));
-    for (int k = 0; k < P.nfac; ++k)
-      if ((B * N / P.fac[k] + nts[axis] - 1) / nts[axis] > inplace_pmax(P.fac[k])) {
+    const FFTPlan& PL = axis == 0 ? P8 : P;
+    for (int k = 0; k < PL.nfac; ++k)
+      if ((B * N / PL.fac[k] + nts[axis] - 1) / nts[axis] > inplace_pmax(PL.fac[k])) {
         set_error("FFT: in-place stage does not cover the batch");
         return LAT_EINVAL;
       }
@@ -548,13 +580,14 @@ static int fft3d_bins(const TIN* f, Cx<R>* data, const Cx<double>* W, int N, int
   do {                                                                                                          \
     if (pow2)                                                                                                   \
       hipLaunchKernelGGL((fft_lines_inplace_kernel<R, true, MODE, ##__VA_ARGS__>), dim3(grid), dim3(nts[axis]), \
-                         shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);                            \
+                         shm_of(axis), s, data, W, PL, axis, Bs[axis], 1.0, 1.0, io);                           \
     else                                                                                                        \
       hipLaunchKernelGGL((fft_lines_inplace_kernel<R, false, MODE, ##__VA_ARGS__>), dim3(grid),                  \
-                         dim3(nts[axis]), shm_of(axis), s, data, W, P, axis, Bs[axis], 1.0, 1.0, io);           \
+                         dim3(nts[axis]), shm_of(axis), s, data, W, PL, axis, Bs[axis], 1.0, 1.0, io);          \
   } while (0)
   for (int axis = 2; axis >= 0; --axis) {
     const int grid = axis == 0 ? nb_bin : (int)((size_t)N * N / Bs[axis]);
+    const FFTPlan& PL = axis == 0 ? P8 : P;
     if (axis == 2) CL_LINES(kLineRealIn, TIN, kLineLoadsZ);
     else if (axis == 1) CL_LINES(kLinePlain);
     else CL_LINES(kLineBinOut);
