@@ -74,6 +74,22 @@ __device__ __forceinline__ double wave_uniform(double x) {
   const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// a^p for the scale-factor powers of the passes and their finishes, p = k +
+// m alpha: an integer whenever alpha is (alpha = 1 in the paper's examples),
+// and an integer power of magnitude up to 8 is formed by repeated squaring (a
+// few ulp from pow, at a fraction of its dependent FP64 chain, which sits on
+// the critical path of every chained pass); other exponents take pow.
+__device__ __forceinline__ double apow(double a, double p) {
+  if (p == rint(p) && fabs(p) <= 8.0) {
+    double r = 1.0, x = a;
+    for (int k = (int)fabs(p); k; k >>= 1) {
+      if (k & 1) r *= x;
+      x *= x;
+    }
+    return p < 0.0 ? 1.0 / r : r;
+  }
+  return pow(a, p);
+}
 template <typename T>
 __device__ __forceinline__ Coef<T> ucoef(double v) {
   const Coef<T> c = coef<T>(v);

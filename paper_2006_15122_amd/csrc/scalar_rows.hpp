@@ -125,9 +125,9 @@ __device__ __forceinline__ void scalar_rows(const ScalarArgs<T>& A, int tile, in
   load_own((x0 + 1) % N, pn, qn);
   const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
-  const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
-  const Coef<T> clap = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const Coef<T> cpot = ucoef<T>(pow(anew, 3.0 + A.alpha));
+  const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * apow(amid, -(3.0 - A.alpha)));
+  const Coef<T> clap = ucoef<T>(apow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const Coef<T> cpot = ucoef<T>(apow(anew, 3.0 + A.alpha));
   auto drift = [&](const VW& qv, const VW& pv) {
     VW r;
 #pragma unroll

@@ -141,7 +141,7 @@ __device__ void finish_state(const ScalarArgs<T>& A, const PassDesc& pd, const D
   const double anew = A.expand ? a_in + pd.wd * A.h * b_in : a_in;
   const double V = (double)A.N * (double)A.N * (double)A.N;
   const double al = A.alpha;
-  const double a6 = pow(anew, 6.0), a2 = anew * anew, dx2 = A.dx * A.dx;
+  const double a2 = anew * anew, a6 = a2 * a2 * a2, dx2 = A.dx * A.dx;
   lattice_obs o;
   o.EK = o.EG = 0.0;
   o.EK_f[0] = o.EK_f[1] = o.EG_f[0] = o.EG_f[1] = 0.0;
@@ -175,11 +175,11 @@ __device__ void finish_state(const ScalarArgs<T>& A, const PassDesc& pd, const D
   const double rho = o.EK + o.EG + o.EV;
   double b_out = b_in, b_sync = b_in, hc = 0.0;
   if (A.expand) {
-    const double Ka = A.fmp2 / 3.0 * pow(anew, 1.0 + 2.0 * al) *
+    const double Ka = A.fmp2 / 3.0 * apow(anew, 1.0 + 2.0 * al) *
                       ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV);
     b_out = b_in + (pd.wk1 + pd.wk2) * A.h * Ka;
     b_sync = (pd.mode == MODE_LF) ? 0.5 * (b_in + b_out) : b_in + pd.wk1 * A.h * Ka;
-    const double rhs = A.fmp2 / 3.0 * pow(anew, 2.0 * (al + 1.0)) * rho;
+    const double rhs = A.fmp2 / 3.0 * apow(anew, 2.0 * (al + 1.0)) * rho;
     hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
   }
   const double eta_new = eta_in + pd.wd * A.h;
@@ -323,9 +323,9 @@ __device__ __forceinline__ void scalar_tile(const ScalarArgs<T>& A, int tile, in
   if (A.XC > 1) load_halo((x0 + 1) % N, hp2, hq2);
   const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
-  const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * pow(amid, -(3.0 - A.alpha)));
-  const Coef<T> clap = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const Coef<T> cpot = ucoef<T>(pow(anew, 3.0 + A.alpha));
+  const Coef<T> cdrift = ucoef<T>(A.pd.wd * A.h * apow(amid, -(3.0 - A.alpha)));
+  const Coef<T> clap = ucoef<T>(apow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const Coef<T> cpot = ucoef<T>(apow(anew, 3.0 + A.alpha));
   // drifted plane into LDS: own columns from registers, halo drifted here
   auto store_lds = [&](const T (&p)[NF][RY], const T (&hp)[NF], const T (&hq)[NF]) {
 #pragma unroll

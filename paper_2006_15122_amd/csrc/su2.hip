@@ -150,9 +150,9 @@ __global__ __launch_bounds__(256) void su2_drift_kernel(Su2Args<T> A) {
   const double anew = A.expand ? a_in + hw * b_in : a_in;
   const double amid = 0.5 * (a_in + anew);
   // coefficients as hi + lo pairs (no coherent rounding of them)
-  const Coef<T> cd = ucoef<T>(hw * pow(amid, -(3.0 - A.alpha)));
-  const Coef<T> cu = ucoef<T>(A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)));
-  const Coef<T> cw = ucoef<T>(A.g * hw * A.dx / (4.0 * pow(amid, 1.0 - A.alpha)));
+  const Coef<T> cd = ucoef<T>(hw * apow(amid, -(3.0 - A.alpha)));
+  const Coef<T> cu = ucoef<T>(A.e * hw * A.dx / (2.0 * apow(amid, 1.0 - A.alpha)));
+  const Coef<T> cw = ucoef<T>(A.g * hw * A.dx / (4.0 * apow(amid, 1.0 - A.alpha)));
 #pragma unroll
   for (int k = 0; k < 4; ++k) A.dst[kPH + k][s] = fma_c(cd, A.src[kPI + k][s], A.src[kPH + k][s]);
 #pragma unroll
@@ -226,12 +226,12 @@ __global__ __launch_bounds__(256, 2) void su2_kick_kernel(Su2Args<T> A) {
 
     const double a_in = A.st->a, b_in = A.st->b;
     const double anew = A.expand ? a_in + A.pd.wd * A.h * b_in : a_in;
-    const Coef<T> cl = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-    const Coef<T> cp = ucoef<T>(pow(anew, 3.0 + A.alpha));
-    const Coef<T> cjA = ucoef<T>(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-    const Coef<T> cjB = ucoef<T>(pow(anew, 1.0 + A.alpha) * A.g / A.dx / A.wf2);
-    const Coef<T> cbA = ucoef<T>(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
-    const Coef<T> cbB = ucoef<T>(pow(anew, A.alpha - 1.0) * 2.0 / (A.g * A.dx * A.dx * A.dx));
+    const Coef<T> cl = ucoef<T>(apow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+    const Coef<T> cp = ucoef<T>(apow(anew, 3.0 + A.alpha));
+    const Coef<T> cjA = ucoef<T>(apow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+    const Coef<T> cjB = ucoef<T>(apow(anew, 1.0 + A.alpha) * A.g / A.dx / A.wf2);
+    const Coef<T> cbA = ucoef<T>(apow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+    const Coef<T> cbB = ucoef<T>(apow(anew, A.alpha - 1.0) * 2.0 / (A.g * A.dx * A.dx * A.dx));
     const Coef<T> ck = ucoef<T>((A.pd.wk1 + A.pd.wk2) * A.h);
     const Coef<T> cE = ucoef<T>((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
     const T lam = (T)A.lam, m2 = (T)A.m2;
@@ -498,11 +498,11 @@ __global__ __launch_bounds__(kSu2FinishThreads) void su2_finish_kernel(Su2Args<T
   const double rho = o.EK + o.EG + o.EV + gauge;
   double b_out = b_in, b_sync = b_in, hc = 0.0;
   if (A.expand) {
-    const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+    const double Ka = A.fmp2 / 3.0 * apow(a, 1.0 + 2.0 * al) *
                       ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * gauge);
     b_out = b_in + (pd.wk1 + pd.wk2) * A.h * Ka;
     b_sync = lf ? 0.5 * (b_in + b_out) : b_in + pd.wk1 * A.h * Ka;
-    const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
+    const double rhs = A.fmp2 / 3.0 * apow(a, 2.0 * (al + 1.0)) * rho;
     hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
   }
   const double eta_new = st->eta + pd.wd * A.h;

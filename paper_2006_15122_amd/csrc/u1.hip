@@ -220,14 +220,14 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const bool dr = A.pd.wd != 0.0;
   const double hw = A.pd.wd * A.h;
   // per-pass coefficients as hi + lo pairs (no coherent rounding of them)
-  const Coef<T> cd = ucoef<T>(dr ? hw * pow(amid, -(3.0 - A.alpha)) : 0.0);
-  const Coef<T> cu = ucoef<T>(dr ? A.e * hw * A.dx / (2.0 * pow(amid, 1.0 - A.alpha)) : 0.0);
-  const Coef<T> cA = ucoef<T>(dr ? hw / pow(amid, 1.0 - A.alpha) : 0.0);  // non-compact A drift
+  const Coef<T> cd = ucoef<T>(dr ? hw * apow(amid, -(3.0 - A.alpha)) : 0.0);
+  const Coef<T> cu = ucoef<T>(dr ? A.e * hw * A.dx / (2.0 * apow(amid, 1.0 - A.alpha)) : 0.0);
+  const Coef<T> cA = ucoef<T>(dr ? hw / apow(amid, 1.0 - A.alpha) : 0.0);  // non-compact A drift
   const Coef<T> mth = ucoef<T>(-A.e * A.dx);                                // theta = -e dx A
-  const Coef<T> cl = ucoef<T>(pow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
-  const Coef<T> cp = ucoef<T>(pow(anew, 3.0 + A.alpha));
-  const Coef<T> cj = ucoef<T>(pow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
-  const Coef<T> cb = ucoef<T>(pow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
+  const Coef<T> cl = ucoef<T>(apow(anew, 1.0 + A.alpha) / (A.dx * A.dx));
+  const Coef<T> cp = ucoef<T>(apow(anew, 3.0 + A.alpha));
+  const Coef<T> cj = ucoef<T>(apow(anew, 1.0 + A.alpha) * 2.0 * A.e / A.dx / A.wf2);
+  const Coef<T> cb = ucoef<T>(apow(anew, A.alpha - 1.0) / (A.e * A.dx * A.dx * A.dx));
   const Coef<T> ck = ucoef<T>((A.pd.wk1 + A.pd.wk2) * A.h);
   const Coef<T> cE = ucoef<T>((A.pd.mode == MODE_LF ? A.pd.wk1 + A.pd.wk2 : A.pd.wk1) * A.h);
   const bool wr = A.pd.write != 0;
@@ -534,11 +534,11 @@ __device__ void u1_finish_state(const U1PassArgs<T>& A, const PassDesc& pd, cons
   const double rho = o.EK + o.EG + o.EV + o.EK_A + o.EG_A;
   double b_out = b_in, b_sync = b_in, hc = 0.0;
   if (A.expand) {
-    const double Ka = A.fmp2 / 3.0 * pow(a, 1.0 + 2.0 * al) *
+    const double Ka = A.fmp2 / 3.0 * apow(a, 1.0 + 2.0 * al) *
                       ((al - 2.0) * o.EK + al * o.EG + (al + 1.0) * o.EV + (al - 1.0) * (o.EK_A + o.EG_A));
     b_out = b_in + (pd.wk1 + pd.wk2) * A.h * Ka;
     b_sync = lf ? 0.5 * (b_in + b_out) : b_in + pd.wk1 * A.h * Ka;
-    const double rhs = A.fmp2 / 3.0 * pow(a, 2.0 * (al + 1.0)) * rho;
+    const double rhs = A.fmp2 / 3.0 * apow(a, 2.0 * (al + 1.0)) * rho;
     hc = fabs(b_sync * b_sync - rhs) / (b_sync * b_sync);
   }
   const double eta_new = in->eta + pd.wd * A.h;
@@ -829,7 +829,7 @@ __global__ void u1_modes_kernel(double2* F, U1ModeArgs M) {
   if (!M.deriv) {
     v = make_double2((Lx + Rx) * is2, (Ly + Ry) * is2);
   } else {
-    const double c = pow(M.a, -(1.0 - M.alpha)) * om * is2;
+    const double c = apow(M.a, -(1.0 - M.alpha)) * om * is2;
     v = make_double2(-c * (Ly - Ry) - M.Hhom * (Lx + Rx) * is2, c * (Lx - Rx) - M.Hhom * (Ly + Ry) * is2);
   }
   F[lin] = v;
