@@ -196,6 +196,40 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const int y0 = ((bid / nzt) % nyt) * TY;
   const int x0 = (bid / (nzt * nyt)) * A.XC;
 
+  // ring site owned by this thread (one at most)
+  const bool has_ring = tid < NH;
+  int rly = 0, rlz = 0;
+  if (tid < LZ) { rly = 0; rlz = tid; }
+  else if (tid < 2 * LZ) { rly = TY + 1; rlz = tid - LZ; }
+  else if (tid < 2 * LZ + TY) { rly = 1 + tid - 2 * LZ; rlz = 0; }
+  else { rly = 1 + tid - 2 * LZ - TY; rlz = TZ + 1; }
+  const int ry_g = (y0 - 1 + rly + N) % N, rz_g = (z0 - 1 + rlz + N) % N;
+  // low-ring site whose plaquette sines this thread computes (row y0-1 or column z0-1)
+  const bool has_low = tid < TZ + TY;
+  const int sly = tid < TZ ? 0 : 1 + tid - TZ;
+  const int slz = tid < TZ ? 1 + tid : 0;
+
+  auto site = [&](int x, int y, int z) -> int { return x * NN + y * N + z; };
+
+  // raw values: own column (RY rows) and the ring site of plane x
+  T raw[10][RY], rraw[10];
+  auto load_plane = [&](int x) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int o = site(x, y0 + r * BY + ty, z0 + tz);
+#pragma unroll
+      for (int c = 0; c < 10; ++c) raw[c][r] = A.src[c][o];
+    }
+    if (has_ring) {
+      const int o = site(x, ry_g, rz_g);
+#pragma unroll
+      for (int c = 0; c < 10; ++c) rraw[c] = A.src[c][o];
+    }
+  };
+  // plane x0-1 is loaded before the previous pass's finish is applied (the
+  // loads need no coefficients), so that their latency overlaps it
+  load_plane((x0 - 1 + N) % N);
+
   // homogeneous coefficients (FP64, the same in every block); a chained pass
   // first applies the previous pass's finish (every block, same order)
   double a_in, b_in;
@@ -234,36 +268,6 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
   const T lam = (T)A.lam, m2 = (T)A.m2;
   const Coef<T> lam2c = ucoef<T>(2.0 * A.lam), m2c = ucoef<T>(A.m2);
 
-  // ring site owned by this thread (one at most)
-  const bool has_ring = tid < NH;
-  int rly = 0, rlz = 0;
-  if (tid < LZ) { rly = 0; rlz = tid; }
-  else if (tid < 2 * LZ) { rly = TY + 1; rlz = tid - LZ; }
-  else if (tid < 2 * LZ + TY) { rly = 1 + tid - 2 * LZ; rlz = 0; }
-  else { rly = 1 + tid - 2 * LZ - TY; rlz = TZ + 1; }
-  const int ry_g = (y0 - 1 + rly + N) % N, rz_g = (z0 - 1 + rlz + N) % N;
-  // low-ring site whose plaquette sines this thread computes (row y0-1 or column z0-1)
-  const bool has_low = tid < TZ + TY;
-  const int sly = tid < TZ ? 0 : 1 + tid - TZ;
-  const int slz = tid < TZ ? 1 + tid : 0;
-
-  auto site = [&](int x, int y, int z) -> int { return x * NN + y * N + z; };
-
-  // raw values: own column (RY rows) and the ring site of plane x
-  T raw[10][RY], rraw[10];
-  auto load_plane = [&](int x) {
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int o = site(x, y0 + r * BY + ty, z0 + tz);
-#pragma unroll
-      for (int c = 0; c < 10; ++c) raw[c][r] = A.src[c][o];
-    }
-    if (has_ring) {
-      const int o = site(x, ry_g, rz_g);
-#pragma unroll
-      for (int c = 0; c < 10; ++c) rraw[c] = A.src[c][o];
-    }
-  };
   // drift the raw values into LDS buffer b
   // (the only transcendentals of the pass: one arctangent and one sincos per link)
   auto drift_into = [&](int b) {
@@ -343,7 +347,6 @@ __global__ __launch_bounds__(TZ* BY) void u1_pass_kernel(U1PassArgs<T> A) {
 
   // prologue: plane x0-1 -> buffer 1, plane x0 -> buffer 0; S_01, S_02 of
   // plane x0-1; then plane x0+1 -> buffer 1
-  load_plane((x0 - 1 + N) % N);
   drift_into(1);
   load_plane(x0);
   drift_into(0);
@@ -572,29 +575,31 @@ __device__ void u1_finish_state(const U1PassArgs<T>& A, const PassDesc& pd, cons
 // (strided per thread, then waves in order); thread 0 returns them in S.
 template <int NT>
 __device__ bool u1_reduce_partials(const double* partials, int nb, double (&S)[kU1Acc]) {
-  constexpr int NACC = kU1Acc, NW = NT / 64;
-  __shared__ double red[NW][NACC];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double tot[NACC];
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) tot[k] = 0.0;
-  for (int b = tid; b < nb; b += NT) {
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) tot[k] += partials[(size_t)b * NACC + k];
-  }
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const double s = wsum(tot[k]);
-    if (lane == 0) red[wv][k] = s;
+  // Thread t < NL reads doubles t, t + NL, t + 2 NL, ... of the nb records
+  // laid end to end; NL is a multiple of the record length, so the loads are
+  // coalesced and every value a thread reads belongs to accumulator t mod
+  // NACC (reading whole records per thread touched a cache line per lane and
+  // load).  The threads of each accumulator are then summed in thread order
+  // by one lane each of the first wave: a fixed order, the same in every block.
+  constexpr int NACC = kU1Acc, NL = (NT / NACC) * NACC;
+  static_assert(NT >= 64 && NACC <= 64, "the first wave finishes the sums");
+  __shared__ double red[NL];
+  const int tid = threadIdx.x;
+  const int64_t nv = (int64_t)nb * NACC;
+  if (tid < NL) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int64_t e = tid; e < nv; e += NL) s += partials[e];
+    red[tid] = s;
   }
   __syncthreads();
-  if (tid != 0) return false;
-  for (int k = 0; k < NACC; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += red[w][k];
-    S[k] = s;
-  }
-  return true;
+  if (tid >= 64) return false;
+  double v = 0.0;
+  if (tid < NACC)
+    for (int j = tid; j < NL; j += NACC) v += red[j];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) S[k] = __shfl(v, k, 64);
+  return tid == 0;
 }
 
 // The finish of the pass described by A, into `out`: one block of
