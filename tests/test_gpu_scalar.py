@@ -572,20 +572,28 @@ def test_flat_space_free_mode_dispersion_on_gpu():
     assert np.max(np.abs(s["pi"][0] - B * mode)) < 1e-11
 
 
-@pytest.mark.parametrize("precision,N", [("fp64", 32), ("fp64", 64), ("fp32", 96), ("fp32", 160), ("fp32", 224),
-                                         ("fp32", 256)])
+@pytest.mark.parametrize("precision,N", [("fp64", 32), ("fp64", 64), ("fp32", 96), ("fp32", 128), ("fp32", 160),
+                                         ("fp32", 224), ("fp32", 256), ("fp32", 384)])
 def test_spectrum_matches_oracle(precision, N):
-    # 96, 160 and 224 take the radix-3, radix-5 and generic (radix-7) FFT stages;
-    # 256 is the benchmarked size, whose binning pass has four times the blocks
+    # 96, 160 and 224 take the radix-3, radix-5 and generic (radix-7) FFT
+    # stages; the binning pass factors 128, 256 and 384 as 8 8 2, 8 8 4 and
+    # 8 8 2 3 (the other passes in radices 4 and 2); 256 is the benchmarked
+    # size; above 256 the binning pass keeps four times the shell histograms
+    # (one field there: the oracle's transform of 384^3 takes seconds)
     cfg = dict(synth.small(synth.config2(q=100.0), N), precision=precision)
     lat = _lattice(cfg)
     s = lat.get_state()
     tol = 1e-10 if precision == "fp64" else 1e-5
-    for which, arr in ((0, s["phi"][0]), (1, s["phi"][1]), (17, s["pi"][1])):
+    cases = ((0, s["phi"][0]), (1, s["phi"][1]), (17, s["pi"][1]))
+    for which, arr in cases[:1] if N > 256 else cases:
         g = lat.spectrum(which)
         o = oracle.spectrum(arr, cfg["kIR"])
         assert np.array_equal(g["count"], o["count"])
-        assert np.allclose(g["k"], o["k"], rtol=1e-12, atol=0)
+        # mean |k| of a shell: the oracle sums its n modes' |k| one after
+        # another in FP64 (relative error up to (n - 1) eps; n reaches 1e6
+        # at 384^3), the device in per-block partial sums (smaller)
+        kt = 2.0 * np.finfo(np.float64).eps * np.maximum(o["count"], 1) * np.abs(o["k"])
+        assert np.all(np.abs(g["k"] - o["k"]) <= kt), np.max(np.abs(g["k"] - o["k"]) / np.maximum(kt, 1e-300))
         check_shells(g, o, tol, f"{precision} N={N} which={which}")
 
 
