@@ -75,7 +75,7 @@ __device__ __forceinline__ double wave_uniform(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 // a^p for the scale-factor powers of the passes and their finishes, p = k +
-// m alpha: an integer whenever alpha is (alpha = 1 in the paper's examples),
+// m alpha: an integer whenever alpha is (conformal time, alpha = 1, say),
 // and an integer power of magnitude up to 8 is formed by repeated squaring (a
 // few ulp from pow, at a fraction of its dependent FP64 chain, which sits on
 // the critical path of every chained pass); other exponents take pow.

@@ -141,6 +141,26 @@ def test_two_field_fp32_parity_64(integ, q, nsteps):
     print(integ, q, "worst relative error", worst)
 
 
+@pytest.mark.parametrize("alpha,integ", [(0.0, "vv2"), (0.5, "vv2"), (0.5, "vv4")])
+def test_non_integer_alpha_fp64_parity(alpha, integ):
+    # alpha-time other than conformal (Sec. 2.2, 4.1): the powers a^(k + m alpha)
+    # of the drift, the kick and the expansion are then not all integers, and
+    # the device forms the others with pow instead of by multiplication
+    cfg = dict(synth.small(synth.config2(q=100.0, integrator=integ), 32), precision="fp64", alpha=alpha)
+    st = oracle.vacuum_ic(cfg)
+    m = oracle.scalar_model(cfg)
+    lat = _lattice(cfg)
+    lat.set_state(st["phi"], st["pi"], st["a"], st["b"])
+    phi, pi = st["phi"].copy(), st["pi"].copy()
+    lat.step(40)
+    a, b = oracle.vv_steps(m, phi, pi, st["a"], st["b"], cfg["dt"], integ, 40)
+    compare_obs(lat.energies(), oracle.sync_observe(m, phi, pi, a, b), 2, 1e-10, f"alpha {alpha} {integ}")
+    s = lat.get_state()
+    assert abs(s["a"] - a) < 1e-12 * a and a > st["a"]
+    assert np.max(np.abs(s["phi"] - phi)) < 1e-10 * np.max(np.abs(phi))
+    assert np.max(np.abs(s["pi"] - pi)) < 1e-10 * np.max(np.abs(pi))
+
+
 @pytest.mark.parametrize("integ", ["vv6", "vv8", "vv10"])
 def test_higher_order_yoshida_fp64_parity(integ):
     # VV6, VV8, VV10 (Sec. 3.4.1, 4.3.2): 7, 15, 31 fused passes per step
