@@ -163,3 +163,34 @@ def test_su2_full_size_128_fp32_against_oracle():
     g = lat.energies()
     print("128^3 worst %.2e gauss %.2e gauss_B %.2e" % (compare(g, o, 1e-5, "128^3"), g["gauss"], g["gauss_B"]))
     assert g["gauss"] < 1e-5 and g["gauss_B"] < 1e-5
+
+
+def test_su2_energy_constraint_ladder_and_orders():
+    """The accuracy tests of the SU(2) x U(1) simulations (Sec. 8.3.1): the
+    Friedmann-constraint violation Delta_e falls with the integrator's order
+    (VV4 about twentyfold below VV2 there), and both Gauss laws hold to
+    round-off whatever the integrator.  Each integrator's order is measured:
+    halving the step from 0.005 to 0.0025 divides Delta_e at eta = 10 by 2^p
+    (p = 2 for the staggered leapfrog and VV2, up to 10 for VV10) within a
+    factor 1.5.  The doublet at 32^3 in FP64 storage with e = g = 0.5."""
+    from paper_2006_15122_amd.lattice import Lattice
+
+    eta = 10.0
+    hc = {}
+    for dt in (0.005, 0.0025):
+        for integ in ("lf2", "vv2", "vv4", "vv6", "vv8", "vv10"):
+            cfg = _cfg(32, "fp64", integrator=integ, dt=dt, e=0.5, g=0.5)
+            lat = Lattice(cfg, device="cuda:0")
+            lat.step(int(round(eta / dt)))
+            e = lat.energies()
+            lat.close()
+            hc[dt, integ] = e["hc"]
+            print(f"dt {dt} {integ}: Delta_e {e['hc']:.3e} gauss {e['gauss']:.1e} {e['gauss_B']:.1e}", flush=True)
+            assert e["gauss"] < 1e-12 and e["gauss_B"] < 1e-12, (dt, integ, e["gauss"], e["gauss_B"])
+    for integ, p in (("lf2", 2), ("vv2", 2), ("vv4", 4), ("vv6", 6), ("vv8", 8), ("vv10", 10)):
+        r = hc[0.005, integ] / hc[0.0025, integ]
+        assert 2.0 ** p / 1.5 < r < 2.0 ** p * 1.5, (integ, p, r)
+    order = ("vv2", "vv4", "vv6", "vv8", "vv10")
+    for lo, hi in zip(order, order[1:]):
+        assert hc[0.0025, hi] <= max(hc[0.0025, lo] / 10.0, 1e-12), (lo, hi)
+    assert 0.5 < hc[0.0025, "lf2"] / hc[0.0025, "vv2"] < 4.0
