@@ -656,6 +656,30 @@ def test_hubble_constraint_ladder_of_the_verlet_family():
     assert hc["vv2"] / max(hc["vv10"], floor) > 1e6
 
 
+def test_integrator_orders_from_the_hubble_constraint():
+    """Each integrator's order (Sec. 3.4, 4.2, 4.3), read off the
+    Hubble-constraint violation at eta = 20: halving the step from 0.01 to
+    0.005 divides it by 2^p within a factor 1.5 (p = 2 for the staggered
+    leapfrog and VV2, 4 and 6 for VV4 and VV6); VV8 and VV10 are at the
+    round-off floor by then.  Two fields, q = 100, 32^3, FP64 storage."""
+    from paper_2006_15122_amd.lattice import Lattice
+
+    eta = 20.0
+    hc = {}
+    for dt in (0.01, 0.005):
+        for integ in ("lf2", "vv2", "vv4", "vv6", "vv8", "vv10"):
+            cfg = dict(synth.small(synth.config2(q=100.0, integrator=integ), 32), precision="fp64", dt=dt)
+            lat = Lattice(cfg, device="cuda:0")
+            lat.step(int(round(eta / dt)))
+            hc[dt, integ] = lat.energies()["hc"]
+            lat.close()
+            print(f"dt {dt} {integ}: hubble-constraint violation {hc[dt, integ]:.3e}", flush=True)
+    for integ, p in (("lf2", 2), ("vv2", 2), ("vv4", 4), ("vv6", 6)):
+        r = hc[0.01, integ] / hc[0.005, integ]
+        assert 2.0 ** p / 1.5 < r < 2.0 ** p * 1.5, (integ, p, r)
+    assert hc[0.005, "vv8"] < 1e-13 and hc[0.005, "vv10"] < 1e-13
+
+
 def test_two_full_size_inits_are_bitwise_equal():
     # the tuner's pick is kept per configuration, so a second 256^3 lattice of the
     # same workload takes the same tile and reproduces the first bit for bit
