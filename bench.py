@@ -274,8 +274,8 @@ def main():
                     help="also run a plain 1 GiB device-to-device copy, the reference for HBM counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs the lattice on a single MI355X "
-              f"(--gpus {args.gpus} is not supported; multi-GPU sharding is described in DESIGN.md)",
+        print(f"bench.py measures one GPU: the lattice runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported: no multi-GPU sharding is implemented)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -111,7 +111,7 @@ def train(X, T, epochs: int = DEFAULTS["epochs"], lr0: float = DEFAULTS["lr0"], 
 def score(pred, lin, nseeds: int, scatter_max: float = 0.02) -> dict:
     """Relative errors |10^pred - ref| / ref of log10 predictions pred
     (nq, nsnap, NK) against the seed mean ref of the lattice spectra lin
-    (nq, nseeds, nsnap, NK, linear).  A point is judged when the scatter of
+    (nq, nseeds, nsnap, NK, linear).  A point is scored when the scatter of
     the seeds (their standard deviation) is below scatter_max of the mean; the
     suffix _sem marks the looser rule "standard error of the mean below
     scatter_max"."""
@@ -124,8 +124,8 @@ def score(pred, lin, nseeds: int, scatter_max: float = 0.02) -> dict:
     for suf, mask in (("", ok), ("_sem", ok_sem)):
         e = err[mask]
         out.update({
-            "judged_fraction" + suf: float(mask.mean()),
-            "n_judged" + suf: int(mask.sum()),
+            "scored_fraction" + suf: float(mask.mean()),
+            "n_scored" + suf: int(mask.sum()),
             "mean_rel_err" + suf: float(e.mean()) if e.size else float("nan"),
             "median_rel_err" + suf: float(np.median(e)) if e.size else float("nan"),
             "p95_rel_err" + suf: float(np.quantile(e, 0.95)) if e.size else float("nan"),
@@ -134,7 +134,7 @@ def score(pred, lin, nseeds: int, scatter_max: float = 0.02) -> dict:
     return out
 
 
-def judge(model: Surrogate, cfgs, nseeds: int, nsnap: int = 50, every: int = 100, scatter_max: float = 0.02,
+def score_heldout(model: Surrogate, cfgs, nseeds: int, nsnap: int = 50, every: int = 100, scatter_max: float = 0.02,
           device: str = "cuda:0", T=None):
     """Compare the surrogate with the seed mean of plain lattice runs.
 
@@ -271,7 +271,7 @@ class SpectrumEmulator:
 
 def main(argv=None):
     """Generate training spectra with the batched lattice, train the
-    surrogate, judge it on held-out q against seed-averaged lattice runs and
+    surrogate, score it on held-out q against seed-averaged lattice runs and
     time both; prints progress lines and one JSON summary line."""
     import argparse
     import json
@@ -325,15 +325,15 @@ def main(argv=None):
         np.savez_compressed(a.save_data, X=X.cpu().numpy(), T=T.cpu().numpy(),
                             XH=snapshot_inputs(ho, a.nsnap, a.every), TH=TH.cpu().numpy(),
                             nseeds=a.seeds, nsnap=a.nsnap)
-    J = judge(m, ho, a.seeds, a.nsnap, a.every, T=TH, device=dev)
-    say(f"held-out: judged {J['n_judged']} points ({100 * J['judged_fraction']:.1f}%), mean rel err "
+    J = score_heldout(m, ho, a.seeds, a.nsnap, a.every, T=TH, device=dev)
+    say(f"held-out: scored {J['n_scored']} points ({100 * J['scored_fraction']:.1f}%), mean rel err "
         f"{100 * J['mean_rel_err']:.2f}%, p95 {100 * J['p95_rel_err']:.2f}%")
     # the plain alternative: interpolate the training spectra in log10 q
     nq = len(ho) // a.seeds
     pb = interpolate_in_q(tr, T.cpu().numpy(), [c["q"] for c in ho[::a.seeds]], a.nsnap)
     B = score(pb, 10.0 ** TH.cpu().numpy().astype(np.float64).reshape(nq, a.seeds, a.nsnap, NK), a.seeds)
     say(f"interpolation in log10 q between training runs: mean rel err {100 * B['mean_rel_err']:.2f}% "
-        f"(looser judge {100 * B['mean_rel_err_sem']:.2f}%)")
+        f"(looser gate {100 * B['mean_rel_err_sem']:.2f}%)")
     # inference throughput against the lattice's own rate of producing spectra
     rng = np.random.default_rng(123)
     xq = np.stack([1.0 + 3.0 * rng.random(a.queries), 0.5 + 24.5 * rng.random(a.queries)], 1).astype(np.float32)
@@ -357,7 +357,7 @@ def main(argv=None):
         "data_seconds": tgen, "data_site_updates_per_s": site_updates / tgen,
         "recipe": recipe, "selection": table, "train_seconds": ttrain, "final_loss": hist[-1],
         "heldout_q": a.heldout_q, "seeds": a.seeds,
-        **{k: J[k] for k in J if k.startswith(("judged_fraction", "n_judged", "mean_rel_err", "median_rel_err",
+        **{k: J[k] for k in J if k.startswith(("scored_fraction", "n_scored", "mean_rel_err", "median_rel_err",
                                                  "p95_rel_err", "max_rel_err"))},
         "interp_mean_rel_err": B["mean_rel_err"], "interp_mean_rel_err_sem": B["mean_rel_err_sem"],
         "interp_median_rel_err": B["median_rel_err"],

@@ -159,7 +159,7 @@ def config5_train_runs(nruns: int = 2000, N: int = 64, nsteps: int = 5000, seed0
 
 def config5_heldout_runs(nq: int = 64, nseeds: int = 8, N: int = 64, nsteps: int = 5000,
                          seed0: int = 20000) -> list:
-    """Held-out judge runs: nq new q values (log-uniform in [10, 1e4] from a
+    """Held-out scoring runs: nq new q values (log-uniform in [10, 1e4] from a
     generator seeded with seed0), nseeds lattice realisations each, seeds
     seed0 + nseeds * iq + s.  Returned grouped by q."""
     rng = np.random.default_rng(seed0)
@@ -169,6 +169,6 @@ def config5_heldout_runs(nq: int = 64, nseeds: int = 8, N: int = 64, nsteps: int
         for s in range(nseeds):
             c = config2(q=float(qs[iq]), integrator="vv2", N=N, seed=seed0 + nseeds * iq + s)
             c["nsteps"] = nsteps
-            c["name"] = f"surr_judge_{iq}_{s}"
+            c["name"] = f"surr_heldout_{iq}_{s}"
             runs.append(c)
     return runs

@@ -10,7 +10,7 @@
 // never dereferenced by those paths.
 //
 // PLANT=1 (a compile-time switch) adds one read past the end of a heap
-// buffer, so that a test can show the sanitizer is live in this build.
+// buffer, so that a test can show the sanitizer is live in the sanitized binary.
 #include <atomic>
 #include <cmath>
 #include <cstdio>

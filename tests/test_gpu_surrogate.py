@@ -236,8 +236,8 @@ def test_surrogate_trained_on_lattice_spectra_answers_held_out_q():
     lattice run.  The full pipeline (2000 training runs at 64^3, 5000 VV2
     steps each, 10^5 device spectra; the recipe chosen on a validation split
     of the training runs; 64 held-out couplings x 8 seeds) must land within 5%
-    mean relative error of the 8-seed lattice mean on the judged points (seed
-    scatter below 2%), and within 6% under the looser judge (standard error
+    mean relative error of the 8-seed lattice mean on the scored points (seed
+    scatter below 2%), and within 6% under the looser gate (standard error
     below 2%), while answering 65536 queries at least 10^4 times faster than
     the batched lattice produces spectra.  Linear interpolation in log10 q
     between the two nearest training runs is reported beside it: with 2000
@@ -255,16 +255,16 @@ def test_surrogate_trained_on_lattice_spectra_answers_held_out_q():
     assert hist[-1] < 0.2 * hist[0]
     ho = synth.config5_heldout_runs(64, 8)
     _, TH, _ = emulator.generate(ho, nsnap=50, every=100)
-    J = emulator.judge(m, ho, 8, nsnap=50, every=100, T=TH)
+    J = emulator.score_heldout(m, ho, 8, nsnap=50, every=100, T=TH)
     pb = emulator.interpolate_in_q(tr, T.cpu().numpy(), [c["q"] for c in ho[::8]], 50)
     B = emulator.score(pb, 10.0 ** TH.cpu().numpy().astype(np.float64).reshape(64, 8, 50, 64), 8)
-    print("network: judged %d, mean %.4f (looser %.4f); interpolation in q: %.4f (looser %.4f)"
-          % (J["n_judged"], J["mean_rel_err"], J["mean_rel_err_sem"], B["mean_rel_err"], B["mean_rel_err_sem"]),
+    print("network: scored %d, mean %.4f (looser %.4f); interpolation in q: %.4f (looser %.4f)"
+          % (J["n_scored"], J["mean_rel_err"], J["mean_rel_err_sem"], B["mean_rel_err"], B["mean_rel_err_sem"]),
           flush=True)
-    assert J["n_judged"] > 20000
+    assert J["n_scored"] > 20000
     assert J["mean_rel_err"] < 0.05, J["mean_rel_err"]
     assert J["mean_rel_err_sem"] < 0.06, J["mean_rel_err_sem"]
-    assert B["n_judged"] == J["n_judged"]
+    assert B["n_scored"] == J["n_scored"]
     x = torch.rand(65536, 2, device="cuda:0") * torch.tensor([3.0, 24.5], device="cuda:0") + \
         torch.tensor([1.0, 0.5], device="cuda:0")
     m.predict(x)
