@@ -186,7 +186,7 @@ def time_surrogate(queries: int = 65536, reps: int = 20) -> dict:
             "bf16_tflops": tflops, "mfma_frac": tflops / 2500.0, "kernel": "predict_kernel"}
 
 
-def time_spectrum(N: int = 256, reps: int = 10) -> dict:
+def time_spectrum(N: int = 256, reps: int = 50) -> dict:
     """One power spectrum of a 256^3 FP32 field (Sec. 3.1): the stored FP32
     values through an FP64 3D FFT, shell binning and the log-k interpolation,
     all queued on the lattice's stream and timed there with HIP events."""
@@ -197,7 +197,7 @@ def time_spectrum(N: int = 256, reps: int = 10) -> dict:
 
     lat = Lattice(dict(synth.config2(q=100.0), N=N), device="cuda:0")
     out = torch.empty(64, dtype=torch.float32, device="cuda:0")
-    for _ in range(2):
+    for _ in range(5):
         lat.spectrum_logk(out)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
